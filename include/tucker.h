@@ -1,0 +1,169 @@
+/*
+ * tucker.h -- C ABI of a GPU (gfx950) library for Tucker decompositions of
+ * sparse third-order tensors by HOOI and Multislice Projection (MP).
+ *
+ * Problem (Turney 2007, Section 4, opening paragraph): given a tensor X of
+ * size I1 x I2 x I3 and a core size J1 x J2 x J3, find a core G and factor
+ * matrices A(n) of size In x Jn with orthonormal columns such that
+ * X ~ [[G; A(1), A(2), A(3)]] (Tucker operator, Section 3). The input is a
+ * list of nonzeros <i, j, k, x> (Section 4.3, slice construction).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * [dev]  = device pointer (memory of the current HIP device, allocated by the
+ *          caller); [host] = host pointer.
+ * Ownership: the caller owns every buffer. The library keeps no state
+ *          between calls and allocates no device memory: all scratch space
+ *          is carved from the caller's `workspace`, whose size is returned by
+ *          tucker_workspace_bytes(). Calls with distinct workspaces and
+ *          streams may run concurrently.
+ * Stream:  `stream` is a hipStream_t passed as void* (NULL = the null
+ *          stream). Work is enqueued on it; every entry point returns after
+ *          its results are complete and visible to the host (the sweep loops
+ *          read one fit value per sweep back to the host).
+ * Indices: 0-based int32 coordinates, structure of arrays: idx[n][p] is the
+ *          mode-n coordinate of nonzero p. Duplicate coordinates are summed;
+ *          explicit zeros are allowed.
+ * Layouts: factor n is In x Jn row-major (row i contiguous). Columns are in
+ *          descending order of the eigenvalue they belong to, and each
+ *          column's largest-magnitude entry is positive. The core is
+ *          J1 x J2 x J3 row-major: G[p][q][r] at (p*J2 + q)*J3 + r.
+ * Errors:  every entry point returns a status code (TK_OK = 0, warnings > 0,
+ *          errors < 0). TK_ERR_ARG is detected on the host before any device
+ *          work is enqueued, and then no output is written. TK_ERR_INDEX and
+ *          TK_ERR_VALUE are detected by the first kernels, before any output
+ *          is written. tucker_strerror() gives a text.
+ */
+#ifndef TUCKER_H
+#define TUCKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define TK_OK              0
+#define TK_WARN_NOCONV     1  /* an eigensolve hit its iteration cap; outputs are valid */
+#define TK_ERR_ARG        -1  /* null pointer, order != 3, nnz < 0 or >= 2^31, In < 1,
+                                 Jn < 1 or Jn > In, max_iters < 0, bad precision/init */
+#define TK_ERR_INDEX      -2  /* a coordinate outside [0, In) */
+#define TK_ERR_VALUE      -3  /* a NaN or infinite value */
+#define TK_ERR_EMPTY      -4  /* ||X|| = 0: the fit is undefined */
+#define TK_ERR_WORKSPACE  -5  /* workspace NULL or smaller than tucker_workspace_bytes() */
+#define TK_ERR_DEVICE     -6  /* a HIP call failed; tucker_strerror() has the HIP text */
+
+/* ---- precision of the projection / Gram / TTMc path ------------------- */
+#define TK_FP64        0  /* FP64 everywhere */
+#define TK_FP32        1  /* FP32 projections, FP32 MFMA Grams; eigensolve, core, fit FP64 */
+#define TK_MIXED_BF16  2  /* BF16 projections for the Grams, BF16 MFMA with FP32
+                             accumulation; eigensolve, core and fit FP64 */
+
+/* ---- initialisation --------------------------------------------------- */
+#define TK_INIT_HOSVD  0  /* B, C from the leading eigenvectors of X_(n) X_(n)^T */
+#define TK_INIT_GIVEN  1  /* B, C read from factors[1], factors[2] (resume) */
+
+/* ---- algorithm selector of the workspace query ------------------------ */
+#define TK_ALGO_HOOI   0
+#define TK_ALGO_MP     1
+#define TK_ALGO_FIT    2
+
+/* Sparse third-order tensor in coordinate form. */
+typedef struct tk_coo {
+    int32_t        order;   /* must be 3 */
+    int64_t        nnz;     /* number of listed entries, 0 <= nnz < 2^31 */
+    const int64_t *dims;    /* [host] order entries: I1, I2, I3 (each >= 1, < 2^31) */
+    const int32_t *idx[3];  /* [dev] nnz coordinates per mode, 0-based */
+    const double  *vals;    /* [dev] nnz values */
+} tk_coo;
+
+/* Options; tucker_default_opts() fills the paper's values. */
+typedef struct tk_opts {
+    int32_t precision;      /* TK_FP64 | TK_FP32 | TK_MIXED_BF16 */
+    int32_t init;           /* TK_INIT_HOSVD | TK_INIT_GIVEN */
+    int32_t max_iters;      /* sweep cap; the paper uses 50 */
+    double  tol;            /* stop after sweep t when fit(t) - fit(t-1) < tol,
+                               with fit(0) = 0 (paper: 1e-4); tol <= 0 runs
+                               exactly max_iters sweeps */
+    int32_t eig_max_iters;  /* cap on filtered subspace iterations per eigensolve */
+    double  eig_tol;        /* relative residual target of the eigensolve */
+    int32_t timing;         /* 1: record HIP events around the projection and
+                               TTMc kernels and report their times in tk_stats */
+} tk_opts;
+
+/* Optional statistics (pass NULL to skip). Times in milliseconds. */
+typedef struct tk_stats {
+    double  prep_ms;        /* validation, duplicate summing, three orderings, ||X||^2 */
+    double  init_ms;        /* initial Grams and eigensolves */
+    double  sweeps_ms;      /* all sweeps, including the per-sweep fit read-back */
+    double  ttmc_ms;        /* sum over sweeps of the projection (+ HOOI TTMc GEMM)
+                               kernel times; only with opts.timing = 1 */
+    double  project_ms;     /* sum of the projection kernel times alone (timing = 1) */
+    int64_t project_calls;  /* number of projection launches in the sweeps */
+    int64_t nnz_unique;     /* nonzeros after duplicate summing */
+    int32_t eig_iters;      /* total filtered subspace iterations */
+    int32_t eig_noconv;     /* eigensolves that hit eig_max_iters */
+    double  norm_x;         /* ||X||_F */
+} tk_stats;
+
+/* Fill *opt with: FP32, HO-SVD init, 50 sweeps, tol 1e-4, eig cap 400,
+   eig tol 1e-10, no timing. */
+void tucker_default_opts(tk_opts *opt);
+
+/* Bytes of device workspace that tucker_hooi (algo TK_ALGO_HOOI),
+   tucker_mp (TK_ALGO_MP) or tucker_fit (TK_ALGO_FIT) needs for this tensor
+   shape, nnz, core size and precision. Host only; enqueues nothing. Returns
+   TK_OK and writes *bytes, or TK_ERR_ARG. */
+int tucker_workspace_bytes(int32_t algo, const tk_coo *X, const int32_t *core_dims,
+                           const tk_opts *opt, size_t *bytes);
+
+/* HOOI (Section 4.2, Figure 3): B and C from the HO-SVD Grams X_(n)X_(n)^T
+   (mode 1 needs no start), then per sweep A, B, C in turn from the leading
+   eigenvectors of Z_(n) Z_(n)^T with Z = X projected on the two other
+   factors; core G = [[X; A^T, B^T, C^T]] and the fit after every sweep.
+     core_dims   [host] J1, J2, J3
+     core        [dev]  J1*J2*J3 doubles (output)
+     factors     [host] array of 3 [dev] pointers to In x Jn doubles (output;
+                 with TK_INIT_GIVEN factors[1] and factors[2] are also read)
+     fit_history [host] max_iters doubles; entry t-1 = fit after sweep t
+     iters_done  [host] number of sweeps run
+     stats       [host] optional, may be NULL                                */
+int tucker_hooi(const tk_coo *X, const int32_t *core_dims, const tk_opts *opt,
+                double *core, double *const *factors, double *fit_history,
+                int32_t *iters_done, tk_stats *stats,
+                void *workspace, size_t workspace_bytes, void *stream);
+
+/* Multislice Projection (Section 4.4, Figure 7): pseudo HO-SVD start of B
+   and C, then per sweep
+     M1 = sum_k X_::k B B^T X_::k^T + sum_j X_:j: C C^T X_:j:^T  -> A
+     M2 = sum_k X_::k^T A A^T X_::k + sum_i X_i:: C C^T X_i::^T  -> B
+     M3 = sum_j X_:j:^T A A^T X_:j: + sum_i X_i::^T B B^T X_i::  -> C
+   (leading eigenvectors), the core and the fit. Arguments as tucker_hooi. */
+int tucker_mp(const tk_coo *X, const int32_t *core_dims, const tk_opts *opt,
+              double *core, double *const *factors, double *fit_history,
+              int32_t *iters_done, tk_stats *stats,
+              void *workspace, size_t workspace_bytes, void *stream);
+
+/* fit(X, Xhat) = 1 - ||X - Xhat||_F / ||X||_F (Section 3, fit equation) of
+   Xhat = [[G; A(1), A(2), A(3)]] for ANY core and factors (orthonormality
+   is not assumed): ||X - Xhat||^2 = ||X||^2 - 2<X, Xhat> + ||Xhat||^2 with
+   <X, Xhat> = <X x_n A(n)^T, G> and ||Xhat||^2 = <G, G x_n A(n)^T A(n)>,
+   all in FP64.
+     core    [dev]  J1*J2*J3 doubles, row-major
+     factors [host] array of 3 [dev] pointers, In x Jn row-major doubles
+     fit     [host] output                                                   */
+int tucker_fit(const tk_coo *X, const int32_t *core_dims, const double *core,
+               const double *const *factors, double *fit,
+               void *workspace, size_t workspace_bytes, void *stream);
+
+/* Static text for a status code (for TK_ERR_DEVICE, the last HIP error text
+   seen by the calling thread). */
+const char *tucker_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TUCKER_H */

@@ -1,0 +1,934 @@
+// C ABI of the library (include/tucker.h) and the host drivers of HOOI
+// (Section 4.2, Figure 3) and Multislice Projection (Section 4.4, Figure 7).
+//
+// The host only validates arguments, carves the caller's workspace and
+// sequences kernels; all arithmetic on tensor data runs on the GPU. The only
+// device-to-host traffic is a few status words during preparation, the
+// Ritz values of the eigensolver's Rayleigh-Ritz steps, and one fit value
+// per sweep.
+#include "../../include/tucker.h"
+#include "common.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+namespace tk {
+
+static thread_local char g_err[320];
+
+void set_hip_error(hipError_t e, const char *where) {
+    if (g_err[0]) return;
+    snprintf(g_err, sizeof(g_err), "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr int kMaxJ = 128;
+constexpr int64_t kMaxHosvdDim = 8192;
+
+// ------------------------------------------------------------------ small kernels
+__global__ void k_fit(const double *normx2, const double *g2, const double *xhx, const double *xh2, double *fit,
+                      int general) {
+    double nx2 = *normx2;
+    double r2 = general ? (nx2 - 2.0 * (*xhx) + (*xh2)) : (nx2 - *g2);
+    if (r2 < 0) r2 = 0;
+    *fit = 1.0 - sqrt(r2) / sqrt(nx2);
+}
+
+// out[p][q][r] = in[perm...]: in is laid out [a][b][c] with (a,b,c) a
+// permutation of (p,q,r) given by where[3] (position of p, q, r in the input).
+__global__ void k_permute3(const double *in, double *out, int J0, int J1, int J2, int d0, int d1, int d2, int w0,
+                           int w1, int w2) {
+    const int64_t tot = (int64_t)J0 * J1 * J2;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        int p = (int)(t / ((int64_t)J1 * J2));
+        int rem = (int)(t - (int64_t)p * J1 * J2);
+        int q = rem / J2, r = rem - q * J2;
+        int c[3];
+        c[w0] = p;
+        c[w1] = q;
+        c[w2] = r;
+        out[t] = in[((int64_t)c[0] * d1 + c[1]) * d2 + c[2]];
+    }
+}
+
+__global__ void k_dot_partial(const double *a, const double *b, int64_t n, double *partials) {
+    double acc = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += a[i] * b[i];
+    __shared__ double ws[16];
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += ws[i];
+        partials[blockIdx.x] = t;
+    }
+}
+__global__ void k_sum_parts(const double *partials, int np, double *out) {
+    double acc = 0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) acc += partials[i];
+    __shared__ double ws[16];
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += ws[i];
+        *out = t;
+    }
+}
+static hipError_t dot(const double *a, const double *b, int64_t n, double *partials, double *out, hipStream_t s) {
+    k_dot_partial<<<kReduceBlocks, 256, 0, s>>>(a, b, n, partials);
+    TK_LAUNCHED();
+    k_sum_parts<<<1, 256, 0, s>>>(partials, kReduceBlocks, out);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------ plan
+static inline int hi_of(int m) { return (m + 2) % 3; }
+static inline int lo_of(int m) { return (m + 1) % 3; }
+
+struct Plan {
+    int algo, prec;
+    int64_t I[3], nnz;
+    int J[3];
+    int64_t nslots[3];
+    int b[3];
+    // device buffers
+    int32_t *flags, *nu;
+    double *scal;  // [0] normx2 [1] g2 [2] fit [3] xhx [4] xh2
+    double *partials;
+    int32_t *perm, *tmp, *heads, *pos, *counts, *cursor, *scan;
+    int32_t *cidx[3];
+    double *cval;
+    int32_t *ptr[3], *lidx[3];
+    double *lval64[3];
+    float *lval32[3];
+    void *T[3];        // projections for the Grams (type by precision)
+    float *Tcore;      // mixed MP: FP32 copy of the last projection, for the core
+    float *T0f;        // mixed HOOI: FP32 T(0) for mode 3 and the core
+    void *Y;           // HOOI second-stage output for the Gram
+    float *Y2f;        // mixed HOOI: FP32 Y2 (core input)
+    double *Mg;        // Gram (max In^2)
+    void *gram_scratch;
+    double *Xblk[3];
+    void *eigw;
+    double *theta;
+    float *F32[3];
+    bf16 *F16[3];
+    double *Z, *Gp, *core_split;
+    int64_t core_split_elems;
+    double *Gx, *Pn[3], *W1, *W2;
+    bool blk_ok[3] = {false, false, false};  // Xblk[n] holds a previous block
+};
+
+static size_t elem_size(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
+
+static GramTerm term_of(const Plan &p, int m, int n, const void *base) {
+    // T(m) is [i_hi][i_lo][r]; rows of the mode-n unfolding are i_n
+    GramTerm t;
+    t.base = base;
+    const int64_t Jm = p.J[m], Ilo = p.I[lo_of(m)], Ihi = p.I[hi_of(m)];
+    if (hi_of(m) == n) {
+        t.s_row = Ilo * Jm;
+        t.chunk_len = Ilo * Jm;
+        t.nchunks = 1;
+        t.s_chunk = 0;
+    } else {
+        t.s_row = Jm;
+        t.chunk_len = Jm;
+        t.nchunks = Ihi;
+        t.s_chunk = Ilo * Jm;
+    }
+    return t;
+}
+
+static void carve(Plan &p, Arena &ar) {
+    const int64_t nnz = p.nnz > 0 ? p.nnz : 1;
+    const int prec = p.prec;
+    int64_t maxslots = 1, maxI = 1;
+    for (int m = 0; m < 3; ++m) {
+        maxslots = std::max(maxslots, p.nslots[m]);
+        maxI = std::max(maxI, p.I[m]);
+    }
+    p.flags = ar.take<int32_t>(4);
+    p.nu = ar.take<int32_t>(4);
+    p.scal = ar.take<double>(8);
+    p.partials = ar.take<double>(kReduceBlocks);
+    p.perm = ar.take<int32_t>(nnz);
+    p.tmp = ar.take<int32_t>(nnz);
+    p.heads = ar.take<int32_t>(nnz + 1);
+    p.pos = ar.take<int32_t>(nnz + 1);
+    p.counts = ar.take<int32_t>(maxslots);
+    p.cursor = ar.take<int32_t>(maxslots);
+    p.scan = ar.take<int32_t>(std::max(scan_scratch_ints(maxslots), scan_scratch_ints(nnz + 1)));
+    for (int n = 0; n < 3; ++n) p.cidx[n] = ar.take<int32_t>(nnz);
+    p.cval = ar.take<double>(nnz);
+    for (int m = 0; m < 3; ++m) {
+        p.ptr[m] = ar.take<int32_t>(p.nslots[m] + 1);
+        p.lidx[m] = ar.take<int32_t>(nnz);
+        p.lval64[m] = ar.take<double>(nnz);
+        p.lval32[m] = prec != P64 ? ar.take<float>(nnz) : nullptr;
+    }
+    p.Tcore = nullptr;
+    p.T0f = nullptr;
+    p.Y = nullptr;
+    p.Y2f = nullptr;
+    for (int m = 0; m < 3; ++m) p.T[m] = nullptr;
+    const size_t es = elem_size(prec);
+    if (p.algo == TK_ALGO_MP) {
+        for (int m = 0; m < 3; ++m) p.T[m] = ar.take<char>((int64_t)(p.nslots[m] * p.J[m] * es));
+        if (prec == PBF16) p.Tcore = ar.take<float>(p.nslots[2] * p.J[2]);
+    } else if (p.algo == TK_ALGO_HOOI) {
+        p.T[2] = ar.take<char>((int64_t)(p.nslots[2] * p.J[2] * es));
+        if (prec == PBF16)
+            p.T0f = ar.take<float>(p.nslots[0] * p.J[0]);
+        else
+            p.T[0] = ar.take<char>((int64_t)(p.nslots[0] * p.J[0] * es));
+        int64_t ymax = 0;
+        for (int n = 0; n < 3; ++n)
+            ymax = std::max(ymax, p.I[n] * (int64_t)p.J[(n + 1) % 3] * p.J[(n + 2) % 3]);
+        p.Y = ar.take<char>(ymax * (prec == P64 ? 8 : 4));
+        if (prec == PBF16) p.Y2f = nullptr;
+    } else {  // fit
+        p.T[2] = ar.take<double>(p.nslots[2] * p.J[2]);
+    }
+    if (p.algo != TK_ALGO_FIT) {
+        p.Mg = ar.take<double>(maxI * maxI);
+        size_t gs = 0;
+        for (int n = 0; n < 3; ++n) {
+            int64_t K[2];
+            int gprec = prec;
+            if (p.algo == TK_ALGO_MP) {
+                int m1 = (n + 1) % 3, m2 = (n + 2) % 3;
+                K[0] = p.nslots[m1] / p.I[n] * p.J[m1];
+                K[1] = p.nslots[m2] / p.I[n] * p.J[m2];
+                gs = std::max(gs, gram_scratch_bytes((int)p.I[n], gprec, 2, K));
+            } else {
+                K[0] = (int64_t)p.J[(n + 1) % 3] * p.J[(n + 2) % 3];
+                gprec = prec == P64 ? P64 : P32;
+                gs = std::max(gs, gram_scratch_bytes((int)p.I[n], gprec, 1, K));
+            }
+        }
+        p.gram_scratch = ar.take<char>((int64_t)gs);
+        size_t ew = 0;
+        int bmax = 1;
+        for (int n = 0; n < 3; ++n) {
+            p.b[n] = eig_block_width((int)p.I[n], p.J[n]);
+            bmax = std::max(bmax, p.b[n]);
+            p.Xblk[n] = ar.take<double>(p.I[n] * p.b[n]);
+            ew = std::max(ew, eig_work_bytes((int)p.I[n], p.b[n]));
+        }
+        p.eigw = ar.take<char>((int64_t)ew);
+        p.theta = ar.take<double>(std::max<int64_t>(bmax, maxI));
+        for (int n = 0; n < 3; ++n) {
+            p.F32[n] = prec != P64 ? ar.take<float>(p.I[n] * p.J[n]) : nullptr;
+            p.F16[n] = prec == PBF16 ? ar.take<bf16>(p.I[n] * p.J[n]) : nullptr;
+        }
+    }
+    const int64_t J0 = p.J[0], J1 = p.J[1], J2 = p.J[2];
+    // core / fit contractions
+    p.Z = ar.take<double>(std::max(p.I[1] * J0 * J2, (int64_t)1));
+    p.Gp = ar.take<double>(J0 * J1 * J2);
+    p.core_split_elems = 8 * J0 * J1 * J2;
+    p.core_split = ar.take<double>(p.core_split_elems);
+    if (p.algo == TK_ALGO_FIT) {
+        p.Gx = ar.take<double>(J0 * J1 * J2);
+        for (int n = 0; n < 3; ++n) p.Pn[n] = ar.take<double>((int64_t)p.J[n] * p.J[n]);
+        p.W1 = ar.take<double>(J0 * J1 * J2);
+        p.W2 = ar.take<double>(J0 * J1 * J2);
+    }
+}
+
+static int check_coo(const tk_coo *X, const int32_t *J) {
+    if (!X || !J || !X->dims || X->order != 3) return TK_ERR_ARG;
+    if (X->nnz < 0 || X->nnz >= (int64_t)INT32_MAX - 1) return TK_ERR_ARG;
+    if (X->nnz > 0 && (!X->idx[0] || !X->idx[1] || !X->idx[2] || !X->vals)) return TK_ERR_ARG;
+    for (int n = 0; n < 3; ++n) {
+        if (X->dims[n] < 1 || X->dims[n] >= INT32_MAX) return TK_ERR_ARG;
+        if (J[n] < 1 || J[n] > X->dims[n] || J[n] > kMaxJ) return TK_ERR_ARG;
+    }
+    for (int m = 0; m < 3; ++m)
+        if (X->dims[hi_of(m)] * X->dims[lo_of(m)] >= (int64_t)INT32_MAX) return TK_ERR_ARG;
+    return TK_OK;
+}
+
+static int check_opts(const tk_opts *o, const tk_coo *X) {
+    if (!o) return TK_ERR_ARG;
+    if (o->precision < 0 || o->precision > 2) return TK_ERR_ARG;
+    if (o->init != TK_INIT_HOSVD && o->init != TK_INIT_GIVEN) return TK_ERR_ARG;
+    if (o->max_iters < 0 || o->eig_max_iters < 1) return TK_ERR_ARG;
+    if (!(o->eig_tol >= 0.0) || std::isnan(o->tol)) return TK_ERR_ARG;
+    if (o->init == TK_INIT_HOSVD)
+        for (int n = 1; n < 3; ++n)
+            if (X->dims[n] > kMaxHosvdDim) return TK_ERR_ARG;
+    return TK_OK;
+}
+
+static void plan_init(Plan &p, int algo, int prec, const tk_coo *X, const int32_t *J) {
+    p.algo = algo;
+    p.prec = prec;
+    p.nnz = X->nnz;
+    for (int n = 0; n < 3; ++n) {
+        p.I[n] = X->dims[n];
+        p.J[n] = J[n];
+    }
+    for (int m = 0; m < 3; ++m) p.nslots[m] = p.I[hi_of(m)] * p.I[lo_of(m)];
+}
+
+}  // namespace tk
+
+using namespace tk;
+
+extern "C" {
+
+void tucker_default_opts(tk_opts *o) {
+    if (!o) return;
+    o->precision = TK_FP32;
+    o->init = TK_INIT_HOSVD;
+    o->max_iters = 50;
+    o->tol = 1e-4;
+    o->eig_max_iters = 400;
+    o->eig_tol = 1e-10;
+    o->timing = 0;
+}
+
+const char *tucker_strerror(int st) {
+    switch (st) {
+        case TK_OK: return "success";
+        case TK_WARN_NOCONV: return "an eigensolve reached its iteration cap (outputs are valid)";
+        case TK_ERR_ARG: return "invalid argument";
+        case TK_ERR_INDEX: return "a coordinate is outside its mode's range";
+        case TK_ERR_VALUE: return "a value is NaN or infinite";
+        case TK_ERR_EMPTY: return "the tensor has zero norm; the fit is undefined";
+        case TK_ERR_WORKSPACE: return "workspace missing or too small";
+        case TK_ERR_DEVICE: return g_err[0] ? g_err : "HIP error";
+        default: return "unknown status";
+    }
+}
+
+int tucker_workspace_bytes(int32_t algo, const tk_coo *X, const int32_t *core_dims, const tk_opts *opt,
+                           size_t *bytes) {
+    if (!bytes) return TK_ERR_ARG;
+    int st = check_coo(X, core_dims);
+    if (st) return st;
+    if (algo != TK_ALGO_HOOI && algo != TK_ALGO_MP && algo != TK_ALGO_FIT) return TK_ERR_ARG;
+    int prec = P64;
+    if (algo != TK_ALGO_FIT) {
+        if ((st = check_opts(opt, X))) return st;
+        prec = opt->precision;
+    }
+    Plan p;
+    plan_init(p, algo, prec, X, core_dims);
+    Arena ar;
+    carve(p, ar);
+    *bytes = ar.used + 256;
+    return TK_OK;
+}
+
+}  // extern "C"
+
+namespace tk {
+
+struct Timer {
+    bool on;
+    hipStream_t s;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;  // 0 projection, 1 ttmc gemm
+    size_t used = 0;
+    double proj_ms = 0, ttmc_ms = 0;
+    int64_t proj_calls = 0;
+    Timer(bool on_, hipStream_t s_) : on(on_), s(s_) {}
+    ~Timer() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    void begin(int k) {
+        if (!on) return;
+        if (used + 2 > ev.size()) {
+            for (int i = 0; i < 2; ++i) {
+                hipEvent_t e;
+                (void)hipEventCreate(&e);
+                ev.push_back(e);
+            }
+        }
+        (void)hipEventRecord(ev[used], s);
+        kind.resize(used / 2 + 1);
+        kind[used / 2] = k;
+    }
+    void end() {
+        if (!on) return;
+        (void)hipEventRecord(ev[used + 1], s);
+        used += 2;
+    }
+    // call after a stream synchronisation
+    void collect() {
+        if (!on) return;
+        for (size_t i = 0; i + 1 < used; i += 2) {
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            if (kind[i / 2] == 0) {
+                proj_ms += ms;
+                ++proj_calls;
+            }
+            ttmc_ms += ms;
+        }
+        used = 0;
+    }
+};
+
+static double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+#define ST(call)                          \
+    do {                                  \
+        hipError_t e_ = (call);           \
+        if (e_ != hipSuccess) {           \
+            set_hip_error(e_, #call);     \
+            return TK_ERR_DEVICE;         \
+        }                                 \
+    } while (0)
+
+// Validation, duplicate summing, orderings, ||X||^2.
+static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double *normx2_out) {
+    const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
+    ST(validate(X->idx, X->vals, p.nnz, dims, p.flags, s));
+    int32_t flags = 0;
+    ST(hipMemcpyAsync(&flags, p.flags, 4, hipMemcpyDeviceToHost, s));
+    ST(hipStreamSynchronize(s));
+    if (flags & 1) return TK_ERR_INDEX;
+    if (flags & 2) return TK_ERR_VALUE;
+    OrderScratch sc{p.counts, p.cursor, p.tmp, p.scan};
+    ST(build_order(X->idx, p.nnz, dims, 2, p.ptr[2], p.perm, sc, s));
+    int32_t *cidx[3] = {p.cidx[0], p.cidx[1], p.cidx[2]};
+    ST(dedup(X->idx, X->vals, p.nnz, p.perm, p.heads, p.pos, p.scan, cidx, p.cval, p.nu, s));
+    int32_t nu = 0;
+    ST(hipMemcpyAsync(&nu, p.nu, 4, hipMemcpyDeviceToHost, s));
+    ST(hipStreamSynchronize(s));
+    ST(sumsq(p.cval, nu, p.partials, p.scal + 0, s));
+    const int32_t *cid[3] = {p.cidx[0], p.cidx[1], p.cidx[2]};
+    for (int m = 0; m < 3; ++m) {
+        ST(build_order(cid, nu, dims, m, p.ptr[m], p.perm, sc, s));
+        ST(gather_leaf<double>(p.cidx[m], p.cval, p.perm, nu, p.lidx[m], p.lval64[m], s));
+        if (p.lval32[m]) ST(gather_leaf<float>(p.cidx[m], p.cval, p.perm, nu, p.lidx[m], p.lval32[m], s));
+    }
+    double nx2 = 0;
+    ST(hipMemcpyAsync(&nx2, p.scal + 0, 8, hipMemcpyDeviceToHost, s));
+    ST(hipStreamSynchronize(s));
+    *nu_out = nu;
+    *normx2_out = nx2;
+    if (!(nx2 > 0.0)) return TK_ERR_EMPTY;
+    return TK_OK;
+}
+
+// T(m) = X x_m F^T for the given output precision. F64 is the FP64 factor;
+// its FP32 copy must be current for FP32 / BF16 outputs.
+static hipError_t project_m(Plan &p, int m, const double *F64, void *T, int out_prec, hipStream_t s) {
+    const int J = p.J[m];
+    if (out_prec == P64)
+        return project<double, double, double>(p.ptr[m], p.lidx[m], p.lval64[m], F64, J, p.nslots[m], (double *)T, s);
+    if (out_prec == P32)
+        return project<float, float, float>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, p.nslots[m], (float *)T, s);
+    return project<float, float, bf16>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, p.nslots[m], (bf16 *)T, s);
+}
+
+static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s) {
+    const int64_t cnt = p.I[n] * p.J[n];
+    if (p.F32[n]) TK_HIP(convert_f64<float>(F, p.F32[n], cnt, s));
+    if (p.F16[n]) TK_HIP(convert_f64<bf16>(F, p.F16[n], cnt, s));
+    return hipSuccess;
+}
+
+// MP core from T(2) = X x_3 C^T stored [i1][i0][r2] (FP64 or FP32):
+// Z[i1][p][r] = sum_i0 A[i0][p] T[i1][i0][r]; G'[q][p][r] = sum_i1 B[i1][q] Z[i1][p][r];
+// core[p][q][r] = G'[q][p][r].
+static hipError_t core_from_T2(Plan &p, const void *T2, bool t2_is_f64, const double *A, const double *B,
+                               double *core, hipStream_t s) {
+    const int J0 = p.J[0], J1 = p.J[1], J2 = p.J[2];
+    GemmArgs g;
+    g.M = J0;
+    g.N = J2;
+    g.K = (int)p.I[0];
+    g.batch = (int)p.I[1];
+    g.A = A;
+    g.lda = J0;
+    g.a_trans = true;
+    g.B = T2;
+    g.ldb = J2;
+    g.sB = p.I[0] * J2;
+    g.C = p.Z;
+    g.ldc = J2;
+    g.sC = (int64_t)J0 * J2;
+    g.prec = t2_is_f64 ? P64 : 3;
+    g.out_type = P64;
+    TK_HIP(gemm(g, s));
+    GemmArgs h;
+    h.M = J1;
+    h.N = J0 * J2;
+    h.K = (int)p.I[1];
+    h.batch = 1;
+    h.A = B;
+    h.lda = J1;
+    h.a_trans = true;
+    h.B = p.Z;
+    h.ldb = (int64_t)J0 * J2;
+    h.sB = 0;
+    h.C = p.Gp;
+    h.ldc = (int64_t)J0 * J2;
+    h.sC = 0;
+    h.prec = P64;
+    h.out_type = P64;
+    int tiles = (int)(ceil_div(J1, 64) * ceil_div((int64_t)J0 * J2, 64));
+    h.splitk = std::max(1, std::min(8, 256 / std::max(1, tiles)));
+    h.split_scratch = p.core_split;
+    TK_HIP(gemm(h, s));
+    // G' is [q][p][r]: core[p][q][r] = G'[q][p][r]
+    k_permute3<<<(unsigned)std::min<int64_t>(ceil_div((int64_t)J0 * J1 * J2, 256), 65536), 256, 0, s>>>(
+        p.Gp, core, J0, J1, J2, J1, J0, J2, 1, 0, 2);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
+static int finish_fit(Plan &p, const double *core, hipStream_t s, double *fit) {
+    const int64_t nJ = (int64_t)p.J[0] * p.J[1] * p.J[2];
+    ST(sumsq(core, nJ, p.partials, p.scal + 1, s));
+    k_fit<<<1, 1, 0, s>>>(p.scal + 0, p.scal + 1, nullptr, nullptr, p.scal + 2, 0);
+    ST(hipGetLastError());
+    ST(hipMemcpyAsync(fit, p.scal + 2, 8, hipMemcpyDeviceToHost, s));
+    ST(hipStreamSynchronize(s));
+    return TK_OK;
+}
+
+static int run_eig(Plan &p, int n, const double *M, double *F, bool warm, const tk_opts *o, tk_stats *st,
+                   int *noconv_any, hipStream_t s) {
+    EigOpts eo;
+    eo.max_iters = o->eig_max_iters;
+    eo.tol = o->eig_tol;
+    eo.warm = warm && p.blk_ok[n];
+    eo.seed = 0x5eed0000ull + (uint64_t)n;
+    int it = 0, nc = 0;
+    ST(lead_eig(M, (int)p.I[n], p.J[n], p.Xblk[n], F, p.theta, p.eigw, eo, &it, &nc, s));
+    if (st) {
+        st->eig_iters += it;
+        st->eig_noconv += nc;
+    }
+    if (nc) *noconv_any = 1;
+    p.blk_ok[n] = true;
+    ST(refresh_copies(p, n, F, s));
+    return TK_OK;
+}
+
+static int common_start(int algo, const tk_coo *X, const int32_t *J, const tk_opts *o, double *core,
+                        double *const *factors, double *fit_history, int32_t *iters_done, void *ws, size_t wsb,
+                        Plan &p) {
+    int st = check_coo(X, J);
+    if (st) return st;
+    if ((st = check_opts(o, X))) return st;
+    if (!core || !factors || !factors[0] || !factors[1] || !factors[2] || !iters_done) return TK_ERR_ARG;
+    if (o->max_iters > 0 && !fit_history) return TK_ERR_ARG;
+    if (X->nnz == 0) return TK_ERR_EMPTY;
+    plan_init(p, algo, o->precision, X, J);
+    Arena ar;
+    carve(p, ar);
+    if (!ws || wsb < ar.used + 256) return TK_ERR_WORKSPACE;
+    ar.base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+    ar.used = 0;
+    carve(p, ar);
+    g_err[0] = 0;
+    return TK_OK;
+}
+
+static int init_factors(Plan &p, const tk_opts *o, double *const *factors, tk_stats *st, int *noconv, hipStream_t s) {
+    const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
+    for (int n = 1; n < 3; ++n) {
+        if (o->init == TK_INIT_GIVEN) {
+            ST(refresh_copies(p, n, factors[n], s));
+            continue;
+        }
+        const int sl = (n + 1) % 3;  // ordering whose slots are the mode-n slices
+        ST(hosvd_gram(n, dims, p.ptr[n], p.lidx[n], p.lval64[n], p.ptr[sl], p.lidx[sl], p.lval64[sl], p.Mg, s));
+        int r = run_eig(p, n, p.Mg, factors[n], false, o, st, noconv, s);
+        if (r) return r;
+    }
+    return TK_OK;
+}
+
+}  // namespace tk
+
+extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, double *core, double *const *factors,
+                         double *fit_history, int32_t *iters_done, tk_stats *stats, void *ws, size_t wsb,
+                         void *stream) {
+    Plan p;
+    int st = common_start(TK_ALGO_MP, X, J, o, core, factors, fit_history, iters_done, ws, wsb, p);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    Timer tm(o->timing != 0, s);
+    double t0 = now_ms();
+    int64_t nu = 0;
+    double nx2 = 0;
+    if ((st = prep(p, X, s, &nu, &nx2))) return st;
+    double t1 = now_ms();
+    int noconv = 0;
+    if ((st = init_factors(p, o, factors, stats, &noconv, s))) return st;
+    ST(hipStreamSynchronize(s));
+    double t2 = now_ms();
+    const int prec = p.prec;
+    double *A = factors[0], *B = factors[1], *C = factors[2];
+    // projections of the start: T(1)(B), T(2)(C)
+    tm.begin(0);
+    ST(project_m(p, 1, B, p.T[1], prec, s));
+    tm.end();
+    tm.begin(0);
+    ST(project_m(p, 2, C, p.T[2], prec, s));
+    tm.end();
+    const int gprec = prec;
+    double prev = 0.0;
+    int t = 0;
+    *iters_done = 0;
+    for (t = 1; t <= o->max_iters; ++t) {
+        // M1 (mode 0) from T(1) and T(2)
+        GramTerm g0[2] = {term_of(p, 1, 0, p.T[1]), term_of(p, 2, 0, p.T[2])};
+        ST(gram((int)p.I[0], gprec, 2, g0, p.Mg, p.gram_scratch, s));
+        if ((st = run_eig(p, 0, p.Mg, A, t > 1, o, stats, &noconv, s))) return st;
+        tm.begin(0);
+        ST(project_m(p, 0, A, p.T[0], prec, s));
+        tm.end();
+        // M2 (mode 1) from T(0) and T(2)
+        GramTerm g1[2] = {term_of(p, 0, 1, p.T[0]), term_of(p, 2, 1, p.T[2])};
+        ST(gram((int)p.I[1], gprec, 2, g1, p.Mg, p.gram_scratch, s));
+        if ((st = run_eig(p, 1, p.Mg, B, true, o, stats, &noconv, s))) return st;
+        tm.begin(0);
+        ST(project_m(p, 1, B, p.T[1], prec, s));
+        tm.end();
+        // M3 (mode 2) from T(0) and T(1)
+        GramTerm g2[2] = {term_of(p, 0, 2, p.T[0]), term_of(p, 1, 2, p.T[1])};
+        ST(gram((int)p.I[2], gprec, 2, g2, p.Mg, p.gram_scratch, s));
+        if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
+        tm.begin(0);
+        ST(project_m(p, 2, C, p.T[2], prec, s));
+        tm.end();
+        // core from T(2)(C) (FP64 or FP32, never BF16)
+        const void *T2c = p.T[2];
+        bool f64 = prec == P64;
+        if (prec == PBF16) {
+            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.nslots[2], p.Tcore,
+                                             s)));
+            T2c = p.Tcore;
+        }
+        ST(core_from_T2(p, T2c, f64, A, B, core, s));
+        double fit = 0;
+        if ((st = finish_fit(p, core, s, &fit))) return st;
+        tm.collect();
+        fit_history[t - 1] = fit;
+        *iters_done = t;
+        if (o->tol > 0 && fit - prev < o->tol) break;
+        prev = fit;
+    }
+    if (o->max_iters == 0) {
+        // no sweep: A from the start factors, then the core
+        GramTerm g0[2] = {term_of(p, 1, 0, p.T[1]), term_of(p, 2, 0, p.T[2])};
+        ST(gram((int)p.I[0], gprec, 2, g0, p.Mg, p.gram_scratch, s));
+        if ((st = run_eig(p, 0, p.Mg, A, false, o, stats, &noconv, s))) return st;
+        const void *T2c = p.T[2];
+        if (prec == PBF16) {
+            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.nslots[2], p.Tcore,
+                                             s)));
+            T2c = p.Tcore;
+        }
+        ST(core_from_T2(p, T2c, prec == P64, A, B, core, s));
+        ST(hipStreamSynchronize(s));
+    }
+    double t3 = now_ms();
+    if (stats) {
+        stats->prep_ms = t1 - t0;
+        stats->init_ms = t2 - t1;
+        stats->sweeps_ms = t3 - t2;
+        stats->project_ms = tm.proj_ms;
+        stats->ttmc_ms = tm.ttmc_ms;
+        stats->project_calls = tm.proj_calls;
+        stats->nnz_unique = nu;
+        stats->norm_x = std::sqrt(nx2);
+    }
+    return noconv ? TK_WARN_NOCONV : TK_OK;
+}
+
+namespace tk {
+// HOOI second stage, see the driver below for the index bookkeeping.
+static hipError_t ttm(int M, int N, int K, int batch, const void *A, int64_t lda, const void *B, int64_t ldb,
+                      int64_t sB, void *C, int64_t ldc, int64_t sC, int prec, int out_type, hipStream_t s) {
+    GemmArgs g;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.batch = batch;
+    g.A = A;
+    g.lda = lda;
+    g.a_trans = true;
+    g.B = B;
+    g.ldb = ldb;
+    g.sB = sB;
+    g.C = C;
+    g.ldc = ldc;
+    g.sC = sC;
+    g.prec = prec;
+    g.out_type = out_type;
+    return gemm(g, s);
+}
+}  // namespace tk
+
+extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, double *core, double *const *factors,
+                           double *fit_history, int32_t *iters_done, tk_stats *stats, void *ws, size_t wsb,
+                           void *stream) {
+    Plan p;
+    int st = common_start(TK_ALGO_HOOI, X, J, o, core, factors, fit_history, iters_done, ws, wsb, p);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    Timer tm(o->timing != 0, s);
+    double t0 = now_ms();
+    int64_t nu = 0;
+    double nx2 = 0;
+    if ((st = prep(p, X, s, &nu, &nx2))) return st;
+    double t1 = now_ms();
+    int noconv = 0;
+    if ((st = init_factors(p, o, factors, stats, &noconv, s))) return st;
+    ST(hipStreamSynchronize(s));
+    double t2 = now_ms();
+    const int prec = p.prec;
+    const int64_t I0 = p.I[0], I1 = p.I[1], I2 = p.I[2];
+    const int J0 = p.J[0], J1 = p.J[1], J2 = p.J[2];
+    double *A = factors[0], *B = factors[1], *C = factors[2];
+    // element types: FP64 mode all double; FP32 mode float; mixed: T(2)
+    // in BF16 with BF16 MFMA for modes 1 and 2, T(0) in FP32 for mode 3
+    const int tprec = prec;                  // T(2) storage
+    const int kprec01 = prec == P64 ? P64 : prec;  // MFMA kind, modes 0/1
+    const int yprec = prec == P64 ? P64 : P32;      // Y storage / Gram precision
+    double prev = 0.0;
+    *iters_done = 0;
+    int maxit = o->max_iters > 0 ? o->max_iters : 0;
+    for (int t = 1; t <= std::max(maxit, 1); ++t) {
+        const bool last_only = (maxit == 0);
+        tm.begin(0);
+        ST(project_m(p, 2, C, p.T[2], tprec, s));
+        tm.end();
+        const void *Bop = prec == P64 ? (const void *)B : (prec == P32 ? (const void *)p.F32[1] : (const void *)p.F16[1]);
+        // mode 0: Y0[q][i0][r2] = sum_i1 B[i1][q] T2[i1][i0][r2]
+        tm.begin(1);
+        ST(ttm(J1, (int)(I0 * J2), (int)I1, 1, Bop, J1, p.T[2], I0 * J2, 0, p.Y, I0 * J2, 0, kprec01,
+               yprec == P64 ? P64 : P32, s));
+        tm.end();
+        {
+            GramTerm g;
+            g.base = p.Y;
+            g.s_row = J2;
+            g.chunk_len = J2;
+            g.nchunks = J1;
+            g.s_chunk = I0 * J2;
+            ST(gram((int)I0, yprec, 1, &g, p.Mg, p.gram_scratch, s));
+        }
+        if ((st = run_eig(p, 0, p.Mg, A, t > 1, o, stats, &noconv, s))) return st;
+        if (last_only) {
+            // max_iters == 0: A only, then the core below
+        }
+        const void *Aop = prec == P64 ? (const void *)A : (prec == P32 ? (const void *)p.F32[0] : (const void *)p.F16[0]);
+        // mode 1: Y1[i1][p][r2] = sum_i0 A[i0][p] T2[i1][i0][r2]
+        if (!last_only) {
+            tm.begin(1);
+            ST(ttm(J0, J2, (int)I0, (int)I1, Aop, J0, p.T[2], J2, I0 * J2, p.Y, J2, (int64_t)J0 * J2, kprec01,
+                   yprec == P64 ? P64 : P32, s));
+            tm.end();
+            GramTerm g;
+            g.base = p.Y;
+            g.s_row = (int64_t)J0 * J2;
+            g.chunk_len = (int64_t)J0 * J2;
+            g.nchunks = 1;
+            g.s_chunk = 0;
+            ST(gram((int)I1, yprec, 1, &g, p.Mg, p.gram_scratch, s));
+            if ((st = run_eig(p, 1, p.Mg, B, true, o, stats, &noconv, s))) return st;
+        }
+        // mode 2 (and the core): T(0)(A) = [i2][i1][r0] in FP64 / FP32
+        void *T0 = prec == PBF16 ? (void *)p.T0f : p.T[0];
+        const int t0prec = prec == P64 ? P64 : P32;
+        tm.begin(0);
+        ST(project_m(p, 0, A, T0, t0prec, s));
+        tm.end();
+        const void *Bop2 = prec == P64 ? (const void *)B : (const void *)p.F32[1];
+        // Y2[i2][q][r0] = sum_i1 B[i1][q] T0[i2][i1][r0]
+        tm.begin(1);
+        ST(ttm(J1, J0, (int)I1, (int)I2, Bop2, J1, T0, J0, I1 * J0, p.Y, J0, (int64_t)J1 * J0, t0prec,
+               yprec == P64 ? P64 : P32, s));
+        tm.end();
+        if (!last_only) {
+            GramTerm g;
+            g.base = p.Y;
+            g.s_row = (int64_t)J1 * J0;
+            g.chunk_len = (int64_t)J1 * J0;
+            g.nchunks = 1;
+            g.s_chunk = 0;
+            ST(gram((int)I2, yprec, 1, &g, p.Mg, p.gram_scratch, s));
+            if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
+        }
+        // core: G'[r][q][p] = sum_i2 C[i2][r] Y2[i2][q][p]; core[p][q][r] = G'[r][q][p]
+        {
+            GemmArgs h;
+            h.M = J2;
+            h.N = J1 * J0;
+            h.K = (int)I2;
+            h.batch = 1;
+            h.A = C;
+            h.lda = J2;
+            h.a_trans = true;
+            h.B = p.Y;
+            h.ldb = (int64_t)J1 * J0;
+            h.sB = 0;
+            h.C = p.Gp;
+            h.ldc = (int64_t)J1 * J0;
+            h.sC = 0;
+            h.prec = yprec == P64 ? P64 : 3;
+            h.out_type = P64;
+            int tiles = (int)(ceil_div(J2, 64) * ceil_div((int64_t)J1 * J0, 64));
+            h.splitk = std::max(1, std::min(8, 256 / std::max(1, tiles)));
+            h.split_scratch = p.core_split;
+            ST(gemm(h, s));
+            k_permute3<<<(unsigned)std::min<int64_t>(ceil_div((int64_t)J0 * J1 * J2, 256), 65536), 256, 0, s>>>(
+                p.Gp, core, J0, J1, J2, J2, J1, J0, 2, 1, 0);
+            ST(hipGetLastError());
+        }
+        if (last_only) {
+            ST(hipStreamSynchronize(s));
+            break;
+        }
+        double fit = 0;
+        if ((st = finish_fit(p, core, s, &fit))) return st;
+        tm.collect();
+        fit_history[t - 1] = fit;
+        *iters_done = t;
+        if (o->tol > 0 && fit - prev < o->tol) break;
+        prev = fit;
+    }
+    double t3 = now_ms();
+    if (stats) {
+        stats->prep_ms = t1 - t0;
+        stats->init_ms = t2 - t1;
+        stats->sweeps_ms = t3 - t2;
+        stats->project_ms = tm.proj_ms;
+        stats->ttmc_ms = tm.ttmc_ms;
+        stats->project_calls = tm.proj_calls;
+        stats->nnz_unique = nu;
+        stats->norm_x = std::sqrt(nx2);
+    }
+    return noconv ? TK_WARN_NOCONV : TK_OK;
+}
+
+extern "C" int tucker_fit(const tk_coo *X, const int32_t *J, const double *core, const double *const *factors,
+                          double *fit, void *ws, size_t wsb, void *stream) {
+    int st = check_coo(X, J);
+    if (st) return st;
+    if (!core || !factors || !factors[0] || !factors[1] || !factors[2] || !fit) return TK_ERR_ARG;
+    if (X->nnz == 0) return TK_ERR_EMPTY;
+    Plan p;
+    plan_init(p, TK_ALGO_FIT, P64, X, J);
+    Arena ar;
+    carve(p, ar);
+    if (!ws || wsb < ar.used + 256) return TK_ERR_WORKSPACE;
+    ar.base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+    ar.used = 0;
+    carve(p, ar);
+    g_err[0] = 0;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t nu = 0;
+    double nx2 = 0;
+    if ((st = prep(p, X, s, &nu, &nx2))) return st;
+    const int J0 = J[0], J1 = J[1], J2 = J[2];
+    const int64_t nJ = (int64_t)J0 * J1 * J2;
+    // Gx = X x_n A(n)^T via T(2)(C) and the two contractions of the MP core
+    ST((project<double, double, double>(p.ptr[2], p.lidx[2], p.lval64[2], factors[2], J2, p.nslots[2],
+                                        (double *)p.T[2], s)));
+    ST(core_from_T2(p, p.T[2], true, factors[0], factors[1], p.Gx, s));
+    ST(dot(p.Gx, core, nJ, p.partials, p.scal + 3, s));
+    // P_n = A(n)^T A(n)
+    for (int n = 0; n < 3; ++n) {
+        GemmArgs g;
+        g.M = J[n];
+        g.N = J[n];
+        g.K = (int)p.I[n];
+        g.batch = 1;
+        g.A = factors[n];
+        g.lda = J[n];
+        g.a_trans = true;
+        g.B = factors[n];
+        g.ldb = J[n];
+        g.sB = 0;
+        g.C = p.Pn[n];
+        g.ldc = J[n];
+        g.sC = 0;
+        g.prec = P64;
+        g.out_type = P64;
+        ST(gemm(g, s));
+    }
+    // W = G x_1 P0 x_2 P1 x_3 P2 (each P symmetric)
+    {
+        GemmArgs g;  // W1[p'][(q,r)] = sum_p P0[p][p'] G[p][(q,r)]
+        g.M = J0;
+        g.N = J1 * J2;
+        g.K = J0;
+        g.batch = 1;
+        g.A = p.Pn[0];
+        g.lda = J0;
+        g.a_trans = true;
+        g.B = core;
+        g.ldb = (int64_t)J1 * J2;
+        g.sB = 0;
+        g.C = p.W1;
+        g.ldc = (int64_t)J1 * J2;
+        g.sC = 0;
+        g.prec = P64;
+        g.out_type = P64;
+        ST(gemm(g, s));
+        GemmArgs h;  // W2[p][q'][r] = sum_q P1[q][q'] W1[p][q][r]
+        h.M = J1;
+        h.N = J2;
+        h.K = J1;
+        h.batch = J0;
+        h.A = p.Pn[1];
+        h.lda = J1;
+        h.a_trans = true;
+        h.B = p.W1;
+        h.ldb = J2;
+        h.sB = (int64_t)J1 * J2;
+        h.C = p.W2;
+        h.ldc = J2;
+        h.sC = (int64_t)J1 * J2;
+        h.prec = P64;
+        h.out_type = P64;
+        ST(gemm(h, s));
+        GemmArgs k;  // W3[(p,q)][r'] = sum_r W2[(p,q)][r] P2[r][r']
+        k.M = J0 * J1;
+        k.N = J2;
+        k.K = J2;
+        k.batch = 1;
+        k.A = p.W2;
+        k.lda = J2;
+        k.a_trans = false;
+        k.B = p.Pn[2];
+        k.ldb = J2;
+        k.sB = 0;
+        k.C = p.W1;
+        k.ldc = J2;
+        k.sC = 0;
+        k.prec = P64;
+        k.out_type = P64;
+        ST(gemm(k, s));
+    }
+    ST(dot(core, p.W1, nJ, p.partials, p.scal + 4, s));
+    k_fit<<<1, 1, 0, s>>>(p.scal + 0, nullptr, p.scal + 3, p.scal + 4, p.scal + 2, 1);
+    ST(hipGetLastError());
+    ST(hipMemcpyAsync(fit, p.scal + 2, 8, hipMemcpyDeviceToHost, s));
+    ST(hipStreamSynchronize(s));
+    return TK_OK;
+}

@@ -1,0 +1,168 @@
+// Internal declarations shared by the HIP sources of the sparse Tucker library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace tk {
+
+typedef __bf16 bf16;
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+enum Prec { P64 = 0, P32 = 1, PBF16 = 2 };
+
+// Records the first failing HIP call of the current thread; returned as text
+// by tucker_strerror(TK_ERR_DEVICE).
+void set_hip_error(hipError_t e, const char *where);
+
+#define TK_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) {                        \
+            ::tk::set_hip_error(e_, #call);            \
+            return e_;                                 \
+        }                                              \
+    } while (0)
+
+#define TK_LAUNCHED()                                  \
+    do {                                               \
+        hipError_t e_ = hipGetLastError();             \
+        if (e_ != hipSuccess) {                        \
+            ::tk::set_hip_error(e_, __func__);         \
+            return e_;                                 \
+        }                                              \
+    } while (0)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over the caller's workspace. With base == nullptr it only
+// counts bytes (used by the size query and by the carve-out, so both agree).
+struct Arena {
+    char *base = nullptr;
+    size_t used = 0;
+    template <class T>
+    T *take(int64_t count) {
+        size_t off = align_up(used, 256);
+        used = off + sizeof(T) * (size_t)(count > 0 ? count : 1);
+        return base ? reinterpret_cast<T *>(base + off) : nullptr;
+    }
+};
+
+// ---------------------------------------------------------------- prep.hip
+// Exclusive scan of n int32 counts into out[0..n]; out[n] = total.
+// scratch: at least scan_scratch_ints(n) ints.
+int64_t scan_scratch_ints(int64_t n);
+hipError_t scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch, hipStream_t s);
+
+hipError_t fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t fill_f64(double *p, int64_t n, double v, hipStream_t s);
+
+// One ordering of the nonzeros: slots are the mode-m fibres (i_hi, i_lo)
+// with hi = (m+2)%3, lo = (m+1)%3, slot = i_hi*I_lo + i_lo; within a slot the
+// entries are sorted by (i_m, input position). perm[q] = input position of
+// the q-th sorted entry. Needs slot_count(m)+1 ints in ptr and the scratch
+// buffers described at the definition.
+struct OrderScratch {
+    int32_t *counts;   // nslots
+    int32_t *cursor;   // nslots
+    int32_t *tmp;      // nnz
+    int32_t *scan;     // scan_scratch_ints(nslots)
+};
+hipError_t build_order(const int32_t *const idx[3], int64_t nnz, const int64_t dims[3], int m,
+                       int32_t *ptr, int32_t *perm, OrderScratch sc, hipStream_t s);
+
+// Validation: flags |= 1 (index out of range), 2 (non-finite value).
+hipError_t validate(const int32_t *const idx[3], const double *vals, int64_t nnz, const int64_t dims[3],
+                    int32_t *flags, hipStream_t s);
+
+// Duplicate summing over a leaf-2 ordering. heads/scan scratch of nnz+1 ints.
+// Writes unique coordinates cidx[3][u] and values cval[u] in sorted order and
+// u to *nu_dev.
+hipError_t dedup(const int32_t *const idx[3], const double *vals, int64_t nnz, const int32_t *perm,
+                 int32_t *heads, int32_t *pos, int32_t *scan_scratch, int32_t *const cidx[3], double *cval,
+                 int32_t *nu_dev, hipStream_t s);
+
+// Gather the leaf index and value of an ordering: lidx[q] = idx_m[perm[q]],
+// lval[q] = (T)vals[perm[q]].
+template <class T>
+hipError_t gather_leaf(const int32_t *idx_m, const double *vals, const int32_t *perm, int64_t n, int32_t *lidx,
+                       T *lval, hipStream_t s);
+
+// Deterministic sum of squares (FP64) into *out.
+hipError_t sumsq(const double *v, int64_t n, double *partials, double *out, hipStream_t s);
+constexpr int kReduceBlocks = 512;
+
+// Unfolding Gram H_n = X_(n) X_(n)^T (FP64, In x In, full). Uses the leaf-n
+// ordering (fibres) and the leaf-(n+1) ordering (slices of mode n).
+hipError_t hosvd_gram(int n, const int64_t dims[3], const int32_t *ptr_n, const int32_t *lidx_n,
+                      const double *lval_n, const int32_t *ptr_s, const int32_t *lidx_s, const double *lval_s,
+                      double *H, hipStream_t s);
+
+// ---------------------------------------------------------------- project.hip
+// T[slot][r] = sum over the slot's entries of lval * F[lidx][r], r < J;
+// slots = I_hi * I_lo, dense and zero-filled.
+template <class TV, class TF, class TO>
+hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int J, int64_t nslots,
+                   TO *T, hipStream_t s);
+
+// ---------------------------------------------------------------- mfma.hip
+// One operand of a Gram: row i, column k = (kc, kr) with kr < chunk_len,
+// element at base + i*s_row + kc*s_chunk + kr.
+struct GramTerm {
+    const void *base;
+    int64_t s_row;
+    int64_t s_chunk;
+    int64_t chunk_len;
+    int64_t nchunks;
+};
+// M (FP64, n x n, symmetric, full) = sum over terms of T_t T_t^T.
+// Element type by precision: P64 double, P32 float, PBF16 bf16.
+size_t gram_scratch_bytes(int n, int prec, int nterms, const int64_t *K);
+hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, void *scratch, hipStream_t s);
+
+// General batched GEMM out[b][i][j] = alpha * sum_k A(i,k) B[b](k,j) (+ epilogue)
+// A(i,k) = a_trans ? A[k*lda + i] : A[i*lda + k]; B[b](k,j) = B[b*sB + k*ldb + j].
+struct GemmArgs {
+    int M, N, K, batch;
+    const void *A;  int64_t lda; bool a_trans;
+    const void *B;  int64_t ldb, sB;
+    void *C;        int64_t ldc, sC;
+    int prec;       // element type of A and B (and MFMA kind)
+    int out_type;   // element type of C: P64 double, P32 float, PBF16 bf16
+    // epilogue (FP64 outputs only): C = alpha*acc + beta*E1 + gamma*E2
+    double alpha = 1.0, beta = 0.0, gamma = 0.0;
+    const double *E1 = nullptr, *E2 = nullptr;  // same layout as C
+    int splitk = 1;                   // >1: partial sums to scratch, then reduced
+    double *split_scratch = nullptr;  // splitk * batch * M * N doubles
+};
+hipError_t gemm(const GemmArgs &g, hipStream_t s);
+
+// ---------------------------------------------------------------- eig.hip
+struct EigWork;  // opaque, carved from the workspace
+size_t eig_work_bytes(int n, int b);
+int eig_block_width(int n, int J);
+// Leading J eigenvectors of the symmetric PSD matrix M (FP64 n x n).
+// X (n x b, b = eig_block_width) holds the start block on entry when warm,
+// and the converged block on exit. F receives the J leading eigenvectors
+// (n x J row-major, sign-canonical); theta (device, b) the Ritz values.
+// Returns 0 or a hip error; *iters / *noconv report convergence.
+struct EigOpts {
+    int max_iters = 400;
+    double tol = 1e-10;
+    int degree = 8;
+    bool warm = false;
+    uint64_t seed = 1234;
+};
+hipError_t lead_eig(const double *M, int n, int J, double *X, double *F, double *theta_dev, void *work,
+                    const EigOpts &o, int *iters, int *noconv, hipStream_t s);
+
+// ---------------------------------------------------------------- small helpers (eig.hip)
+template <class TO>
+hipError_t convert_f64(const double *in, TO *out, int64_t n, hipStream_t s);
+
+}  // namespace tk
