@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the sparse Tucker hot path on one GPU.
+
+Workload (default): sparse 1000 x 1000 x 1000 tensor with 1,000,000
+uniformly random distinct nonzeros, values U(0,1) (seeded, synthetic), core
+50 x 50 x 50, Multislice Projection, 10 sweeps, BF16 Grams with FP32
+accumulation and FP64 eigensolve / core / fit. One step = one complete
+decomposition (validation, orderings, HO-SVD start, 10 sweeps) with the
+tensor already resident in HBM.
+
+The JSON line reports:
+* value: projected nonzeros per second over the TTMc phase of the sweeps
+  (every projection launch projects all nonzeros onto one factor; the sum of
+  their HIP-event times is the TTMc phase), median over the timed steps;
+* time-to-fit of plain FP32 vs mixed BF16 runs that stop on the paper's
+  Delta-fit < 1e-4 rule;
+* roofline of the dominant kernel (live HIP-event times on the library's
+  stream x algorithmic bytes or flops per launch);
+* cpu_baseline: one sweep of the FP64 oracle on the host cores, same input.
+"""
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}
+METRIC = "projected nnz/s per TTMc sweep + time-to-fit (|Δfit|≤1e-4) mixed vs plain"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def project_bytes(nnz, nslots, J, I_m, out_bytes):
+    """Bytes one projection launch must move: leaf index + FP32 value per
+    nonzero, slot pointers, the dense projected tensor, the factor."""
+    return nnz * 8 + (nslots + 1) * 4 + nslots * J * out_bytes + I_m * J * 4
+
+
+def gram_flops(I, J, n):
+    """Useful flops of the MP Gram of mode n: both projected terms, lower
+    triangle with diagonal, multiply+add = 2 flops."""
+    total = 0
+    for m in range(3):
+        if m == n:
+            continue
+        K = (I[0] * I[1] * I[2] // (I[n] * I[m])) * J[m]
+        total += I[n] * (I[n] + 1) * K
+    return total
+
+
+def traffic_from_profile(kernel_file):
+    """HBM bytes per launch of the projection kernel measured by rocprofv3
+    counters, if the committed measurement matches the current source."""
+    path = os.path.join(ROOT, "profiles", "k_project_c2_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    with open(kernel_file, "rb") as f:
+        h = hashlib.sha256(f.read()).hexdigest()
+    if d.get("source_sha256") != h:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(idx, vals, dims, J, sweeps=1):
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    X = O.SparseTensor3(idx, vals, dims)
+    rng = np.random.default_rng(11)
+    B0 = np.linalg.qr(rng.standard_normal((dims[1], J[1])))[0]
+    C0 = np.linalg.qr(rng.standard_normal((dims[2], J[2])))[0]
+    t0 = time.perf_counter()
+    O.mp(X, J, sweeps, 0.0, init=(None, B0, C0))
+    dt = time.perf_counter() - t0
+    return {"value": 3 * X.nnz * sweeps / dt, "unit": "nnz/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{sweeps} full sweep(s) of the FP64 oracle's Multislice Projection (slice-wise Grams, "
+                      f"eigendecomposition of M M^T, slice-wise core and fit) on the same input; "
+                      f"3*nnz*sweeps / wall time; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2_1000cube")
+    ap.add_argument("--algo", default="mp", choices=["mp", "hooi"])
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
+    ap.add_argument("--sweeps", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-ttf", action="store_true", help="skip the time-to-fit runs")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration for profiles)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark measures one GPU; multi-GPU runs are not part of this build",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_0711_2023_amd as tk
+    import synth
+
+    tk.lib()  # fail loudly if the HIP library is missing
+    w = synth.WORKLOADS[args.workload]
+    dims, J, nnz = tuple(w["dims"]), tuple(w["core"]), int(w["nnz"])
+    log(f"generating {args.workload}: dims {dims} nnz {nnz} core {J}")
+    idx, vals, dims = synth.uniform_sparse(dims, nnz, w["seed"])
+    dev = torch.device("cuda:0")
+    di = torch.from_numpy(idx).to(dev)
+    dv = torch.from_numpy(vals).to(dev)
+    fn = tk.mp if args.algo == "mp" else tk.hooi
+    algo_id = tk.ALGO_MP if args.algo == "mp" else tk.ALGO_HOOI
+    wsb = tk.workspace_bytes(algo_id, di, dv, dims, J, precision=args.precision)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    log(f"workspace {wsb / 2**30:.2f} GiB")
+
+    if args.copy_calib:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration done (3 x 1 GiB)")
+
+    def step(prec, sweeps, tol):
+        return fn(di, dv, dims, J, precision=prec, max_iters=sweeps, tol=tol, timing=True, workspace=ws)
+
+    for i in range(args.warmup):
+        r = step(args.precision, args.sweeps, 0.0)
+        log(f"warmup {i}: fits {r.fits[-1]:.6e} sweeps_ms {r.stats['sweeps_ms']:.1f}")
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = step(args.precision, args.sweeps, 0.0)
+        results.append(r)
+        log(f"step {i}: fit {r.fits[-1]:.6e} prep {r.stats['prep_ms']:.1f} init {r.stats['init_ms']:.1f} "
+            f"sweeps {r.stats['sweeps_ms']:.1f} ms (proj {r.stats['project_ms']:.2f}, gram {r.stats['gram_ms']:.2f}, "
+            f"eig {r.stats['eig_ms']:.2f}, core {r.stats['core_ms']:.2f})")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1000.0 * wall / max(1, args.steps)
+
+    nu = results[0].stats["nnz_unique"]
+    if args.algo == "mp":
+        # every MP projection launch projects all nonzeros onto one factor
+        rates = [r.stats["project_calls"] * nu / (r.stats["ttmc_ms"] / 1000.0) for r in results]
+    else:
+        # a HOOI sweep projects the nonzeros onto all three factors (two
+        # projections plus three second-stage GEMMs)
+        rates = [3 * nu * r.iters / (r.stats["ttmc_ms"] / 1000.0) for r in results]
+    value = statistics.median(rates)
+    st = results[len(results) // 2].stats
+    sweeps = results[0].iters
+    out_bytes = {"mixed": 2, "fp32": 4, "fp64": 8}[args.precision]
+    # per-launch averages
+    proj_ms = st["project_ms"] / max(1, st["project_calls"])
+    gram_ms = st["gram_ms"] / max(1, st["gram_calls"])
+    nslots = [dims[(m + 2) % 3] * dims[(m + 1) % 3] for m in range(3)]
+    pbytes = statistics.mean(project_bytes(nu, nslots[m], J[m], dims[m], out_bytes) for m in range(3))
+    proj_gbs = pbytes / (proj_ms / 1000.0) / 1e9
+    gflops = statistics.mean(gram_flops(dims, J, n) for n in range(3))
+    gram_tf = gflops / (gram_ms / 1000.0) / 1e12
+    gpeak = PEAK_TFLOPS["bf16" if args.precision == "mixed" else args.precision]
+    kfile = os.path.join(ROOT, "paper_0711_2023_amd", "csrc", "project.hip")
+    traffic = traffic_from_profile(kfile)
+    roof_proj = {"kernel": "k_project", "bound": "hbm", "achieved": round(proj_gbs, 1), "peak": PEAK_HBM_GBS,
+                 "unit": "GB/s", "frac": round(proj_gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
+                 "algorithmic_bytes_per_launch": int(pbytes), "avg_launch_ms": round(proj_ms, 5)}
+    roof_gram = {"kernel": "k_gram", "bound": "mfma", "achieved": round(gram_tf, 2), "peak": gpeak,
+                 "unit": "TFLOP/s", "frac": round(gram_tf / gpeak, 4), "traffic": None,
+                 "algorithmic_flops_per_launch": int(gflops), "avg_launch_ms": round(gram_ms, 5)}
+    if args.algo == "hooi":
+        dominant, other = roof_proj, None
+    else:
+        dominant, other = (roof_gram, roof_proj) if st["gram_ms"] >= st["project_ms"] else (roof_proj, roof_gram)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "nnz/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"mixed": "bf16(gram)+fp32(proj,acc)+fp64(eig,core,fit)", "fp32": "fp32+fp64(eig,core,fit)",
+                  "fp64": "fp64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"sparse {dims[0]}x{dims[1]}x{dims[2]}, {nnz} uniform distinct nonzeros, U(0,1) "
+                               f"values, core {J[0]}x{J[1]}x{J[2]}, {args.algo.upper()}, {args.sweeps} sweeps",
+                   "dims": list(dims), "nnz": nnz, "core": list(J), "algo": args.algo,
+                   "precision": args.precision, "sweeps": sweeps, "seed": w["seed"]},
+        "roofline": dominant,
+        "phase_ms_per_sweep": {k: round(st[k] / max(1, sweeps), 4) for k in
+                               ("project_ms", "ttmc_ms", "gram_ms", "eig_ms", "core_ms")},
+        "whole_sweep_nnz_per_s": 3 * nu / (st["sweeps_ms"] / 1000.0 / max(1, sweeps)),
+        "prep_ms": round(st["prep_ms"], 3),
+        "init_ms": round(st["init_ms"], 3),
+        "fit": results[0].fits[-1],
+    }
+    if other is not None:
+        line["roofline_other"] = other
+
+    if not args.no_ttf:
+        ttf = {}
+        for prec in ("fp32", "mixed"):
+            runs = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                r = fn(di, dv, dims, J, precision=prec, max_iters=50, tol=1e-4, workspace=ws)
+                torch.cuda.synchronize()
+                runs.append((time.perf_counter() - t1, r))
+            runs.sort(key=lambda x: x[0])
+            tw, r = runs[1]
+            ttf[prec] = {"wall_ms": round(1000 * tw, 2), "sweeps": r.iters, "fit": r.fits[-1],
+                         "prep_excluded_ms": round(r.stats["init_ms"] + r.stats["sweeps_ms"], 2)}
+            log(f"time-to-fit {prec}: {ttf[prec]}")
+        ttf["speedup_plain_over_mixed"] = round(ttf["fp32"]["wall_ms"] / ttf["mixed"]["wall_ms"], 3)
+        ttf["mixed_reaches_plain_fit"] = bool(ttf["mixed"]["fit"] >= ttf["fp32"]["fit"] - 1e-4)
+        line["time_to_fit"] = ttf
+
+    if not args.no_cpu:
+        log("timing the FP64 oracle (one sweep) on the host")
+        line["cpu_baseline"] = cpu_baseline(idx, vals, dims, J, 1)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

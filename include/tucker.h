@@ -98,10 +98,15 @@ typedef struct tk_stats {
     double  prep_ms;        /* validation, duplicate summing, three orderings, ||X||^2 */
     double  init_ms;        /* initial Grams and eigensolves */
     double  sweeps_ms;      /* all sweeps, including the per-sweep fit read-back */
-    double  ttmc_ms;        /* sum over sweeps of the projection (+ HOOI TTMc GEMM)
-                               kernel times; only with opts.timing = 1 */
-    double  project_ms;     /* sum of the projection kernel times alone (timing = 1) */
+    /* With opts.timing = 1, HIP events recorded on `stream` around each
+       phase of the sweeps give these sums (milliseconds over all sweeps): */
+    double  ttmc_ms;        /* projections + HOOI second-stage GEMMs (the TTMc phase) */
+    double  project_ms;     /* projection kernels alone */
     int64_t project_calls;  /* number of projection launches in the sweeps */
+    double  gram_ms;        /* Gram (SYRK) kernels, including their FP64 partial-sum pass */
+    int64_t gram_calls;
+    double  eig_ms;         /* leading-eigenvector solves (including their host round trips) */
+    double  core_ms;        /* core contractions */
     int64_t nnz_unique;     /* nonzeros after duplicate summing */
     int32_t eig_iters;      /* total filtered subspace iterations */
     int32_t eig_noconv;     /* eigensolves that hit eig_max_iters */

@@ -30,7 +30,7 @@ _PREC = {"fp64": FP64, "fp32": FP32, "mixed": MIXED_BF16, "bf16": MIXED_BF16}
 
 # every function declared in include/tucker.h
 SYMBOLS = ["tucker_default_opts", "tucker_workspace_bytes", "tucker_hooi", "tucker_mp", "tucker_fit",
-           "tucker_strerror"]
+           "tucker_strerror", "tucker_step_lead_eig_workspace", "tucker_step_lead_eig"]
 
 
 class tk_coo(ctypes.Structure):
@@ -47,6 +47,8 @@ class tk_opts(ctypes.Structure):
 class tk_stats(ctypes.Structure):
     _fields_ = [("prep_ms", ctypes.c_double), ("init_ms", ctypes.c_double), ("sweeps_ms", ctypes.c_double),
                 ("ttmc_ms", ctypes.c_double), ("project_ms", ctypes.c_double), ("project_calls", ctypes.c_int64),
+                ("gram_ms", ctypes.c_double), ("gram_calls", ctypes.c_int64), ("eig_ms", ctypes.c_double),
+                ("core_ms", ctypes.c_double),
                 ("nnz_unique", ctypes.c_int64), ("eig_iters", ctypes.c_int32), ("eig_noconv", ctypes.c_int32),
                 ("norm_x", ctypes.c_double)]
 
@@ -82,6 +84,12 @@ def lib():
         L.tucker_fit.argtypes = [P(tk_coo), P(ctypes.c_int32), ctypes.c_void_p, P(ctypes.c_void_p),
                                  P(ctypes.c_double), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.tucker_fit.restype = ctypes.c_int
+        L.tucker_step_lead_eig_workspace.argtypes = [ctypes.c_int32, ctypes.c_int32, P(ctypes.c_size_t)]
+        L.tucker_step_lead_eig_workspace.restype = ctypes.c_int
+        L.tucker_step_lead_eig.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                           ctypes.c_void_p, P(ctypes.c_int32), ctypes.c_double, ctypes.c_int32,
+                                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.tucker_step_lead_eig.restype = ctypes.c_int
         L.tucker_strerror.argtypes = [ctypes.c_int]
         L.tucker_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -201,6 +209,29 @@ def hooi(idx, vals, dims, core_dims, **kw) -> Result:
 def mp(idx, vals, dims, core_dims, **kw) -> Result:
     """Multislice Projection (Figure 7). Same arguments as ``hooi``."""
     return _run("tucker_mp", ALGO_MP, idx, vals, dims, core_dims, **kw)
+
+
+def lead_eig(M, J, tol=1e-10, warm=False, workspace=None, stream=None):
+    """The J leading eigenvectors and eigenvalues of the symmetric PSD
+    matrix M (float64, on the GPU). With warm=True the block left in
+    `workspace` by the previous call starts the iteration. Returns
+    (F, theta, matvecs, status, workspace)."""
+    import torch
+    n = int(M.shape[0])
+    M = M.to(torch.float64).contiguous()
+    need = ctypes.c_size_t(0)
+    _check(lib().tucker_step_lead_eig_workspace(n, int(J), ctypes.byref(need)))
+    ws = workspace
+    if ws is None or ws.numel() < need.value:
+        ws = torch.empty(int(need.value), dtype=torch.uint8, device=M.device)
+    F = torch.empty((n, int(J)), dtype=torch.float64, device=M.device)
+    th = torch.empty(int(J), dtype=torch.float64, device=M.device)
+    it = ctypes.c_int32(0)
+    s = stream if stream is not None else torch.cuda.current_stream(M.device)
+    st = _check(lib().tucker_step_lead_eig(M.data_ptr(), n, int(J), F.data_ptr(), th.data_ptr(), ctypes.byref(it),
+                                           float(tol), 1 if warm else 0, ws.data_ptr(), int(ws.numel()),
+                                           ctypes.c_void_p(s.cuda_stream)))
+    return F, th, int(it.value), st, ws
 
 
 def fit(idx, vals, dims, core, factors, workspace=None, stream=None) -> float:

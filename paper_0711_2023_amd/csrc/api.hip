@@ -334,14 +334,16 @@ int tucker_workspace_bytes(int32_t algo, const tk_coo *X, const int32_t *core_di
 
 namespace tk {
 
+// HIP events around the phases of a sweep, on the call's stream.
+enum TimedKind { kProj = 0, kTtmc = 1, kGram = 2, kEig = 3, kCore = 4 };
 struct Timer {
     bool on;
     hipStream_t s;
     std::vector<hipEvent_t> ev;
-    std::vector<int> kind;  // 0 projection, 1 ttmc gemm
+    std::vector<int> kind;
     size_t used = 0;
-    double proj_ms = 0, ttmc_ms = 0;
-    int64_t proj_calls = 0;
+    double ms[5] = {0, 0, 0, 0, 0};
+    int64_t calls[5] = {0, 0, 0, 0, 0};
     Timer(bool on_, hipStream_t s_) : on(on_), s(s_) {}
     ~Timer() {
         for (auto e : ev) (void)hipEventDestroy(e);
@@ -368,15 +370,22 @@ struct Timer {
     void collect() {
         if (!on) return;
         for (size_t i = 0; i + 1 < used; i += 2) {
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
-            if (kind[i / 2] == 0) {
-                proj_ms += ms;
-                ++proj_calls;
-            }
-            ttmc_ms += ms;
+            float t = 0;
+            (void)hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+            ms[kind[i / 2]] += t;
+            calls[kind[i / 2]] += 1;
         }
         used = 0;
+    }
+    void report(tk_stats *st) const {
+        if (!st) return;
+        st->project_ms = ms[kProj];
+        st->project_calls = calls[kProj];
+        st->ttmc_ms = ms[kProj] + ms[kTtmc];
+        st->gram_ms = ms[kGram];
+        st->gram_calls = calls[kGram];
+        st->eig_ms = ms[kEig];
+        st->core_ms = ms[kCore];
     }
 };
 
@@ -503,7 +512,7 @@ static int finish_fit(Plan &p, const double *core, hipStream_t s, double *fit) {
     return TK_OK;
 }
 
-static int run_eig(Plan &p, int n, const double *M, double *F, bool warm, const tk_opts *o, tk_stats *st,
+static int run_eig(Plan &p, int n, double *M, double *F, bool warm, const tk_opts *o, tk_stats *st,
                    int *noconv_any, hipStream_t s) {
     EigOpts eo;
     eo.max_iters = o->eig_max_iters;
@@ -580,10 +589,10 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     const int prec = p.prec;
     double *A = factors[0], *B = factors[1], *C = factors[2];
     // projections of the start: T(1)(B), T(2)(C)
-    tm.begin(0);
+    tm.begin(kProj);
     ST(project_m(p, 1, B, p.T[1], prec, s));
     tm.end();
-    tm.begin(0);
+    tm.begin(kProj);
     ST(project_m(p, 2, C, p.T[2], prec, s));
     tm.end();
     const int gprec = prec;
@@ -593,23 +602,35 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     for (t = 1; t <= o->max_iters; ++t) {
         // M1 (mode 0) from T(1) and T(2)
         GramTerm g0[2] = {term_of(p, 1, 0, p.T[1]), term_of(p, 2, 0, p.T[2])};
+        tm.begin(kGram);
         ST(gram((int)p.I[0], gprec, 2, g0, p.Mg, p.gram_scratch, s));
+        tm.end();
+        tm.begin(kEig);
         if ((st = run_eig(p, 0, p.Mg, A, t > 1, o, stats, &noconv, s))) return st;
-        tm.begin(0);
+        tm.end();
+        tm.begin(kProj);
         ST(project_m(p, 0, A, p.T[0], prec, s));
         tm.end();
         // M2 (mode 1) from T(0) and T(2)
         GramTerm g1[2] = {term_of(p, 0, 1, p.T[0]), term_of(p, 2, 1, p.T[2])};
+        tm.begin(kGram);
         ST(gram((int)p.I[1], gprec, 2, g1, p.Mg, p.gram_scratch, s));
+        tm.end();
+        tm.begin(kEig);
         if ((st = run_eig(p, 1, p.Mg, B, true, o, stats, &noconv, s))) return st;
-        tm.begin(0);
+        tm.end();
+        tm.begin(kProj);
         ST(project_m(p, 1, B, p.T[1], prec, s));
         tm.end();
         // M3 (mode 2) from T(0) and T(1)
         GramTerm g2[2] = {term_of(p, 0, 2, p.T[0]), term_of(p, 1, 2, p.T[1])};
+        tm.begin(kGram);
         ST(gram((int)p.I[2], gprec, 2, g2, p.Mg, p.gram_scratch, s));
+        tm.end();
+        tm.begin(kEig);
         if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
-        tm.begin(0);
+        tm.end();
+        tm.begin(kProj);
         ST(project_m(p, 2, C, p.T[2], prec, s));
         tm.end();
         // core from T(2)(C) (FP64 or FP32, never BF16)
@@ -620,7 +641,9 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
                                              s)));
             T2c = p.Tcore;
         }
+        tm.begin(kCore);
         ST(core_from_T2(p, T2c, f64, A, B, core, s));
+        tm.end();
         double fit = 0;
         if ((st = finish_fit(p, core, s, &fit))) return st;
         tm.collect();
@@ -632,15 +655,21 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     if (o->max_iters == 0) {
         // no sweep: A from the start factors, then the core
         GramTerm g0[2] = {term_of(p, 1, 0, p.T[1]), term_of(p, 2, 0, p.T[2])};
+        tm.begin(kGram);
         ST(gram((int)p.I[0], gprec, 2, g0, p.Mg, p.gram_scratch, s));
+        tm.end();
+        tm.begin(kEig);
         if ((st = run_eig(p, 0, p.Mg, A, false, o, stats, &noconv, s))) return st;
+        tm.end();
         const void *T2c = p.T[2];
         if (prec == PBF16) {
             ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.nslots[2], p.Tcore,
                                              s)));
             T2c = p.Tcore;
         }
+        tm.begin(kCore);
         ST(core_from_T2(p, T2c, prec == P64, A, B, core, s));
+        tm.end();
         ST(hipStreamSynchronize(s));
     }
     double t3 = now_ms();
@@ -648,9 +677,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         stats->prep_ms = t1 - t0;
         stats->init_ms = t2 - t1;
         stats->sweeps_ms = t3 - t2;
-        stats->project_ms = tm.proj_ms;
-        stats->ttmc_ms = tm.ttmc_ms;
-        stats->project_calls = tm.proj_calls;
+        tm.report(stats);
         stats->nnz_unique = nu;
         stats->norm_x = std::sqrt(nx2);
     }
@@ -713,12 +740,12 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
     int maxit = o->max_iters > 0 ? o->max_iters : 0;
     for (int t = 1; t <= std::max(maxit, 1); ++t) {
         const bool last_only = (maxit == 0);
-        tm.begin(0);
+        tm.begin(kProj);
         ST(project_m(p, 2, C, p.T[2], tprec, s));
         tm.end();
         const void *Bop = prec == P64 ? (const void *)B : (prec == P32 ? (const void *)p.F32[1] : (const void *)p.F16[1]);
         // mode 0: Y0[q][i0][r2] = sum_i1 B[i1][q] T2[i1][i0][r2]
-        tm.begin(1);
+        tm.begin(kTtmc);
         ST(ttm(J1, (int)(I0 * J2), (int)I1, 1, Bop, J1, p.T[2], I0 * J2, 0, p.Y, I0 * J2, 0, kprec01,
                yprec == P64 ? P64 : P32, s));
         tm.end();
@@ -729,16 +756,20 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
             g.chunk_len = J2;
             g.nchunks = J1;
             g.s_chunk = I0 * J2;
+            tm.begin(kGram);
             ST(gram((int)I0, yprec, 1, &g, p.Mg, p.gram_scratch, s));
+            tm.end();
         }
+        tm.begin(kEig);
         if ((st = run_eig(p, 0, p.Mg, A, t > 1, o, stats, &noconv, s))) return st;
+        tm.end();
         if (last_only) {
             // max_iters == 0: A only, then the core below
         }
         const void *Aop = prec == P64 ? (const void *)A : (prec == P32 ? (const void *)p.F32[0] : (const void *)p.F16[0]);
         // mode 1: Y1[i1][p][r2] = sum_i0 A[i0][p] T2[i1][i0][r2]
         if (!last_only) {
-            tm.begin(1);
+            tm.begin(kTtmc);
             ST(ttm(J0, J2, (int)I0, (int)I1, Aop, J0, p.T[2], J2, I0 * J2, p.Y, J2, (int64_t)J0 * J2, kprec01,
                    yprec == P64 ? P64 : P32, s));
             tm.end();
@@ -748,18 +779,22 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
             g.chunk_len = (int64_t)J0 * J2;
             g.nchunks = 1;
             g.s_chunk = 0;
+            tm.begin(kGram);
             ST(gram((int)I1, yprec, 1, &g, p.Mg, p.gram_scratch, s));
+            tm.end();
+            tm.begin(kEig);
             if ((st = run_eig(p, 1, p.Mg, B, true, o, stats, &noconv, s))) return st;
+            tm.end();
         }
         // mode 2 (and the core): T(0)(A) = [i2][i1][r0] in FP64 / FP32
         void *T0 = prec == PBF16 ? (void *)p.T0f : p.T[0];
         const int t0prec = prec == P64 ? P64 : P32;
-        tm.begin(0);
+        tm.begin(kProj);
         ST(project_m(p, 0, A, T0, t0prec, s));
         tm.end();
         const void *Bop2 = prec == P64 ? (const void *)B : (const void *)p.F32[1];
         // Y2[i2][q][r0] = sum_i1 B[i1][q] T0[i2][i1][r0]
-        tm.begin(1);
+        tm.begin(kTtmc);
         ST(ttm(J1, J0, (int)I1, (int)I2, Bop2, J1, T0, J0, I1 * J0, p.Y, J0, (int64_t)J1 * J0, t0prec,
                yprec == P64 ? P64 : P32, s));
         tm.end();
@@ -770,8 +805,12 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
             g.chunk_len = (int64_t)J1 * J0;
             g.nchunks = 1;
             g.s_chunk = 0;
+            tm.begin(kGram);
             ST(gram((int)I2, yprec, 1, &g, p.Mg, p.gram_scratch, s));
+            tm.end();
+            tm.begin(kEig);
             if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
+            tm.end();
         }
         // core: G'[r][q][p] = sum_i2 C[i2][r] Y2[i2][q][p]; core[p][q][r] = G'[r][q][p]
         {
@@ -816,9 +855,7 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
         stats->prep_ms = t1 - t0;
         stats->init_ms = t2 - t1;
         stats->sweeps_ms = t3 - t2;
-        stats->project_ms = tm.proj_ms;
-        stats->ttmc_ms = tm.ttmc_ms;
-        stats->project_calls = tm.proj_calls;
+        tm.report(stats);
         stats->nnz_unique = nu;
         stats->norm_x = std::sqrt(nx2);
     }
@@ -931,4 +968,50 @@ extern "C" int tucker_fit(const tk_coo *X, const int32_t *J, const double *core,
     ST(hipMemcpyAsync(fit, p.scal + 2, 8, hipMemcpyDeviceToHost, s));
     ST(hipStreamSynchronize(s));
     return TK_OK;
+}
+
+// ------------------------------------------------------------------ step-level entry points
+#include "../../include/tucker_steps.h"
+
+namespace tk {
+static void eig_step_layout(Arena &ar, int n, int J, double **Mc, double **Xb, void **w) {
+    const int b = eig_block_width(n, J);
+    *Mc = ar.take<double>((int64_t)n * n);
+    *Xb = ar.take<double>((int64_t)n * b);
+    *w = ar.take<char>((int64_t)eig_work_bytes(n, b));
+}
+}  // namespace tk
+
+extern "C" int tucker_step_lead_eig_workspace(int32_t n, int32_t J, size_t *bytes) {
+    if (!bytes || n < 1 || J < 1 || J > n || J > kMaxJ) return TK_ERR_ARG;
+    Arena ar;
+    double *a, *b;
+    void *c;
+    eig_step_layout(ar, n, J, &a, &b, &c);
+    *bytes = ar.used + 256;
+    return TK_OK;
+}
+
+extern "C" int tucker_step_lead_eig(const double *M, int32_t n, int32_t J, double *F, double *theta, int32_t *matvecs,
+                                    double tol, int32_t warm, void *ws, size_t wsb, void *stream) {
+    if (!M || !F || !theta || !matvecs || n < 1 || J < 1 || J > n || J > kMaxJ || !(tol >= 0.0)) return TK_ERR_ARG;
+    Arena ar;
+    double *Mc, *Xb;
+    void *w;
+    eig_step_layout(ar, n, J, &Mc, &Xb, &w);
+    if (!ws || wsb < ar.used + 256) return TK_ERR_WORKSPACE;
+    ar.base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+    ar.used = 0;
+    eig_step_layout(ar, n, J, &Mc, &Xb, &w);
+    g_err[0] = 0;
+    hipStream_t s = (hipStream_t)stream;
+    ST(hipMemcpyAsync(Mc, M, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s));
+    EigOpts eo;
+    eo.tol = tol;
+    eo.warm = warm != 0;
+    int it = 0, nc = 0;
+    ST(lead_eig(Mc, n, J, Xb, F, theta, w, eo, &it, &nc, s));
+    ST(hipStreamSynchronize(s));
+    *matvecs = it;
+    return nc ? TK_WARN_NOCONV : TK_OK;
 }

@@ -146,7 +146,8 @@ hipError_t gemm(const GemmArgs &g, hipStream_t s);
 struct EigWork;  // opaque, carved from the workspace
 size_t eig_work_bytes(int n, int b);
 int eig_block_width(int n, int J);
-// Leading J eigenvectors of the symmetric PSD matrix M (FP64 n x n).
+// Leading J eigenvectors of the symmetric PSD matrix M (FP64 n x n). M is
+// overwritten (converged pairs are deflated out of it).
 // X (n x b, b = eig_block_width) holds the start block on entry when warm,
 // and the converged block on exit. F receives the J leading eigenvectors
 // (n x J row-major, sign-canonical); theta (device, b) the Ritz values.
@@ -154,11 +155,11 @@ int eig_block_width(int n, int J);
 struct EigOpts {
     int max_iters = 400;
     double tol = 1e-10;
-    int degree = 8;
+    int degree = 12;
     bool warm = false;
     uint64_t seed = 1234;
 };
-hipError_t lead_eig(const double *M, int n, int J, double *X, double *F, double *theta_dev, void *work,
+hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta_dev, void *work,
                     const EigOpts &o, int *iters, int *noconv, hipStream_t s);
 
 // ---------------------------------------------------------------- small helpers (eig.hip)

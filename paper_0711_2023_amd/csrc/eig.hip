@@ -14,7 +14,7 @@
 //   a Chebyshev filter of degree d on the remaining columns damps [0, mu]
 //   (mu = smallest Ritz value of the block) and amplifies the top;
 //   the filtered columns are re-orthogonalised against the locked ones and
-//   orthonormalised by shifted CholeskyQR (one shifted pass, two plain).
+//   orthonormalised by shifted CholeskyQR (one shifted pass, one plain).
 // It stops when the sum of the J leading Ritz values changes by at most
 // tol (relative) between Rayleigh-Ritz steps, or when all J are locked.
 #include "common.h"
@@ -100,15 +100,21 @@ __global__ void k_colscale(double *X, int64_t n, int ld, int c0, int w, const do
     }
 }
 
-// Upper Cholesky factor of S + shift*trace(S)/w*I (S is w x w with leading
-// dimension lds) and its inverse, in one workgroup. Non-positive pivots are
-// clamped to a tiny positive value (the caller's block then keeps a
-// direction it cannot resolve instead of failing).
+// Upper Cholesky factor R of S + shift*trace(S)*I (S is w x w with leading
+// dimension lds) and its inverse, in one workgroup with everything in LDS.
+// Right-looking elimination with one barrier per column: the trailing update
+// of step k uses row k unscaled (A_ij -= A_ki A_kj / A_kk) and row k is scaled
+// by 1/sqrt(A_kk) during step k+1, when no thread reads it. Non-positive
+// pivots are clamped to a tiny positive value (the caller's block then keeps
+// a direction it cannot resolve instead of failing). The inverse is formed
+// column by column (one thread per column) into the strictly lower triangle,
+// transposed, with its diagonal kept apart.
 __global__ void __launch_bounds__(256) k_chol_inv(const double *S, int lds, int w, double shift, double *Rinv) {
-    extern __shared__ double A[];  // w*w
+    extern __shared__ double A[];  // w*w, then w for the inverse's diagonal
+    double *dinv = A + (size_t)w * w;
     __shared__ double tr;
-    const int tid = threadIdx.x;
-    for (int t = tid; t < w * w; t += blockDim.x) {
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int t = tid; t < w * w; t += nth) {
         int i = t / w, j = t - i * w;
         A[t] = 0.5 * (S[i * lds + j] + S[j * lds + i]);
     }
@@ -120,36 +126,57 @@ __global__ void __launch_bounds__(256) k_chol_inv(const double *S, int lds, int 
     }
     __syncthreads();
     const double add = shift * tr;
-    for (int i = tid; i < w; i += blockDim.x) A[i * w + i] += add;
+    for (int i = tid; i < w; i += nth) A[i * w + i] += add;
     __syncthreads();
     const double tiny = 1e-300 + 1e-30 * (tr > 0 ? tr : 1.0);
     for (int k = 0; k < w; ++k) {
-        if (tid == 0) {
-            double d = A[k * w + k];
-            A[k * w + k] = sqrt(d > tiny ? d : tiny);
+        if (k > 0) {
+            // scale row k-1 by the square root of its (clamped) pivot; no
+            // thread reads row k-1 during this step
+            const double pk = fmax(A[(k - 1) * w + (k - 1)], tiny);
+            const double sq = sqrt(pk);
+            for (int j = k + tid; j < w; j += nth) A[(k - 1) * w + j] /= sq;
         }
-        __syncthreads();
-        const double dk = A[k * w + k];
-        for (int j = k + 1 + tid; j < w; j += blockDim.x) A[k * w + j] /= dk;
-        __syncthreads();
-        const int m = w - k - 1;
-        for (int t = tid; t < m * m; t += blockDim.x) {
-            int i = k + 1 + t / m, j = k + 1 + t % m;
-            if (j >= i) A[i * w + j] -= A[k * w + i] * A[k * w + j];
+        const double rd = 1.0 / fmax(A[k * w + k], tiny);
+        // trailing upper triangle (i, j), k < i <= j: thread (g, c) with
+        // g < groups = nth / w takes column k+1+c and rows k+1+g, k+1+g+groups, ...
+        // (w <= nth is guaranteed by the host)
+        const int groups = nth / w;
+        const int g = tid / w, c = tid - g * w;
+        if (g < groups) {
+            const int j = k + 1 + c;
+            if (j < w) {
+                const double akj = A[k * w + j] * rd;
+                for (int i = k + 1 + g; i <= j; i += groups) A[i * w + j] -= A[k * w + i] * akj;
+            }
         }
         __syncthreads();
     }
-    // inverse of the upper triangle, one column per thread
-    for (int j = tid; j < w; j += blockDim.x) {
-        for (int i = w - 1; i >= 0; --i) {
-            double v = 0;
-            if (i <= j) {
-                v = (i == j) ? 1.0 : 0.0;
-                for (int k = i + 1; k <= j; ++k) v -= A[i * w + k] * Rinv[k * w + j];
-                v /= A[i * w + i];
-            }
-            Rinv[i * w + j] = v;
+    for (int k = tid; k < w; k += nth) A[k * w + k] = sqrt(fmax(A[k * w + k], tiny));
+    __syncthreads();
+    // R is now the upper triangle of A. Its inverse is upper triangular too;
+    // row i of it needs only rows below i: Rinv[i][j] = (delta_ij - sum_{k=i+1..j}
+    // R[i][k] Rinv[k][j]) / R[i][i], parallel over j. Rinv[i][j] (i < j) is
+    // kept at A[j][i] (strictly lower triangle, transposed), its diagonal in dinv.
+    for (int j = tid; j < w; j += nth) dinv[j] = 1.0 / A[j * w + j];
+    __syncthreads();
+    for (int i = w - 2; i >= 0; --i) {
+        const double rii = dinv[i];
+        for (int j = i + 1 + tid; j < w; j += nth) {
+            double v = -A[i * w + j] * dinv[j];  // k = j term
+            for (int k = i + 1; k < j; ++k) v -= A[i * w + k] * A[j * w + k];
+            A[j * w + i] = v * rii;
         }
+        __syncthreads();
+    }
+    for (int t = tid; t < w * w; t += nth) {
+        int i = t / w, j = t - i * w;
+        double v = 0;
+        if (i == j)
+            v = dinv[j];
+        else if (i < j)
+            v = A[j * w + i];
+        Rinv[t] = v;
     }
 }
 
@@ -157,8 +184,8 @@ __global__ void __launch_bounds__(256) k_chol_inv(const double *S, int lds, int 
 // dimension ldh). Outputs the eigenvalues in descending order (theta) and
 // the matching eigenvectors as columns of Vout (b x b row-major).
 template <bool V_LDS>
-__global__ void __launch_bounds__(1024) k_jacobi(const double *Hin, int ldh, int b, int max_sweeps, double *theta,
-                                                 double *Vout, double *Vglob) {
+__global__ void __launch_bounds__(512) k_jacobi(const double *Hin, int ldh, int b, int max_sweeps, double *theta,
+                                                double *Vout, double *Vglob) {
     extern __shared__ double sm[];
     double *H = sm;
     double *V = V_LDS ? sm + (size_t)b * b : Vglob;
@@ -168,7 +195,8 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double *Hin, int ldh, int
     int *pp = reinterpret_cast<int *>(sn + half);
     int *qq = pp + half;
     __shared__ double red[32];
-    __shared__ int done;
+    __shared__ double hmax;
+    __shared__ int done, any_rot, idle_pair;
     const int tid = threadIdx.x, nth = blockDim.x;
     for (int t = tid; t < b * b; t += nth) {
         int i = t / b, j = t - i * b;
@@ -176,8 +204,24 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double *Hin, int ldh, int
         V[t] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
+    if (tid == 0) {
+        double m0 = 0;
+        for (int i = 0; i < b; ++i) m0 = fmax(m0, fabs(H[i * b + i]));
+        hmax = m0;
+    }
+    // static thread maps (no divisions inside the rounds):
+    // blocks (k1, k2) of the pair grid: k2 = tid % half fixed, k1 = tid / half + s*bstep
+    const int bstep = nth / half > 0 ? nth / half : 1;
+    const int bk2 = tid % half, bk1 = tid / half;
+    const bool bact = tid < bstep * half;
+    // V rows: pair k = tid % half fixed, row = tid / half + s*bstep
+    __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        if (tid == 0) any_rot = 0;
+        int nrot = 0;
         for (int r = 0; r < m - 1; ++r) {
+            if (tid == 0) idle_pair = -1;
+            __syncthreads();
             for (int k = tid; k < half; k += nth) {
                 int a, c;
                 if (k == 0) {
@@ -191,13 +235,16 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double *Hin, int ldh, int
                 double cc = 1.0, ss = 0.0;
                 if (q < b) {
                     double apq = H[p * b + q], app = H[p * b + p], aqq = H[q * b + q];
-                    if (fabs(apq) > 1e-300 && fabs(apq) > 1e-17 * sqrt(fabs(app * aqq))) {
+                    if (fabs(apq) > 1e-300 && fabs(apq) > 1e-16 * hmax) {
+                        nrot = 1;
                         double tau = (aqq - app) / (2.0 * apq);
                         double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         if (fabs(tau) > 1e150) t = 0.5 / tau;
                         cc = 1.0 / sqrt(1.0 + t * t);
                         ss = t * cc;
                     }
+                } else {
+                    idle_pair = k;
                 }
                 cs[k] = cc;
                 sn[k] = ss;
@@ -205,65 +252,70 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double *Hin, int ldh, int
                 qq[k] = q;
             }
             __syncthreads();
-            // H <- G^T H G on 2x2 blocks (pair K1 rows, pair K2 columns)
-            for (int t = tid; t < half * half; t += nth) {
-                int k1 = t / half, k2 = t - k1 * half;
-                int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
-                if (q1 >= b || q2 >= b) {
-                    // a dummy index: only one real row/column pair to rotate
-                    // (handled below by the single-sided pass)
-                    continue;
+            const int kd = idle_pair;
+            // H <- G^T H G on 2x2 blocks (pair k1 rows, pair k2 columns)
+            if (bact) {
+                const int k2 = bk2;
+                const int p2 = pp[k2], q2 = qq[k2];
+                const double c2 = cs[k2], s2 = sn[k2];
+                for (int k1 = bk1; k1 < half; k1 += bstep) {
+                    const int p1 = pp[k1], q1 = qq[k1];
+                    if (k1 == kd || k2 == kd) {
+                        // the idle real index x of the dummy pair meets the
+                        // rotation of the other pair on one side only
+                        if (k1 == kd && k2 != kd) {
+                            const int x = p1;
+                            double hp = H[x * b + p2], hq = H[x * b + q2];
+                            double np_ = c2 * hp - s2 * hq, nq = s2 * hp + c2 * hq;
+                            H[x * b + p2] = np_;
+                            H[x * b + q2] = nq;
+                            H[p2 * b + x] = np_;
+                            H[q2 * b + x] = nq;
+                        }
+                        continue;
+                    }
+                    const double c1 = cs[k1], s1 = sn[k1];
+                    double a = H[p1 * b + p2], bb = H[p1 * b + q2], c = H[q1 * b + p2], d = H[q1 * b + q2];
+                    double za, zb, zc, zd;
+                    if (k1 == k2) {
+                        const double t1 = c1 != 0.0 ? s1 / c1 : 0.0;
+                        za = a - t1 * bb;
+                        zd = d + t1 * bb;
+                        zb = 0.0;
+                        zc = 0.0;
+                        if (s1 == 0.0) {
+                            za = a;
+                            zd = d;
+                            zb = bb;
+                            zc = c;
+                        }
+                    } else {
+                        double ya = c1 * a - s1 * c, yb = c1 * bb - s1 * d;
+                        double yc = s1 * a + c1 * c, yd = s1 * bb + c1 * d;
+                        za = c2 * ya - s2 * yb;
+                        zb = s2 * ya + c2 * yb;
+                        zc = c2 * yc - s2 * yd;
+                        zd = s2 * yc + c2 * yd;
+                    }
+                    H[p1 * b + p2] = za;
+                    H[p1 * b + q2] = zb;
+                    H[q1 * b + p2] = zc;
+                    H[q1 * b + q2] = zd;
                 }
-                double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
-                double a = H[p1 * b + p2], bb = H[p1 * b + q2], c = H[q1 * b + p2], d = H[q1 * b + q2];
-                double ya = c1 * a - s1 * c, yb = c1 * bb - s1 * d;
-                double yc = s1 * a + c1 * c, yd = s1 * bb + c1 * d;
-                double za = c2 * ya - s2 * yb, zb = s2 * ya + c2 * yb;
-                double zc = c2 * yc - s2 * yd, zd = s2 * yc + c2 * yd;
-                if (k1 == k2 && s1 != 0.0) {
-                    za = a - (s1 / c1) * bb;
-                    zd = d + (s1 / c1) * bb;
-                    zb = 0.0;
-                    zc = 0.0;
+                // V <- V G: rows bk1, bk1 + bstep, ... of pair k2
+                if (k2 != kd) {
+                    for (int row = bk1; row < b; row += bstep) {
+                        double vp = V[row * b + p2], vq = V[row * b + q2];
+                        V[row * b + p2] = c2 * vp - s2 * vq;
+                        V[row * b + q2] = s2 * vp + c2 * vq;
+                    }
                 }
-                H[p1 * b + p2] = za;
-                H[p1 * b + q2] = zb;
-                H[q1 * b + p2] = zc;
-                H[q1 * b + q2] = zd;
-            }
-            // rows/columns paired with the dummy index are not rotated, but
-            // they still meet rotations of the other pairs on one side
-            if (m != b) {
-                for (int t = tid; t < half; t += nth) {
-                    int kd = -1;
-                    for (int k = 0; k < half; ++k)
-                        if (qq[k] >= b) kd = k;
-                    if (kd < 0 || t == kd) continue;
-                    int x = pp[kd];  // the idle real index
-                    int p = pp[t], q = qq[t];
-                    double c = cs[t], s = sn[t];
-                    // row x, columns p, q (H G) and column x, rows p, q (G^T H)
-                    double hp = H[x * b + p], hq = H[x * b + q];
-                    double np = c * hp - s * hq, nq = s * hp + c * hq;
-                    H[x * b + p] = np;
-                    H[x * b + q] = nq;
-                    H[p * b + x] = np;
-                    H[q * b + x] = nq;
-                }
-            }
-            // V <- V G
-            for (int t = tid; t < b * half; t += nth) {
-                int row = t / half, k = t - row * half;
-                int p = pp[k], q = qq[k];
-                if (q >= b) continue;
-                double c = cs[k], s = sn[k];
-                double vp = V[row * b + p], vq = V[row * b + q];
-                V[row * b + p] = c * vp - s * vq;
-                V[row * b + q] = s * vp + c * vq;
             }
             __syncthreads();
         }
-        // convergence: off-diagonal mass relative to the diagonal
+        if (nrot) any_rot = 1;
+        __syncthreads();
+        if (!any_rot) break;
         double off = 0, dia = 0;
         for (int t = tid; t < b * b; t += nth) {
             int i = t / b, j = t - i * b;
@@ -288,7 +340,7 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double *Hin, int ldh, int
                 o += red[i];
                 dd += red[16 + i];
             }
-            done = (o <= 1e-30 * dd) || (dd == 0.0);
+            done = (o <= 1e-26 * (o + dd)) || (dd == 0.0);
         }
         __syncthreads();
         if (done) break;
@@ -328,12 +380,13 @@ __global__ void k_resid(const double *W, const double *X, const double *theta, i
 
 // F[:, j] = sign_j * X[:, j] for j < J, sign making the largest-magnitude
 // entry (first one on ties) positive. One block per column.
-__global__ void k_extract(const double *X, int64_t n, int ldx, int J, double *F) {
+__global__ void k_extract(const double *X, int64_t n, int ldx, int J, double *F, const int *colmap) {
     const int j = blockIdx.x;
+    const int src = colmap ? colmap[j] : j;
     double best = -1;
     int64_t bi = 0;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        double a = fabs(X[i * ldx + j]);
+        double a = fabs(X[i * ldx + src]);
         if (a > best) {
             best = a;
             bi = i;
@@ -355,8 +408,19 @@ __global__ void k_extract(const double *X, int64_t n, int ldx, int J, double *F)
         }
         __syncthreads();
     }
-    const double sgn = X[si[0] * ldx + j] < 0 ? -1.0 : 1.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) F[i * J + j] = sgn * X[i * ldx + j];
+    const double sgn = X[si[0] * ldx + src] < 0 ? -1.0 : 1.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) F[i * J + j] = sgn * X[i * ldx + src];
+}
+
+// M <- M - sum_l theta_l x_l x_l^T over the columns X[:, c0:c0+k] (leading
+// dimension ldx); symmetric bit for bit (theta * (x_r x_c)).
+__global__ void k_deflate(double *M, int64_t n, const double *X, int ldx, int c0, int k, const double *theta) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n * n; t += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = t / n, c = t - r * n;
+        double acc = 0;
+        for (int l = 0; l < k; ++l) acc += theta[l] * (X[r * ldx + c0 + l] * X[c * ldx + c0 + l]);
+        M[t] -= acc;
+    }
 }
 
 template <class TO>
@@ -383,7 +447,8 @@ template hipError_t convert_f64<bf16>(const double *, bf16 *, int64_t, hipStream
 
 // ------------------------------------------------------------------ workspace
 struct EigLayout {
-    double *W, *Y0, *Y1, *Y2, *S, *V, *Vg, *Rinv, *theta, *res, *norms, *split;
+    double *W, *Y0, *Y1, *Y2, *S, *V, *Vg, *Rinv, *theta, *res, *norms, *split, *thall;
+    int *colmap;
     int64_t split_elems;
 };
 static int splitk_for(int64_t K, int64_t tiles) {
@@ -405,6 +470,8 @@ static EigLayout eig_layout(Arena &ar, int n, int b) {
     L.theta = ar.take<double>(b);
     L.res = ar.take<double>(b);
     L.norms = ar.take<double>(b);
+    L.thall = ar.take<double>(b);
+    L.colmap = ar.take<int>(b);
     // split-K partial sums: M*X (K = n) and X^T Y (K = n)
     int64_t t_mx = ceil_div(n, 64) * ceil_div(b, 64);
     int64_t s1 = (int64_t)splitk_for(n, t_mx) * nb;
@@ -426,11 +493,11 @@ static hipError_t jacobi(const double *H, int ldh, int b, double *theta, double 
     if (b <= kJacobiVLds) {
         size_t lds = sizeof(double) * 2 * (size_t)b * b + small;
         hipFuncSetAttribute((const void *)k_jacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_jacobi<true><<<1, 1024, lds, s>>>(H, ldh, b, 30, theta, Vout, Vg);
+        k_jacobi<true><<<1, 512, lds, s>>>(H, ldh, b, 30, theta, Vout, Vg);
     } else {
         size_t lds = sizeof(double) * (size_t)b * b + small;
         hipFuncSetAttribute((const void *)k_jacobi<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_jacobi<false><<<1, 1024, lds, s>>>(H, ldh, b, 30, theta, Vout, Vg);
+        k_jacobi<false><<<1, 512, lds, s>>>(H, ldh, b, 30, theta, Vout, Vg);
     }
     TK_LAUNCHED();
     return hipSuccess;
@@ -470,7 +537,20 @@ static hipError_t dgemm(int M, int N, int K, const double *A, int64_t lda, bool 
 }
 
 // Orthonormalise columns [c0, c0+w) of X (n x b, row-major) in place:
-// column scaling, one shifted CholeskyQR pass, two plain passes.
+// column scaling, one shifted CholeskyQR pass, one plain pass.
+static hipError_t project_out(double *X, int64_t n, int b, int c0, int w, EigLayout &L, hipStream_t s) {
+    // X[:, c0:c0+w] -= X[:, :c0] (X[:, :c0]^T X[:, c0:c0+w])
+    TK_HIP(dgemm(c0, w, (int)n, X, b, true, X + c0, b, L.S, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split,
+                 L.split_elems, s));
+    TK_HIP(dgemm((int)n, w, c0, X, b, false, L.S, w, X + c0, b, -1.0, 1.0, X + c0, 0.0, nullptr, L.split,
+                 L.split_elems, s));
+    return hipSuccess;
+}
+
+// Orthonormalise columns [c0, c0+w) of X (n x b, row-major) in place and
+// against the columns [0, c0), which are orthonormal already: column
+// scaling (collapsed columns replaced by pseudo-random ones), then two
+// passes of (projection against [0, c0), CholeskyQR), the first shifted.
 static hipError_t orthonormalise(double *X, int64_t n, int b, int c0, int w, EigLayout &L, uint64_t seed,
                                  hipStream_t s) {
     if (w <= 0) return hipSuccess;
@@ -480,16 +560,15 @@ static hipError_t orthonormalise(double *X, int64_t n, int b, int c0, int w, Eig
                                                                                           seed);
     TK_LAUNCHED();
     const double u = 1.1102230246251565e-16;
-    for (int pass = 0; pass < 3; ++pass) {
+    for (int pass = 0; pass < 2; ++pass) {
+        if (c0 > 0) TK_HIP(project_out(X, n, b, c0, w, L, s));
         double shift = pass == 0 ? 11.0 * ((double)n * w + (double)w * (w + 1)) * u / w : 0.0;
-        // S = Xa^T Xa
         TK_HIP(dgemm(w, w, (int)n, X + c0, b, true, X + c0, b, L.S, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split,
                      L.split_elems, s));
-        size_t lds = sizeof(double) * (size_t)w * w;
+        size_t lds = sizeof(double) * ((size_t)w * w + w);
         hipFuncSetAttribute((const void *)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         k_chol_inv<<<1, 256, lds, s>>>(L.S, w, w, shift, L.Rinv);
         TK_LAUNCHED();
-        // Y0[:, :w] = Xa Rinv, then copy back into X[:, c0:c0+w]
         TK_HIP(dgemm((int)n, w, w, X + c0, b, false, L.Rinv, w, L.Y0, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split,
                      L.split_elems, s));
         TK_HIP(hipMemcpy2DAsync(X + c0, sizeof(double) * b, L.Y0, sizeof(double) * w, sizeof(double) * w, n,
@@ -498,7 +577,7 @@ static hipError_t orthonormalise(double *X, int64_t n, int b, int c0, int w, Eig
     return hipSuccess;
 }
 
-hipError_t lead_eig(const double *M, int n, int J, double *X, double *F, double *theta_dev, void *work,
+hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta_dev, void *work,
                     const EigOpts &o, int *iters, int *noconv, hipStream_t s) {
     *iters = 0;
     *noconv = 0;
@@ -508,7 +587,7 @@ hipError_t lead_eig(const double *M, int n, int J, double *X, double *F, double 
     EigLayout L = eig_layout(ar, n, b);
     if (n <= kDirectMax) {
         TK_HIP(jacobi(M, n, n, L.theta, L.V, L.Vg, s));
-        k_extract<<<J, 256, 0, s>>>(L.V, n, n, J, F);
+        k_extract<<<J, 256, 0, s>>>(L.V, n, n, J, F, nullptr);
         TK_LAUNCHED();
         TK_HIP(hipMemcpyAsync(theta_dev, L.theta, sizeof(double) * J, hipMemcpyDeviceToDevice, s));
         *iters = 1;
@@ -520,71 +599,95 @@ hipError_t lead_eig(const double *M, int n, int J, double *X, double *F, double 
         TK_LAUNCHED();
         TK_HIP(orthonormalise(X, n, b, 0, b, L, o.seed + 1, s));
     }
-    std::vector<double> h(2 * (size_t)b);
+    // Locked (converged leading) Ritz pairs occupy X[:, :Lk]; they are
+    // deflated out of M, so the filter and the Rayleigh-Ritz steps only see
+    // the active columns X[:, Lk:b].
+    std::vector<double> h(2 * (size_t)b), thL;
     double Eold = -1.0;
-    int matvecs = 0;
-    double *Xc = X;  // current block lives in X throughout
+    int matvecs = 0, Lk = 0;
+    double *Xc = X;
+    double *Md = M;  // deflated in place
+    std::vector<double> tha;
     for (int outer = 0;; ++outer) {
-        // Rayleigh-Ritz
-        TK_HIP(dgemm(n, b, n, M, n, false, Xc, b, L.W, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
+        const int w = b - Lk;
+        double *Xa = Xc + Lk, *Wa = L.W + Lk;
+        // Rayleigh-Ritz on the active columns
+        TK_HIP(dgemm(n, w, n, Md, n, false, Xa, b, Wa, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
         ++matvecs;
-        TK_HIP(dgemm(b, b, n, Xc, b, true, L.W, b, L.S, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
-        TK_HIP(jacobi(L.S, b, b, L.theta, L.V, L.Vg, s));
-        TK_HIP(dgemm(n, b, b, Xc, b, false, L.V, b, L.Y0, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
+        TK_HIP(dgemm(w, w, n, Xa, b, true, Wa, b, L.S, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
+        TK_HIP(jacobi(L.S, w, w, L.theta, L.V, L.Vg, s));
+        TK_HIP(dgemm(n, w, w, Xa, b, false, L.V, w, L.Y0, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
                      s));
-        TK_HIP(dgemm(n, b, b, L.W, b, false, L.V, b, L.Y1, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
+        TK_HIP(dgemm(n, w, w, Wa, b, false, L.V, w, L.Y1, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
                      s));
-        TK_HIP(hipMemcpyAsync(Xc, L.Y0, sizeof(double) * nb, hipMemcpyDeviceToDevice, s));
-        TK_HIP(hipMemcpyAsync(L.W, L.Y1, sizeof(double) * nb, hipMemcpyDeviceToDevice, s));
-        k_resid<<<b, 256, 0, s>>>(L.W, Xc, L.theta, n, b, L.res);
+        TK_HIP(hipMemcpy2DAsync(Xa, sizeof(double) * b, L.Y0, sizeof(double) * w, sizeof(double) * w, n,
+                                hipMemcpyDeviceToDevice, s));
+        TK_HIP(hipMemcpy2DAsync(Wa, sizeof(double) * b, L.Y1, sizeof(double) * w, sizeof(double) * w, n,
+                                hipMemcpyDeviceToDevice, s));
+        k_resid<<<w, 256, 0, s>>>(Wa, Xa, L.theta, n, b, L.res);
         TK_LAUNCHED();
-        TK_HIP(hipMemcpyAsync(h.data(), L.theta, sizeof(double) * b, hipMemcpyDeviceToHost, s));
-        TK_HIP(hipMemcpyAsync(h.data() + b, L.res, sizeof(double) * b, hipMemcpyDeviceToHost, s));
+        TK_HIP(hipMemcpyAsync(h.data(), L.theta, sizeof(double) * w, hipMemcpyDeviceToHost, s));
+        TK_HIP(hipMemcpyAsync(h.data() + b, L.res, sizeof(double) * w, hipMemcpyDeviceToHost, s));
         TK_HIP(hipStreamSynchronize(s));
-        const double *th = h.data(), *res = h.data() + b;
+        tha.assign(h.data(), h.data() + w);
+        const double *res = h.data() + b;
         double E = 0;
-        for (int j = 0; j < J; ++j) E += th[j];
-        int Lk = 0;
-        const double lock_tol = 1e-11 * std::max(th[0], 1e-300);
-        while (Lk < J && res[Lk] <= lock_tol) ++Lk;
-        bool conv = (Eold >= 0 && std::fabs(E - Eold) <= o.tol * std::fabs(E)) || Lk == J || th[0] <= 0.0;
+        for (double v : thL) E += v;
+        for (int j = 0; j < J - Lk; ++j) E += tha[j];
+        const double thmax = std::max(thL.empty() ? 0.0 : thL[0], tha[0]);
+        bool conv = (Eold >= 0 && std::fabs(E - Eold) <= o.tol * std::fabs(E)) || !(thmax > 0.0);
+        // newly converged leading pairs
+        int newl = 0;
+        const double lock_tol = 1e-11 * std::max(thmax, 1e-300);
+        while (Lk + newl < J && res[newl] <= lock_tol) ++newl;
+        if (Lk + newl == J) conv = true;
         if (conv) break;
         if (matvecs >= o.max_iters) {
             *noconv = 1;
             break;
         }
         Eold = E;
-        // Chebyshev filter on columns [Lk, b)
-        const int w = b - Lk;
-        double mu = th[b - 1], top = th[Lk];
-        if (!(mu > 0.0) || !(top > mu * (1.0 + 1e-12))) {
-            // no usable interval: a plain power step
-            mu = 0.0;
+        if (newl > 0) {
+            k_deflate<<<(unsigned)std::min<int64_t>(ceil_div((int64_t)n * n, 256), 65536), 256, 0, s>>>(
+                Md, n, Xc, b, Lk, newl, L.theta);
+            TK_LAUNCHED();
+            for (int j = 0; j < newl; ++j) thL.push_back(tha[j]);
+            Lk += newl;
         }
-        double *Xa = Xc + Lk;
+        // Chebyshev filter on the active columns with the deflated matrix:
+        // damp [0, mu] (mu = smallest active Ritz value), scale by the top
+        const int wa = b - Lk;
+        double *Xf = Xc + Lk;
+        double mu = tha[w - 1], top = tha[newl];
+        if (!(mu > 0.0) || !(top > mu * (1.0 + 1e-12))) mu = 0.0;  // no interval: power step
         double *Ya = L.Y0 + Lk, *Yb = L.Y1 + Lk, *Yc = L.Y2 + Lk;
+        double *cur = Ya;
         if (mu <= 0.0) {
-            TK_HIP(dgemm(n, w, n, M, n, false, Xa, b, Ya, b, 1.0 / std::max(top, 1e-300), 0.0, nullptr, 0.0, nullptr,
-                         L.split, L.split_elems, s));
+            TK_HIP(dgemm(n, wa, n, Md, n, false, Xf, b, Ya, b, 1.0 / std::max(top, 1e-300), 0.0, nullptr, 0.0,
+                         nullptr, L.split, L.split_elems, s));
             ++matvecs;
         } else {
             const double c = 0.5 * mu, e = 0.5 * mu, t = (top - c) / e;
+            // The filter scales the block's top by T_d(t) relative to its
+            // bottom; rounding-level parts along a not yet locked outlier grow
+            // by the same factor. Keeping T_d(t) <= 1e8 keeps the filtered
+            // block well within what shifted CholeskyQR orthonormalises.
+            const int dmax = (int)std::floor(std::acosh(1e8) / std::acosh(std::max(t, 1.0 + 1e-12)));
+            const int degree = std::max(1, std::min(o.degree, dmax));
             double sig = 1.0 / t;
-            // Y1 = (M X - c X) * sig / e
-            TK_HIP(dgemm(n, w, n, M, n, false, Xa, b, Ya, b, sig / e, -c * sig / e, Xa, 0.0, nullptr, L.split,
+            TK_HIP(dgemm(n, wa, n, Md, n, false, Xf, b, Ya, b, sig / e, -c * sig / e, Xf, 0.0, nullptr, L.split,
                          L.split_elems, s));
             ++matvecs;
-            const double *prev = Xa;
-            double *cur = Ya;
+            const double *prev = Xf;
             double *bufs[3] = {Ya, Yb, Yc};
             int ci = 0;
-            for (int k = 1; k < o.degree; ++k) {
+            for (int k = 1; k < degree; ++k) {
                 const double sig2 = 1.0 / (2.0 * t - sig);
                 const double al = 2.0 * sig2 / e;
                 int ni = (ci + 1) % 3;
                 if (bufs[ni] == prev) ni = (ni + 1) % 3;
                 double *nxt = bufs[ni];
-                TK_HIP(dgemm(n, w, n, M, n, false, cur, b, nxt, b, al, -c * al, cur, -sig * sig2, prev, L.split,
+                TK_HIP(dgemm(n, wa, n, Md, n, false, cur, b, nxt, b, al, -c * al, cur, -sig * sig2, prev, L.split,
                              L.split_elems, s));
                 ++matvecs;
                 prev = cur;
@@ -592,34 +695,27 @@ hipError_t lead_eig(const double *M, int n, int J, double *X, double *F, double 
                 ci = ni;
                 sig = sig2;
             }
-            if (cur != Ya) TK_HIP(hipMemcpy2DAsync(Ya, sizeof(double) * b, cur, sizeof(double) * b,
-                                                    sizeof(double) * w, n, hipMemcpyDeviceToDevice, s));
         }
-        // Ya holds the filtered active columns; re-orthogonalise against locked
-        if (Lk > 0) {
-            for (int rep = 0; rep < 2; ++rep) {
-                TK_HIP(dgemm(Lk, w, n, Xc, b, true, Ya, b, L.S, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split,
-                             L.split_elems, s));
-                TK_HIP(dgemm(n, w, Lk, Xc, b, false, L.S, w, Ya, b, -1.0, 1.0, Ya, 0.0, nullptr, L.split,
-                             L.split_elems, s));
-            }
-        }
-        TK_HIP(hipMemcpy2DAsync(Xa, sizeof(double) * b, Ya, sizeof(double) * b, sizeof(double) * w, n,
+        // orthonormalise against the locked vectors and among themselves
+        TK_HIP(hipMemcpy2DAsync(Xf, sizeof(double) * b, cur, sizeof(double) * b, sizeof(double) * wa, n,
                                 hipMemcpyDeviceToDevice, s));
-        TK_HIP(orthonormalise(Xc, n, b, Lk, w, L, o.seed + 17 * (outer + 2), s));
-        if (Lk > 0) {
-            // the CholeskyQR passes do not see the locked columns: project once more
-            TK_HIP(dgemm(Lk, w, n, Xc, b, true, Xa, b, L.S, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split,
-                         L.split_elems, s));
-            TK_HIP(dgemm(n, w, Lk, Xc, b, false, L.S, w, Xa, b, -1.0, 1.0, Xa, 0.0, nullptr, L.split, L.split_elems,
-                         s));
-            TK_HIP(orthonormalise(Xc, n, b, Lk, w, L, o.seed + 31 * (outer + 2), s));
-        }
+        TK_HIP(orthonormalise(Xc, n, b, Lk, wa, L, o.seed + 17 * (outer + 2), s));
     }
     *iters = matvecs;
-    k_extract<<<J, 256, 0, s>>>(Xc, n, b, J, F);
+    // the J leading pairs: locked ones, then the leading active ones; order
+    // them by value (locking order is almost always already descending)
+    std::vector<double> all(thL);
+    for (int j = 0; (int)all.size() < J; ++j) all.push_back(tha[j]);
+    std::vector<int> perm(J);
+    for (int j = 0; j < J; ++j) perm[j] = j;
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) { return all[a] > all[c]; });
+    std::vector<double> sorted(J);
+    for (int j = 0; j < J; ++j) sorted[j] = all[perm[j]];
+    TK_HIP(hipMemcpyAsync(L.colmap, perm.data(), sizeof(int) * J, hipMemcpyHostToDevice, s));
+    TK_HIP(hipMemcpyAsync(theta_dev, sorted.data(), sizeof(double) * J, hipMemcpyHostToDevice, s));
+    k_extract<<<J, 256, 0, s>>>(Xc, n, b, J, F, L.colmap);
     TK_LAUNCHED();
-    TK_HIP(hipMemcpyAsync(theta_dev, L.theta, sizeof(double) * J, hipMemcpyDeviceToDevice, s));
+    TK_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
     return hipSuccess;
 }
 
