@@ -88,7 +88,9 @@ typedef struct tk_opts {
                                with fit(0) = 0 (paper: 1e-4); tol <= 0 runs
                                exactly max_iters sweeps */
     int32_t eig_max_iters;  /* cap on filtered subspace iterations per eigensolve */
-    double  eig_tol;        /* relative residual target of the eigensolve */
+    double  eig_tol;        /* relative change of the sum of the J leading Ritz values at
+                               which an eigensolve stops; 0 = by precision (1e-12 for
+                               FP64, 1e-8 for FP32 and mixed) */
     int32_t timing;         /* 1: record HIP events around the projection and
                                TTMc kernels and report their times in tk_stats */
 } tk_opts;
@@ -113,8 +115,8 @@ typedef struct tk_stats {
     double  norm_x;         /* ||X||_F */
 } tk_stats;
 
-/* Fill *opt with: FP32, HO-SVD init, 50 sweeps, tol 1e-4, eig cap 400,
-   eig tol 1e-10, no timing. */
+/* Fill *opt with: FP32, HO-SVD init, 50 sweeps, tol 1e-4, eig cap 400
+   products, eig tol 0 (by precision), no timing. */
 void tucker_default_opts(tk_opts *opt);
 
 /* Bytes of device workspace that tucker_hooi (algo TK_ALGO_HOOI),

@@ -97,6 +97,7 @@ struct Plan {
     int64_t I[3], nnz;
     int J[3];
     int64_t nslots[3];
+    int ldT[3];  // row stride of the projections T(m) (MP pads rows to 16 bytes)
     int b[3];
     // device buffers
     int32_t *flags, *nu;
@@ -129,10 +130,11 @@ struct Plan {
 static size_t elem_size(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
 
 static GramTerm term_of(const Plan &p, int m, int n, const void *base) {
-    // T(m) is [i_hi][i_lo][r]; rows of the mode-n unfolding are i_n
+    // T(m) is [i_hi][i_lo][r < ldT]; rows of the mode-n unfolding are i_n.
+    // Padding columns are zero and only add zero products.
     GramTerm t;
     t.base = base;
-    const int64_t Jm = p.J[m], Ilo = p.I[lo_of(m)], Ihi = p.I[hi_of(m)];
+    const int64_t Jm = p.ldT[m], Ilo = p.I[lo_of(m)], Ihi = p.I[hi_of(m)];
     if (hi_of(m) == n) {
         t.s_row = Ilo * Jm;
         t.chunk_len = Ilo * Jm;
@@ -181,7 +183,7 @@ static void carve(Plan &p, Arena &ar) {
     for (int m = 0; m < 3; ++m) p.T[m] = nullptr;
     const size_t es = elem_size(prec);
     if (p.algo == TK_ALGO_MP) {
-        for (int m = 0; m < 3; ++m) p.T[m] = ar.take<char>((int64_t)(p.nslots[m] * p.J[m] * es));
+        for (int m = 0; m < 3; ++m) p.T[m] = ar.take<char>((int64_t)(p.nslots[m] * p.ldT[m] * es));
         if (prec == PBF16) p.Tcore = ar.take<float>(p.nslots[2] * p.J[2]);
     } else if (p.algo == TK_ALGO_HOOI) {
         p.T[2] = ar.take<char>((int64_t)(p.nslots[2] * p.J[2] * es));
@@ -205,8 +207,8 @@ static void carve(Plan &p, Arena &ar) {
             int gprec = prec;
             if (p.algo == TK_ALGO_MP) {
                 int m1 = (n + 1) % 3, m2 = (n + 2) % 3;
-                K[0] = p.nslots[m1] / p.I[n] * p.J[m1];
-                K[1] = p.nslots[m2] / p.I[n] * p.J[m2];
+                K[0] = p.nslots[m1] / p.I[n] * p.ldT[m1];
+                K[1] = p.nslots[m2] / p.I[n] * p.ldT[m2];
                 gs = std::max(gs, gram_scratch_bytes((int)p.I[n], gprec, 2, K));
             } else {
                 K[0] = (int64_t)p.J[(n + 1) % 3] * p.J[(n + 2) % 3];
@@ -278,6 +280,8 @@ static void plan_init(Plan &p, int algo, int prec, const tk_coo *X, const int32_
         p.J[n] = J[n];
     }
     for (int m = 0; m < 3; ++m) p.nslots[m] = p.I[hi_of(m)] * p.I[lo_of(m)];
+    const int vec = prec == P64 ? 2 : (prec == P32 ? 4 : 8);  // elements per 16 bytes
+    for (int m = 0; m < 3; ++m) p.ldT[m] = algo == TK_ALGO_MP ? (int)ceil_div(p.J[m], vec) * vec : p.J[m];
 }
 
 }  // namespace tk
@@ -293,7 +297,7 @@ void tucker_default_opts(tk_opts *o) {
     o->max_iters = 50;
     o->tol = 1e-4;
     o->eig_max_iters = 400;
-    o->eig_tol = 1e-10;
+    o->eig_tol = 0.0;
     o->timing = 0;
 }
 
@@ -436,13 +440,16 @@ static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double
 
 // T(m) = X x_m F^T for the given output precision. F64 is the FP64 factor;
 // its FP32 copy must be current for FP32 / BF16 outputs.
-static hipError_t project_m(Plan &p, int m, const double *F64, void *T, int out_prec, hipStream_t s) {
+static hipError_t project_m(Plan &p, int m, const double *F64, void *T, int out_prec, hipStream_t s, int ld = 0) {
     const int J = p.J[m];
+    if (ld <= 0) ld = p.ldT[m];
     if (out_prec == P64)
-        return project<double, double, double>(p.ptr[m], p.lidx[m], p.lval64[m], F64, J, p.nslots[m], (double *)T, s);
+        return project<double, double, double>(p.ptr[m], p.lidx[m], p.lval64[m], F64, J, ld, p.nslots[m], (double *)T,
+                                               s);
     if (out_prec == P32)
-        return project<float, float, float>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, p.nslots[m], (float *)T, s);
-    return project<float, float, bf16>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, p.nslots[m], (bf16 *)T, s);
+        return project<float, float, float>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, ld, p.nslots[m],
+                                            (float *)T, s);
+    return project<float, float, bf16>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, ld, p.nslots[m], (bf16 *)T, s);
 }
 
 static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s) {
@@ -455,7 +462,7 @@ static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s)
 // MP core from T(2) = X x_3 C^T stored [i1][i0][r2] (FP64 or FP32):
 // Z[i1][p][r] = sum_i0 A[i0][p] T[i1][i0][r]; G'[q][p][r] = sum_i1 B[i1][q] Z[i1][p][r];
 // core[p][q][r] = G'[q][p][r].
-static hipError_t core_from_T2(Plan &p, const void *T2, bool t2_is_f64, const double *A, const double *B,
+static hipError_t core_from_T2(Plan &p, const void *T2, int ldt, bool t2_is_f64, const double *A, const double *B,
                                double *core, hipStream_t s) {
     const int J0 = p.J[0], J1 = p.J[1], J2 = p.J[2];
     GemmArgs g;
@@ -467,8 +474,8 @@ static hipError_t core_from_T2(Plan &p, const void *T2, bool t2_is_f64, const do
     g.lda = J0;
     g.a_trans = true;
     g.B = T2;
-    g.ldb = J2;
-    g.sB = p.I[0] * J2;
+    g.ldb = ldt;
+    g.sB = p.I[0] * ldt;
     g.C = p.Z;
     g.ldc = J2;
     g.sC = (int64_t)J0 * J2;
@@ -516,7 +523,9 @@ static int run_eig(Plan &p, int n, double *M, double *F, bool warm, const tk_opt
                    int *noconv_any, hipStream_t s) {
     EigOpts eo;
     eo.max_iters = o->eig_max_iters;
-    eo.tol = o->eig_tol;
+    // 0 = by precision: FP64 follows the oracle's exact eigensolver closely;
+    // FP32 / BF16 projections already limit the fit to about 1e-7 relative
+    eo.tol = o->eig_tol > 0 ? o->eig_tol : (p.prec == P64 ? 1e-12 : 1e-8);
     eo.warm = warm && p.blk_ok[n];
     eo.seed = 0x5eed0000ull + (uint64_t)n;
     int it = 0, nc = 0;
@@ -637,12 +646,12 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         const void *T2c = p.T[2];
         bool f64 = prec == P64;
         if (prec == PBF16) {
-            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.nslots[2], p.Tcore,
-                                             s)));
+            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.J[2], p.nslots[2],
+                                             p.Tcore, s)));
             T2c = p.Tcore;
         }
         tm.begin(kCore);
-        ST(core_from_T2(p, T2c, f64, A, B, core, s));
+        ST(core_from_T2(p, T2c, prec == PBF16 ? p.J[2] : p.ldT[2], f64, A, B, core, s));
         tm.end();
         double fit = 0;
         if ((st = finish_fit(p, core, s, &fit))) return st;
@@ -663,12 +672,12 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         tm.end();
         const void *T2c = p.T[2];
         if (prec == PBF16) {
-            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.nslots[2], p.Tcore,
-                                             s)));
+            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.J[2], p.nslots[2],
+                                             p.Tcore, s)));
             T2c = p.Tcore;
         }
         tm.begin(kCore);
-        ST(core_from_T2(p, T2c, prec == P64, A, B, core, s));
+        ST(core_from_T2(p, T2c, prec == PBF16 ? p.J[2] : p.ldT[2], prec == P64, A, B, core, s));
         tm.end();
         ST(hipStreamSynchronize(s));
     }
@@ -884,9 +893,9 @@ extern "C" int tucker_fit(const tk_coo *X, const int32_t *J, const double *core,
     const int J0 = J[0], J1 = J[1], J2 = J[2];
     const int64_t nJ = (int64_t)J0 * J1 * J2;
     // Gx = X x_n A(n)^T via T(2)(C) and the two contractions of the MP core
-    ST((project<double, double, double>(p.ptr[2], p.lidx[2], p.lval64[2], factors[2], J2, p.nslots[2],
+    ST((project<double, double, double>(p.ptr[2], p.lidx[2], p.lval64[2], factors[2], J2, J2, p.nslots[2],
                                         (double *)p.T[2], s)));
-    ST(core_from_T2(p, p.T[2], true, factors[0], factors[1], p.Gx, s));
+    ST(core_from_T2(p, p.T[2], J2, true, factors[0], factors[1], p.Gx, s));
     ST(dot(p.Gx, core, nJ, p.partials, p.scal + 3, s));
     // P_n = A(n)^T A(n)
     for (int n = 0; n < 3; ++n) {

@@ -104,11 +104,11 @@ hipError_t hosvd_gram(int n, const int64_t dims[3], const int32_t *ptr_n, const 
                       double *H, hipStream_t s);
 
 // ---------------------------------------------------------------- project.hip
-// T[slot][r] = sum over the slot's entries of lval * F[lidx][r], r < J;
-// slots = I_hi * I_lo, dense and zero-filled.
+// T[slot * ldT + r] = sum over the slot's entries of lval * F[lidx][r] for
+// r < J, zero for J <= r < ldT; slots = I_hi * I_lo, dense and zero-filled.
 template <class TV, class TF, class TO>
-hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int J, int64_t nslots,
-                   TO *T, hipStream_t s);
+hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int J, int ldT,
+                   int64_t nslots, TO *T, hipStream_t s);
 
 // ---------------------------------------------------------------- mfma.hip
 // One operand of a Gram: row i, column k = (kc, kr) with kr < chunk_len,
@@ -155,7 +155,7 @@ int eig_block_width(int n, int J);
 struct EigOpts {
     int max_iters = 400;
     double tol = 1e-10;
-    int degree = 12;
+    int degree = 20;
     bool warm = false;
     uint64_t seed = 1234;
 };

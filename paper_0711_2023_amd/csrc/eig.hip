@@ -109,7 +109,7 @@ __global__ void k_colscale(double *X, int64_t n, int ld, int c0, int w, const do
 // a direction it cannot resolve instead of failing). The inverse is formed
 // column by column (one thread per column) into the strictly lower triangle,
 // transposed, with its diagonal kept apart.
-__global__ void __launch_bounds__(256) k_chol_inv(const double *S, int lds, int w, double shift, double *Rinv) {
+__global__ void __launch_bounds__(1024) k_chol_inv(const double *S, int lds, int w, double shift, double *Rinv) {
     extern __shared__ double A[];  // w*w, then w for the inverse's diagonal
     double *dinv = A + (size_t)w * w;
     __shared__ double tr;
@@ -140,7 +140,7 @@ __global__ void __launch_bounds__(256) k_chol_inv(const double *S, int lds, int 
         const double rd = 1.0 / fmax(A[k * w + k], tiny);
         // trailing upper triangle (i, j), k < i <= j: thread (g, c) with
         // g < groups = nth / w takes column k+1+c and rows k+1+g, k+1+g+groups, ...
-        // (w <= nth is guaranteed by the host)
+        // (w <= 140 < nth)
         const int groups = nth / w;
         const int g = tid / w, c = tid - g * w;
         if (g < groups) {
@@ -160,12 +160,19 @@ __global__ void __launch_bounds__(256) k_chol_inv(const double *S, int lds, int 
     // kept at A[j][i] (strictly lower triangle, transposed), its diagonal in dinv.
     for (int j = tid; j < w; j += nth) dinv[j] = 1.0 / A[j * w + j];
     __syncthreads();
+    // Each dot product is split over 4 consecutive lanes and combined with
+    // two shuffles (groups of 4 lanes are always wholly active).
     for (int i = w - 2; i >= 0; --i) {
         const double rii = dinv[i];
-        for (int j = i + 1 + tid; j < w; j += nth) {
-            double v = -A[i * w + j] * dinv[j];  // k = j term
-            for (int k = i + 1; k < j; ++k) v -= A[i * w + k] * A[j * w + k];
-            A[j * w + i] = v * rii;
+        const int ncol = w - 1 - i;
+        for (int t = tid; t < ncol * 4; t += nth) {
+            const int j = i + 1 + (t >> 2), part = t & 3;
+            double v = 0.0;
+            for (int k = i + 1 + part; k < j; k += 4) v -= A[i * w + k] * A[j * w + k];
+            if (part == 0) v -= A[i * w + j] * dinv[j];  // k = j term
+            v += __shfl_xor(v, 1, 64);
+            v += __shfl_xor(v, 2, 64);
+            if (part == 0) A[j * w + i] = v * rii;
         }
         __syncthreads();
     }
@@ -487,17 +494,18 @@ size_t eig_work_bytes(int n, int b) {
 }
 
 // ------------------------------------------------------------------ host helpers
-static hipError_t jacobi(const double *H, int ldh, int b, double *theta, double *Vout, double *Vg, hipStream_t s) {
+static hipError_t jacobi(const double *H, int ldh, int b, double *theta, double *Vout, double *Vg, hipStream_t s,
+                         int sweeps = 30) {
     const int half = (b + 1) / 2;
     size_t small = sizeof(double) * 2 * half + sizeof(int) * 2 * half;
     if (b <= kJacobiVLds) {
         size_t lds = sizeof(double) * 2 * (size_t)b * b + small;
         hipFuncSetAttribute((const void *)k_jacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_jacobi<true><<<1, 512, lds, s>>>(H, ldh, b, 30, theta, Vout, Vg);
+        k_jacobi<true><<<1, 512, lds, s>>>(H, ldh, b, sweeps, theta, Vout, Vg);
     } else {
         size_t lds = sizeof(double) * (size_t)b * b + small;
         hipFuncSetAttribute((const void *)k_jacobi<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_jacobi<false><<<1, 512, lds, s>>>(H, ldh, b, 30, theta, Vout, Vg);
+        k_jacobi<false><<<1, 512, lds, s>>>(H, ldh, b, sweeps, theta, Vout, Vg);
     }
     TK_LAUNCHED();
     return hipSuccess;
@@ -567,7 +575,7 @@ static hipError_t orthonormalise(double *X, int64_t n, int b, int c0, int w, Eig
                      L.split_elems, s));
         size_t lds = sizeof(double) * ((size_t)w * w + w);
         hipFuncSetAttribute((const void *)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_chol_inv<<<1, 256, lds, s>>>(L.S, w, w, shift, L.Rinv);
+        k_chol_inv<<<1, 1024, lds, s>>>(L.S, w, w, shift, L.Rinv);
         TK_LAUNCHED();
         TK_HIP(dgemm((int)n, w, w, X + c0, b, false, L.Rinv, w, L.Y0, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split,
                      L.split_elems, s));
@@ -608,6 +616,11 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
     double *Xc = X;
     double *Md = M;  // deflated in place
     std::vector<double> tha;
+    // Intermediate Rayleigh-Ritz steps use two Jacobi sweeps: an approximate
+    // rotation is enough to pick the leading directions of the block (it is
+    // inexact only among nearly tied Ritz pairs); the step after the energy
+    // test has passed diagonalises fully and provides the output.
+    bool final_rr = false;
     for (int outer = 0;; ++outer) {
         const int w = b - Lk;
         double *Xa = Xc + Lk, *Wa = L.W + Lk;
@@ -615,7 +628,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
         TK_HIP(dgemm(n, w, n, Md, n, false, Xa, b, Wa, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
         ++matvecs;
         TK_HIP(dgemm(w, w, n, Xa, b, true, Wa, b, L.S, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
-        TK_HIP(jacobi(L.S, w, w, L.theta, L.V, L.Vg, s));
+        TK_HIP(jacobi(L.S, w, w, L.theta, L.V, L.Vg, s, final_rr ? 30 : 2));
         TK_HIP(dgemm(n, w, w, Xa, b, false, L.V, w, L.Y0, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
                      s));
         TK_HIP(dgemm(n, w, w, Wa, b, false, L.V, w, L.Y1, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
@@ -641,10 +654,11 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
         const double lock_tol = 1e-11 * std::max(thmax, 1e-300);
         while (Lk + newl < J && res[newl] <= lock_tol) ++newl;
         if (Lk + newl == J) conv = true;
-        if (conv) break;
-        if (matvecs >= o.max_iters) {
-            *noconv = 1;
-            break;
+        if (final_rr) break;
+        if (conv || matvecs >= o.max_iters) {
+            if (!conv) *noconv = 1;
+            final_rr = true;  // one more Rayleigh-Ritz, diagonalised fully
+            continue;
         }
         Eold = E;
         if (newl > 0) {

@@ -33,9 +33,13 @@ struct PolF32 {
     typedef floatx16 Frag;
     static constexpr int BT = 32, NB = WT / BT, KS = 16, KI = 2, LDK = KS + 1, NV = 16;
     __device__ static void mma(const E *As, const E *Bs, int arow, int brow, int kk, Frag &c) {
+        mma_ld<LDK>(As, Bs, arow, brow, kk, c);
+    }
+    template <int L>
+    __device__ static void mma_ld(const E *As, const E *Bs, int arow, int brow, int kk, Frag &c) {
         const int l = threadIdx.x & 63;
-        float a = As[(arow + (l & 31)) * LDK + kk + (l >> 5)];
-        float b = Bs[(brow + (l & 31)) * LDK + kk + (l >> 5)];
+        float a = As[(arow + (l & 31)) * L + kk + (l >> 5)];
+        float b = Bs[(brow + (l & 31)) * L + kk + (l >> 5)];
         c = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
     }
     __device__ static int orow(int v, int l) { return 8 * (v >> 2) + 4 * (l >> 5) + (v & 3); }
@@ -49,9 +53,13 @@ struct PolBF16 {
     typedef floatx16 Frag;
     static constexpr int BT = 32, NB = WT / BT, KS = 32, KI = 16, LDK = KS + 8, NV = 16;
     __device__ static void mma(const E *As, const E *Bs, int arow, int brow, int kk, Frag &c) {
+        mma_ld<LDK>(As, Bs, arow, brow, kk, c);
+    }
+    template <int L>
+    __device__ static void mma_ld(const E *As, const E *Bs, int arow, int brow, int kk, Frag &c) {
         const int l = threadIdx.x & 63;
-        bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[(arow + (l & 31)) * LDK + kk + 8 * (l >> 5)]);
-        bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[(brow + (l & 31)) * LDK + kk + 8 * (l >> 5)]);
+        bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[(arow + (l & 31)) * L + kk + 8 * (l >> 5)]);
+        bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[(brow + (l & 31)) * L + kk + 8 * (l >> 5)]);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
     }
     __device__ static int orow(int v, int l) { return 8 * (v >> 2) + 4 * (l >> 5) + (v & 3); }
@@ -65,9 +73,13 @@ struct PolF64 {
     typedef doublex4 Frag;
     static constexpr int BT = 16, NB = WT / BT, KS = 16, KI = 4, LDK = KS + 1, NV = 4;
     __device__ static void mma(const E *As, const E *Bs, int arow, int brow, int kk, Frag &c) {
+        mma_ld<LDK>(As, Bs, arow, brow, kk, c);
+    }
+    template <int L>
+    __device__ static void mma_ld(const E *As, const E *Bs, int arow, int brow, int kk, Frag &c) {
         const int l = threadIdx.x & 63;
-        double a = As[(arow + (l & 15)) * LDK + kk + (l >> 4)];
-        double b = Bs[(brow + (l & 15)) * LDK + kk + (l >> 4)];
+        double a = As[(arow + (l & 15)) * L + kk + (l >> 4)];
+        double b = Bs[(brow + (l & 15)) * L + kk + (l >> 4)];
         c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
     __device__ static int orow(int v, int l) { return 4 * v + (l >> 4); }
@@ -89,13 +101,14 @@ __device__ inline bf16 cvt<bf16, double>(double x) { return (bf16)(float)x; }
 struct GramTermK {
     const void *base;
     int64_t s_row, s_chunk, chunk_len, nchunks;
-    int64_t kper;        // K elements per split (multiple of KS)
+    int64_t kper;         // K elements per split (multiple of the stage depth)
     int32_t split_begin;  // first split index of this term
 };
 struct GramKArgs {
     GramTermK t[2];
     int32_t nterms;
     int32_t splits_total;
+    int32_t npairs;
     int32_t n;
 };
 
@@ -107,32 +120,109 @@ __device__ inline void pair_decode(int pair, int &ti, int &tj) {
     tj = pair - t * (t + 1) / 2;
 }
 
-template <class P, int WT>
-__global__ void __launch_bounds__(256) k_gram(GramKArgs g, typename P::Acc *partials) {
+// Stage depth per element type: 64 BF16, 32 FP32, 16 FP64 (128 bytes per row).
+template <class E> struct GramKS { static constexpr int v = 128 / sizeof(E); };
+template <> struct GramKS<bf16> { static constexpr int v = 64; };
+
+template <class P, int WT> struct GramCfg {
     typedef typename P::E E;
-    constexpr int TBK = 2 * WT;
-    constexpr int KS = P::KS, LDK = P::LDK;
-    __shared__ E As[TBK * LDK];
-    __shared__ E Bs[TBK * LDK];
-    const int item = blockIdx.x;
-    const int pair = item / g.splits_total;
-    const int sidx = item - pair * g.splits_total;
+    static constexpr int TBK = 2 * WT;            // output tile
+    static constexpr int KS = GramKS<E>::v;       // stage depth
+    static constexpr int VW = 16 / sizeof(E);     // elements per 16-byte vector
+    static constexpr int TPR = KS / VW;           // threads per row per stage (8)
+    static constexpr int RPP = 256 / TPR;         // rows per load pass (32)
+    static constexpr int PASSES = TBK / RPP;      // load passes per operand
+    static constexpr int LDK = sizeof(E) == 2 ? KS + 8 : KS + 1;
+};
+
+// One operand row-block of one stage: TBK rows x KS columns, loaded as
+// 16-byte vectors (VEC: chunk length, strides and base are multiples of the
+// vector) or element by element.
+template <class Cfg, bool VEC>
+struct StageRegs {
+    typename Cfg::E v[Cfg::PASSES][Cfg::VW];
+};
+
+template <class Cfg, bool VEC>
+__device__ inline void load_stage(StageRegs<Cfg, VEC> &R, const typename Cfg::E *base, const GramTermK &t,
+                                  int64_t row0, int n, int64_t k, int64_t kend, int64_t kc, int64_t kr, int rr) {
+    typedef typename Cfg::E E;
+#pragma unroll
+    for (int ps = 0; ps < Cfg::PASSES; ++ps) {
+        const int64_t row = row0 + ps * Cfg::RPP + rr;
+        if (VEC) {
+            if (row < n && k < kend) {
+                typedef E __attribute__((ext_vector_type(Cfg::VW))) V;
+                V x = *reinterpret_cast<const V *>(base + row * t.s_row + kc * t.s_chunk + kr);
+#pragma unroll
+                for (int e = 0; e < Cfg::VW; ++e) R.v[ps][e] = x[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < Cfg::VW; ++e) R.v[ps][e] = (E)0;
+            }
+        } else {
+            int64_t c = kc, r = kr;
+#pragma unroll
+            for (int e = 0; e < Cfg::VW; ++e) {
+                const bool ok = row < n && k + e < kend;
+                R.v[ps][e] = ok ? base[row * t.s_row + c * t.s_chunk + r] : (E)0;
+                if (++r == t.chunk_len) {
+                    r = 0;
+                    ++c;
+                }
+            }
+        }
+    }
+}
+
+template <class Cfg, bool VEC>
+__device__ inline void store_stage(const StageRegs<Cfg, VEC> &R, typename Cfg::E *S, int rr, int kv) {
+#pragma unroll
+    for (int ps = 0; ps < Cfg::PASSES; ++ps) {
+        const int row = ps * Cfg::RPP + rr;
+        if (sizeof(typename Cfg::E) == 2) {
+            typedef typename Cfg::E __attribute__((ext_vector_type(Cfg::VW))) V;
+            V x;
+#pragma unroll
+            for (int e = 0; e < Cfg::VW; ++e) x[e] = R.v[ps][e];
+            *reinterpret_cast<V *>(&S[row * Cfg::LDK + kv * Cfg::VW]) = x;
+        } else {
+#pragma unroll
+            for (int e = 0; e < Cfg::VW; ++e) S[row * Cfg::LDK + kv * Cfg::VW + e] = R.v[ps][e];
+        }
+    }
+}
+
+template <class P, int WT, bool VEC>
+__global__ void __launch_bounds__(256) k_gram(GramKArgs g, typename P::Acc *partials) {
+    typedef GramCfg<P, WT> Cfg;
+    typedef typename P::E E;
+    constexpr int TBK = Cfg::TBK, KS = Cfg::KS, LDK = Cfg::LDK;
+    __shared__ __attribute__((aligned(16))) E As[TBK * LDK];
+    __shared__ __attribute__((aligned(16))) E Bs[TBK * LDK];
+    // XCD-aware item map: consecutive blocks go to different XCDs, so block
+    // g runs on XCD g % 8; all tile pairs of one K-split share one XCD (and
+    // its L2) by giving split s to XCD s % 8.
+    const int gx = blockIdx.x % 8, gq = blockIdx.x / 8;
+    const int rnd = gq / g.npairs, pair = gq - rnd * g.npairs;
+    const int sidx = rnd * 8 + gx;
+    if (sidx >= g.splits_total) return;
     const int term = (g.nterms > 1 && sidx >= g.t[1].split_begin) ? 1 : 0;
     const GramTermK t = g.t[term];
     const int split = sidx - t.split_begin;
     int ti, tj;
     pair_decode(pair, ti, tj);
+    const bool diag = ti == tj;
     const int64_t K = t.chunk_len * t.nchunks;
     const int64_t kbeg = (int64_t)split * t.kper;
     const int64_t kend = kbeg + t.kper < K ? kbeg + t.kper : K;
     const E *base = reinterpret_cast<const E *>(t.base);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
-    constexpr int RPI = 256 / KS;  // rows loaded per iteration
-    constexpr int LPT = TBK / RPI;  // iterations
-    const int kk = tid % KS, rr = tid / KS;
-    int64_t k = kbeg + kk;
+    const int kv = tid % Cfg::TPR, rr = tid / Cfg::TPR;
+    int64_t k = kbeg + kv * Cfg::VW;
     int64_t kc = k / t.chunk_len, kr = k - kc * t.chunk_len;
+    const int64_t rowA0 = (int64_t)ti * TBK, rowB0 = (int64_t)tj * TBK;
 
     typename P::Frag acc[P::NB][P::NB];
 #pragma unroll
@@ -140,36 +230,35 @@ __global__ void __launch_bounds__(256) k_gram(GramKArgs g, typename P::Acc *part
 #pragma unroll
         for (int b = 0; b < P::NB; ++b) frag_zero<typename P::Frag, P::NV>(acc[a][b]);
 
-    const int64_t rowA0 = (int64_t)ti * TBK, rowB0 = (int64_t)tj * TBK;
+    StageRegs<Cfg, VEC> ra, rb;
+    load_stage<Cfg, VEC>(ra, base, t, rowA0, g.n, k, kend, kc, kr, rr);
+    if (!diag) load_stage<Cfg, VEC>(rb, base, t, rowB0, g.n, k, kend, kc, kr, rr);
+    const E *Bsrc = diag ? As : Bs;
     for (int64_t k0 = kbeg; k0 < kend; k0 += KS) {
-        const bool kval = k < kend;
-        const int64_t koff = kc * t.s_chunk + kr;
-#pragma unroll
-        for (int it = 0; it < LPT; ++it) {
-            const int row = it * RPI + rr;
-            const int64_t ga = rowA0 + row, gb = rowB0 + row;
-            E va = (kval && ga < g.n) ? base[ga * t.s_row + koff] : (E)0;
-            E vb = (kval && gb < g.n) ? base[gb * t.s_row + koff] : (E)0;
-            As[row * LDK + kk] = va;
-            Bs[row * LDK + kk] = vb;
-        }
+        store_stage<Cfg, VEC>(ra, As, rr, kv);
+        if (!diag) store_stage<Cfg, VEC>(rb, Bs, rr, kv);
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < KS; q += P::KI)
-#pragma unroll
-            for (int a = 0; a < P::NB; ++a)
-#pragma unroll
-                for (int b = 0; b < P::NB; ++b)
-                    P::mma(As, Bs, wr * WT + a * P::BT, wc * WT + b * P::BT, q, acc[a][b]);
-        __syncthreads();
+        // prefetch the next stage while the matrix cores work on this one
         k += KS;
         kr += KS;
         while (kr >= t.chunk_len) {
             kr -= t.chunk_len;
             ++kc;
         }
+        if (k0 + KS < kend) {
+            load_stage<Cfg, VEC>(ra, base, t, rowA0, g.n, k, kend, kc, kr, rr);
+            if (!diag) load_stage<Cfg, VEC>(rb, base, t, rowB0, g.n, k, kend, kc, kr, rr);
+        }
+#pragma unroll
+        for (int q = 0; q < KS; q += P::KI)
+#pragma unroll
+            for (int a = 0; a < P::NB; ++a)
+#pragma unroll
+                for (int b = 0; b < P::NB; ++b)
+                    P::template mma_ld<LDK>(As, Bsrc, wr * WT + a * P::BT, wc * WT + b * P::BT, q, acc[a][b]);
+        __syncthreads();
     }
-    typename P::Acc *out = partials + (int64_t)item * TBK * TBK;
+    typename P::Acc *out = partials + ((int64_t)pair * g.splits_total + sidx) * TBK * TBK;
 #pragma unroll
     for (int a = 0; a < P::NB; ++a)
 #pragma unroll
@@ -213,15 +302,16 @@ struct GramPlan {
 static GramPlan gram_plan(int n, int prec, int nterms, const int64_t *K) {
     GramPlan p;
     p.TBK = prec == P64 ? 64 : 128;
-    p.KS = prec == P64 ? 16 : (prec == P32 ? 16 : 32);
+    p.KS = prec == P64 ? 16 : (prec == P32 ? 32 : 64);
     p.acc_size = prec == P64 ? 8 : 4;
     int nt = (int)ceil_div(n, p.TBK);
     p.npairs = nt * (nt + 1) / 2;
-    int want = (int)std::max<int64_t>(1, ceil_div(2048, (int64_t)p.npairs * nterms));
+    // about 1024 blocks in flight, at least 4 stages per block
+    int want = (int)std::max<int64_t>(1, ceil_div(1024, (int64_t)p.npairs * nterms));
     p.splits_total = 0;
     for (int t = 0; t < nterms; ++t) {
         int64_t Kt = K[t] > 0 ? K[t] : 1;
-        int64_t maxs = std::max<int64_t>(1, ceil_div(Kt, (int64_t)p.KS * 8));
+        int64_t maxs = std::max<int64_t>(1, ceil_div(Kt, (int64_t)p.KS * 4));
         int64_t s = std::min<int64_t>(want, maxs);
         int64_t kper = ceil_div(ceil_div(Kt, s), p.KS) * p.KS;
         s = ceil_div(Kt, kper);
@@ -237,6 +327,16 @@ size_t gram_scratch_bytes(int n, int prec, int nterms, const int64_t *K) {
     return (size_t)p.npairs * p.splits_total * p.TBK * p.TBK * p.acc_size;
 }
 
+template <class P, int WT, class Acc>
+static hipError_t launch_gram(const GramKArgs &g, bool vec, unsigned blocks, Acc *scratch, hipStream_t s) {
+    if (vec)
+        k_gram<P, WT, true><<<blocks, 256, 0, s>>>(g, scratch);
+    else
+        k_gram<P, WT, false><<<blocks, 256, 0, s>>>(g, scratch);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
 hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, void *scratch, hipStream_t s) {
     int64_t K[2] = {0, 0};
     for (int t = 0; t < nterms; ++t) K[t] = terms[t].chunk_len * terms[t].nchunks;
@@ -244,7 +344,11 @@ hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, v
     GramKArgs g{};
     g.nterms = nterms;
     g.splits_total = p.splits_total;
+    g.npairs = p.npairs;
     g.n = n;
+    const int es = prec == P64 ? 8 : (prec == P32 ? 4 : 2);
+    const int vw = 16 / es;
+    bool vec = true;
     for (int t = 0; t < nterms; ++t) {
         g.t[t].base = terms[t].base;
         g.t[t].s_row = terms[t].s_row;
@@ -253,21 +357,21 @@ hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, v
         g.t[t].nchunks = terms[t].nchunks;
         g.t[t].kper = p.kper[t];
         g.t[t].split_begin = p.split_begin[t];
+        vec = vec && terms[t].chunk_len % vw == 0 && terms[t].s_row % vw == 0 &&
+              (terms[t].nchunks == 1 || terms[t].s_chunk % vw == 0) &&
+              reinterpret_cast<uintptr_t>(terms[t].base) % 16 == 0;
     }
-    const unsigned items = (unsigned)(p.npairs * p.splits_total);
+    const unsigned blocks = (unsigned)(8 * p.npairs * ceil_div(p.splits_total, 8));
     const int64_t total = (int64_t)p.npairs * p.TBK * p.TBK;
     const int rblocks = (int)std::min<int64_t>(ceil_div(total, 256), 65536);
     if (prec == P64) {
-        k_gram<PolF64<32>, 32><<<items, 256, 0, s>>>(g, (double *)scratch);
-        TK_LAUNCHED();
+        TK_HIP((launch_gram<PolF64<32>, 32>(g, vec, blocks, (double *)scratch, s)));
         k_gram_reduce<double><<<rblocks, 256, 0, s>>>((const double *)scratch, p.splits_total, p.TBK, n, total, M);
     } else if (prec == P32) {
-        k_gram<PolF32<64>, 64><<<items, 256, 0, s>>>(g, (float *)scratch);
-        TK_LAUNCHED();
+        TK_HIP((launch_gram<PolF32<64>, 64>(g, vec, blocks, (float *)scratch, s)));
         k_gram_reduce<float><<<rblocks, 256, 0, s>>>((const float *)scratch, p.splits_total, p.TBK, n, total, M);
     } else {
-        k_gram<PolBF16<64>, 64><<<items, 256, 0, s>>>(g, (float *)scratch);
-        TK_LAUNCHED();
+        TK_HIP((launch_gram<PolBF16<64>, 64>(g, vec, blocks, (float *)scratch, s)));
         k_gram_reduce<float><<<rblocks, 256, 0, s>>>((const float *)scratch, p.splits_total, p.TBK, n, total, M);
     }
     TK_LAUNCHED();

@@ -5,11 +5,19 @@
 // the first stage of the HOOI tensor-times-matrix chain (Figure 3: U, V, W).
 //
 // Output layout: T[slot][r] with slot = i_hi * I_lo + i_lo (the two other
-// modes) and r < J contiguous; every element is written once, empty fibres
-// as zeros. The kernel is bound by HBM writes of T: each thread produces one
-// output element; lanes that share a slot read the same slot pointer and
-// nonzeros (broadcast) and consecutive factor entries (coalesced), and the
-// factor matrix itself stays in L2.
+// modes), r < ldT contiguous; r in [J, ldT) is zero padding; every element
+// is written exactly once, empty fibres as zeros.
+//
+// The kernel is bound by HBM writes of T. A workgroup owns a contiguous run
+// of slots (about 8192 output elements). It first stages the run's slot
+// pointers and its nonzeros (leaf index, value) in LDS with coalesced loads,
+// so the dependent chain pointer -> nonzero -> factor row costs two bulk
+// loads per workgroup instead of three trips to memory per element. Then
+// lanes cover consecutive output elements: lanes in the same slot read the
+// same staged nonzeros and consecutive entries of a factor row (coalesced,
+// served by L2), and stores write contiguous memory. Each thread takes its
+// elements in batches of 8 and issues the factor loads of a batch together. Nonzeros beyond the LDS
+// capacity (a run with very long fibres) are read from global memory.
 #include "common.h"
 
 namespace tk {
@@ -19,48 +27,217 @@ struct AccOf { typedef float type; };
 template <>
 struct AccOf<double> { typedef double type; };
 
-template <class TO, class TA>
-__device__ inline TO to_out(TA v) { return (TO)v; }
+constexpr int kProjThreads = 256;
+constexpr int kProjElems = 8192;  // output elements per workgroup (about)
+constexpr int kProjU = 8;         // independent elements (or chunks) per thread per batch
 
-template <class TV, class TF, class TO, int EPT>
-__global__ void __launch_bounds__(256) k_project(const int32_t *__restrict__ ptr, const int32_t *__restrict__ lidx,
-                                                 const TV *__restrict__ lval, const TF *__restrict__ F, int32_t J,
-                                                 int64_t total, double rJ, TO *__restrict__ T) {
+template <class TO>
+struct Vec16;
+template <>
+struct Vec16<double> { typedef double __attribute__((ext_vector_type(2))) type; };
+template <>
+struct Vec16<float> { typedef float __attribute__((ext_vector_type(4))) type; };
+template <>
+struct Vec16<bf16> { typedef bf16 __attribute__((ext_vector_type(8))) type; };
+
+// Stage the run's slot pointers and nonzeros into LDS: sptr[0..ns], then up to
+// cap nonzeros. Returns the number staged.
+template <class TV>
+__device__ inline int stage_run(const int32_t *__restrict__ ptr, const int32_t *__restrict__ lidx,
+                                const TV *__restrict__ lval, int64_t s0, int ns, int cap, int32_t *sptr,
+                                int32_t *sidx, TV *sval, int32_t &q0) {
+    const int tid = threadIdx.x;
+    for (int i = tid; i <= ns; i += kProjThreads) sptr[i] = ptr[s0 + i];
+    __syncthreads();
+    q0 = sptr[0];
+    const int nq = sptr[ns] - q0;
+    const int nst = nq < cap ? nq : cap;
+    for (int i = tid; i < nst; i += kProjThreads) {
+        sidx[i] = lidx[q0 + i];
+        sval[i] = lval[q0 + i];
+    }
+    __syncthreads();
+    return nst;
+}
+
+template <class TV>
+__device__ inline void nz_at(int p, int nst, int32_t q0, const int32_t *sidx, const TV *sval,
+                             const int32_t *__restrict__ lidx, const TV *__restrict__ lval, int32_t &id, TV &v) {
+    if (p < nst) {
+        id = sidx[p];
+        v = sval[p];
+    } else {
+        id = lidx[q0 + p];
+        v = lval[q0 + p];
+    }
+}
+
+// General form: any row stride; lanes cover consecutive elements.
+template <class TV, class TF, class TO>
+__global__ void __launch_bounds__(kProjThreads) k_project(const int32_t *__restrict__ ptr,
+                                                          const int32_t *__restrict__ lidx,
+                                                          const TV *__restrict__ lval, const TF *__restrict__ F,
+                                                          int32_t J, int32_t ldT, int32_t spw, int32_t cap,
+                                                          int64_t nslots, TO *__restrict__ T) {
     typedef typename AccOf<TV>::type Acc;
-    const int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    extern __shared__ __attribute__((aligned(16))) int32_t smem[];
+    int32_t *sptr = smem, *sidx = smem + ((spw + 4) & ~3);
+    TV *sval = reinterpret_cast<TV *>(sidx + ((cap + 3) & ~3));
+    const int tid = threadIdx.x;
+    const int64_t s0 = (int64_t)blockIdx.x * spw;
+    const int ns = (int)(s0 + spw <= nslots ? spw : nslots - s0);
+    int32_t q0;
+    const int nst = stage_run(ptr, lidx, lval, s0, ns, cap, sptr, sidx, sval, q0);
+    const int nel = ns * ldT;
+    const float rld = 1.0f / (float)ldT;
+    TO *out = T + s0 * ldT;
+    for (int qb = tid; qb < nel; qb += kProjThreads * kProjU) {
+        int r[kProjU], a[kProjU], b[kProjU], id[kProjU];
+        Acc acc[kProjU];
+        TV v[kProjU];
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        const int64_t e = e0 + (int64_t)u * stride;
-        if (e >= total) return;
-        int64_t s = (int64_t)((double)e * rJ);
-        if (s * J > e) --s;
-        if ((s + 1) * J <= e) ++s;
-        const int32_t r = (int32_t)(e - s * J);
-        const int32_t p0 = ptr[s], p1 = ptr[s + 1];
-        Acc acc = 0;
-        for (int32_t p = p0; p < p1; ++p) acc += (Acc)lval[p] * (Acc)F[(int64_t)lidx[p] * J + r];
-        T[e] = to_out<TO, Acc>(acc);
+        for (int u = 0; u < kProjU; ++u) {
+            const int q = qb + u * kProjThreads;
+            int sl = (int)((float)q * rld);
+            if (sl * ldT > q) --sl;
+            if ((sl + 1) * ldT <= q) ++sl;
+            r[u] = q - sl * ldT;
+            a[u] = 0;
+            b[u] = 0;
+            if (q < nel && r[u] < J) {
+                a[u] = sptr[sl] - q0;
+                b[u] = sptr[sl + 1] - q0;
+            }
+            id[u] = 0;
+            v[u] = 0;
+            if (a[u] < b[u]) nz_at(a[u], nst, q0, sidx, sval, lidx, lval, id[u], v[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kProjU; ++u)
+            acc[u] = a[u] < b[u] ? (Acc)v[u] * (Acc)F[(int64_t)id[u] * J + r[u]] : (Acc)0;
+#pragma unroll
+        for (int u = 0; u < kProjU; ++u)
+            for (int p = a[u] + 1; p < b[u]; ++p) {
+                int32_t i2;
+                TV v2;
+                nz_at(p, nst, q0, sidx, sval, lidx, lval, i2, v2);
+                acc[u] += (Acc)v2 * (Acc)F[(int64_t)i2 * J + r[u]];
+            }
+#pragma unroll
+        for (int u = 0; u < kProjU; ++u) {
+            const int q = qb + u * kProjThreads;
+            if (q < nel) out[q] = (TO)acc[u];
+        }
+    }
+}
+
+// Row stride a multiple of 16 bytes: each thread produces whole 16-byte
+// chunks, which never cross a slot, with one vector store per chunk.
+template <class TV, class TF, class TO>
+__global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__restrict__ ptr,
+                                                              const int32_t *__restrict__ lidx,
+                                                              const TV *__restrict__ lval,
+                                                              const TF *__restrict__ F, int32_t J, int32_t ldT,
+                                                              int32_t spw, int32_t cap, int64_t nslots,
+                                                              TO *__restrict__ T) {
+    typedef typename AccOf<TV>::type Acc;
+    constexpr int V = 16 / sizeof(TO);
+    constexpr int U = kProjU / 2;
+    extern __shared__ __attribute__((aligned(16))) int32_t smem[];
+    int32_t *sptr = smem, *sidx = smem + ((spw + 4) & ~3);
+    TV *sval = reinterpret_cast<TV *>(sidx + ((cap + 3) & ~3));
+    const int tid = threadIdx.x;
+    const int64_t s0 = (int64_t)blockIdx.x * spw;
+    const int ns = (int)(s0 + spw <= nslots ? spw : nslots - s0);
+    int32_t q0;
+    const int nst = stage_run(ptr, lidx, lval, s0, ns, cap, sptr, sidx, sval, q0);
+    const int cps = ldT / V;  // chunks per slot
+    const int nch = ns * cps;
+    const float rcps = 1.0f / (float)cps;
+    TO *out = T + s0 * ldT;
+    for (int cb = tid; cb < nch; cb += kProjThreads * U) {
+        int r0[U], a[U], b[U], id[U];
+        TV v[U];
+        Acc acc[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = cb + u * kProjThreads;
+            int sl = (int)((float)c * rcps);
+            if (sl * cps > c) --sl;
+            if ((sl + 1) * cps <= c) ++sl;
+            r0[u] = (c - sl * cps) * V;
+            a[u] = 0;
+            b[u] = 0;
+            if (c < nch && r0[u] < J) {
+                a[u] = sptr[sl] - q0;
+                b[u] = sptr[sl + 1] - q0;
+            }
+            id[u] = 0;
+            v[u] = 0;
+            if (a[u] < b[u]) nz_at(a[u], nst, q0, sidx, sval, lidx, lval, id[u], v[u]);
+#pragma unroll
+            for (int t = 0; t < V; ++t) acc[u][t] = 0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (a[u] < b[u]) {
+                const TF *row = F + (int64_t)id[u] * J + r0[u];
+#pragma unroll
+                for (int t = 0; t < V; ++t)
+                    if (r0[u] + t < J) acc[u][t] = (Acc)v[u] * (Acc)row[t];
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            for (int p = a[u] + 1; p < b[u]; ++p) {
+                int32_t i2;
+                TV v2;
+                nz_at(p, nst, q0, sidx, sval, lidx, lval, i2, v2);
+                const TF *row = F + (int64_t)i2 * J + r0[u];
+#pragma unroll
+                for (int t = 0; t < V; ++t)
+                    if (r0[u] + t < J) acc[u][t] += (Acc)v2 * (Acc)row[t];
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int c = cb + u * kProjThreads;
+            if (c < nch) {
+                typename Vec16<TO>::type o;
+#pragma unroll
+                for (int t = 0; t < V; ++t) o[t] = (TO)acc[u][t];
+                *reinterpret_cast<typename Vec16<TO>::type *>(out + (int64_t)c * V) = o;
+            }
+        }
     }
 }
 
 template <class TV, class TF, class TO>
-hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int J, int64_t nslots, TO *T,
-                   hipStream_t s) {
-    const int64_t total = nslots * (int64_t)J;
-    if (total <= 0) return hipSuccess;
-    constexpr int EPT = 4;
-    int64_t blocks = ceil_div(total, 256 * EPT);
-    k_project<TV, TF, TO, EPT><<<(unsigned)blocks, 256, 0, s>>>(ptr, lidx, lval, F, J, total, 1.0 / (double)J, T);
+hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int J, int ldT,
+                   int64_t nslots, TO *T, hipStream_t s) {
+    if (nslots <= 0 || ldT <= 0) return hipSuccess;
+    int spw = kProjElems / ldT;
+    if (spw < 1) spw = 1;
+    if (spw > 4096) spw = 4096;
+    // staged nonzeros: room for 4 per slot on average (at most 4096, so LDS
+    // stays under 64 KiB); longer runs read the rest from global memory
+    int cap = spw * 4 < 256 ? 256 : spw * 4;
+    if (cap > 4096) cap = 4096;
+    const size_t lds = sizeof(int32_t) * (((spw + 4) & ~3) + ((cap + 3) & ~3)) + sizeof(TV) * cap;
+    const int64_t blocks = ceil_div(nslots, spw);
+    if (ldT % (16 / (int)sizeof(TO)) == 0)
+        k_project_vec<TV, TF, TO><<<(unsigned)blocks, kProjThreads, lds, s>>>(ptr, lidx, lval, F, J, ldT, spw, cap,
+                                                                             nslots, T);
+    else
+        k_project<TV, TF, TO><<<(unsigned)blocks, kProjThreads, lds, s>>>(ptr, lidx, lval, F, J, ldT, spw, cap,
+                                                                         nslots, T);
     TK_LAUNCHED();
     return hipSuccess;
 }
 
 template hipError_t project<double, double, double>(const int32_t *, const int32_t *, const double *, const double *,
-                                                    int, int64_t, double *, hipStream_t);
+                                                    int, int, int64_t, double *, hipStream_t);
 template hipError_t project<float, float, float>(const int32_t *, const int32_t *, const float *, const float *, int,
-                                                 int64_t, float *, hipStream_t);
+                                                 int, int64_t, float *, hipStream_t);
 template hipError_t project<float, float, bf16>(const int32_t *, const int32_t *, const float *, const float *, int,
-                                                int64_t, bf16 *, hipStream_t);
+                                                int, int64_t, bf16 *, hipStream_t);
 
 }  // namespace tk
