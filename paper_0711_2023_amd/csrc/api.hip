@@ -119,8 +119,9 @@ struct Plan {
     double *Xblk[3];
     void *eigw;
     double *theta;
-    float *F32[3];
-    bf16 *F16[3];
+    float *F32[3] = {nullptr, nullptr, nullptr};
+    bf16 *F16[3] = {nullptr, nullptr, nullptr};
+    void *Fp[3] = {nullptr, nullptr, nullptr};  // MP: factor rows padded to ldT (FP64 or FP32), zero padding
     double *Z, *Gp, *core_split;
     int64_t core_split_elems;
     double *Gx, *Pn[3], *W1, *W2;
@@ -230,6 +231,7 @@ static void carve(Plan &p, Arena &ar) {
         for (int n = 0; n < 3; ++n) {
             p.F32[n] = prec != P64 ? ar.take<float>(p.I[n] * p.J[n]) : nullptr;
             p.F16[n] = prec == PBF16 ? ar.take<bf16>(p.I[n] * p.J[n]) : nullptr;
+            p.Fp[n] = p.algo == TK_ALGO_MP ? ar.take<char>(p.I[n] * p.ldT[n] * (prec == P64 ? 8 : 4)) : nullptr;
         }
     }
     const int64_t J0 = p.J[0], J1 = p.J[1], J2 = p.J[2];
@@ -443,19 +445,30 @@ static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double
 static hipError_t project_m(Plan &p, int m, const double *F64, void *T, int out_prec, hipStream_t s, int ld = 0) {
     const int J = p.J[m];
     if (ld <= 0) ld = p.ldT[m];
+    // the padded copy (rows of ldT) when T has that stride, else rows of J
+    const bool padded = p.Fp[m] && ld == p.ldT[m];
+    const int ldF = padded ? ld : J;
     if (out_prec == P64)
-        return project<double, double, double>(p.ptr[m], p.lidx[m], p.lval64[m], F64, J, ld, p.nslots[m], (double *)T,
-                                               s);
+        return project<double, double, double>(p.ptr[m], p.lidx[m], p.lval64[m],
+                                               padded ? (const double *)p.Fp[m] : F64, ldF, J, ld, p.nslots[m],
+                                               (double *)T, s);
+    const float *F = padded ? (const float *)p.Fp[m] : p.F32[m];
     if (out_prec == P32)
-        return project<float, float, float>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, ld, p.nslots[m],
-                                            (float *)T, s);
-    return project<float, float, bf16>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, ld, p.nslots[m], (bf16 *)T, s);
+        return project<float, float, float>(p.ptr[m], p.lidx[m], p.lval32[m], F, ldF, J, ld, p.nslots[m], (float *)T,
+                                            s);
+    return project<float, float, bf16>(p.ptr[m], p.lidx[m], p.lval32[m], F, ldF, J, ld, p.nslots[m], (bf16 *)T, s);
 }
 
 static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s) {
     const int64_t cnt = p.I[n] * p.J[n];
     if (p.F32[n]) TK_HIP(convert_f64<float>(F, p.F32[n], cnt, s));
     if (p.F16[n]) TK_HIP(convert_f64<bf16>(F, p.F16[n], cnt, s));
+    if (p.Fp[n]) {
+        if (p.prec == P64)
+            TK_HIP(pad_rows<double>(F, p.I[n], p.J[n], p.ldT[n], (double *)p.Fp[n], s));
+        else
+            TK_HIP(pad_rows<float>(F, p.I[n], p.J[n], p.ldT[n], (float *)p.Fp[n], s));
+    }
     return hipSuccess;
 }
 
@@ -646,7 +659,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         const void *T2c = p.T[2];
         bool f64 = prec == P64;
         if (prec == PBF16) {
-            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.J[2], p.nslots[2],
+            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.J[2], p.J[2], p.nslots[2],
                                              p.Tcore, s)));
             T2c = p.Tcore;
         }
@@ -672,7 +685,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         tm.end();
         const void *T2c = p.T[2];
         if (prec == PBF16) {
-            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.J[2], p.nslots[2],
+            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.J[2], p.J[2], p.nslots[2],
                                              p.Tcore, s)));
             T2c = p.Tcore;
         }
@@ -893,7 +906,7 @@ extern "C" int tucker_fit(const tk_coo *X, const int32_t *J, const double *core,
     const int J0 = J[0], J1 = J[1], J2 = J[2];
     const int64_t nJ = (int64_t)J0 * J1 * J2;
     // Gx = X x_n A(n)^T via T(2)(C) and the two contractions of the MP core
-    ST((project<double, double, double>(p.ptr[2], p.lidx[2], p.lval64[2], factors[2], J2, J2, p.nslots[2],
+    ST((project<double, double, double>(p.ptr[2], p.lidx[2], p.lval64[2], factors[2], J2, J2, J2, p.nslots[2],
                                         (double *)p.T[2], s)));
     ST(core_from_T2(p, p.T[2], J2, true, factors[0], factors[1], p.Gx, s));
     ST(dot(p.Gx, core, nJ, p.partials, p.scal + 3, s));

@@ -104,11 +104,16 @@ hipError_t hosvd_gram(int n, const int64_t dims[3], const int32_t *ptr_n, const 
                       double *H, hipStream_t s);
 
 // ---------------------------------------------------------------- project.hip
-// T[slot * ldT + r] = sum over the slot's entries of lval * F[lidx][r] for
-// r < J, zero for J <= r < ldT; slots = I_hi * I_lo, dense and zero-filled.
+// T[slot * ldT + r] = sum over the slot's entries of lval * F[lidx * ldF + r]
+// for r < J, zero for J <= r < ldT; slots = I_hi * I_lo, dense and
+// zero-filled. With ldF == ldT, 16-byte rows and F's padding columns zero
+// (as pad_rows leaves them), whole 16-byte chunks are computed at once.
 template <class TV, class TF, class TO>
-hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int J, int ldT,
+hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int ldF, int J, int ldT,
                    int64_t nslots, TO *T, hipStream_t s);
+// out[i * ld + r] = in[i * J + r] for r < J, zero for J <= r < ld.
+template <class TO>
+hipError_t pad_rows(const double *in, int64_t rows, int J, int ld, TO *out, hipStream_t s);
 
 // ---------------------------------------------------------------- mfma.hip
 // One operand of a Gram: row i, column k = (kc, kr) with kr < chunk_len,

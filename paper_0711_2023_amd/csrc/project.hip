@@ -77,7 +77,8 @@ template <class TV, class TF, class TO>
 __global__ void __launch_bounds__(kProjThreads) k_project(const int32_t *__restrict__ ptr,
                                                           const int32_t *__restrict__ lidx,
                                                           const TV *__restrict__ lval, const TF *__restrict__ F,
-                                                          int32_t J, int32_t ldT, int32_t spw, int32_t cap,
+                                                          int32_t ldF, int32_t J, int32_t ldT, int32_t spw,
+                                                          int32_t cap,
                                                           int64_t nslots, TO *__restrict__ T) {
     typedef typename AccOf<TV>::type Acc;
     extern __shared__ __attribute__((aligned(16))) int32_t smem[];
@@ -114,14 +115,14 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const int32_t *__restr
         }
 #pragma unroll
         for (int u = 0; u < kProjU; ++u)
-            acc[u] = a[u] < b[u] ? (Acc)v[u] * (Acc)F[(int64_t)id[u] * J + r[u]] : (Acc)0;
+            acc[u] = a[u] < b[u] ? (Acc)v[u] * (Acc)F[(int64_t)id[u] * ldF + r[u]] : (Acc)0;
 #pragma unroll
         for (int u = 0; u < kProjU; ++u)
             for (int p = a[u] + 1; p < b[u]; ++p) {
                 int32_t i2;
                 TV v2;
                 nz_at(p, nst, q0, sidx, sval, lidx, lval, i2, v2);
-                acc[u] += (Acc)v2 * (Acc)F[(int64_t)i2 * J + r[u]];
+                acc[u] += (Acc)v2 * (Acc)F[(int64_t)i2 * ldF + r[u]];
             }
 #pragma unroll
         for (int u = 0; u < kProjU; ++u) {
@@ -131,8 +132,9 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const int32_t *__restr
     }
 }
 
-// Row stride a multiple of 16 bytes: each thread produces whole 16-byte
-// chunks, which never cross a slot, with one vector store per chunk.
+// Row strides of T and F equal and a multiple of 16 bytes, F's padding
+// columns zero: each thread produces whole 16-byte chunks of T, which never
+// cross a slot, from 16-byte loads of F rows and one vector store per chunk.
 template <class TV, class TF, class TO>
 __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__restrict__ ptr,
                                                               const int32_t *__restrict__ lidx,
@@ -141,7 +143,10 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
                                                               int32_t spw, int32_t cap, int64_t nslots,
                                                               TO *__restrict__ T) {
     typedef typename AccOf<TV>::type Acc;
-    constexpr int V = 16 / sizeof(TO);
+    typedef typename Vec16<TF>::type FV;
+    constexpr int V = 16 / sizeof(TO);            // outputs per chunk
+    constexpr int FPV = 16 / sizeof(TF);          // factor entries per 16-byte load
+    constexpr int NL = V / FPV;                   // loads per chunk
     constexpr int U = kProjU / 2;
     extern __shared__ __attribute__((aligned(16))) int32_t smem[];
     int32_t *sptr = smem, *sidx = smem + ((spw + 4) & ~3);
@@ -175,27 +180,33 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
             id[u] = 0;
             v[u] = 0;
             if (a[u] < b[u]) nz_at(a[u], nst, q0, sidx, sval, lidx, lval, id[u], v[u]);
-#pragma unroll
-            for (int t = 0; t < V; ++t) acc[u][t] = 0;
         }
+        FV f[U][NL];
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (a[u] < b[u]) {
-                const TF *row = F + (int64_t)id[u] * J + r0[u];
 #pragma unroll
-                for (int t = 0; t < V; ++t)
-                    if (r0[u] + t < J) acc[u][t] = (Acc)v[u] * (Acc)row[t];
-            }
+            for (int l = 0; l < NL; ++l)
+                f[u][l] = a[u] < b[u] ? *reinterpret_cast<const FV *>(F + (int64_t)id[u] * ldT + r0[u] + l * FPV)
+                                      : FV(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int l = 0; l < NL; ++l)
+#pragma unroll
+                for (int t = 0; t < FPV; ++t) acc[u][l * FPV + t] = (Acc)v[u] * (Acc)f[u][l][t];
 #pragma unroll
         for (int u = 0; u < U; ++u)
             for (int p = a[u] + 1; p < b[u]; ++p) {
                 int32_t i2;
                 TV v2;
                 nz_at(p, nst, q0, sidx, sval, lidx, lval, i2, v2);
-                const TF *row = F + (int64_t)i2 * J + r0[u];
+                const FV *row = reinterpret_cast<const FV *>(F + (int64_t)i2 * ldT + r0[u]);
 #pragma unroll
-                for (int t = 0; t < V; ++t)
-                    if (r0[u] + t < J) acc[u][t] += (Acc)v2 * (Acc)row[t];
+                for (int l = 0; l < NL; ++l) {
+                    const FV g = row[l];
+#pragma unroll
+                    for (int t = 0; t < FPV; ++t) acc[u][l * FPV + t] += (Acc)v2 * (Acc)g[t];
+                }
             }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -210,8 +221,28 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
     }
 }
 
+template <class TO>
+__global__ void k_pad_rows(const double *__restrict__ in, int64_t rows, int J, int ld, TO *__restrict__ out) {
+    const int64_t n = rows * ld;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q / ld;
+        const int r = (int)(q - i * ld);
+        out[q] = r < J ? (TO)in[i * J + r] : (TO)0;
+    }
+}
+
+template <class TO>
+hipError_t pad_rows(const double *in, int64_t rows, int J, int ld, TO *out, hipStream_t s) {
+    const int64_t n = rows * ld;
+    if (n <= 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>(ceil_div(n, 256), 4096);
+    k_pad_rows<TO><<<(unsigned)g, 256, 0, s>>>(in, rows, J, ld, out);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
 template <class TV, class TF, class TO>
-hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int J, int ldT,
+hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int ldF, int J, int ldT,
                    int64_t nslots, TO *T, hipStream_t s) {
     if (nslots <= 0 || ldT <= 0) return hipSuccess;
     int spw = kProjElems / ldT;
@@ -223,21 +254,25 @@ hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, cons
     if (cap > 4096) cap = 4096;
     const size_t lds = sizeof(int32_t) * (((spw + 4) & ~3) + ((cap + 3) & ~3)) + sizeof(TV) * cap;
     const int64_t blocks = ceil_div(nslots, spw);
-    if (ldT % (16 / (int)sizeof(TO)) == 0)
+    const bool vec = ldF == ldT && ldT % (16 / (int)sizeof(TO)) == 0 && ((uintptr_t)F & 15) == 0 &&
+                     ((uintptr_t)T & 15) == 0;
+    if (vec)
         k_project_vec<TV, TF, TO><<<(unsigned)blocks, kProjThreads, lds, s>>>(ptr, lidx, lval, F, J, ldT, spw, cap,
                                                                              nslots, T);
     else
-        k_project<TV, TF, TO><<<(unsigned)blocks, kProjThreads, lds, s>>>(ptr, lidx, lval, F, J, ldT, spw, cap,
-                                                                         nslots, T);
+        k_project<TV, TF, TO><<<(unsigned)blocks, kProjThreads, lds, s>>>(ptr, lidx, lval, F, ldF, J, ldT, spw,
+                                                                         cap, nslots, T);
     TK_LAUNCHED();
     return hipSuccess;
 }
 
 template hipError_t project<double, double, double>(const int32_t *, const int32_t *, const double *, const double *,
-                                                    int, int, int64_t, double *, hipStream_t);
+                                                    int, int, int, int64_t, double *, hipStream_t);
 template hipError_t project<float, float, float>(const int32_t *, const int32_t *, const float *, const float *, int,
-                                                 int, int64_t, float *, hipStream_t);
+                                                 int, int, int64_t, float *, hipStream_t);
 template hipError_t project<float, float, bf16>(const int32_t *, const int32_t *, const float *, const float *, int,
-                                                int, int64_t, bf16 *, hipStream_t);
+                                                int, int, int64_t, bf16 *, hipStream_t);
+template hipError_t pad_rows<double>(const double *, int64_t, int, int, double *, hipStream_t);
+template hipError_t pad_rows<float>(const double *, int64_t, int, int, float *, hipStream_t);
 
 }  // namespace tk
