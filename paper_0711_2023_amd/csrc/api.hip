@@ -121,7 +121,7 @@ struct Plan {
     double *theta;
     float *F32[3] = {nullptr, nullptr, nullptr};
     bf16 *F16[3] = {nullptr, nullptr, nullptr};
-    void *Fp[3] = {nullptr, nullptr, nullptr};  // MP: factor rows padded to ldT (FP64 or FP32), zero padding
+    void *Fp[3] = {nullptr, nullptr, nullptr};  // MP: factor rows padded to ldT, zero padding, type of T
     double *Z, *Gp, *core_split;
     int64_t core_split_elems;
     double *Gx, *Pn[3], *W1, *W2;
@@ -231,7 +231,7 @@ static void carve(Plan &p, Arena &ar) {
         for (int n = 0; n < 3; ++n) {
             p.F32[n] = prec != P64 ? ar.take<float>(p.I[n] * p.J[n]) : nullptr;
             p.F16[n] = prec == PBF16 ? ar.take<bf16>(p.I[n] * p.J[n]) : nullptr;
-            p.Fp[n] = p.algo == TK_ALGO_MP ? ar.take<char>(p.I[n] * p.ldT[n] * (prec == P64 ? 8 : 4)) : nullptr;
+            p.Fp[n] = p.algo == TK_ALGO_MP ? ar.take<char>(p.I[n] * p.ldT[n] * (int64_t)elem_size(prec)) : nullptr;
         }
     }
     const int64_t J0 = p.J[0], J1 = p.J[1], J2 = p.J[2];
@@ -445,18 +445,27 @@ static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double
 static hipError_t project_m(Plan &p, int m, const double *F64, void *T, int out_prec, hipStream_t s, int ld = 0) {
     const int J = p.J[m];
     if (ld <= 0) ld = p.ldT[m];
-    // the padded copy (rows of ldT) when T has that stride, else rows of J
-    const bool padded = p.Fp[m] && ld == p.ldT[m];
-    const int ldF = padded ? ld : J;
+    // the padded copy (rows of ldT, type of T) when T has that stride and
+    // type, else rows of J
+    const bool padded = p.Fp[m] && ld == p.ldT[m] && out_prec == p.prec;
+    if (padded) {
+        if (out_prec == P64)
+            return project<double, double, double>(p.ptr[m], p.lidx[m], p.lval64[m], (const double *)p.Fp[m], ld, J,
+                                                   ld, p.nslots[m], (double *)T, s);
+        if (out_prec == P32)
+            return project<float, float, float>(p.ptr[m], p.lidx[m], p.lval32[m], (const float *)p.Fp[m], ld, J, ld,
+                                                p.nslots[m], (float *)T, s);
+        return project<float, bf16, bf16>(p.ptr[m], p.lidx[m], p.lval32[m], (const bf16 *)p.Fp[m], ld, J, ld,
+                                          p.nslots[m], (bf16 *)T, s);
+    }
     if (out_prec == P64)
-        return project<double, double, double>(p.ptr[m], p.lidx[m], p.lval64[m],
-                                               padded ? (const double *)p.Fp[m] : F64, ldF, J, ld, p.nslots[m],
+        return project<double, double, double>(p.ptr[m], p.lidx[m], p.lval64[m], F64, J, J, ld, p.nslots[m],
                                                (double *)T, s);
-    const float *F = padded ? (const float *)p.Fp[m] : p.F32[m];
     if (out_prec == P32)
-        return project<float, float, float>(p.ptr[m], p.lidx[m], p.lval32[m], F, ldF, J, ld, p.nslots[m], (float *)T,
-                                            s);
-    return project<float, float, bf16>(p.ptr[m], p.lidx[m], p.lval32[m], F, ldF, J, ld, p.nslots[m], (bf16 *)T, s);
+        return project<float, float, float>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, J, ld, p.nslots[m],
+                                            (float *)T, s);
+    return project<float, float, bf16>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, J, ld, p.nslots[m], (bf16 *)T,
+                                       s);
 }
 
 static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s) {
@@ -466,8 +475,10 @@ static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s)
     if (p.Fp[n]) {
         if (p.prec == P64)
             TK_HIP(pad_rows<double>(F, p.I[n], p.J[n], p.ldT[n], (double *)p.Fp[n], s));
-        else
+        else if (p.prec == P32)
             TK_HIP(pad_rows<float>(F, p.I[n], p.J[n], p.ldT[n], (float *)p.Fp[n], s));
+        else
+            TK_HIP(pad_rows<bf16>(F, p.I[n], p.J[n], p.ldT[n], (bf16 *)p.Fp[n], s));
     }
     return hipSuccess;
 }

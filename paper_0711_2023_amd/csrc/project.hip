@@ -28,8 +28,10 @@ template <>
 struct AccOf<double> { typedef double type; };
 
 constexpr int kProjThreads = 256;
-constexpr int kProjElems = 8192;  // output elements per workgroup (about)
-constexpr int kProjU = 8;         // independent elements (or chunks) per thread per batch
+constexpr int kProjElems = 32768;  // output elements per workgroup, at most
+constexpr int kProjMinBlocks = 1536; // workgroups wanted (6 per compute unit) before runs grow
+constexpr int kProjU = 8;          // independent elements per thread per batch (general form)
+constexpr int kProjUV = 2;         // independent 16-byte chunks per thread per batch (vector form)
 
 template <class TO>
 struct Vec16;
@@ -147,7 +149,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
     constexpr int V = 16 / sizeof(TO);            // outputs per chunk
     constexpr int FPV = 16 / sizeof(TF);          // factor entries per 16-byte load
     constexpr int NL = V / FPV;                   // loads per chunk
-    constexpr int U = kProjU / 2;
+    constexpr int U = kProjUV;
     extern __shared__ __attribute__((aligned(16))) int32_t smem[];
     int32_t *sptr = smem, *sidx = smem + ((spw + 4) & ~3);
     TV *sval = reinterpret_cast<TV *>(sidx + ((cap + 3) & ~3));
@@ -222,12 +224,17 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
 }
 
 template <class TO>
+__device__ inline TO from_f64(double x) { return (TO)(float)x; }
+template <>
+__device__ inline double from_f64<double>(double x) { return x; }
+
+template <class TO>
 __global__ void k_pad_rows(const double *__restrict__ in, int64_t rows, int J, int ld, TO *__restrict__ out) {
     const int64_t n = rows * ld;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = q / ld;
         const int r = (int)(q - i * ld);
-        out[q] = r < J ? (TO)in[i * J + r] : (TO)0;
+        out[q] = r < J ? from_f64<TO>(in[i * J + r]) : (TO)0;
     }
 }
 
@@ -245,7 +252,9 @@ template <class TV, class TF, class TO>
 hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int ldF, int J, int ldT,
                    int64_t nslots, TO *T, hipStream_t s) {
     if (nslots <= 0 || ldT <= 0) return hipSuccess;
-    int spw = kProjElems / ldT;
+    // runs of slots: large enough to amortise the staging, small enough that
+    // the grid still fills the chip
+    int spw = (int)std::min<int64_t>(kProjElems / ldT, ceil_div(nslots, kProjMinBlocks));
     if (spw < 1) spw = 1;
     if (spw > 4096) spw = 4096;
     // staged nonzeros: room for 4 per slot on average (at most 4096, so LDS
@@ -272,7 +281,10 @@ template hipError_t project<float, float, float>(const int32_t *, const int32_t 
                                                  int, int, int64_t, float *, hipStream_t);
 template hipError_t project<float, float, bf16>(const int32_t *, const int32_t *, const float *, const float *, int,
                                                 int, int, int64_t, bf16 *, hipStream_t);
+template hipError_t project<float, bf16, bf16>(const int32_t *, const int32_t *, const float *, const bf16 *, int,
+                                               int, int, int64_t, bf16 *, hipStream_t);
 template hipError_t pad_rows<double>(const double *, int64_t, int, int, double *, hipStream_t);
+template hipError_t pad_rows<bf16>(const double *, int64_t, int, int, bf16 *, hipStream_t);
 template hipError_t pad_rows<float>(const double *, int64_t, int, int, float *, hipStream_t);
 
 }  // namespace tk
