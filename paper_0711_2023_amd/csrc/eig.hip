@@ -452,17 +452,165 @@ template hipError_t convert_f64<float>(const double *, float *, int64_t, hipStre
 template hipError_t convert_f64<double>(const double *, double *, int64_t, hipStream_t);
 template hipError_t convert_f64<bf16>(const double *, bf16 *, int64_t, hipStream_t);
 
+// ------------------------------------------------------------------ skinny FP64 products
+// C (M x N, row-major, ldc) = alpha * op(A) B + beta * E1 + gamma * E2 with
+// op(A) = A (M x K, row-major, lda) or A^T (A stored K x M), B K x N
+// (row-major, ldb), N <= kSkinnyN, and E1, E2 laid out as C. Every product of
+// the eigensolver has this shape: M X (n x n times n x w), X^T Y (w x n times
+// n x w) and X V (n x w times w x w).
+//
+// FP64 MFMA 16x16x4 (lane l holds A[l%16][l/16] and B[l/16][l%16]; result v
+// lands in row 4v + l/16, column l%16). A workgroup owns a strip of 16 rows,
+// all columns, and one K range; its four waves interleave over that range in
+// steps of 4 (so the waves of a workgroup read the same cache lines) and are
+// combined in LDS in a fixed order. With S > 1 K ranges, the workgroups write
+// partial strips and a second kernel sums them in a fixed order, so results
+// do not depend on scheduling.
+constexpr int kSkinnyN = 144;
+
+struct SkinnyArgs {
+    int M, N, K;
+    const double *A;
+    int64_t lda;
+    int at;
+    const double *B;
+    int64_t ldb;
+    double *C;
+    int64_t ldc;
+    double alpha, beta, gamma;
+    const double *E1, *E2;
+    int S, Kc;
+    double *part;
+};
+
+__device__ inline void skinny_out(const SkinnyArgs &g, int i, int j, double acc) {
+    const int64_t o = (int64_t)i * g.ldc + j;
+    double r = g.alpha * acc;
+    if (g.E1) r += g.beta * g.E1[o];
+    if (g.E2) r += g.gamma * g.E2[o];
+    g.C[o] = r;
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_skinny(SkinnyArgs g) {
+    extern __shared__ double red[];  // [4][16][NT*16]
+    constexpr int NC = NT * 16;
+    const int strip = blockIdx.x / g.S, sp = blockIdx.x - strip * g.S;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int i = strip * 16 + (l & 15), kq = l >> 4;
+    const int kb = sp * g.Kc, ke = min(g.K, kb + g.Kc);
+    doublex4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = doublex4{0, 0, 0, 0};
+#pragma unroll 2
+    for (int k0 = kb + 4 * wave; k0 < ke; k0 += 16) {
+        const int k = k0 + kq;
+        const bool kin = k < ke;
+        double a = 0.0;
+        if (kin && i < g.M) a = g.at ? g.A[(int64_t)k * g.lda + i] : g.A[(int64_t)i * g.lda + k];
+        double bv[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int j = t * 16 + (l & 15);
+            bv[t] = (kin && j < g.N) ? g.B[(int64_t)k * g.ldb + j] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[t], acc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(wave * 16 + 4 * v + (l >> 4)) * NC + t * 16 + (l & 15)] = acc[t][v];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * NC; e += 256) {
+        const double sum = ((red[e] + red[16 * NC + e]) + red[32 * NC + e]) + red[48 * NC + e];
+        const int r = e / NC, j = e - r * NC;
+        if (g.S == 1) {
+            if (strip * 16 + r < g.M && j < g.N) skinny_out(g, strip * 16 + r, j, sum);
+        } else {
+            g.part[((int64_t)(strip * g.S + sp) * 16 + r) * NC + j] = sum;
+        }
+    }
+}
+
+__global__ void k_skinny_reduce(SkinnyArgs g, int NC) {
+    const int64_t total = (int64_t)g.M * g.N;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / g.N), j = (int)(e - (int64_t)i * g.N);
+        const int strip = i >> 4, r = i & 15;
+        const double *p = g.part + ((int64_t)strip * g.S * 16 + r) * NC + j;
+        double sum = 0.0;
+        for (int q = 0; q < g.S; ++q) sum += p[(int64_t)q * 16 * NC];
+        skinny_out(g, i, j, sum);
+    }
+}
+
+// K ranges: enough workgroups to cover the chip (about 512), each range at
+// least 64 long and a multiple of 16.
+static void skinny_split(int M, int K, int *S, int *Kc) {
+    const int strips = (M + 15) / 16;
+    int s = std::max(1, std::min(512 / std::max(1, strips), K / 64));
+    int kc = (int)ceil_div(K, s);
+    kc = (int)ceil_div(kc, 16) * 16;
+    *S = (int)ceil_div(K, std::max(kc, 1));
+    *Kc = kc;
+}
+static int64_t skinny_part_elems(int M, int N, int K) {
+    int S, Kc;
+    skinny_split(M, K, &S, &Kc);
+    if (S <= 1) return 0;
+    return (int64_t)((M + 15) / 16) * S * 16 * ((N + 15) / 16 * 16);
+}
+
+template <int NT>
+static void skinny_launch(const SkinnyArgs &g, hipStream_t s) {
+    const int strips = (g.M + 15) / 16;
+    const size_t lds = sizeof(double) * 4 * 16 * NT * 16;
+    hipFuncSetAttribute((const void *)k_skinny<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_skinny<NT><<<(unsigned)(strips * g.S), 256, lds, s>>>(g);
+}
+
+static hipError_t skinny(SkinnyArgs g, double *part, int64_t part_elems, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0) return hipSuccess;
+    if (g.N > kSkinnyN) return hipErrorInvalidValue;
+    const int NT = (g.N + 15) / 16;
+    if (g.K <= 0) {  // empty sum: the epilogue alone (the reduction over S = 0 parts)
+        g.S = 0;
+        g.part = nullptr;
+        const int64_t total = (int64_t)g.M * g.N;
+        k_skinny_reduce<<<(unsigned)std::min<int64_t>(ceil_div(total, 256), 2048), 256, 0, s>>>(g, NT * 16);
+        TK_LAUNCHED();
+        return hipSuccess;
+    }
+    skinny_split(g.M, g.K, &g.S, &g.Kc);
+    g.part = part;
+    if (g.S > 1 && skinny_part_elems(g.M, g.N, g.K) > part_elems) return hipErrorInvalidValue;
+    switch (NT) {
+        case 1: skinny_launch<1>(g, s); break;
+        case 2: skinny_launch<2>(g, s); break;
+        case 3: skinny_launch<3>(g, s); break;
+        case 4: skinny_launch<4>(g, s); break;
+        case 5: skinny_launch<5>(g, s); break;
+        case 6: skinny_launch<6>(g, s); break;
+        case 7: skinny_launch<7>(g, s); break;
+        case 8: skinny_launch<8>(g, s); break;
+        default: skinny_launch<9>(g, s); break;
+    }
+    TK_LAUNCHED();
+    if (g.S > 1) {
+        const int64_t total = (int64_t)g.M * g.N;
+        k_skinny_reduce<<<(unsigned)std::min<int64_t>(ceil_div(total, 256), 2048), 256, 0, s>>>(g, NT * 16);
+        TK_LAUNCHED();
+    }
+    return hipSuccess;
+}
+
 // ------------------------------------------------------------------ workspace
 struct EigLayout {
     double *W, *Y0, *Y1, *Y2, *S, *V, *Vg, *Rinv, *theta, *res, *norms, *split, *thall;
     int *colmap;
     int64_t split_elems;
 };
-static int splitk_for(int64_t K, int64_t tiles) {
-    int64_t want = std::max<int64_t>(1, 256 / std::max<int64_t>(1, tiles));
-    int64_t maxs = std::max<int64_t>(1, K / 64);
-    return (int)std::min<int64_t>(want, maxs);
-}
 static EigLayout eig_layout(Arena &ar, int n, int b) {
     EigLayout L;
     int64_t nb = (int64_t)n * b;
@@ -479,11 +627,9 @@ static EigLayout eig_layout(Arena &ar, int n, int b) {
     L.norms = ar.take<double>(b);
     L.thall = ar.take<double>(b);
     L.colmap = ar.take<int>(b);
-    // split-K partial sums: M*X (K = n) and X^T Y (K = n)
-    int64_t t_mx = ceil_div(n, 64) * ceil_div(b, 64);
-    int64_t s1 = (int64_t)splitk_for(n, t_mx) * nb;
-    int64_t s2 = (int64_t)splitk_for(n, ceil_div(b, 64) * ceil_div(b, 64)) * b * b;
-    L.split_elems = std::max(s1, s2);
+    // split-K partial strips: (strips x K ranges) <= 512 for every product
+    // (see skinny_split), each 16 rows by at most b columns rounded up to 16
+    L.split_elems = (int64_t)512 * 16 * (ceil_div(b, 16) * 16);
     L.split = ar.take<double>(L.split_elems);
     return L;
 }
@@ -511,37 +657,30 @@ static hipError_t jacobi(const double *H, int ldh, int b, double *theta, double 
     return hipSuccess;
 }
 
-// C (ldc, column offset in pointer) = alpha * A B (+ beta E1 + gamma E2)
+// C (ldc, column offset in pointer) = alpha * op(A) B (+ beta E1 + gamma E2)
 static hipError_t dgemm(int M, int N, int K, const double *A, int64_t lda, bool at, const double *B, int64_t ldb,
                         double *C, int64_t ldc, double alpha, double beta, const double *E1, double gamma,
                         const double *E2, double *split, int64_t split_elems, hipStream_t s) {
-    GemmArgs g;
+    SkinnyArgs g;
     g.M = M;
     g.N = N;
     g.K = K;
-    g.batch = 1;
     g.A = A;
     g.lda = lda;
-    g.a_trans = at;
+    g.at = at ? 1 : 0;
     g.B = B;
     g.ldb = ldb;
-    g.sB = 0;
     g.C = C;
     g.ldc = ldc;
-    g.sC = 0;
-    g.prec = P64;
-    g.out_type = P64;
     g.alpha = alpha;
     g.beta = beta;
     g.gamma = gamma;
-    g.E1 = E1;
-    g.E2 = E2;
-    int64_t tiles = ceil_div(M, 64) * ceil_div(N, 64);
-    int sk = splitk_for(K, tiles);
-    while (sk > 1 && (int64_t)sk * M * N > split_elems) --sk;
-    g.splitk = sk;
-    g.split_scratch = split;
-    return gemm(g, s);
+    g.E1 = beta != 0.0 ? E1 : nullptr;
+    g.E2 = gamma != 0.0 ? E2 : nullptr;
+    g.S = 1;
+    g.Kc = K;
+    g.part = nullptr;
+    return skinny(g, split, split_elems, s);
 }
 
 // Orthonormalise columns [c0, c0+w) of X (n x b, row-major) in place:
