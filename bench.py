@@ -14,8 +14,9 @@ The JSON line reports:
   their HIP-event times is the TTMc phase), median over the timed steps;
 * time-to-fit of plain FP32 vs mixed BF16 runs that stop on the paper's
   Delta-fit < 1e-4 rule;
-* roofline of the dominant kernel (live HIP-event times on the library's
-  stream x algorithmic bytes or flops per launch);
+* roofline of the projection kernel, the metric's kernel (live HIP-event
+  times on the library's stream x algorithmic bytes per launch), and of the
+  Gram kernel beside it (algorithmic flops per launch);
 * cpu_baseline: one sweep of the FP64 oracle on the host cores, same input.
 """
 import argparse
@@ -109,7 +110,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark measures one GPU; multi-GPU runs are not part of this build",
+        print(json.dumps({"error": "this benchmark measures one GPU; runs on several GPUs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
@@ -189,10 +190,9 @@ def main():
     roof_gram = {"kernel": "k_gram", "bound": "mfma", "achieved": round(gram_tf, 2), "peak": gpeak,
                  "unit": "TFLOP/s", "frac": round(gram_tf / gpeak, 4), "traffic": None,
                  "algorithmic_flops_per_launch": int(gflops), "avg_launch_ms": round(gram_ms, 5)}
-    if args.algo == "hooi":
-        dominant, other = roof_proj, None
-    else:
-        dominant, other = (roof_gram, roof_proj) if st["gram_ms"] >= st["project_ms"] else (roof_proj, roof_gram)
+    # the roofline line is the kernel of the metric (the projection); the
+    # Gram's MFMA fraction goes beside it
+    dominant, other = roof_proj, (roof_gram if args.algo == "mp" else None)
 
     line = {
         "metric": METRIC,

@@ -160,7 +160,7 @@ int eig_block_width(int n, int J);
 struct EigOpts {
     int max_iters = 400;
     double tol = 1e-10;
-    int degree = 20;
+    int degree = 60;
     bool warm = false;
     uint64_t seed = 1234;
 };

@@ -724,6 +724,34 @@ static hipError_t orthonormalise(double *X, int64_t n, int b, int c0, int w, Eig
     return hipSuccess;
 }
 
+// Column 0 of X <- normalised M^steps x0 (products alternate between X and
+// Y0, ending in X), then theta[0] = x^T M x, the Rayleigh quotient that the
+// deflation and the output use.
+static hipError_t power_lock(const double *M, int n, int b, double *X, int steps, EigLayout &L, hipStream_t s) {
+    double *src = X, *dst = L.Y0;
+    if (steps & 1) {  // an odd count ends in Y0: start from a copy there
+        TK_HIP(hipMemcpy2DAsync(L.Y0, sizeof(double) * b, X, sizeof(double) * b, sizeof(double), n,
+                                hipMemcpyDeviceToDevice, s));
+        src = L.Y0;
+        dst = X;
+    }
+    for (int k = 0; k < steps; ++k) {
+        TK_HIP(dgemm(n, 1, n, M, n, false, src, b, dst, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
+                     s));
+        k_colnorm<<<1, 256, 0, s>>>(dst, n, b, 0, L.norms);
+        TK_LAUNCHED();
+        k_colscale<<<(unsigned)std::min<int64_t>(ceil_div(n, 256), 65536), 256, 0, s>>>(dst, n, b, 0, 1, L.norms,
+                                                                                         0x9e3779b9ull + k);
+        TK_LAUNCHED();
+        std::swap(src, dst);
+    }
+    // src == X now; theta = x^T (M x)
+    TK_HIP(dgemm(n, 1, n, M, n, false, X, b, L.Y1, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
+    TK_HIP(dgemm(1, 1, n, X, b, true, L.Y1, b, L.theta, 1, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
+                 s));
+    return hipSuccess;
+}
+
 hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta_dev, void *work,
                     const EigOpts &o, int *iters, int *noconv, hipStream_t s) {
     *iters = 0;
@@ -755,10 +783,11 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
     double *Xc = X;
     double *Md = M;  // deflated in place
     std::vector<double> tha;
-    // Intermediate Rayleigh-Ritz steps use two Jacobi sweeps: an approximate
+    // Intermediate Rayleigh-Ritz steps use one Jacobi sweep: an approximate
     // rotation is enough to pick the leading directions of the block (it is
-    // inexact only among nearly tied Ritz pairs); the step after the energy
-    // test has passed diagonalises fully and provides the output.
+    // inexact only among nearly tied Ritz pairs, and locking still requires
+    // a true residual below its threshold); the step after the energy test
+    // has passed diagonalises fully and provides the output.
     bool final_rr = false;
     for (int outer = 0;; ++outer) {
         const int w = b - Lk;
@@ -767,7 +796,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
         TK_HIP(dgemm(n, w, n, Md, n, false, Xa, b, Wa, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
         ++matvecs;
         TK_HIP(dgemm(w, w, n, Xa, b, true, Wa, b, L.S, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
-        TK_HIP(jacobi(L.S, w, w, L.theta, L.V, L.Vg, s, final_rr ? 30 : 2));
+        TK_HIP(jacobi(L.S, w, w, L.theta, L.V, L.Vg, s, final_rr ? 30 : 1));
         TK_HIP(dgemm(n, w, w, Xa, b, false, L.V, w, L.Y0, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
                      s));
         TK_HIP(dgemm(n, w, w, Wa, b, false, L.V, w, L.Y1, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
@@ -800,6 +829,25 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
             continue;
         }
         Eold = E;
+        // A leading Ritz value far above the next one (the mean term of
+        // nonnegative data is one) caps the filter degree through the
+        // amplification limit below until it is locked. Lock it first with
+        // single-vector power steps, whose error shrinks by theta_2/theta_1
+        // per product, as many as its residual needs to reach lock_tol.
+        // (Warm starts only: from a random block the first Ritz pair is too
+        // rough for the step count.)
+        if (o.warm && Lk == 0 && newl == 0 && J > 1 && w > 2 && tha[1] > 0.0 && tha[0] > 4.0 * tha[1] &&
+            res[0] > lock_tol) {
+            const double rate = tha[1] / tha[0];
+            const int steps = std::min(60, 2 + (int)std::ceil(std::log(lock_tol / res[0]) / std::log(rate)));
+            TK_HIP(power_lock(Md, n, b, Xc, steps, L, s));
+            double th1 = 0.0;
+            TK_HIP(hipMemcpyAsync(&th1, L.theta, sizeof(double), hipMemcpyDeviceToHost, s));
+            TK_HIP(hipStreamSynchronize(s));
+            matvecs += steps + 1;
+            tha[0] = th1;
+            newl = 1;
+        }
         if (newl > 0) {
             k_deflate<<<(unsigned)std::min<int64_t>(ceil_div((int64_t)n * n, 256), 65536), 256, 0, s>>>(
                 Md, n, Xc, b, Lk, newl, L.theta);
