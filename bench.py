@@ -61,7 +61,7 @@ def gram_flops(I, J, n):
 def traffic_from_profile(kernel_file):
     """HBM bytes per launch of the projection kernel measured by rocprofv3
     counters, if the committed measurement matches the current source."""
-    path = os.path.join(ROOT, "profiles", "k_project_c2_traffic.json")
+    path = os.path.join(ROOT, "profiles", "k_project_mixed_1000cube_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -99,7 +99,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2_1000cube")
+    ap.add_argument("--workload", default="cube1000_nnz1m")
     ap.add_argument("--algo", default="mp", choices=["mp", "hooi"])
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp32", "fp64"])
     ap.add_argument("--sweeps", type=int, default=10)

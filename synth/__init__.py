@@ -174,9 +174,9 @@ def batch_configs(count: int = 64, seed_base: int = 3000):
 
 # Named workloads (sizes of the benchmarked configurations).
 WORKLOADS = {
-    "c1_100cube": {"dims": (100, 100, 100), "nnz": 10_000, "core": (10, 10, 10), "seed": 5678},
-    "c2_1000cube": {"dims": (1000, 1000, 1000), "nnz": 1_000_000, "core": (50, 50, 50), "seed": 1},
-    "c3a_unbalanced": {"dims": (2000, 1000, 500), "nnz": 2_000_000, "core": (100, 20, 5), "seed": 2},
-    "c3b_unbalanced": {"dims": (2000, 1000, 500), "nnz": 2_000_000, "core": (10, 50, 100), "seed": 2},
-    "c5_4000cube": {"dims": (4000, 4000, 4000), "nnz": 10_000_000, "core": (100, 100, 100), "seed": 4},
+    "cube100_nnz10k": {"dims": (100, 100, 100), "nnz": 10_000, "core": (10, 10, 10), "seed": 5678},
+    "cube1000_nnz1m": {"dims": (1000, 1000, 1000), "nnz": 1_000_000, "core": (50, 50, 50), "seed": 1},
+    "unbal_2000x1000x500_core100x20x5": {"dims": (2000, 1000, 500), "nnz": 2_000_000, "core": (100, 20, 5), "seed": 2},
+    "unbal_2000x1000x500_core10x50x100": {"dims": (2000, 1000, 500), "nnz": 2_000_000, "core": (10, 50, 100), "seed": 2},
+    "cube4000_nnz10m_planted": {"dims": (4000, 4000, 4000), "nnz": 10_000_000, "core": (100, 100, 100), "seed": 4},
 }

@@ -46,17 +46,17 @@ def _orth_err(F):
 
 # ------------------------------------------------------------ 100^3 workload, FP64, 10 sweeps
 @pytest.fixture(scope="module")
-def c1():
-    w = synth.WORKLOADS["c1_100cube"]
+def cube100():
+    w = synth.WORKLOADS["cube100_nnz10k"]
     idx, vals, dims = synth.uniform_sparse(w["dims"], w["nnz"], w["seed"])
     X = O.SparseTensor3(idx, vals, dims)
     return idx, vals, dims, X, w["core"]
 
 
 @pytest.mark.parametrize("algo", ["mp", "hooi"])
-def test_c1_fp64_trajectory_matches_oracle(tk, c1, algo):
-    idx, vals, dims, X, J = c1
-    _say(f"c1 fp64 {algo}")
+def test_cube100_fp64_trajectory_matches_oracle(tk, cube100, algo):
+    idx, vals, dims, X, J = cube100
+    _say(f"cube100 fp64 {algo}")
     ref = (O.mp if algo == "mp" else O.hooi)(X, J, 10, 0.0, fit="identity")
     di, dv = _dev(idx, vals)
     r = getattr(tk, algo)(di, dv, dims, J, precision="fp64", max_iters=10, tol=0.0, eig_tol=1e-14)
@@ -70,9 +70,9 @@ def test_c1_fp64_trajectory_matches_oracle(tk, c1, algo):
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("mixed", 1e-4)])
 @pytest.mark.parametrize("algo", ["mp", "hooi"])
-def test_c1_reduced_precision_fit(tk, c1, algo, prec, tol):
-    idx, vals, dims, X, J = c1
-    _say(f"c1 {prec} {algo}")
+def test_cube100_reduced_precision_fit(tk, cube100, algo, prec, tol):
+    idx, vals, dims, X, J = cube100
+    _say(f"cube100 {prec} {algo}")
     ref = (O.mp if algo == "mp" else O.hooi)(X, J, 10, 0.0, fit="identity")
     di, dv = _dev(idx, vals)
     r = getattr(tk, algo)(di, dv, dims, J, precision=prec, max_iters=10, tol=0.0)
