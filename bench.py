@@ -73,6 +73,73 @@ def traffic_from_profile(kernel_file):
     return d.get("bytes_per_launch")
 
 
+def learned_model(tk, dev):
+    """Train the learned start's network on the GPU from the generator
+    tensors and the oracle-converged factors stored with the tests (written
+    by tests/golden/make_learn_targets.py, which runs the oracle only)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_0711_2023_amd import learn as TL
+    d = np.load(os.path.join(ROOT, "tests", "golden", "learn_targets.npz"), allow_pickle=False)
+    samples = []
+    for k, r in enumerate(d["recipes"]):
+        kind, I1, I2, I3, J1, J2, J3, nnz, seed, noise, held = r
+        if held:
+            continue
+        dims, core = (int(I1), int(I2), int(I3)), (int(J1), int(J2), int(J3))
+        if int(kind) == 0:
+            idx, vals, dims = synth.planted_tucker(dims, core, int(nnz), float(noise), int(seed))
+        else:
+            idx, vals, dims = synth.uniform_sparse(dims, int(nnz), int(seed))
+        di = torch.from_numpy(idx.astype(np.int32)).to(dev)
+        dv = torch.from_numpy(vals).to(dev)
+        for mode in (1, 2):
+            samples.append(TL.make_sample(di, dv, dims, mode, d[f"t{k}_m{mode}"]))
+    params = TL.init_params(3, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = TL.train(params, samples, steps=600, lr=2e-3)
+    torch.cuda.synchronize()
+    info = {"samples": len(samples), "steps": 600, "seconds": round(time.perf_counter() - t0, 3),
+            "loss_first_pass": round(float(np.mean(losses[:len(samples)])), 4),
+            "loss_last_pass": round(float(np.mean(losses[-len(samples):])), 4)}
+    return params, info
+
+
+def batched_leg(tk, dev, sweeps):
+    """64 tensors (mode sizes U{200..800}, density 0.5 %, cores U{10..40},
+    U(0,1) values), MP with BF16 Grams, `sweeps` sweeps each: one call on 8
+    streams against the same call on one stream."""
+    import numpy as np
+    import torch
+    import synth
+    cfgs = synth.batch_configs(64, 3000)
+    tensors, cores, total = [], [], 0
+    for c in cfgs:
+        idx, vals, dims = synth.uniform_sparse(c["dims"], c["nnz"], c["seed"])
+        tensors.append((torch.from_numpy(idx.astype(np.int32)).to(dev), torch.from_numpy(vals).to(dev), dims))
+        cores.append(c["core"])
+        total += c["nnz"]
+    out = {"workload": "64 sparse tensors, mode sizes U{200..800}, density 0.5 %, cores U{10..40}, U(0,1) values, "
+                       f"MP mixed, {sweeps} sweeps each", "tensors": 64, "nnz_total": total}
+    for ns in (8, 1):
+        streams = [torch.cuda.Stream(device=dev) for _ in range(ns)]
+        tk.batched(tk.ALGO_MP, tensors[:ns], cores[:ns], streams=streams, precision="mixed", max_iters=2, tol=0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, st = tk.batched(tk.ALGO_MP, tensors, cores, streams=streams, precision="mixed", max_iters=sweeps,
+                             tol=0.0)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[f"wall_ms_{ns}_streams"] = round(1000 * wall, 1)
+        out[f"tensors_per_s_{ns}_streams"] = round(64 / wall, 2)
+        out[f"swept_nnz_per_s_{ns}_streams"] = round(total * sweeps / wall, 1)
+        log(f"batched: {ns} stream(s) {1000 * wall:.1f} ms for 64 tensors")
+    out["speedup_8_over_1_stream"] = round(out["wall_ms_1_streams"] / out["wall_ms_8_streams"], 3)
+    return out
+
+
 def cpu_baseline(idx, vals, dims, J, sweeps=1):
     import numpy as np
     import oracle as O
@@ -105,6 +172,8 @@ def main():
     ap.add_argument("--sweeps", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-ttf", action="store_true", help="skip the time-to-fit runs")
+    ap.add_argument("--no-learn", action="store_true", help="skip the learned-start leg of the time-to-fit runs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the many-tensor leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -240,7 +309,30 @@ def main():
             log(f"time-to-fit {prec}: {ttf[prec]}")
         ttf["speedup_plain_over_mixed"] = round(ttf["fp32"]["wall_ms"] / ttf["mixed"]["wall_ms"], 3)
         ttf["mixed_reaches_plain_fit"] = bool(ttf["mixed"]["fit"] >= ttf["fp32"]["fit"] - 1e-4)
+        if not args.no_learn:
+            model, info = learned_model(tk, dev)
+            log(f"learned start trained: {info}")
+            runs = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                r = fn(di, dv, dims, J, precision="mixed", max_iters=50, tol=1e-4, workspace=None,
+                       init=tk.INIT_LEARNED, model=model)
+                torch.cuda.synchronize()
+                runs.append((time.perf_counter() - t1, r))
+            runs.sort(key=lambda x: x[0])
+            tw, r = runs[1]
+            ttf["mixed_learned"] = {"wall_ms": round(1000 * tw, 2), "sweeps": r.iters, "fit": r.fits[-1],
+                                    "prep_excluded_ms": round(r.stats["init_ms"] + r.stats["sweeps_ms"], 2),
+                                    "init_ms": round(r.stats["init_ms"], 2),
+                                    "init_fallbacks": r.stats["init_fallbacks"], "training": info}
+            log(f"time-to-fit mixed + learned start: {ttf['mixed_learned']}")
+            ttf["speedup_plain_over_mixed_learned"] = round(ttf["fp32"]["wall_ms"] / (1000 * tw), 3)
+            ttf["mixed_learned_reaches_plain_fit"] = bool(r.fits[-1] >= ttf["fp32"]["fit"] - 1e-4)
         line["time_to_fit"] = ttf
+
+    if not args.no_batch:
+        line["batched"] = batched_leg(tk, dev, args.sweeps)
 
     if not args.no_cpu:
         log("timing the FP64 oracle (one sweep) on the host")

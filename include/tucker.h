@@ -64,6 +64,10 @@ extern "C" {
 /* ---- initialisation --------------------------------------------------- */
 #define TK_INIT_HOSVD  0  /* B, C from the leading eigenvectors of X_(n) X_(n)^T */
 #define TK_INIT_GIVEN  1  /* B, C read from factors[1], factors[2] (resume) */
+#define TK_INIT_LEARNED 2 /* B, C from the learned start of tucker_learn.h (opts.model,
+                             opts.seed); a mode whose start is rank-deficient or
+                             captures no more of ||X||^2 than a random subspace
+                             would on average (Jn/In of it) falls back to HO-SVD */
 
 /* ---- algorithm selector of the workspace query ------------------------ */
 #define TK_ALGO_HOOI   0
@@ -93,6 +97,10 @@ typedef struct tk_opts {
                                FP64, 1e-8 for FP32 and mixed) */
     int32_t timing;         /* 1: record HIP events around the projection and
                                TTMc kernels and report their times in tk_stats */
+    const float *model;     /* [dev] TK_INIT_LEARNED: the network parameters
+                               (tucker_learn_param_count() floats, layout in
+                               tucker_learn.h); NULL otherwise */
+    uint64_t seed;          /* TK_INIT_LEARNED: seed of the sketch generator */
 } tk_opts;
 
 /* Optional statistics (pass NULL to skip). Times in milliseconds. */
@@ -113,10 +121,11 @@ typedef struct tk_stats {
     int32_t eig_iters;      /* total filtered subspace iterations */
     int32_t eig_noconv;     /* eigensolves that hit eig_max_iters */
     double  norm_x;         /* ||X||_F */
+    int32_t init_fallbacks; /* TK_INIT_LEARNED: modes that fell back to HO-SVD */
 } tk_stats;
 
 /* Fill *opt with: FP32, HO-SVD init, 50 sweeps, tol 1e-4, eig cap 400
-   products, eig tol 0 (by precision), no timing. */
+   products, eig tol 0 (by precision), no timing, no model, seed 0x5eed. */
 void tucker_default_opts(tk_opts *opt);
 
 /* Bytes of device workspace that tucker_hooi (algo TK_ALGO_HOOI),

@@ -11,12 +11,13 @@ reference for the learned start that the GPU library offers beside them:
 2. row features: each sketch row divided by its norm rho_i;
 3. a two-layer perceptron applied to every row, R_i = rho_i (W2^T relu(W1^T
    s_i + b1) + b2);
-4. the start factor: the leading J left singular vectors of R[:, :J]
-   (an orthonormal basis of its column space, by decreasing singular value);
-5. training: a subspace-alignment loss between span(R[:, :J]) and converged
-   factors A*, L = 1 - tr(B^T C^-1 B) / J with C = Rj^T Rj + lam I (lam held
-   fixed) and B = Rj^T A*, and its gradient, written out by hand, and the
-   backward pass of the perceptron.
+4. the start factor: the leading J-dimensional subspace of H_n = X_(n)
+   X_(n)^T within the span of the first K = min(128, 2J) network outputs
+   (Rayleigh-Ritz on an orthonormal basis Q of span(R[:, :K]));
+5. training: a subspace-alignment loss that asks span(R[:, :K]) to contain
+   converged factors A*, L = 1 - tr(B^T C^-1 B) / J with C = Rk^T Rk + lam I
+   (lam held fixed) and B = Rk^T A*, its gradient, written out by hand, and
+   the backward pass of the perceptron.
 
 Every step is written out in FP64 NumPy; the tests pin them against central
 finite differences, dense brute force and the generator's published test
@@ -27,7 +28,7 @@ import numpy as np
 __all__ = [
     "GAMMA", "splitmix64", "splitmix64_at", "sketch_omega", "sketch_dense_omega", "sketch",
     "row_features", "N_IN", "N_HID", "N_OUT", "param_count", "unpack", "mlp_forward",
-    "mlp_backward", "align_loss", "start_factor",
+    "mlp_backward", "align_loss", "start_factor", "bf16_round", "round_weights", "test_width",
 ]
 
 MASK = (1 << 64) - 1
@@ -150,26 +151,60 @@ def mlp_backward(F: np.ndarray, rho: np.ndarray, theta: np.ndarray, Z1: np.ndarr
     return np.concatenate([dW1.ravel(), db1, dW2.ravel(), db2])
 
 
-def align_loss(R: np.ndarray, J: int, A: np.ndarray, lam: float):
-    """L = 1 - tr(B^T C^-1 B) / J, C = Rj^T Rj + lam I, B = Rj^T A, Rj the
-    first J columns of R; A has orthonormal columns, so L is the mean
-    squared sine of the principal angles between span(Rj) and span(A) (for
-    lam = 0). Gradient (lam held fixed): dL/dRj = -(2/J) (A - Rj C^-1 B)
-    (C^-1 B)^T, zero for the other columns. Returns (L, dR)."""
-    Rj = R[:, :J]
-    C = Rj.T @ Rj + lam * np.eye(J)
-    B = Rj.T @ A
+def test_width(J: int) -> int:
+    """K = min(128, 2J): columns of the network output that span the test
+    subspace of a rank-J start."""
+    return min(N_OUT, 2 * J)
+
+
+def align_loss(R: np.ndarray, K: int, A: np.ndarray, lam: float):
+    """L = 1 - tr(B^T C^-1 B) / J, C = Rk^T Rk + lam I, B = Rk^T A, Rk the
+    first K columns of R and A (n x J) with orthonormal columns: for lam = 0,
+    the mean squared sine of the principal angles between span(A) and its
+    projection on span(Rk); 0 when span(Rk) contains span(A). Gradient (lam
+    held fixed): dL/dRk = -(2/J) (A - Rk C^-1 B) (C^-1 B)^T, zero for the
+    other columns. Returns (L, dR)."""
+    J = A.shape[1]
+    Rk = R[:, :K]
+    C = Rk.T @ Rk + lam * np.eye(K)
+    B = Rk.T @ A
     CB = np.linalg.solve(C, B)
     L = 1.0 - np.trace(B.T @ CB) / J
     dR = np.zeros_like(R)
-    dR[:, :J] = -(2.0 / J) * (A - Rj @ CB) @ CB.T
+    dR[:, :K] = -(2.0 / J) * (A - Rk @ CB) @ CB.T
     return L, dR
 
 
-def start_factor(R: np.ndarray, J: int) -> np.ndarray:
-    """The leading J left singular vectors of R[:, :J] (canonical signs)."""
-    U = np.linalg.svd(R[:, :J], full_matrices=False)[0]
-    for c in range(U.shape[1]):
+def start_factor(R: np.ndarray, H: np.ndarray, J: int):
+    """Rayleigh-Ritz of H on span(R[:, :K]), K = test_width(J): Q = an
+    orthonormal basis of that span (from the eigenpairs of Rk^T Rk), the J
+    leading eigenpairs (theta, V) of Q^T H Q, start = Q V with canonical
+    signs. Returns (start, theta, eigenvalues of Rk^T Rk)."""
+    K = test_width(J)
+    Rk = R[:, :K]
+    g, W = np.linalg.eigh(Rk.T @ Rk)
+    g, W = g[::-1], W[:, ::-1]
+    Q = Rk @ W / np.sqrt(g)
+    th, V = np.linalg.eigh(Q.T @ H @ Q)
+    th, V = th[::-1][:J], V[:, ::-1][:, :J]
+    U = Q @ V
+    for c in range(J):
         if U[np.argmax(np.abs(U[:, c])), c] < 0:
             U[:, c] = -U[:, c]
-    return U
+    return U, th, g
+
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round float32 values to the nearest bfloat16 (8-bit significand, ties
+    to even) and return them as float64: the upper 16 bits of the float32
+    pattern after adding 0x7FFF plus the lowest kept bit (finite inputs)."""
+    b = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def round_weights(theta: np.ndarray) -> np.ndarray:
+    """The parameters as the network uses them: W1 and W2 rounded to
+    bfloat16, the biases kept (FP32 values)."""
+    W1, b1, W2, b2 = unpack(np.asarray(theta, dtype=np.float32).astype(np.float64))
+    return np.concatenate([bf16_round(W1).ravel(), b1, bf16_round(W2).ravel(), b2])

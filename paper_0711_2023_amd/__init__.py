@@ -14,8 +14,9 @@ from dataclasses import dataclass
 
 __all__ = [
     "TuckerError", "lib", "hooi", "mp", "fit", "workspace_bytes", "default_opts",
-    "FP64", "FP32", "MIXED_BF16", "INIT_HOSVD", "INIT_GIVEN",
-    "Result", "LIB_PATH", "SYMBOLS",
+    "FP64", "FP32", "MIXED_BF16", "INIT_HOSVD", "INIT_GIVEN", "INIT_LEARNED",
+    "Result", "LIB_PATH", "SYMBOLS", "lead_eig", "learn_param_count", "learn_sketch", "learn_forward",
+    "learn_backward", "learn_align", "learn_adam", "learn_test_width", "batched",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -24,13 +25,17 @@ LIB_PATH = os.path.join(HERE, "libtucker.so")
 TK_OK, TK_WARN_NOCONV = 0, 1
 TK_ERR_ARG, TK_ERR_INDEX, TK_ERR_VALUE, TK_ERR_EMPTY, TK_ERR_WORKSPACE, TK_ERR_DEVICE = -1, -2, -3, -4, -5, -6
 FP64, FP32, MIXED_BF16 = 0, 1, 2
-INIT_HOSVD, INIT_GIVEN = 0, 1
+INIT_HOSVD, INIT_GIVEN, INIT_LEARNED = 0, 1, 2
 ALGO_HOOI, ALGO_MP, ALGO_FIT = 0, 1, 2
 _PREC = {"fp64": FP64, "fp32": FP32, "mixed": MIXED_BF16, "bf16": MIXED_BF16}
 
-# every function declared in include/tucker.h
+# every function declared in include/*.h
 SYMBOLS = ["tucker_default_opts", "tucker_workspace_bytes", "tucker_hooi", "tucker_mp", "tucker_fit",
-           "tucker_strerror", "tucker_step_lead_eig_workspace", "tucker_step_lead_eig"]
+           "tucker_strerror", "tucker_step_lead_eig_workspace", "tucker_step_lead_eig",
+           "tucker_learn_param_count", "tucker_learn_sketch_workspace", "tucker_learn_sketch",
+           "tucker_learn_forward", "tucker_learn_backward_workspace", "tucker_learn_backward",
+           "tucker_learn_test_width", "tucker_learn_align_workspace", "tucker_learn_align", "tucker_learn_adam",
+           "tucker_batched_workspace_bytes", "tucker_batched"]
 
 
 class tk_coo(ctypes.Structure):
@@ -41,7 +46,7 @@ class tk_coo(ctypes.Structure):
 class tk_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("init", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("eig_max_iters", ctypes.c_int32), ("eig_tol", ctypes.c_double),
-                ("timing", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("model", ctypes.c_void_p), ("seed", ctypes.c_uint64)]
 
 
 class tk_stats(ctypes.Structure):
@@ -50,7 +55,7 @@ class tk_stats(ctypes.Structure):
                 ("gram_ms", ctypes.c_double), ("gram_calls", ctypes.c_int64), ("eig_ms", ctypes.c_double),
                 ("core_ms", ctypes.c_double),
                 ("nnz_unique", ctypes.c_int64), ("eig_iters", ctypes.c_int32), ("eig_noconv", ctypes.c_int32),
-                ("norm_x", ctypes.c_double)]
+                ("norm_x", ctypes.c_double), ("init_fallbacks", ctypes.c_int32)]
 
 
 class TuckerError(RuntimeError):
@@ -92,6 +97,25 @@ def lib():
         L.tucker_step_lead_eig.restype = ctypes.c_int
         L.tucker_strerror.argtypes = [ctypes.c_int]
         L.tucker_strerror.restype = ctypes.c_char_p
+        vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+        L.tucker_learn_param_count.argtypes = []
+        L.tucker_learn_sketch_workspace.argtypes = [P(tk_coo), P(sz)]
+        L.tucker_learn_sketch.argtypes = [P(tk_coo), i32, ctypes.c_uint64, vp, vp, vp, sz, vp]
+        L.tucker_learn_forward.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+        L.tucker_learn_backward_workspace.argtypes = [i64, P(sz)]
+        L.tucker_learn_backward.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, sz, vp]
+        L.tucker_learn_test_width.argtypes = [i32]
+        L.tucker_learn_align_workspace.argtypes = [i64, i32, i32, P(sz)]
+        L.tucker_learn_align.argtypes = [vp, i64, i32, vp, i32, ctypes.c_double, P(ctypes.c_double), vp, vp, sz,
+                                         vp]
+        L.tucker_learn_adam.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float, i32, vp]
+        L.tucker_batched_workspace_bytes.argtypes = [i32, i32, P(tk_coo), P(i32), P(tk_opts), P(sz)]
+        L.tucker_batched.argtypes = [i32, i32, P(tk_coo), P(i32), P(tk_opts), P(vp), P(vp), P(ctypes.c_double),
+                                     P(i32), P(i32), P(tk_stats), i32, P(vp), sz, P(vp)]
+        for name in SYMBOLS:
+            if name.startswith("tucker_learn") or name.startswith("tucker_batched"):
+                getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -113,8 +137,12 @@ def default_opts() -> tk_opts:
 
 
 def _opts(precision="fp32", init=INIT_HOSVD, max_iters=50, tol=1e-4, eig_max_iters=None, eig_tol=None,
-          timing=False) -> tk_opts:
+          timing=False, model=None, seed=None) -> tk_opts:
     o = default_opts()
+    if model is not None:
+        o.model = model.data_ptr()
+    if seed is not None:
+        o.seed = int(seed)
     o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
     o.init = int(init)
     o.max_iters = int(max_iters)
@@ -173,11 +201,15 @@ def _stats_dict(s: tk_stats) -> dict:
 
 def _run(fn_name: str, algo: int, idx, vals, dims, core_dims, *, precision="fp32", init=INIT_HOSVD,
          max_iters=50, tol=1e-4, eig_max_iters=None, eig_tol=None, timing=False, factors=None, workspace=None,
-         stream=None) -> Result:
+         stream=None, model=None, seed=None) -> Result:
+    """`model`: float32 tensor of learn_param_count() parameters on the GPU,
+    used with init=INIT_LEARNED."""
     import torch
     dev = vals.device
     coo = _Coo(idx, vals, dims)
-    o = _opts(precision, init, max_iters, tol, eig_max_iters, eig_tol, timing)
+    if model is not None and (model.dtype != torch.float32 or not model.is_cuda or not model.is_contiguous()):
+        raise TypeError("model must be a contiguous float32 tensor on the GPU")
+    o = _opts(precision, init, max_iters, tol, eig_max_iters, eig_tol, timing, model, seed)
     J = [int(j) for j in core_dims]
     Jc = (ctypes.c_int32 * 3)(*J)
     need = ctypes.c_size_t(0)
@@ -254,3 +286,126 @@ def fit(idx, vals, dims, core, factors, workspace=None, stream=None) -> float:
     _check(lib().tucker_fit(ctypes.byref(coo.c), Jc, G.data_ptr(), fptrs, ctypes.byref(out), workspace.data_ptr(),
                             int(workspace.numel()), ctypes.c_void_p(s.cuda_stream)))
     return float(out.value)
+
+
+# ---------------------------------------------------------------- learned start
+def _stream_ptr(dev, stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def learn_param_count() -> int:
+    return int(lib().tucker_learn_param_count())
+
+
+def learn_sketch(idx, vals, dims, mode: int, seed: int, stream=None):
+    """Row features (In x 64) and row norms (In) of the mode's sketch."""
+    import torch
+    coo = _Coo(idx, vals, dims)
+    need = ctypes.c_size_t(0)
+    _check(lib().tucker_learn_sketch_workspace(ctypes.byref(coo.c), ctypes.byref(need)))
+    ws = torch.empty(int(need.value), dtype=torch.uint8, device=vals.device)
+    In = int(dims[mode])
+    F = torch.empty((In, 64), dtype=torch.float32, device=vals.device)
+    rho = torch.empty(In, dtype=torch.float32, device=vals.device)
+    _check(lib().tucker_learn_sketch(ctypes.byref(coo.c), int(mode), ctypes.c_uint64(int(seed)), F.data_ptr(),
+                                     rho.data_ptr(), ws.data_ptr(), int(ws.numel()),
+                                     _stream_ptr(vals.device, stream)))
+    return F, rho
+
+
+def learn_forward(F, rho, params, want_z1=True, stream=None):
+    """Network output R (rows x 128) and the hidden pre-activations."""
+    import torch
+    rows = int(F.shape[0])
+    R = torch.empty((rows, 128), dtype=torch.float32, device=F.device)
+    Z1 = torch.empty((rows, 128), dtype=torch.float32, device=F.device) if want_z1 else None
+    _check(lib().tucker_learn_forward(F.data_ptr(), rho.data_ptr(), rows, params.data_ptr(), R.data_ptr(),
+                                      Z1.data_ptr() if Z1 is not None else None, _stream_ptr(F.device, stream)))
+    return R, Z1
+
+
+def learn_backward(F, rho, params, Z1, dR, stream=None):
+    """Gradient of a scalar w.r.t. the parameters given its gradient dR."""
+    import torch
+    rows = int(F.shape[0])
+    need = ctypes.c_size_t(0)
+    _check(lib().tucker_learn_backward_workspace(rows, ctypes.byref(need)))
+    ws = torch.empty(int(need.value), dtype=torch.uint8, device=F.device)
+    g = torch.empty(learn_param_count(), dtype=torch.float32, device=F.device)
+    _check(lib().tucker_learn_backward(F.data_ptr(), rho.data_ptr(), rows, params.data_ptr(), Z1.data_ptr(),
+                                       dR.data_ptr(), g.data_ptr(), ws.data_ptr(), int(ws.numel()),
+                                       _stream_ptr(F.device, stream)))
+    return g
+
+
+def learn_test_width(J: int) -> int:
+    return int(_check(lib().tucker_learn_test_width(int(J))))
+
+
+def learn_align(R, K: int, A, shift=1e-8, want_grad=True, stream=None):
+    """(loss, dL/dR or None): how much of span(A) lies outside the span of
+    R's first K columns."""
+    import torch
+    rows = int(R.shape[0])
+    J = int(A.shape[1])
+    need = ctypes.c_size_t(0)
+    _check(lib().tucker_learn_align_workspace(rows, int(K), J, ctypes.byref(need)))
+    ws = torch.empty(int(need.value), dtype=torch.uint8, device=R.device)
+    A = A.to(torch.float64).contiguous()
+    dR = torch.empty((rows, 128), dtype=torch.float32, device=R.device) if want_grad else None
+    loss = ctypes.c_double(0)
+    _check(lib().tucker_learn_align(R.data_ptr(), rows, int(K), A.data_ptr(), J, float(shift), ctypes.byref(loss),
+                                    dR.data_ptr() if dR is not None else None, ws.data_ptr(), int(ws.numel()),
+                                    _stream_ptr(R.device, stream)))
+    return float(loss.value), dR
+
+
+def learn_adam(params, grad, m, v, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().tucker_learn_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                   int(params.numel()), float(lr), float(beta1), float(beta2), float(eps), int(step),
+                                   _stream_ptr(params.device, stream)))
+
+
+# ---------------------------------------------------------------- many tensors
+def batched(algo: int, tensors, cores, nstreams: int = 8, streams=None, workspaces=None, **opts):
+    """Decompose many tensors in one call (ALGO_MP or ALGO_HOOI): `tensors` is
+    a list of (idx, vals, dims) on the GPU, `cores` the core sizes. Returns
+    (list of Result, overall status). The streams (default: `nstreams` new
+    ones) and per-stream workspaces can be passed in to reuse them."""
+    import torch
+    count = len(tensors)
+    dev = tensors[0][1].device
+    coos = [_Coo(i, v, d) for (i, v, d) in tensors]
+    carr = (tk_coo * count)(*[c.c for c in coos])
+    J = [int(j) for core in cores for j in core]
+    Jc = (ctypes.c_int32 * (3 * count))(*J)
+    o = _opts(**opts)
+    need = ctypes.c_size_t(0)
+    _check(lib().tucker_batched_workspace_bytes(int(algo), count, carr, Jc, ctypes.byref(o), ctypes.byref(need)))
+    if streams is None:
+        streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)]
+    nstreams = len(streams)
+    if workspaces is None or any(w.numel() < need.value for w in workspaces):
+        workspaces = [torch.empty(int(need.value), dtype=torch.uint8, device=dev) for _ in range(nstreams)]
+    Gs = [torch.empty(tuple(int(x) for x in core), dtype=torch.float64, device=dev) for core in cores]
+    facs = [[torch.empty((int(d[n]), int(core[n])), dtype=torch.float64, device=dev) for n in range(3)]
+            for (_, _, d), core in zip(tensors, cores)]
+    cptr = (ctypes.c_void_p * count)(*[g.data_ptr() for g in Gs])
+    fptr = (ctypes.c_void_p * (3 * count))(*[f.data_ptr() for fs in facs for f in fs])
+    mi = max(1, int(o.max_iters))
+    hist = (ctypes.c_double * (mi * count))()
+    done = (ctypes.c_int32 * count)()
+    stat = (ctypes.c_int32 * count)()
+    sts = (tk_stats * count)()
+    wptr = (ctypes.c_void_p * nstreams)(*[w.data_ptr() for w in workspaces])
+    sptr = (ctypes.c_void_p * nstreams)(*[s.cuda_stream for s in streams])
+    torch.cuda.synchronize(dev)  # inputs are complete before the workers start
+    overall = lib().tucker_batched(int(algo), count, carr, Jc, ctypes.byref(o), cptr, fptr, hist, done, stat, sts,
+                                   nstreams, wptr, int(need.value), sptr)
+    _check(overall)
+    hm = int(o.max_iters)
+    res = [Result(Gs[t], facs[t], [hist[hm * t + i] for i in range(done[t])], int(done[t]), _stats_dict(sts[t]),
+                  int(stat[t])) for t in range(count)]
+    return res, overall

@@ -93,7 +93,7 @@ static inline int hi_of(int m) { return (m + 2) % 3; }
 static inline int lo_of(int m) { return (m + 1) % 3; }
 
 struct Plan {
-    int algo, prec;
+    int algo, prec, init = TK_INIT_HOSVD;
     int64_t I[3], nnz;
     int J[3];
     int64_t nslots[3];
@@ -125,6 +125,15 @@ struct Plan {
     double *Z, *Gp, *core_split;
     int64_t core_split_elems;
     double *Gx, *Pn[3], *W1, *W2;
+    // learned start (modes 1 and 2, one at a time): features, norms, network
+    // output, FP64 leading columns / H U, J x J Gram and eigenvectors, eigen-
+    // values, skinny partial strips, eigensolver workspace, back-propagation
+    // scratch
+    float *LF = nullptr, *Lrho = nullptr, *LR = nullptr;
+    double *LQ = nullptr, *LHQ = nullptr, *LC = nullptr, *LV = nullptr, *Ltheta = nullptr, *Lg = nullptr;
+    double *Lpart = nullptr;
+    int64_t Lpart_elems = 0;
+    void *Leigw = nullptr;
     bool blk_ok[3] = {false, false, false};  // Xblk[n] holds a previous block
 };
 
@@ -246,6 +255,22 @@ static void carve(Plan &p, Arena &ar) {
         p.W1 = ar.take<double>(J0 * J1 * J2);
         p.W2 = ar.take<double>(J0 * J1 * J2);
     }
+    if (p.init == TK_INIT_LEARNED && p.algo != TK_ALGO_FIT) {
+        int64_t In = std::max(p.I[1], p.I[2]);
+        int Km = learn_test_width(std::max(p.J[1], p.J[2]));
+        p.LF = ar.take<float>(In * 64);
+        p.Lrho = ar.take<float>(In);
+        p.LR = ar.take<float>(In * 128);
+        p.LQ = ar.take<double>(In * Km);
+        p.LHQ = ar.take<double>(In * Km);
+        p.LC = ar.take<double>((int64_t)Km * Km);
+        p.LV = ar.take<double>((int64_t)Km * Km);
+        p.Ltheta = ar.take<double>(Km);
+        p.Lg = ar.take<double>(Km);
+        p.Lpart_elems = skinny_part_bound(Km);
+        p.Lpart = ar.take<double>(p.Lpart_elems);
+        p.Leigw = ar.take<char>((int64_t)eig_work_bytes(Km, Km));
+    }
 }
 
 static int check_coo(const tk_coo *X, const int32_t *J) {
@@ -264,18 +289,20 @@ static int check_coo(const tk_coo *X, const int32_t *J) {
 static int check_opts(const tk_opts *o, const tk_coo *X) {
     if (!o) return TK_ERR_ARG;
     if (o->precision < 0 || o->precision > 2) return TK_ERR_ARG;
-    if (o->init != TK_INIT_HOSVD && o->init != TK_INIT_GIVEN) return TK_ERR_ARG;
+    if (o->init != TK_INIT_HOSVD && o->init != TK_INIT_GIVEN && o->init != TK_INIT_LEARNED) return TK_ERR_ARG;
+    if (o->init == TK_INIT_LEARNED && !o->model) return TK_ERR_ARG;
     if (o->max_iters < 0 || o->eig_max_iters < 1) return TK_ERR_ARG;
     if (!(o->eig_tol >= 0.0) || std::isnan(o->tol)) return TK_ERR_ARG;
-    if (o->init == TK_INIT_HOSVD)
+    if (o->init != TK_INIT_GIVEN)  // HO-SVD, or its fallback for the learned start
         for (int n = 1; n < 3; ++n)
             if (X->dims[n] > kMaxHosvdDim) return TK_ERR_ARG;
     return TK_OK;
 }
 
-static void plan_init(Plan &p, int algo, int prec, const tk_coo *X, const int32_t *J) {
+static void plan_init(Plan &p, int algo, int prec, const tk_coo *X, const int32_t *J, int init = TK_INIT_HOSVD) {
     p.algo = algo;
     p.prec = prec;
+    p.init = init;
     p.nnz = X->nnz;
     for (int n = 0; n < 3; ++n) {
         p.I[n] = X->dims[n];
@@ -301,6 +328,8 @@ void tucker_default_opts(tk_opts *o) {
     o->eig_max_iters = 400;
     o->eig_tol = 0.0;
     o->timing = 0;
+    o->model = nullptr;
+    o->seed = 0x5eedull;
 }
 
 const char *tucker_strerror(int st) {
@@ -329,7 +358,7 @@ int tucker_workspace_bytes(int32_t algo, const tk_coo *X, const int32_t *core_di
         prec = opt->precision;
     }
     Plan p;
-    plan_init(p, algo, prec, X, core_dims);
+    plan_init(p, algo, prec, X, core_dims, algo != TK_ALGO_FIT ? opt->init : TK_INIT_HOSVD);
     Arena ar;
     carve(p, ar);
     *bytes = ar.used + 256;
@@ -573,7 +602,7 @@ static int common_start(int algo, const tk_coo *X, const int32_t *J, const tk_op
     if (!core || !factors || !factors[0] || !factors[1] || !factors[2] || !iters_done) return TK_ERR_ARG;
     if (o->max_iters > 0 && !fit_history) return TK_ERR_ARG;
     if (X->nnz == 0) return TK_ERR_EMPTY;
-    plan_init(p, algo, o->precision, X, J);
+    plan_init(p, algo, o->precision, X, J, o->init);
     Arena ar;
     carve(p, ar);
     if (!ws || wsb < ar.used + 256) return TK_ERR_WORKSPACE;
@@ -584,11 +613,59 @@ static int common_start(int algo, const tk_coo *X, const int32_t *J, const tk_op
     return TK_OK;
 }
 
-static int init_factors(Plan &p, const tk_opts *o, double *const *factors, tk_stats *st, int *noconv, hipStream_t s) {
+// Learned start of mode n into F (In x Jn): sketch, network, Rayleigh-Ritz of
+// H_n on the span of the network's first K outputs. Returns 1 when the start
+// is accepted, 0 when the mode must fall back to HO-SVD (H_n is left in p.Mg
+// either way), or a negative status.
+static int learned_mode(Plan &p, int n, const tk_opts *o, double *F, double nx2, hipStream_t s) {
+    const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
+    const int64_t In = p.I[n];
+    const int J = p.J[n], K = learn_test_width(J);
+    const int sl = (n + 1) % 3;  // ordering whose slots are the mode-n slices
+    if (p.lval32[sl])
+        ST(learn_sketch<float>(p.ptr[sl], p.lidx[sl], p.lval32[sl], In, p.I[lo_of(sl)], n, o->seed, p.LF, p.Lrho, s));
+    else
+        ST(learn_sketch<double>(p.ptr[sl], p.lidx[sl], p.lval64[sl], In, p.I[lo_of(sl)], n, o->seed, p.LF, p.Lrho,
+                                s));
+    ST(learn_forward(p.LF, p.Lrho, In, o->model, p.LR, nullptr, s));
+    ST(hosvd_gram(n, dims, p.ptr[n], p.lidx[n], p.lval64[n], p.ptr[sl], p.lidx[sl], p.lval64[sl], p.Mg, s));
+    if (K > In) return 0;  // no room for a test subspace: HO-SVD
+    ST(learn_start(p.LR, In, J, p.Mg, F, p.Ltheta, p.Lg, p.LQ, p.LHQ, p.LC, p.LV, p.Leigw, p.Lpart, p.Lpart_elems,
+                   s));
+    std::vector<double> th(J), g(K);
+    ST(hipMemcpyAsync(th.data(), p.Ltheta, sizeof(double) * J, hipMemcpyDeviceToHost, s));
+    ST(hipMemcpyAsync(g.data(), p.Lg, sizeof(double) * K, hipMemcpyDeviceToHost, s));
+    ST(hipStreamSynchronize(s));
+    // the start's captured energy tr(F^T H_n F) = sum of the Ritz values,
+    // against Jn/In of ||X||^2 (a random Jn-dimensional subspace's mean)
+    double e = 0.0;
+    for (double v : th) e += v;
+    const bool full_rank = std::isfinite(g[0]) && g[0] > 0.0 && g[K - 1] >= 1e-12 * g[0];
+    const bool better = std::isfinite(e) && e > (double)J / (double)In * nx2;
+    return full_rank && better ? 1 : 0;
+}
+
+static int init_factors(Plan &p, const tk_opts *o, double *const *factors, tk_stats *st, int *noconv, double nx2,
+                        hipStream_t s) {
     const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
     for (int n = 1; n < 3; ++n) {
         if (o->init == TK_INIT_GIVEN) {
             ST(refresh_copies(p, n, factors[n], s));
+            continue;
+        }
+        if (o->init == TK_INIT_LEARNED) {
+            const int ok = learned_mode(p, n, o, factors[n], nx2, s);
+            if (ok < 0) return ok;
+            if (ok == 1) {
+                // the eigensolves of the sweeps start from this factor
+                ST(eig_seed_block(p.Xblk[n], (int)p.I[n], p.J[n], factors[n], p.eigw, 0x1ea7ull + n, s));
+                p.blk_ok[n] = true;
+                ST(refresh_copies(p, n, factors[n], s));
+                continue;
+            }
+            if (st) st->init_fallbacks += 1;
+            int r = run_eig(p, n, p.Mg, factors[n], false, o, st, noconv, s);  // H_n is in p.Mg
+            if (r) return r;
             continue;
         }
         const int sl = (n + 1) % 3;  // ordering whose slots are the mode-n slices
@@ -616,7 +693,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     if ((st = prep(p, X, s, &nu, &nx2))) return st;
     double t1 = now_ms();
     int noconv = 0;
-    if ((st = init_factors(p, o, factors, stats, &noconv, s))) return st;
+    if ((st = init_factors(p, o, factors, stats, &noconv, nx2, s))) return st;
     ST(hipStreamSynchronize(s));
     double t2 = now_ms();
     const int prec = p.prec;
@@ -756,7 +833,7 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
     if ((st = prep(p, X, s, &nu, &nx2))) return st;
     double t1 = now_ms();
     int noconv = 0;
-    if ((st = init_factors(p, o, factors, stats, &noconv, s))) return st;
+    if ((st = init_factors(p, o, factors, stats, &noconv, nx2, s))) return st;
     ST(hipStreamSynchronize(s));
     double t2 = now_ms();
     const int prec = p.prec;
@@ -1047,4 +1124,188 @@ extern "C" int tucker_step_lead_eig(const double *M, int32_t n, int32_t J, doubl
     ST(hipStreamSynchronize(s));
     *matvecs = it;
     return nc ? TK_WARN_NOCONV : TK_OK;
+}
+
+// ------------------------------------------------------------------ learned start
+#include "../../include/tucker_learn.h"
+
+extern "C" int tucker_learn_param_count(void) { return learn_param_count(); }
+
+namespace tk {
+static void sketch_plan(Plan &p, const tk_coo *X) {
+    const int32_t ones[3] = {1, 1, 1};
+    plan_init(p, TK_ALGO_FIT, P32, X, ones);
+}
+}  // namespace tk
+
+extern "C" int tucker_learn_sketch_workspace(const tk_coo *X, size_t *bytes) {
+    const int32_t ones[3] = {1, 1, 1};
+    if (!bytes) return TK_ERR_ARG;
+    int st = check_coo(X, ones);
+    if (st) return st;
+    Plan p;
+    sketch_plan(p, X);
+    Arena ar;
+    carve(p, ar);
+    *bytes = ar.used + 256;
+    return TK_OK;
+}
+
+extern "C" int tucker_learn_sketch(const tk_coo *X, int32_t mode, uint64_t seed, float *F, float *rho, void *ws,
+                                   size_t wsb, void *stream) {
+    const int32_t ones[3] = {1, 1, 1};
+    int st = check_coo(X, ones);
+    if (st) return st;
+    if (mode < 0 || mode > 2 || !F || !rho) return TK_ERR_ARG;
+    if (X->nnz == 0) return TK_ERR_EMPTY;
+    Plan p;
+    sketch_plan(p, X);
+    Arena ar;
+    carve(p, ar);
+    if (!ws || wsb < ar.used + 256) return TK_ERR_WORKSPACE;
+    ar.base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+    ar.used = 0;
+    carve(p, ar);
+    g_err[0] = 0;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t nu = 0;
+    double nx2 = 0;
+    if ((st = prep(p, X, s, &nu, &nx2))) return st;
+    const int sl = (mode + 1) % 3;
+    ST(learn_sketch<float>(p.ptr[sl], p.lidx[sl], p.lval32[sl], p.I[mode], p.I[lo_of(sl)], mode, seed, F, rho, s));
+    ST(hipStreamSynchronize(s));
+    return TK_OK;
+}
+
+extern "C" int tucker_learn_forward(const float *F, const float *rho, int64_t rows, const float *params, float *R,
+                                    float *Z1, void *stream) {
+    if (rows < 0 || (rows > 0 && (!F || !rho || !params || !R))) return TK_ERR_ARG;
+    g_err[0] = 0;
+    hipStream_t s = (hipStream_t)stream;
+    ST(learn_forward(F, rho, rows, params, R, Z1, s));
+    ST(hipStreamSynchronize(s));
+    return TK_OK;
+}
+
+extern "C" int tucker_learn_backward_workspace(int64_t rows, size_t *bytes) {
+    if (!bytes || rows < 0) return TK_ERR_ARG;
+    *bytes = learn_backward_scratch(rows) + 256;
+    return TK_OK;
+}
+
+extern "C" int tucker_learn_backward(const float *F, const float *rho, int64_t rows, const float *params,
+                                     const float *Z1, const float *dR, float *grad, void *ws, size_t wsb,
+                                     void *stream) {
+    if (rows < 0 || !grad || (rows > 0 && (!F || !rho || !params || !Z1 || !dR))) return TK_ERR_ARG;
+    if (!ws || wsb < learn_backward_scratch(rows) + 256) return TK_ERR_WORKSPACE;
+    g_err[0] = 0;
+    hipStream_t s = (hipStream_t)stream;
+    float *part = reinterpret_cast<float *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+    ST(learn_backward(F, rho, rows, params, Z1, dR, grad, part, s));
+    ST(hipStreamSynchronize(s));
+    return TK_OK;
+}
+
+extern "C" int tucker_learn_test_width(int32_t J) { return J >= 1 && J <= 128 ? learn_test_width(J) : TK_ERR_ARG; }
+
+extern "C" int tucker_learn_align_workspace(int64_t rows, int32_t K, int32_t J, size_t *bytes) {
+    if (!bytes || rows < 1 || K < 1 || K > 128 || J < 1 || J > 128 || J > rows) return TK_ERR_ARG;
+    *bytes = sizeof(double) * (size_t)learn_align_scratch_doubles(rows, K, J) + 256;
+    return TK_OK;
+}
+
+extern "C" int tucker_learn_align(const float *R, int64_t rows, int32_t K, const double *A, int32_t J, double shift,
+                                  double *loss, float *dR, void *ws, size_t wsb, void *stream) {
+    if (!R || !A || !loss || rows < 1 || K < 1 || K > 128 || J < 1 || J > 128 || J > rows || !(shift >= 0.0))
+        return TK_ERR_ARG;
+    if (rows >= (int64_t)INT32_MAX) return TK_ERR_ARG;
+    if (!ws || wsb < sizeof(double) * (size_t)learn_align_scratch_doubles(rows, K, J) + 256)
+        return TK_ERR_WORKSPACE;
+    g_err[0] = 0;
+    hipStream_t s = (hipStream_t)stream;
+    double *scr = reinterpret_cast<double *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+    double *loss_dev = scr;  // first 8 doubles, the rest for the computation
+    ST(learn_align(R, rows, K, A, J, shift, loss_dev, dR, scr + 8, s));
+    ST(hipMemcpyAsync(loss, loss_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    ST(hipStreamSynchronize(s));
+    return TK_OK;
+}
+
+extern "C" int tucker_learn_adam(float *params, const float *grad, float *m, float *v, int64_t n, float lr,
+                                 float beta1, float beta2, float eps, int32_t step, void *stream) {
+    if (!params || !grad || !m || !v || n < 1 || step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+        !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return TK_ERR_ARG;
+    g_err[0] = 0;
+    hipStream_t s = (hipStream_t)stream;
+    ST(learn_adam(params, grad, m, v, n, lr, beta1, beta2, eps, step, s));
+    ST(hipStreamSynchronize(s));
+    return TK_OK;
+}
+
+// ------------------------------------------------------------------ many tensors
+#include "../../include/tucker_batch.h"
+
+#include <atomic>
+#include <thread>
+
+extern "C" int tucker_batched_workspace_bytes(int32_t algo, int32_t count, const tk_coo *X, const int32_t *core_dims,
+                                              const tk_opts *opt, size_t *bytes) {
+    if (!bytes || !X || !core_dims || !opt || count < 1) return TK_ERR_ARG;
+    if (algo != TK_ALGO_HOOI && algo != TK_ALGO_MP) return TK_ERR_ARG;
+    size_t best = 0;
+    for (int32_t t = 0; t < count; ++t) {
+        size_t b = 0;
+        int st = tucker_workspace_bytes(algo, X + t, core_dims + 3 * t, opt, &b);
+        if (st) return st;
+        best = std::max(best, b);
+    }
+    *bytes = best;
+    return TK_OK;
+}
+
+extern "C" int tucker_batched(int32_t algo, int32_t count, const tk_coo *X, const int32_t *core_dims,
+                              const tk_opts *opt, double *const *cores, double *const *factors, double *fit_history,
+                              int32_t *iters_done, int32_t *status, tk_stats *stats, int32_t nstreams,
+                              void *const *workspaces, size_t workspace_bytes, void *const *streams) {
+    if (!X || !core_dims || !opt || !cores || !factors || !iters_done || !status || !workspaces || !streams)
+        return TK_ERR_ARG;
+    if (count < 1 || nstreams < 1 || nstreams > 64) return TK_ERR_ARG;
+    if (algo != TK_ALGO_HOOI && algo != TK_ALGO_MP) return TK_ERR_ARG;
+    if (opt->max_iters > 0 && !fit_history) return TK_ERR_ARG;
+    size_t need = 0;
+    int st = tucker_batched_workspace_bytes(algo, count, X, core_dims, opt, &need);
+    if (st) return st;
+    for (int32_t s = 0; s < nstreams; ++s)
+        if (!workspaces[s] || workspace_bytes < need) return TK_ERR_WORKSPACE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TK_ERR_DEVICE;
+    std::atomic<int32_t> next{0};
+    const int64_t hist = opt->max_iters > 0 ? opt->max_iters : 0;
+    auto worker = [&](int32_t s) {
+        if (hipSetDevice(dev) != hipSuccess) {
+            for (int32_t t; (t = next.fetch_add(1)) < count;) status[t] = TK_ERR_DEVICE;
+            return;
+        }
+        for (int32_t t; (t = next.fetch_add(1)) < count;) {
+            double *const *f = factors + 3 * (int64_t)t;
+            double *h = hist ? fit_history + hist * t : nullptr;
+            tk_stats *stt = stats ? stats + t : nullptr;
+            status[t] = algo == TK_ALGO_MP
+                            ? tucker_mp(X + t, core_dims + 3 * t, opt, cores[t], f, h, iters_done + t, stt,
+                                        workspaces[s], workspace_bytes, streams[s])
+                            : tucker_hooi(X + t, core_dims + 3 * t, opt, cores[t], f, h, iters_done + t, stt,
+                                          workspaces[s], workspace_bytes, streams[s]);
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int32_t s = 1; s < nstreams; ++s) pool.emplace_back(worker, s);
+    worker(0);
+    for (auto &th : pool) th.join();
+    int worst = TK_OK;
+    for (int32_t t = 0; t < count; ++t) {
+        if (status[t] < 0) return status[t];
+        if (status[t] > 0) worst = status[t];
+    }
+    return worst;
 }

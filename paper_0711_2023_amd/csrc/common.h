@@ -166,9 +166,50 @@ struct EigOpts {
 };
 hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta_dev, void *work,
                     const EigOpts &o, int *iters, int *noconv, hipStream_t s);
+// Skinny FP64 products C (M x N, N <= 144) = alpha op(A) B + beta E1 with
+// split-K partial strips in `part` (at most skinny_part_bound(N) doubles).
+hipError_t skinny_gemm(int M, int N, int K, const double *A, int64_t lda, bool at, const double *B, int64_t ldb,
+                       double *C, int64_t ldc, double alpha, double beta, const double *E1, double *part,
+                       int64_t part_elems, hipStream_t s);
+int64_t skinny_part_bound(int max_n);
+// Upper Cholesky factor of S + shift * trace(S) * I (w x w, w <= 140) and its
+// inverse (one workgroup).
+hipError_t chol_inv_upper(const double *S, int w, double shift, double *Rinv, hipStream_t s);
+// F (n x J) = columns of X (leading dimension ldx) with the sign that makes
+// each column's largest-magnitude entry positive.
+hipError_t canonical_cols(const double *X, int64_t n, int ldx, int J, double *F, hipStream_t s);
+// Start block of the eigensolver (n x eig_block_width(n, J)) from J
+// orthonormal columns U plus pseudo-random columns orthonormalised against
+// them; `work` is an eigensolver workspace of eig_work_bytes.
+hipError_t eig_seed_block(double *X, int n, int J, const double *U, void *work, uint64_t seed, hipStream_t s);
 
 // ---------------------------------------------------------------- small helpers (eig.hip)
 template <class TO>
 hipError_t convert_f64(const double *in, TO *out, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------- learn.hip
+// Learned start: sketch features of mode n from the ordering whose slots are
+// the mode-n slices (I_lo = size of mode n+2), the row-wise network, its
+// backward pass (scratch learn_backward_scratch(rows) bytes), Adam, the
+// subspace-alignment loss (scratch learn_align_scratch_doubles doubles) and
+// the start factor.
+int learn_param_count();
+template <class TV>
+hipError_t learn_sketch(const int32_t *ptr, const int32_t *lidx, const TV *lval, int64_t In, int64_t Ilo, int n,
+                        uint64_t seed, float *F, float *rho, hipStream_t s);
+hipError_t learn_forward(const float *F, const float *rho, int64_t rows, const float *P, float *R, float *Z1,
+                         hipStream_t s);
+size_t learn_backward_scratch(int64_t rows);
+hipError_t learn_backward(const float *F, const float *rho, int64_t rows, const float *P, const float *Z1,
+                          const float *dR, float *grad, float *part, hipStream_t s);
+hipError_t learn_adam(float *P, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2,
+                      float eps, int step, hipStream_t s);
+int64_t learn_align_scratch_doubles(int64_t rows, int K, int J);
+hipError_t learn_align(const float *R, int64_t rows, int K, const double *A, int J, double shift, double *loss_dev,
+                       float *dR, double *scratch, hipStream_t s);
+int learn_test_width(int J);
+hipError_t learn_start(const float *R, int64_t rows, int J, const double *H, double *F, double *theta, double *gC,
+                       double *Q, double *HQ, double *C, double *V, void *eigw, double *part, int64_t part_elems,
+                       hipStream_t s);
 
 }  // namespace tk

@@ -752,6 +752,44 @@ static hipError_t power_lock(const double *M, int n, int b, double *X, int steps
     return hipSuccess;
 }
 
+// ------------------------------------------------------------------ shared with the learned start
+hipError_t skinny_gemm(int M, int N, int K, const double *A, int64_t lda, bool at, const double *B, int64_t ldb,
+                       double *C, int64_t ldc, double alpha, double beta, const double *E1, double *part,
+                       int64_t part_elems, hipStream_t s) {
+    return dgemm(M, N, K, A, lda, at, B, ldb, C, ldc, alpha, beta, E1, 0.0, nullptr, part, part_elems, s);
+}
+int64_t skinny_part_bound(int max_n) { return (int64_t)512 * 16 * (ceil_div(max_n, 16) * 16); }
+
+hipError_t chol_inv_upper(const double *S, int w, double shift, double *Rinv, hipStream_t s) {
+    const size_t lds = sizeof(double) * ((size_t)w * w + w);
+    hipFuncSetAttribute((const void *)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_chol_inv<<<1, 1024, lds, s>>>(S, w, w, shift, Rinv);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
+hipError_t canonical_cols(const double *X, int64_t n, int ldx, int J, double *F, hipStream_t s) {
+    k_extract<<<J, 256, 0, s>>>(X, n, ldx, J, F, nullptr);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
+hipError_t eig_seed_block(double *X, int n, int J, const double *U, void *work, uint64_t seed, hipStream_t s) {
+    const int b = eig_block_width(n, J);
+    Arena ar;
+    ar.base = reinterpret_cast<char *>(work);
+    EigLayout L = eig_layout(ar, n, b);
+    TK_HIP(hipMemcpy2DAsync(X, sizeof(double) * b, U, sizeof(double) * J, sizeof(double) * J, n,
+                            hipMemcpyDeviceToDevice, s));
+    if (b > J) {
+        k_random_cols<<<(unsigned)std::min<int64_t>(ceil_div((int64_t)n * (b - J), 256), 65536), 256, 0, s>>>(
+            X, n, b, J, b, seed);
+        TK_LAUNCHED();
+        TK_HIP(orthonormalise(X, n, b, J, b - J, L, seed + 1, s));
+    }
+    return hipSuccess;
+}
+
 hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta_dev, void *work,
                     const EigOpts &o, int *iters, int *noconv, hipStream_t s) {
     *iters = 0;

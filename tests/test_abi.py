@@ -131,3 +131,95 @@ def test_entry_points_reject_before_device_work():
     st = L.tucker_mp(ctypes.byref(c0), J2, ctypes.byref(o), 0x40, facs, hist, ctypes.byref(done), None, 0x50,
                      1 << 30, None)
     assert st == tk.TK_ERR_EMPTY
+
+
+def test_learn_param_count_and_queries():
+    L = tk.lib()
+    assert L.tucker_learn_param_count() == 64 * 128 + 128 + 128 * 128 + 128
+    out = ctypes.c_size_t(0)
+    assert L.tucker_learn_backward_workspace(1000, ctypes.byref(out)) == 0 and out.value > 0
+    assert L.tucker_learn_backward_workspace(-1, ctypes.byref(out)) == tk.TK_ERR_ARG
+    assert L.tucker_learn_align_workspace(500, 100, 50, ctypes.byref(out)) == 0 and out.value > 500 * 150 * 8
+    for rows, K, J in ((0, 3, 3), (10, 3, 0), (10, 129, 3), (10, 0, 3), (5, 3, 6)):
+        assert L.tucker_learn_align_workspace(rows, K, J, ctypes.byref(out)) == tk.TK_ERR_ARG
+    assert L.tucker_learn_test_width(5) == 10 and L.tucker_learn_test_width(100) == 128
+    assert L.tucker_learn_test_width(0) == tk.TK_ERR_ARG and L.tucker_learn_test_width(129) == tk.TK_ERR_ARG
+    c, d = _coo(nnz=100)
+    assert L.tucker_learn_sketch_workspace(ctypes.byref(c), ctypes.byref(out)) == 0 and out.value > 0
+
+
+def test_learn_entry_points_reject_before_device_work():
+    L = tk.lib()
+    c, d = _coo(nnz=5)
+    assert L.tucker_learn_sketch(ctypes.byref(c), 3, 1, 0x10, 0x20, 0x30, 1 << 30, None) == tk.TK_ERR_ARG
+    assert L.tucker_learn_sketch(ctypes.byref(c), 0, 1, None, 0x20, 0x30, 1 << 30, None) == tk.TK_ERR_ARG
+    assert L.tucker_learn_sketch(ctypes.byref(c), 0, 1, 0x10, 0x20, 0x30, 8, None) == tk.TK_ERR_WORKSPACE
+    c0, d0 = _coo(nnz=0)
+    assert L.tucker_learn_sketch(ctypes.byref(c0), 0, 1, 0x10, 0x20, 0x30, 1 << 30, None) == tk.TK_ERR_EMPTY
+    assert L.tucker_learn_forward(None, 0x10, 4, 0x20, 0x30, None, None) == tk.TK_ERR_ARG
+    assert L.tucker_learn_forward(0x10, 0x10, -1, 0x20, 0x30, None, None) == tk.TK_ERR_ARG
+    assert L.tucker_learn_backward(0x10, 0x10, 4, 0x20, None, 0x30, 0x40, 0x50, 1 << 30, None) == tk.TK_ERR_ARG
+    assert L.tucker_learn_backward(0x10, 0x10, 4, 0x20, 0x28, 0x30, 0x40, 0x50, 8, None) == tk.TK_ERR_WORKSPACE
+    loss = ctypes.c_double(0)
+    assert L.tucker_learn_align(0x10, 10, 6, 0x20, 11, 0.0, ctypes.byref(loss), None, 0x30, 1 << 30,
+                                None) == tk.TK_ERR_ARG
+    assert L.tucker_learn_align(0x10, 10, 6, 0x20, 3, -1.0, ctypes.byref(loss), None, 0x30, 1 << 30,
+                                None) == tk.TK_ERR_ARG
+    assert L.tucker_learn_align(0x10, 10, 6, 0x20, 3, 0.0, ctypes.byref(loss), None, 0x30, 8, None) == \
+        tk.TK_ERR_WORKSPACE
+    f = ctypes.c_float
+    assert L.tucker_learn_adam(0x10, 0x20, 0x30, 0x40, 10, f(1e-3), f(0.9), f(0.999), f(1e-8), 0, None) == \
+        tk.TK_ERR_ARG
+    assert L.tucker_learn_adam(0x10, 0x20, 0x30, 0x40, 10, f(1e-3), f(1.0), f(0.999), f(1e-8), 1, None) == \
+        tk.TK_ERR_ARG
+
+
+def test_learned_init_requires_a_model():
+    c, d = _coo(nnz=10)
+    o = tk.default_opts()
+    o.init = tk.INIT_LEARNED
+    st, _ = _ws(c, (3, 3, 3), o)
+    assert st == tk.TK_ERR_ARG
+    o.model = 0x1000
+    st, b = _ws(c, (3, 3, 3), o)
+    assert st == 0
+    o.init = tk.INIT_HOSVD
+    st, b0 = _ws(c, (3, 3, 3), o)
+    assert st == 0 and b > b0  # the learned start's buffers
+
+
+def test_batched_rejects_bad_arguments_on_host():
+    L = tk.lib()
+    c1, d1 = _coo(nnz=10)
+    c2, d2 = _coo(dims=(12, 11, 10), nnz=20)
+    arr = (tk.tk_coo * 2)(c1, c2)
+    J = (ctypes.c_int32 * 6)(3, 3, 3, 4, 4, 4)
+    o = tk.default_opts()
+    out = ctypes.c_size_t(0)
+    assert L.tucker_batched_workspace_bytes(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), ctypes.byref(out)) == 0
+    b2 = _ws(c2, (4, 4, 4), o)[1]
+    assert out.value == max(_ws(c1, (3, 3, 3), o)[1], b2)
+    assert L.tucker_batched_workspace_bytes(tk.ALGO_FIT, 2, arr, J, ctypes.byref(o), ctypes.byref(out)) == \
+        tk.TK_ERR_ARG
+    assert L.tucker_batched_workspace_bytes(tk.ALGO_MP, 0, arr, J, ctypes.byref(o), ctypes.byref(out)) == \
+        tk.TK_ERR_ARG
+    Jbad = (ctypes.c_int32 * 6)(3, 3, 3, 4, 40, 4)
+    assert L.tucker_batched_workspace_bytes(tk.ALGO_MP, 2, arr, Jbad, ctypes.byref(o), ctypes.byref(out)) == \
+        tk.TK_ERR_ARG
+    vp = ctypes.c_void_p
+    cores = (vp * 2)(0x10, 0x20)
+    facs = (vp * 6)(*[0x30] * 6)
+    hist = (ctypes.c_double * 100)()
+    done = (ctypes.c_int32 * 2)()
+    stat = (ctypes.c_int32 * 2)()
+    ws = (vp * 2)(0x40, 0x50)
+    st = (vp * 2)(None, None)
+    for n in (0, 65):
+        assert L.tucker_batched(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), cores, facs, hist, done, stat, None, n, ws,
+                                1 << 30, st) == tk.TK_ERR_ARG
+    assert L.tucker_batched(tk.ALGO_MP, 2, arr, Jbad, ctypes.byref(o), cores, facs, hist, done, stat, None, 2, ws,
+                            1 << 30, st) == tk.TK_ERR_ARG
+    assert L.tucker_batched(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), cores, facs, hist, done, stat, None, 2, ws,
+                            16, st) == tk.TK_ERR_WORKSPACE
+    assert L.tucker_batched(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), None, facs, hist, done, stat, None, 2, ws,
+                            1 << 30, st) == tk.TK_ERR_ARG

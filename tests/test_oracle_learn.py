@@ -113,44 +113,72 @@ def _orth(rng, n, J):
 
 def test_align_loss_values_and_invariance():
     rng = np.random.default_rng(2)
-    n, J = 40, 6
+    n, J, K = 40, 6, 9
     A = _orth(rng, n, J)
-    M = rng.standard_normal((J, J)) + 3 * np.eye(J)
-    R = np.concatenate([A @ M, rng.standard_normal((n, 3))], axis=1)
-    assert abs(L.align_loss(R, J, A, 0.0)[0]) < 1e-12          # same subspace
-    Rp = np.concatenate([_orth(rng, n, J), np.zeros((n, 1))], axis=1)
-    l1 = L.align_loss(Rp, J, A, 0.0)[0]
+    M = rng.standard_normal((K, K)) + 3 * np.eye(K)
+    # span(Rk) contains span(A): loss 0
+    Rk = np.concatenate([A, rng.standard_normal((n, K - J))], axis=1) @ M
+    R = np.concatenate([Rk, rng.standard_normal((n, 3))], axis=1)
+    assert abs(L.align_loss(R, K, A, 0.0)[0]) < 1e-12
+    Rp = _orth(rng, n, K)
+    l1 = L.align_loss(Rp, K, A, 0.0)[0]
     assert 0.0 <= l1 <= 1.0
-    # column mixing of Rj leaves the loss unchanged
-    l2 = L.align_loss(np.concatenate([Rp[:, :J] @ M, Rp[:, J:]], axis=1), J, A, 0.0)[0]
-    assert abs(l1 - l2) < 1e-12
+    # column mixing of Rk leaves the loss unchanged
+    assert abs(L.align_loss(Rp @ M, K, A, 0.0)[0] - l1) < 1e-12
+    # mean squared sine of the principal angles (textbook definition via SVD)
+    s = np.linalg.svd(A.T @ Rp, compute_uv=False)
+    assert abs(l1 - (1.0 - np.sum(s ** 2) / J)) < 1e-12
     # orthogonal complement: loss 1
-    Q = np.linalg.qr(np.concatenate([A, rng.standard_normal((n, J))], axis=1))[0][:, J:]
-    assert abs(L.align_loss(Q, J, A, 0.0)[0] - 1.0) < 1e-12
+    Q = np.linalg.qr(np.concatenate([A, rng.standard_normal((n, K))], axis=1))[0][:, J:]
+    assert abs(L.align_loss(Q, K, A, 0.0)[0] - 1.0) < 1e-12
 
 
 def test_align_loss_gradient_against_central_differences():
     rng = np.random.default_rng(4)
-    n, J, W = 30, 5, 8
+    n, J, K, W = 30, 5, 7, 10
     A = _orth(rng, n, J)
     R = rng.standard_normal((n, W))
     lam = 1e-3
-    Lv, dR = L.align_loss(R, J, A, lam)
+    Lv, dR = L.align_loss(R, K, A, lam)
     h = 1e-6
     for _ in range(40):
         i, c = rng.integers(n), rng.integers(W)
         E = np.zeros_like(R)
         E[i, c] = h
-        fd = (L.align_loss(R + E, J, A, lam)[0] - L.align_loss(R - E, J, A, lam)[0]) / (2 * h)
+        fd = (L.align_loss(R + E, K, A, lam)[0] - L.align_loss(R - E, K, A, lam)[0]) / (2 * h)
         assert abs(fd - dR[i, c]) <= 1e-7 * max(1.0, abs(fd)), (i, c, fd, dR[i, c])
-    assert np.all(dR[:, J:] == 0)
+    assert np.all(dR[:, K:] == 0)
 
 
-def test_start_factor_is_orthonormal_basis_of_leading_columns():
+def test_start_factor_is_rayleigh_ritz_on_the_test_span():
     rng = np.random.default_rng(6)
-    R = rng.standard_normal((50, 12))
-    U = L.start_factor(R, 7)
-    assert np.abs(U.T @ U - np.eye(7)).max() < 1e-12
-    # span(U) = span(R[:, :7])
-    P = U @ U.T
-    assert np.abs(P @ R[:, :7] - R[:, :7]).max() < 1e-10
+    n, J = 60, 5
+    K = L.test_width(J)
+    assert K == 10 and L.test_width(100) == 128
+    Y = rng.standard_normal((n, 3 * n))
+    H = Y @ Y.T
+    R = rng.standard_normal((n, 16))
+    U, th, g = L.start_factor(R, H, J)
+    assert np.abs(U.T @ U - np.eye(J)).max() < 1e-12
+    P = np.linalg.qr(R[:, :K])[0]
+    assert np.abs(P @ (P.T @ U) - U).max() < 1e-10            # inside span(R[:, :K])
+    np.testing.assert_allclose(np.diag(U.T @ H @ U), th, rtol=1e-10)
+    # the best J-dimensional subspace of H within the span (Courant-Fischer)
+    w = np.linalg.eigvalsh(P.T @ H @ P)[::-1][:J]
+    np.testing.assert_allclose(th, w, rtol=1e-10)
+    # when the span contains H's leading eigenvectors, they are recovered
+    E = np.linalg.eigh(H)[1][:, ::-1][:, :J]
+    R2 = np.concatenate([E, rng.standard_normal((n, K - J))], axis=1) @ rng.standard_normal((K, K))
+    U2 = L.start_factor(R2, H, J)[0]
+    assert np.abs(U2 @ U2.T - E @ E.T).max() < 1e-9
+
+
+def test_bf16_round_values():
+    # exactly representable values stay, ties go to the even significand
+    x = np.array([1.0, -2.5, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -9, 65504.0, 0.0], dtype=np.float32)
+    want = [1.0, -2.5, 1.0, 1.0 + 4 * 2.0 ** -8, 1.0, 65536.0, 0.0]
+    np.testing.assert_array_equal(L.bf16_round(x), want)
+    # relative rounding error at most 2^-8 (half a unit in the 8-bit significand)
+    r = np.random.default_rng(0).standard_normal(10000).astype(np.float32)
+    rel = np.abs(L.bf16_round(r) - r) / np.abs(r)
+    assert rel.max() <= 2.0 ** -8 * (1 + 1e-6)
