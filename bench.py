@@ -24,6 +24,7 @@ import hashlib
 import json
 import os
 import statistics
+import subprocess
 import sys
 import time
 
@@ -107,6 +108,41 @@ def learned_model(tk, dev):
     return params, info
 
 
+def learned_leg(args):
+    """Time-to-fit of the mixed run started from the learned start (the
+    network trained first, not timed), printed as one JSON line."""
+    import numpy as np
+    import torch
+    import paper_0711_2023_amd as tk
+    import synth
+    tk.lib()
+    dev = torch.device("cuda:0")
+    w = synth.WORKLOADS[args.workload]
+    dims, J, nnz = tuple(w["dims"]), tuple(w["core"]), int(w["nnz"])
+    idx, vals, dims = synth.uniform_sparse(dims, nnz, w["seed"])
+    di = torch.from_numpy(idx.astype(np.int32)).to(dev)
+    dv = torch.from_numpy(vals).to(dev)
+    fn = tk.mp if args.algo == "mp" else tk.hooi
+    log("learned leg: training")
+    model, info = learned_model(tk, dev)
+    log(f"learned leg: trained {info}")
+    runs = []
+    for k in range(3):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = fn(di, dv, dims, J, precision="mixed", max_iters=50, tol=1e-4, init=tk.INIT_LEARNED, model=model)
+        torch.cuda.synchronize()
+        runs.append((time.perf_counter() - t1, r))
+        log(f"learned leg: run {k} {1000 * runs[-1][0]:.1f} ms, {r.iters} sweeps, fit {r.fits[-1]:.6e}")
+    runs.sort(key=lambda x: x[0])
+    tw, r = runs[1]
+    print(json.dumps({"wall_ms": round(1000 * tw, 2), "sweeps": r.iters, "fit": r.fits[-1],
+                      "prep_excluded_ms": round(r.stats["init_ms"] + r.stats["sweeps_ms"], 2),
+                      "init_ms": round(r.stats["init_ms"], 2), "init_fallbacks": r.stats["init_fallbacks"],
+                      "training": info}), flush=True)
+    return 0
+
+
 def batched_leg(tk, dev, sweeps):
     """64 tensors (mode sizes U{200..800}, density 0.5 %, cores U{10..40},
     U(0,1) values), MP with BF16 Grams, `sweeps` sweeps each: one call on 8
@@ -174,9 +210,13 @@ def main():
     ap.add_argument("--no-ttf", action="store_true", help="skip the time-to-fit runs")
     ap.add_argument("--no-learn", action="store_true", help="skip the learned-start leg of the time-to-fit runs")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-tensor leg")
+    ap.add_argument("--learned-leg", action="store_true",
+                    help="internal: train the learned start, time the mixed run from it, print one JSON line")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
+    if args.learned_leg:
+        return learned_leg(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark measures one GPU; runs on several GPUs are not supported",
@@ -310,25 +350,21 @@ def main():
         ttf["speedup_plain_over_mixed"] = round(ttf["fp32"]["wall_ms"] / ttf["mixed"]["wall_ms"], 3)
         ttf["mixed_reaches_plain_fit"] = bool(ttf["mixed"]["fit"] >= ttf["fp32"]["fit"] - 1e-4)
         if not args.no_learn:
-            model, info = learned_model(tk, dev)
-            log(f"learned start trained: {info}")
-            runs = []
-            for _ in range(3):
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                r = fn(di, dv, dims, J, precision="mixed", max_iters=50, tol=1e-4, workspace=None,
-                       init=tk.INIT_LEARNED, model=model)
-                torch.cuda.synchronize()
-                runs.append((time.perf_counter() - t1, r))
-            runs.sort(key=lambda x: x[0])
-            tw, r = runs[1]
-            ttf["mixed_learned"] = {"wall_ms": round(1000 * tw, 2), "sweeps": r.iters, "fit": r.fits[-1],
-                                    "prep_excluded_ms": round(r.stats["init_ms"] + r.stats["sweeps_ms"], 2),
-                                    "init_ms": round(r.stats["init_ms"], 2),
-                                    "init_fallbacks": r.stats["init_fallbacks"], "training": info}
-            log(f"time-to-fit mixed + learned start: {ttf['mixed_learned']}")
-            ttf["speedup_plain_over_mixed_learned"] = round(ttf["fp32"]["wall_ms"] / (1000 * tw), 3)
-            ttf["mixed_learned_reaches_plain_fit"] = bool(r.fits[-1] >= ttf["fp32"]["fit"] - 1e-4)
+            # in a child process with a time limit, so that this line is
+            # printed whatever happens there
+            cmd = [sys.executable, os.path.abspath(__file__), "--learned-leg", "--workload", args.workload,
+                   "--algo", args.algo]
+            try:
+                # progress lines of the child go straight to this process's stderr
+                r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=300)
+                leg = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 and r.stdout.strip() \
+                    else {"error": f"exit {r.returncode}"}
+            except subprocess.TimeoutExpired:
+                leg = {"error": "timed out after 300 s"}
+            ttf["mixed_learned"] = leg
+            if "wall_ms" in leg:
+                ttf["speedup_plain_over_mixed_learned"] = round(ttf["fp32"]["wall_ms"] / leg["wall_ms"], 3)
+                ttf["mixed_learned_reaches_plain_fit"] = bool(leg["fit"] >= ttf["fp32"]["fit"] - 1e-4)
         line["time_to_fit"] = ttf
 
     if not args.no_batch:
@@ -341,4 +377,4 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    sys.exit(main() or 0)
