@@ -577,8 +577,10 @@ static int run_eig(Plan &p, int n, double *M, double *F, bool warm, const tk_opt
     EigOpts eo;
     eo.max_iters = o->eig_max_iters;
     // 0 = by precision: FP64 follows the oracle's exact eigensolver closely;
-    // FP32 / BF16 projections already limit the fit to about 1e-7 relative
-    eo.tol = o->eig_tol > 0 ? o->eig_tol : (p.prec == P64 ? 1e-12 : 1e-8);
+    // FP32 projections limit the Gram to about 1e-7 relative, BF16 ones (8
+    // significant bits) to about 1e-3, so the sum of the leading Ritz values
+    // is resolved to 1e-8 and 1e-6 of itself respectively
+    eo.tol = o->eig_tol > 0 ? o->eig_tol : (p.prec == P64 ? 1e-12 : (p.prec == P32 ? 1e-8 : 1e-6));
     eo.warm = warm && p.blk_ok[n];
     eo.seed = 0x5eed0000ull + (uint64_t)n;
     int it = 0, nc = 0;
@@ -640,7 +642,15 @@ static int learned_mode(Plan &p, int n, const tk_opts *o, double *F, double nx2,
     // against Jn/In of ||X||^2 (a random Jn-dimensional subspace's mean)
     double e = 0.0;
     for (double v : th) e += v;
-    const bool full_rank = std::isfinite(g[0]) && g[0] > 0.0 && g[K - 1] >= 1e-12 * g[0];
+    // squared Cholesky pivots of Rk^T Rk: their spread measures the rank
+    double gmax = 0.0, gmin = HUGE_VAL;
+    bool finite = true;
+    for (double v : g) {
+        finite = finite && std::isfinite(v);
+        gmax = std::max(gmax, v);
+        gmin = std::min(gmin, v);
+    }
+    const bool full_rank = finite && gmax > 0.0 && gmin >= 1e-12 * gmax;
     const bool better = std::isfinite(e) && e > (double)J / (double)In * nx2;
     return full_rank && better ? 1 : 0;
 }

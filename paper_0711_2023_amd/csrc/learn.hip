@@ -13,9 +13,8 @@
 //   network    R_i = rho_i (W2^T relu(W1^T F_i + b1) + b2), 64 -> 128 -> 128,
 //              weights rounded to BF16, FP32 accumulation.
 //   start      Rayleigh-Ritz of H_n = X_(n) X_(n)^T on the span of the first
-//              K = min(128, 2J) outputs: Q = Rk V diag(g)^-1/2 from the
-//              eigenpairs (g, V) of Rk^T Rk, then the J leading eigenpairs of
-//              Q^T H_n Q (FP64).
+//              K = min(128, 2J) outputs: Q from CholeskyQR of Rk (two passes),
+//              then the J leading eigenpairs of Q^T H_n Q (FP64).
 //   training   subspace-alignment loss that asks span(Rk) to contain
 //              converged factors A* (n x J), L = 1 - tr(B^T C^-1 B) / J,
 //              C = Rk^T Rk + lam I, B = Rk^T A*, its gradient (lam held
@@ -283,16 +282,6 @@ __global__ void k_align_value(const double *__restrict__ B, const double *__rest
     if (threadIdx.x == 0) loss[0] = 1.0 - red[0] / J;
 }
 
-// U[:, c] /= sqrt(theta[c]) (rows x J); columns with theta <= 0 become zero
-// (the caller rejects such a start).
-__global__ void k_scale_cols(double *__restrict__ U, int64_t rows, int J, const double *__restrict__ theta) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < rows * J; e += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(e % J);
-        const double t = theta[c];
-        U[e] = t > 0.0 ? U[e] / sqrt(t) : 0.0;
-    }
-}
-
 // ------------------------------------------------------------------ host side
 template <class TV>
 hipError_t learn_sketch(const int32_t *ptr, const int32_t *lidx, const TV *lval, int64_t In, int64_t Ilo, int n,
@@ -375,10 +364,19 @@ hipError_t learn_align(const float *R, int64_t rows, int K, const double *A, int
 int learn_test_width(int J) { return std::min(kOut, 2 * J); }
 
 // Start factor F (rows x J): Rayleigh-Ritz of H (rows x rows) on the span of
-// the first K = learn_test_width(J) network outputs. gC (K) receives the
-// eigenvalues of Rk^T Rk (the rank test), theta (J) the Ritz values.
+// the first K = learn_test_width(J) network outputs. The basis Q of that span
+// comes from two CholeskyQR passes (Rk^T Rk = U^T U, Q = Rk U^-1, then once
+// more on Q); gC (K) receives the diagonal of the first Cholesky factor
+// squared, whose spread is the rank test, theta (J) the Ritz values.
 // Scratch: Q and HQ (rows x K each), C and V (K x K), the eigensolver
 // workspace `eigw` (eig_work_bytes(K, K)) and skinny partial strips.
+__global__ void k_diag_sq(const double *__restrict__ U, int K, double *__restrict__ d) {
+    for (int i = threadIdx.x; i < K; i += blockDim.x) {
+        const double u = U[i * K + i];  // inverse factor: diagonal is 1 / r_ii
+        d[i] = u != 0.0 ? 1.0 / (u * u) : 0.0;
+    }
+}
+
 hipError_t learn_start(const float *R, int64_t rows, int J, const double *H, double *F, double *theta, double *gC,
                        double *Q, double *HQ, double *C, double *V, void *eigw, double *part, int64_t part_elems,
                        hipStream_t s) {
@@ -386,16 +384,24 @@ hipError_t learn_start(const float *R, int64_t rows, int J, const double *H, dou
     const unsigned g = (unsigned)std::min<int64_t>(ceil_div(rows * K, 256), 4096);
     k_take_cols<<<g, 256, 0, s>>>(R, rows, K, HQ);
     TK_LAUNCHED();
-    TK_HIP(skinny_gemm(K, K, (int)rows, HQ, K, true, HQ, K, C, K, 1.0, 0.0, nullptr, part, part_elems, s));
-    EigOpts eo;
-    int it = 0, nc = 0;
-    // K <= 128 is within the direct (Jacobi) size: V holds all K eigenvectors
-    TK_HIP(lead_eig(C, K, K, V, V, gC, eigw, eo, &it, &nc, s));
-    TK_HIP(skinny_gemm((int)rows, K, K, HQ, K, false, V, K, Q, K, 1.0, 0.0, nullptr, part, part_elems, s));
-    k_scale_cols<<<g, 256, 0, s>>>(Q, rows, K, gC);
-    TK_LAUNCHED();
+    double *src = HQ, *dst = Q;
+    for (int pass = 0; pass < 2; ++pass) {
+        TK_HIP(skinny_gemm(K, K, (int)rows, src, K, true, src, K, C, K, 1.0, 0.0, nullptr, part, part_elems, s));
+        TK_HIP(chol_inv_upper(C, K, pass == 0 ? 1e-14 : 0.0, V, s));
+        if (pass == 0) {
+            k_diag_sq<<<1, 128, 0, s>>>(V, K, gC);
+            TK_LAUNCHED();
+        }
+        TK_HIP(skinny_gemm((int)rows, K, K, src, K, false, V, K, dst, K, 1.0, 0.0, nullptr, part, part_elems, s));
+        std::swap(src, dst);
+    }
+    // src == HQ holds Q now: move it to Q, then H Q, Q^T H Q and its leading pairs
+    TK_HIP(hipMemcpyAsync(Q, HQ, sizeof(double) * rows * K, hipMemcpyDeviceToDevice, s));
     TK_HIP(skinny_gemm((int)rows, K, (int)rows, H, rows, false, Q, K, HQ, K, 1.0, 0.0, nullptr, part, part_elems, s));
     TK_HIP(skinny_gemm(K, K, (int)rows, Q, K, true, HQ, K, C, K, 1.0, 0.0, nullptr, part, part_elems, s));
+    EigOpts eo;
+    int it = 0, nc = 0;
+    // K <= 128 is within the direct (Jacobi) size
     TK_HIP(lead_eig(C, K, J, V, V, theta, eigw, eo, &it, &nc, s));
     TK_HIP(skinny_gemm((int)rows, J, K, Q, K, false, V, J, HQ, J, 1.0, 0.0, nullptr, part, part_elems, s));
     TK_HIP(canonical_cols(HQ, rows, J, J, F, s));
