@@ -256,8 +256,8 @@ static void carve(Plan &p, Arena &ar) {
         p.W2 = ar.take<double>(J0 * J1 * J2);
     }
     if (p.init == TK_INIT_LEARNED && p.algo != TK_ALGO_FIT) {
-        int64_t In = std::max(p.I[1], p.I[2]);
-        int Km = learn_test_width(std::max(p.J[1], p.J[2]));
+        int64_t In = std::max({p.I[0], p.I[1], p.I[2]});
+        int Km = learn_test_width(std::max({p.J[0], p.J[1], p.J[2]}));
         p.LF = ar.take<float>(In * 64);
         p.Lrho = ar.take<float>(In);
         p.LR = ar.take<float>(In * 128);
@@ -658,6 +658,17 @@ static int learned_mode(Plan &p, int n, const tk_opts *o, double *F, double nx2,
 static int init_factors(Plan &p, const tk_opts *o, double *const *factors, tk_stats *st, int *noconv, double nx2,
                         hipStream_t s) {
     const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
+    if (o->init == TK_INIT_LEARNED) {
+        // mode 1 has no start in HOOI and MP (Figures 3 and 7), but its first
+        // eigensolve can start from a learned block instead of a random one
+        // (factors[0] is only scratch here; the first sweep overwrites it)
+        const int ok = learned_mode(p, 0, o, factors[0], nx2, s);
+        if (ok < 0) return ok;
+        if (ok == 1) {
+            ST(eig_seed_block(p.Xblk[0], (int)p.I[0], p.J[0], factors[0], p.eigw, 0x1ea7ull, s));
+            p.blk_ok[0] = true;
+        }
+    }
     for (int n = 1; n < 3; ++n) {
         if (o->init == TK_INIT_GIVEN) {
             ST(refresh_copies(p, n, factors[n], s));
@@ -726,7 +737,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         ST(gram((int)p.I[0], gprec, 2, g0, p.Mg, p.gram_scratch, s));
         tm.end();
         tm.begin(kEig);
-        if ((st = run_eig(p, 0, p.Mg, A, t > 1, o, stats, &noconv, s))) return st;
+        if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
         tm.end();
         tm.begin(kProj);
         ST(project_m(p, 0, A, p.T[0], prec, s));
@@ -779,7 +790,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         ST(gram((int)p.I[0], gprec, 2, g0, p.Mg, p.gram_scratch, s));
         tm.end();
         tm.begin(kEig);
-        if ((st = run_eig(p, 0, p.Mg, A, false, o, stats, &noconv, s))) return st;
+        if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
         tm.end();
         const void *T2c = p.T[2];
         if (prec == PBF16) {
@@ -881,7 +892,7 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
             tm.end();
         }
         tm.begin(kEig);
-        if ((st = run_eig(p, 0, p.Mg, A, t > 1, o, stats, &noconv, s))) return st;
+        if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
         tm.end();
         if (last_only) {
             // max_iters == 0: A only, then the core below

@@ -163,6 +163,7 @@ struct EigOpts {
     int degree = 60;
     bool warm = false;
     uint64_t seed = 1234;
+    int direct_sweeps = 30;  // Jacobi sweep cap when the matrix is diagonalised directly
 };
 hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta_dev, void *work,
                     const EigOpts &o, int *iters, int *noconv, hipStream_t s);

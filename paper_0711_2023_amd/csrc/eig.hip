@@ -799,7 +799,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
     ar.base = reinterpret_cast<char *>(work);
     EigLayout L = eig_layout(ar, n, b);
     if (n <= kDirectMax) {
-        TK_HIP(jacobi(M, n, n, L.theta, L.V, L.Vg, s));
+        TK_HIP(jacobi(M, n, n, L.theta, L.V, L.Vg, s, o.direct_sweeps));
         k_extract<<<J, 256, 0, s>>>(L.V, n, n, J, F, nullptr);
         TK_LAUNCHED();
         TK_HIP(hipMemcpyAsync(theta_dev, L.theta, sizeof(double) * J, hipMemcpyDeviceToDevice, s));

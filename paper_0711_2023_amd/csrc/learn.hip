@@ -47,56 +47,61 @@ __device__ inline double unit53(uint64_t x) { return (double)(x >> 11) * 0x1.0p-
 
 // One workgroup per row i_n of the mode-n sketch; the slots of the ordering
 // (hi = n, lo = n+2) for this row are i_n * I_lo .. (i_n + 1) * I_lo - 1 and
-// the leaf coordinate is mode n+1.
+// the leaf coordinate is mode n+1. The 64 columns are formed in four passes
+// of 16 (8 Box-Muller pairs), which keeps the accumulators in few registers.
+constexpr int kSkPass = 16;
+
 template <class TV>
 __global__ void __launch_bounds__(256) k_sketch(const int32_t *__restrict__ ptr, const int32_t *__restrict__ lidx,
                                                 const TV *__restrict__ lval, int64_t Ilo, int64_t Ib, int n,
                                                 uint64_t seed, float *__restrict__ F, float *__restrict__ rho) {
     const int64_t row = blockIdx.x;
-    float acc[kIn];
-#pragma unroll
-    for (int c = 0; c < kIn; ++c) acc[c] = 0.f;
     const uint64_t mode_base = (uint64_t)n << 40;
-    for (int64_t sl = threadIdx.x; sl < Ilo; sl += blockDim.x) {
-        const int64_t slot = row * Ilo + sl;
-        const int32_t q0 = ptr[slot], q1 = ptr[slot + 1];
-        for (int32_t q = q0; q < q1; ++q) {
-            // a = n+1 is the leaf, b = n+2 is the slot's low coordinate
-            const uint64_t lin = (uint64_t)lidx[q] * (uint64_t)Ib + (uint64_t)sl;
-            const uint64_t base = (mode_base + lin) * 64;
-            const float v = (float)lval[q];
-#pragma unroll
-            for (int p = 0; p < kIn / 2; ++p) {
-                const float u1 = (float)(1.0 - unit53(sm64_at(seed, base + 2 * p)));
-                const float u2 = (float)unit53(sm64_at(seed, base + 2 * p + 1));
-                const float r = sqrtf(-2.0f * logf(u1));
-                float sn, cs;
-                sincosf(6.283185307179586f * u2, &sn, &cs);
-                acc[2 * p] += v * r * cs;
-                acc[2 * p + 1] += v * r * sn;
-            }
-        }
-    }
-    // fixed-order reduction: waves by shuffles, then the four waves in LDS
-    __shared__ float part[4][kIn];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int c = 0; c < kIn; ++c) {
-        float x = acc[c];
-        for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-        acc[c] = x;
-    }
-    if (lane == 0)
-#pragma unroll
-        for (int c = 0; c < kIn; ++c) part[wave][c] = acc[c];
-    __syncthreads();
+    __shared__ float part[4][kSkPass];
     __shared__ float srow[kIn];
     __shared__ float snorm;
-    if (threadIdx.x < kIn) {
-        const int c = threadIdx.x;
-        srow[c] = ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
+    for (int pass = 0; pass < kIn / kSkPass; ++pass) {
+        float acc[kSkPass];
+#pragma unroll
+        for (int c = 0; c < kSkPass; ++c) acc[c] = 0.f;
+        for (int64_t sl = threadIdx.x; sl < Ilo; sl += blockDim.x) {
+            const int64_t slot = row * Ilo + sl;
+            const int32_t q0 = ptr[slot], q1 = ptr[slot + 1];
+            for (int32_t q = q0; q < q1; ++q) {
+                // a = n+1 is the leaf, b = n+2 is the slot's low coordinate
+                const uint64_t lin = (uint64_t)lidx[q] * (uint64_t)Ib + (uint64_t)sl;
+                const uint64_t base = (mode_base + lin) * 64 + (uint64_t)pass * kSkPass;
+                const float v = (float)lval[q];
+#pragma unroll
+                for (int p = 0; p < kSkPass / 2; ++p) {
+                    const float u1 = (float)(1.0 - unit53(sm64_at(seed, base + 2 * p)));
+                    const float u2 = (float)unit53(sm64_at(seed, base + 2 * p + 1));
+                    const float r = sqrtf(-2.0f * logf(u1));
+                    float sn, cs;
+                    sincosf(6.283185307179586f * u2, &sn, &cs);
+                    acc[2 * p] += v * r * cs;
+                    acc[2 * p + 1] += v * r * sn;
+                }
+            }
+        }
+        // fixed-order reduction: waves by shuffles, then the four waves in LDS
+#pragma unroll
+        for (int c = 0; c < kSkPass; ++c) {
+            float x = acc[c];
+            for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+            acc[c] = x;
+        }
+        if (lane == 0)
+#pragma unroll
+            for (int c = 0; c < kSkPass; ++c) part[wave][c] = acc[c];
+        __syncthreads();
+        if (threadIdx.x < kSkPass) {
+            const int c = threadIdx.x;
+            srow[pass * kSkPass + c] = ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0;
         for (int c = 0; c < kIn; ++c) t += (double)srow[c] * srow[c];
@@ -400,6 +405,9 @@ hipError_t learn_start(const float *R, int64_t rows, int J, const double *H, dou
     TK_HIP(skinny_gemm((int)rows, K, (int)rows, H, rows, false, Q, K, HQ, K, 1.0, 0.0, nullptr, part, part_elems, s));
     TK_HIP(skinny_gemm(K, K, (int)rows, Q, K, true, HQ, K, C, K, 1.0, 0.0, nullptr, part, part_elems, s));
     EigOpts eo;
+    // a start needs the leading subspace only roughly (the first sweep's
+    // eigensolve refines it): three Jacobi sweeps of the K x K problem
+    eo.direct_sweeps = 3;
     int it = 0, nc = 0;
     // K <= 128 is within the direct (Jacobi) size
     TK_HIP(lead_eig(C, K, J, V, V, theta, eigw, eo, &it, &nc, s));
