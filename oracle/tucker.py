@@ -57,6 +57,7 @@ __all__ = [
     "tucker_dense",
     "project_dense",
     "core_from_slices",
+    "core_entry",
     "fit_slicewise",
     "fit_identity",
     "fit_dense",
@@ -334,6 +335,13 @@ def core_from_slices(X: SparseTensor3, A, B, C) -> np.ndarray:
     for i in range(I1):
         H[i] = np.ravel(B.T @ np.asarray(X.horizontal(i) @ C))
     return (A.T @ H).reshape(J1, J2, J3)
+
+
+def core_entry(X: SparseTensor3, A, B, C, p: int, q: int, r: int) -> float:
+    """One entry of G = X x_1 A^T x_2 B^T x_3 C^T (Section 3, n-mode product)
+    by its definition: the sum over the (summed) nonzeros x_ijk of
+    x_ijk A[i, p] B[j, q] C[k, r]."""
+    return float(np.sum(X.v * A[X.i, p] * B[X.j, q] * C[X.k, r]))
 
 
 def fit_slicewise(X: SparseTensor3, G, A, B, C) -> float:

@@ -57,9 +57,12 @@ __device__ inline int32_t wave_incl_scan(int32_t x) {
     return x;
 }
 
-// Exclusive block scan of one value per thread; returns the block total.
+// Exclusive block scan of one value per thread (blocks of up to 1024
+// threads, 16 waves); returns the block total. The total has a slot of its
+// own: with 16 waves every entry of wsum is a wave prefix.
 __device__ inline int32_t block_excl_scan(int32_t x, int32_t &excl) {
     __shared__ int32_t wsum[16];
+    __shared__ int32_t wtotal;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     int32_t inc = wave_incl_scan(x);
     if (lane == 63) wsum[w] = inc;
@@ -71,11 +74,11 @@ __device__ inline int32_t block_excl_scan(int32_t x, int32_t &excl) {
             wsum[i] = run;
             run += t;
         }
-        wsum[15] = run;
+        wtotal = run;
     }
     __syncthreads();
     excl = inc - x + wsum[w];
-    int32_t total = wsum[15];
+    int32_t total = wtotal;
     __syncthreads();
     return total;
 }

@@ -329,3 +329,14 @@ def test_paper_fits_250cube(golden_dir):
     band = g["band_percent_points"]
     for name, pct in g["fit_percent"].items():
         assert abs(100 * got[name] - pct) <= band, (name, 100 * got[name], pct)
+
+
+def test_core_entry_definition_matches_slicewise_core():
+    idx, vals, dims = synth.uniform_sparse((13, 11, 9), 300, 77)
+    idx2, vals2 = synth.with_duplicates(idx, vals, 40, 3)
+    X = O.SparseTensor3(idx2, vals2, dims)
+    rng = np.random.default_rng(5)
+    A, B, C = (np.linalg.qr(rng.standard_normal((d, j)))[0] for d, j in zip(dims, (4, 3, 5)))
+    G = O.core_from_slices(X, A, B, C)
+    for p, q, r in [(0, 0, 0), (3, 2, 4), (1, 2, 3), (2, 0, 1)]:
+        assert abs(O.core_entry(X, A, B, C, p, q, r) - G[p, q, r]) <= 1e-12 * max(1.0, np.abs(G).max())
