@@ -48,7 +48,8 @@ extern "C" {
 #define TK_OK              0
 #define TK_WARN_NOCONV     1  /* an eigensolve hit its iteration cap; outputs are valid */
 #define TK_ERR_ARG        -1  /* null pointer, order != 3, nnz < 0 or >= 2^31, In < 1,
-                                 Jn < 1 or Jn > In, max_iters < 0, bad precision/init */
+                                 Jn < 1 or Jn > In, max_iters < 0, bad precision/init,
+                                 a launch choice out of its range */
 #define TK_ERR_INDEX      -2  /* a coordinate outside [0, In) */
 #define TK_ERR_VALUE      -3  /* a NaN or infinite value */
 #define TK_ERR_EMPTY      -4  /* ||X|| = 0: the fit is undefined */
@@ -83,10 +84,28 @@ typedef struct tk_coo {
     const double  *vals;    /* [dev] nnz values */
 } tk_coo;
 
+/* Launch choices: 0 in a field = the built-in choice. The projection's
+   choices change no result bit (each output sums its nonzeros in the same
+   order whatever the run length). The Gram's choices set its split over the
+   summed dimension: results stay deterministic for a given choice but the
+   FP32 partial sums (BF16/FP32 Grams) round differently, within the same
+   bound. A tuner (paper_0711_2023_amd.autotune) measures them per tensor
+   shape and caches them as JSON. */
+typedef struct tk_tune {
+    int32_t proj_elems;       /* output elements per projection workgroup, at most
+                                 (1024 .. 65536; built-in 32768) */
+    int32_t proj_min_blocks;  /* projection workgroups wanted before runs of slots
+                                 grow (64 .. 16384; built-in 1536) */
+    int32_t gram_items;       /* Gram workgroups (tile pairs x K splits) wanted
+                                 (64 .. 16384; built-in 1024) */
+    int32_t gram_min_stages;  /* K stages per Gram workgroup, at least (1 .. 64;
+                                 built-in 4) */
+} tk_tune;
+
 /* Options; tucker_default_opts() fills the paper's values. */
 typedef struct tk_opts {
     int32_t precision;      /* TK_FP64 | TK_FP32 | TK_MIXED_BF16 */
-    int32_t init;           /* TK_INIT_HOSVD | TK_INIT_GIVEN */
+    int32_t init;           /* TK_INIT_HOSVD | TK_INIT_GIVEN | TK_INIT_LEARNED */
     int32_t max_iters;      /* sweep cap; the paper uses 50 */
     double  tol;            /* stop after sweep t when fit(t) - fit(t-1) < tol,
                                with fit(0) = 0 (paper: 1e-4); tol <= 0 runs
@@ -101,6 +120,7 @@ typedef struct tk_opts {
                                (tucker_learn_param_count() floats, layout in
                                tucker_learn.h); NULL otherwise */
     uint64_t seed;          /* TK_INIT_LEARNED: seed of the sketch generator */
+    const tk_tune *tune;    /* [host] launch choices, or NULL for the built-in ones */
 } tk_opts;
 
 /* Optional statistics (pass NULL to skip). Times in milliseconds. */
@@ -125,7 +145,8 @@ typedef struct tk_stats {
 } tk_stats;
 
 /* Fill *opt with: FP32, HO-SVD init, 50 sweeps, tol 1e-4, eig cap 400
-   products, eig tol 0 (by precision), no timing, no model, seed 0x5eed. */
+   products, eig tol 0 (by precision), no timing, no model, seed 0x5eed,
+   built-in launch choices. */
 void tucker_default_opts(tk_opts *opt);
 
 /* Bytes of device workspace that tucker_hooi (algo TK_ALGO_HOOI),

@@ -20,9 +20,10 @@ extern "C" {
 
 /* Bytes of ONE per-stream workspace of tucker_batched: the largest
    tucker_workspace_bytes over the `count` tensors (algo TK_ALGO_HOOI or
-   TK_ALGO_MP). Host only. */
+   TK_ALGO_MP), each with its own launch choices when `tunes` is given.
+   Host only. */
 int tucker_batched_workspace_bytes(int32_t algo, int32_t count, const tk_coo *X, const int32_t *core_dims,
-                                   const tk_opts *opt, size_t *bytes);
+                                   const tk_opts *opt, const tk_tune *tunes, size_t *bytes);
 
 /* Decompose tensors X[0..count) with core sizes core_dims[3t..3t+3).
      cores        [host] count [dev] pointers (J1*J2*J3 doubles each)
@@ -31,6 +32,8 @@ int tucker_batched_workspace_bytes(int32_t algo, int32_t count, const tk_coo *X,
      iters_done   [host] count
      status       [host] count: each tensor's own status code
      stats        [host] count tk_stats, or NULL
+     tunes        [host] count launch choices (tensor t uses tunes[t] in place
+                  of opt->tune), or NULL
      nstreams     1..64 streams; workspaces[s] (bytes each) serves streams[s]
    Returns TK_OK when every tensor succeeded, TK_WARN_NOCONV if one only
    warned, else the first (lowest index) error status; TK_ERR_ARG (before
@@ -39,8 +42,8 @@ int tucker_batched_workspace_bytes(int32_t algo, int32_t count, const tk_coo *X,
    thread is used by every worker. */
 int tucker_batched(int32_t algo, int32_t count, const tk_coo *X, const int32_t *core_dims, const tk_opts *opt,
                    double *const *cores, double *const *factors, double *fit_history, int32_t *iters_done,
-                   int32_t *status, tk_stats *stats, int32_t nstreams, void *const *workspaces,
-                   size_t workspace_bytes, void *const *streams);
+                   int32_t *status, tk_stats *stats, const tk_tune *tunes, int32_t nstreams,
+                   void *const *workspaces, size_t workspace_bytes, void *const *streams);
 
 #ifdef __cplusplus
 }

@@ -46,7 +46,30 @@ class tk_coo(ctypes.Structure):
 class tk_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("init", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("eig_max_iters", ctypes.c_int32), ("eig_tol", ctypes.c_double),
-                ("timing", ctypes.c_int32), ("model", ctypes.c_void_p), ("seed", ctypes.c_uint64)]
+                ("timing", ctypes.c_int32), ("model", ctypes.c_void_p), ("seed", ctypes.c_uint64),
+                ("tune", ctypes.c_void_p)]
+
+
+class tk_tune(ctypes.Structure):
+    """Launch choices of the projection and Gram kernels (0 = the default)."""
+    _fields_ = [("proj_elems", ctypes.c_int32), ("proj_min_blocks", ctypes.c_int32),
+                ("gram_items", ctypes.c_int32), ("gram_min_stages", ctypes.c_int32)]
+
+    def key(self):
+        return (self.proj_elems, self.proj_min_blocks, self.gram_items, self.gram_min_stages)
+
+
+def make_tune(tune) -> tk_tune:
+    """A tk_tune from a tk_tune, a dict of its fields or a 4-tuple."""
+    if isinstance(tune, tk_tune):
+        return tune
+    t = tk_tune()
+    if isinstance(tune, dict):
+        for k, v in tune.items():
+            setattr(t, k, int(v))
+    else:
+        t.proj_elems, t.proj_min_blocks, t.gram_items, t.gram_min_stages = (int(v) for v in tune)
+    return t
 
 
 class tk_stats(ctypes.Structure):
@@ -110,9 +133,9 @@ def lib():
                                          vp]
         L.tucker_learn_adam.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, i32, vp]
-        L.tucker_batched_workspace_bytes.argtypes = [i32, i32, P(tk_coo), P(i32), P(tk_opts), P(sz)]
+        L.tucker_batched_workspace_bytes.argtypes = [i32, i32, P(tk_coo), P(i32), P(tk_opts), P(tk_tune), P(sz)]
         L.tucker_batched.argtypes = [i32, i32, P(tk_coo), P(i32), P(tk_opts), P(vp), P(vp), P(ctypes.c_double),
-                                     P(i32), P(i32), P(tk_stats), i32, P(vp), sz, P(vp)]
+                                     P(i32), P(i32), P(tk_stats), P(tk_tune), i32, P(vp), sz, P(vp)]
         for name in SYMBOLS:
             if name.startswith("tucker_learn") or name.startswith("tucker_batched"):
                 getattr(L, name).restype = ctypes.c_int
@@ -137,12 +160,15 @@ def default_opts() -> tk_opts:
 
 
 def _opts(precision="fp32", init=INIT_HOSVD, max_iters=50, tol=1e-4, eig_max_iters=None, eig_tol=None,
-          timing=False, model=None, seed=None) -> tk_opts:
+          timing=False, model=None, seed=None, tune=None) -> tk_opts:
     o = default_opts()
     if model is not None:
         o.model = model.data_ptr()
     if seed is not None:
         o.seed = int(seed)
+    if tune is not None:
+        o._tune = make_tune(tune)  # kept alive with the options
+        o.tune = ctypes.addressof(o._tune)
     o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
     o.init = int(init)
     o.max_iters = int(max_iters)
@@ -201,15 +227,15 @@ def _stats_dict(s: tk_stats) -> dict:
 
 def _run(fn_name: str, algo: int, idx, vals, dims, core_dims, *, precision="fp32", init=INIT_HOSVD,
          max_iters=50, tol=1e-4, eig_max_iters=None, eig_tol=None, timing=False, factors=None, workspace=None,
-         stream=None, model=None, seed=None) -> Result:
+         stream=None, model=None, seed=None, tune=None) -> Result:
     """`model`: float32 tensor of learn_param_count() parameters on the GPU,
-    used with init=INIT_LEARNED."""
+    used with init=INIT_LEARNED. `tune`: launch choices (see make_tune)."""
     import torch
     dev = vals.device
     coo = _Coo(idx, vals, dims)
     if model is not None and (model.dtype != torch.float32 or not model.is_cuda or not model.is_contiguous()):
         raise TypeError("model must be a contiguous float32 tensor on the GPU")
-    o = _opts(precision, init, max_iters, tol, eig_max_iters, eig_tol, timing, model, seed)
+    o = _opts(precision, init, max_iters, tol, eig_max_iters, eig_tol, timing, model, seed, tune)
     J = [int(j) for j in core_dims]
     Jc = (ctypes.c_int32 * 3)(*J)
     need = ctypes.c_size_t(0)
@@ -369,11 +395,12 @@ def learn_adam(params, grad, m, v, step: int, lr=1e-3, beta1=0.9, beta2=0.999, e
 
 
 # ---------------------------------------------------------------- many tensors
-def batched(algo: int, tensors, cores, nstreams: int = 8, streams=None, workspaces=None, **opts):
+def batched(algo: int, tensors, cores, nstreams: int = 8, streams=None, workspaces=None, tunes=None, **opts):
     """Decompose many tensors in one call (ALGO_MP or ALGO_HOOI): `tensors` is
     a list of (idx, vals, dims) on the GPU, `cores` the core sizes. Returns
     (list of Result, overall status). The streams (default: `nstreams` new
-    ones) and per-stream workspaces can be passed in to reuse them."""
+    ones) and per-stream workspaces can be passed in to reuse them; `tunes`
+    (one launch choice per tensor, see make_tune) overrides the shared one."""
     import torch
     count = len(tensors)
     dev = tensors[0][1].device
@@ -382,8 +409,14 @@ def batched(algo: int, tensors, cores, nstreams: int = 8, streams=None, workspac
     J = [int(j) for core in cores for j in core]
     Jc = (ctypes.c_int32 * (3 * count))(*J)
     o = _opts(**opts)
+    tarr = None
+    if tunes is not None:
+        if len(tunes) != count:
+            raise ValueError("one tune per tensor")
+        tarr = (tk_tune * count)(*[make_tune(t) for t in tunes])
     need = ctypes.c_size_t(0)
-    _check(lib().tucker_batched_workspace_bytes(int(algo), count, carr, Jc, ctypes.byref(o), ctypes.byref(need)))
+    _check(lib().tucker_batched_workspace_bytes(int(algo), count, carr, Jc, ctypes.byref(o), tarr,
+                                                ctypes.byref(need)))
     if streams is None:
         streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)]
     nstreams = len(streams)
@@ -403,7 +436,7 @@ def batched(algo: int, tensors, cores, nstreams: int = 8, streams=None, workspac
     sptr = (ctypes.c_void_p * nstreams)(*[s.cuda_stream for s in streams])
     torch.cuda.synchronize(dev)  # inputs are complete before the workers start
     overall = lib().tucker_batched(int(algo), count, carr, Jc, ctypes.byref(o), cptr, fptr, hist, done, stat, sts,
-                                   nstreams, wptr, int(need.value), sptr)
+                                   tarr, nstreams, wptr, int(need.value), sptr)
     _check(overall)
     hm = int(o.max_iters)
     res = [Result(Gs[t], facs[t], [hist[hm * t + i] for i in range(done[t])], int(done[t]), _stats_dict(sts[t]),

@@ -94,6 +94,7 @@ static inline int lo_of(int m) { return (m + 1) % 3; }
 
 struct Plan {
     int algo, prec, init = TK_INIT_HOSVD;
+    Tune tune;
     int64_t I[3], nnz;
     int J[3];
     int64_t nslots[3];
@@ -219,11 +220,11 @@ static void carve(Plan &p, Arena &ar) {
                 int m1 = (n + 1) % 3, m2 = (n + 2) % 3;
                 K[0] = p.nslots[m1] / p.I[n] * p.ldT[m1];
                 K[1] = p.nslots[m2] / p.I[n] * p.ldT[m2];
-                gs = std::max(gs, gram_scratch_bytes((int)p.I[n], gprec, 2, K));
+                gs = std::max(gs, gram_scratch_bytes((int)p.I[n], gprec, 2, K, p.tune));
             } else {
                 K[0] = (int64_t)p.J[(n + 1) % 3] * p.J[(n + 2) % 3];
                 gprec = prec == P64 ? P64 : P32;
-                gs = std::max(gs, gram_scratch_bytes((int)p.I[n], gprec, 1, K));
+                gs = std::max(gs, gram_scratch_bytes((int)p.I[n], gprec, 1, K, p.tune));
             }
         }
         p.gram_scratch = ar.take<char>((int64_t)gs);
@@ -291,6 +292,13 @@ static int check_opts(const tk_opts *o, const tk_coo *X) {
     if (o->precision < 0 || o->precision > 2) return TK_ERR_ARG;
     if (o->init != TK_INIT_HOSVD && o->init != TK_INIT_GIVEN && o->init != TK_INIT_LEARNED) return TK_ERR_ARG;
     if (o->init == TK_INIT_LEARNED && !o->model) return TK_ERR_ARG;
+    if (o->tune) {
+        const tk_tune *t = o->tune;
+        auto in = [](int32_t v, int32_t lo, int32_t hi) { return v == 0 || (v >= lo && v <= hi); };
+        if (!in(t->proj_elems, 1024, 65536) || !in(t->proj_min_blocks, 64, 16384) ||
+            !in(t->gram_items, 64, 16384) || !in(t->gram_min_stages, 1, 64))
+            return TK_ERR_ARG;
+    }
     if (o->max_iters < 0 || o->eig_max_iters < 1) return TK_ERR_ARG;
     if (!(o->eig_tol >= 0.0) || std::isnan(o->tol)) return TK_ERR_ARG;
     if (o->init != TK_INIT_GIVEN)  // HO-SVD, or its fallback for the learned start
@@ -299,10 +307,23 @@ static int check_opts(const tk_opts *o, const tk_coo *X) {
     return TK_OK;
 }
 
-static void plan_init(Plan &p, int algo, int prec, const tk_coo *X, const int32_t *J, int init = TK_INIT_HOSVD) {
+static Tune tune_of(const tk_tune *t) {
+    Tune tn;
+    if (t) {
+        if (t->proj_elems) tn.proj_elems = t->proj_elems;
+        if (t->proj_min_blocks) tn.proj_min_blocks = t->proj_min_blocks;
+        if (t->gram_items) tn.gram_items = t->gram_items;
+        if (t->gram_min_stages) tn.gram_min_stages = t->gram_min_stages;
+    }
+    return tn;
+}
+
+static void plan_init(Plan &p, int algo, int prec, const tk_coo *X, const int32_t *J, int init = TK_INIT_HOSVD,
+                      const tk_tune *tune = nullptr) {
     p.algo = algo;
     p.prec = prec;
     p.init = init;
+    p.tune = tune_of(tune);
     p.nnz = X->nnz;
     for (int n = 0; n < 3; ++n) {
         p.I[n] = X->dims[n];
@@ -330,6 +351,7 @@ void tucker_default_opts(tk_opts *o) {
     o->timing = 0;
     o->model = nullptr;
     o->seed = 0x5eedull;
+    o->tune = nullptr;
 }
 
 const char *tucker_strerror(int st) {
@@ -358,7 +380,8 @@ int tucker_workspace_bytes(int32_t algo, const tk_coo *X, const int32_t *core_di
         prec = opt->precision;
     }
     Plan p;
-    plan_init(p, algo, prec, X, core_dims, algo != TK_ALGO_FIT ? opt->init : TK_INIT_HOSVD);
+    plan_init(p, algo, prec, X, core_dims, algo != TK_ALGO_FIT ? opt->init : TK_INIT_HOSVD,
+              algo != TK_ALGO_FIT ? opt->tune : nullptr);
     Arena ar;
     carve(p, ar);
     *bytes = ar.used + 256;
@@ -480,21 +503,21 @@ static hipError_t project_m(Plan &p, int m, const double *F64, void *T, int out_
     if (padded) {
         if (out_prec == P64)
             return project<double, double, double>(p.ptr[m], p.lidx[m], p.lval64[m], (const double *)p.Fp[m], ld, J,
-                                                   ld, p.nslots[m], (double *)T, s);
+                                                   ld, p.nslots[m], (double *)T, s, p.tune);
         if (out_prec == P32)
             return project<float, float, float>(p.ptr[m], p.lidx[m], p.lval32[m], (const float *)p.Fp[m], ld, J, ld,
-                                                p.nslots[m], (float *)T, s);
+                                                p.nslots[m], (float *)T, s, p.tune);
         return project<float, bf16, bf16>(p.ptr[m], p.lidx[m], p.lval32[m], (const bf16 *)p.Fp[m], ld, J, ld,
-                                          p.nslots[m], (bf16 *)T, s);
+                                          p.nslots[m], (bf16 *)T, s, p.tune);
     }
     if (out_prec == P64)
         return project<double, double, double>(p.ptr[m], p.lidx[m], p.lval64[m], F64, J, J, ld, p.nslots[m],
-                                               (double *)T, s);
+                                               (double *)T, s, p.tune);
     if (out_prec == P32)
         return project<float, float, float>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, J, ld, p.nslots[m],
-                                            (float *)T, s);
+                                            (float *)T, s, p.tune);
     return project<float, float, bf16>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, J, ld, p.nslots[m], (bf16 *)T,
-                                       s);
+                                       s, p.tune);
 }
 
 static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s) {
@@ -604,7 +627,7 @@ static int common_start(int algo, const tk_coo *X, const int32_t *J, const tk_op
     if (!core || !factors || !factors[0] || !factors[1] || !factors[2] || !iters_done) return TK_ERR_ARG;
     if (o->max_iters > 0 && !fit_history) return TK_ERR_ARG;
     if (X->nnz == 0) return TK_ERR_EMPTY;
-    plan_init(p, algo, o->precision, X, J, o->init);
+    plan_init(p, algo, o->precision, X, J, o->init, o->tune);
     Arena ar;
     carve(p, ar);
     if (!ws || wsb < ar.used + 256) return TK_ERR_WORKSPACE;
@@ -734,7 +757,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         // M1 (mode 0) from T(1) and T(2)
         GramTerm g0[2] = {term_of(p, 1, 0, p.T[1]), term_of(p, 2, 0, p.T[2])};
         tm.begin(kGram);
-        ST(gram((int)p.I[0], gprec, 2, g0, p.Mg, p.gram_scratch, s));
+        ST(gram((int)p.I[0], gprec, 2, g0, p.Mg, p.gram_scratch, s, p.tune));
         tm.end();
         tm.begin(kEig);
         if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
@@ -745,7 +768,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         // M2 (mode 1) from T(0) and T(2)
         GramTerm g1[2] = {term_of(p, 0, 1, p.T[0]), term_of(p, 2, 1, p.T[2])};
         tm.begin(kGram);
-        ST(gram((int)p.I[1], gprec, 2, g1, p.Mg, p.gram_scratch, s));
+        ST(gram((int)p.I[1], gprec, 2, g1, p.Mg, p.gram_scratch, s, p.tune));
         tm.end();
         tm.begin(kEig);
         if ((st = run_eig(p, 1, p.Mg, B, true, o, stats, &noconv, s))) return st;
@@ -756,7 +779,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         // M3 (mode 2) from T(0) and T(1)
         GramTerm g2[2] = {term_of(p, 0, 2, p.T[0]), term_of(p, 1, 2, p.T[1])};
         tm.begin(kGram);
-        ST(gram((int)p.I[2], gprec, 2, g2, p.Mg, p.gram_scratch, s));
+        ST(gram((int)p.I[2], gprec, 2, g2, p.Mg, p.gram_scratch, s, p.tune));
         tm.end();
         tm.begin(kEig);
         if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
@@ -787,7 +810,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         // no sweep: A from the start factors, then the core
         GramTerm g0[2] = {term_of(p, 1, 0, p.T[1]), term_of(p, 2, 0, p.T[2])};
         tm.begin(kGram);
-        ST(gram((int)p.I[0], gprec, 2, g0, p.Mg, p.gram_scratch, s));
+        ST(gram((int)p.I[0], gprec, 2, g0, p.Mg, p.gram_scratch, s, p.tune));
         tm.end();
         tm.begin(kEig);
         if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
@@ -888,7 +911,7 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
             g.nchunks = J1;
             g.s_chunk = I0 * J2;
             tm.begin(kGram);
-            ST(gram((int)I0, yprec, 1, &g, p.Mg, p.gram_scratch, s));
+            ST(gram((int)I0, yprec, 1, &g, p.Mg, p.gram_scratch, s, p.tune));
             tm.end();
         }
         tm.begin(kEig);
@@ -911,7 +934,7 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
             g.nchunks = 1;
             g.s_chunk = 0;
             tm.begin(kGram);
-            ST(gram((int)I1, yprec, 1, &g, p.Mg, p.gram_scratch, s));
+            ST(gram((int)I1, yprec, 1, &g, p.Mg, p.gram_scratch, s, p.tune));
             tm.end();
             tm.begin(kEig);
             if ((st = run_eig(p, 1, p.Mg, B, true, o, stats, &noconv, s))) return st;
@@ -937,7 +960,7 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
             g.nchunks = 1;
             g.s_chunk = 0;
             tm.begin(kGram);
-            ST(gram((int)I2, yprec, 1, &g, p.Mg, p.gram_scratch, s));
+            ST(gram((int)I2, yprec, 1, &g, p.Mg, p.gram_scratch, s, p.tune));
             tm.end();
             tm.begin(kEig);
             if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
@@ -1271,13 +1294,15 @@ extern "C" int tucker_learn_adam(float *params, const float *grad, float *m, flo
 #include <thread>
 
 extern "C" int tucker_batched_workspace_bytes(int32_t algo, int32_t count, const tk_coo *X, const int32_t *core_dims,
-                                              const tk_opts *opt, size_t *bytes) {
+                                              const tk_opts *opt, const tk_tune *tunes, size_t *bytes) {
     if (!bytes || !X || !core_dims || !opt || count < 1) return TK_ERR_ARG;
     if (algo != TK_ALGO_HOOI && algo != TK_ALGO_MP) return TK_ERR_ARG;
     size_t best = 0;
     for (int32_t t = 0; t < count; ++t) {
         size_t b = 0;
-        int st = tucker_workspace_bytes(algo, X + t, core_dims + 3 * t, opt, &b);
+        tk_opts ot = *opt;
+        if (tunes) ot.tune = tunes + t;
+        int st = tucker_workspace_bytes(algo, X + t, core_dims + 3 * t, &ot, &b);
         if (st) return st;
         best = std::max(best, b);
     }
@@ -1287,15 +1312,16 @@ extern "C" int tucker_batched_workspace_bytes(int32_t algo, int32_t count, const
 
 extern "C" int tucker_batched(int32_t algo, int32_t count, const tk_coo *X, const int32_t *core_dims,
                               const tk_opts *opt, double *const *cores, double *const *factors, double *fit_history,
-                              int32_t *iters_done, int32_t *status, tk_stats *stats, int32_t nstreams,
-                              void *const *workspaces, size_t workspace_bytes, void *const *streams) {
+                              int32_t *iters_done, int32_t *status, tk_stats *stats, const tk_tune *tunes,
+                              int32_t nstreams, void *const *workspaces, size_t workspace_bytes,
+                              void *const *streams) {
     if (!X || !core_dims || !opt || !cores || !factors || !iters_done || !status || !workspaces || !streams)
         return TK_ERR_ARG;
     if (count < 1 || nstreams < 1 || nstreams > 64) return TK_ERR_ARG;
     if (algo != TK_ALGO_HOOI && algo != TK_ALGO_MP) return TK_ERR_ARG;
     if (opt->max_iters > 0 && !fit_history) return TK_ERR_ARG;
     size_t need = 0;
-    int st = tucker_batched_workspace_bytes(algo, count, X, core_dims, opt, &need);
+    int st = tucker_batched_workspace_bytes(algo, count, X, core_dims, opt, tunes, &need);
     if (st) return st;
     for (int32_t s = 0; s < nstreams; ++s)
         if (!workspaces[s] || workspace_bytes < need) return TK_ERR_WORKSPACE;
@@ -1312,10 +1338,12 @@ extern "C" int tucker_batched(int32_t algo, int32_t count, const tk_coo *X, cons
             double *const *f = factors + 3 * (int64_t)t;
             double *h = hist ? fit_history + hist * t : nullptr;
             tk_stats *stt = stats ? stats + t : nullptr;
+            tk_opts ot = *opt;
+            if (tunes) ot.tune = tunes + t;
             status[t] = algo == TK_ALGO_MP
-                            ? tucker_mp(X + t, core_dims + 3 * t, opt, cores[t], f, h, iters_done + t, stt,
+                            ? tucker_mp(X + t, core_dims + 3 * t, &ot, cores[t], f, h, iters_done + t, stt,
                                         workspaces[s], workspace_bytes, streams[s])
-                            : tucker_hooi(X + t, core_dims + 3 * t, opt, cores[t], f, h, iters_done + t, stt,
+                            : tucker_hooi(X + t, core_dims + 3 * t, &ot, cores[t], f, h, iters_done + t, stt,
                                           workspaces[s], workspace_bytes, streams[s]);
         }
     };

@@ -103,6 +103,16 @@ hipError_t hosvd_gram(int n, const int64_t dims[3], const int32_t *ptr_n, const 
                       const double *lval_n, const int32_t *ptr_s, const int32_t *lidx_s, const double *lval_s,
                       double *H, hipStream_t s);
 
+// Launch choices that do not change results (run lengths of the projection,
+// split-K items of the Gram); the defaults are the built-in ones, a tuned
+// table can replace them per tensor shape.
+struct Tune {
+    int proj_elems = 32768;     // output elements per projection workgroup, at most
+    int proj_min_blocks = 1536; // projection workgroups wanted before runs grow
+    int gram_items = 1024;      // Gram workgroups (tile pairs x K splits) wanted
+    int gram_min_stages = 4;    // K stages per Gram workgroup, at least
+};
+
 // ---------------------------------------------------------------- project.hip
 // T[slot * ldT + r] = sum over the slot's entries of lval * F[lidx * ldF + r]
 // for r < J, zero for J <= r < ldT; slots = I_hi * I_lo, dense and
@@ -110,7 +120,7 @@ hipError_t hosvd_gram(int n, const int64_t dims[3], const int32_t *ptr_n, const 
 // (as pad_rows leaves them), whole 16-byte chunks are computed at once.
 template <class TV, class TF, class TO>
 hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int ldF, int J, int ldT,
-                   int64_t nslots, TO *T, hipStream_t s);
+                   int64_t nslots, TO *T, hipStream_t s, const Tune &tn = Tune());
 // out[i * ld + r] = in[i * J + r] for r < J, zero for J <= r < ld.
 template <class TO>
 hipError_t pad_rows(const double *in, int64_t rows, int J, int ld, TO *out, hipStream_t s);
@@ -127,8 +137,9 @@ struct GramTerm {
 };
 // M (FP64, n x n, symmetric, full) = sum over terms of T_t T_t^T.
 // Element type by precision: P64 double, P32 float, PBF16 bf16.
-size_t gram_scratch_bytes(int n, int prec, int nterms, const int64_t *K);
-hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, void *scratch, hipStream_t s);
+size_t gram_scratch_bytes(int n, int prec, int nterms, const int64_t *K, const Tune &tn = Tune());
+hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, void *scratch, hipStream_t s,
+                const Tune &tn = Tune());
 
 // General batched GEMM out[b][i][j] = alpha * sum_k A(i,k) B[b](k,j) (+ epilogue)
 // A(i,k) = a_trans ? A[k*lda + i] : A[i*lda + k]; B[b](k,j) = B[b*sB + k*ldb + j].

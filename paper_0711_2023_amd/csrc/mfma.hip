@@ -299,19 +299,19 @@ struct GramPlan {
     size_t acc_size;
 };
 
-static GramPlan gram_plan(int n, int prec, int nterms, const int64_t *K) {
+static GramPlan gram_plan(int n, int prec, int nterms, const int64_t *K, const Tune &tn) {
     GramPlan p;
     p.TBK = prec == P64 ? 64 : 128;
     p.KS = prec == P64 ? 16 : (prec == P32 ? 32 : 64);
     p.acc_size = prec == P64 ? 8 : 4;
     int nt = (int)ceil_div(n, p.TBK);
     p.npairs = nt * (nt + 1) / 2;
-    // about 1024 blocks in flight, at least 4 stages per block
-    int want = (int)std::max<int64_t>(1, ceil_div(1024, (int64_t)p.npairs * nterms));
+    // about tn.gram_items blocks in flight, at least tn.gram_min_stages stages per block
+    int want = (int)std::max<int64_t>(1, ceil_div(tn.gram_items, (int64_t)p.npairs * nterms));
     p.splits_total = 0;
     for (int t = 0; t < nterms; ++t) {
         int64_t Kt = K[t] > 0 ? K[t] : 1;
-        int64_t maxs = std::max<int64_t>(1, ceil_div(Kt, (int64_t)p.KS * 4));
+        int64_t maxs = std::max<int64_t>(1, ceil_div(Kt, (int64_t)p.KS * tn.gram_min_stages));
         int64_t s = std::min<int64_t>(want, maxs);
         int64_t kper = ceil_div(ceil_div(Kt, s), p.KS) * p.KS;
         s = ceil_div(Kt, kper);
@@ -322,8 +322,8 @@ static GramPlan gram_plan(int n, int prec, int nterms, const int64_t *K) {
     return p;
 }
 
-size_t gram_scratch_bytes(int n, int prec, int nterms, const int64_t *K) {
-    GramPlan p = gram_plan(n, prec, nterms, K);
+size_t gram_scratch_bytes(int n, int prec, int nterms, const int64_t *K, const Tune &tn) {
+    GramPlan p = gram_plan(n, prec, nterms, K, tn);
     return (size_t)p.npairs * p.splits_total * p.TBK * p.TBK * p.acc_size;
 }
 
@@ -337,10 +337,11 @@ static hipError_t launch_gram(const GramKArgs &g, bool vec, unsigned blocks, Acc
     return hipSuccess;
 }
 
-hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, void *scratch, hipStream_t s) {
+hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, void *scratch, hipStream_t s,
+                const Tune &tn) {
     int64_t K[2] = {0, 0};
     for (int t = 0; t < nterms; ++t) K[t] = terms[t].chunk_len * terms[t].nchunks;
-    GramPlan p = gram_plan(n, prec, nterms, K);
+    GramPlan p = gram_plan(n, prec, nterms, K, tn);
     GramKArgs g{};
     g.nterms = nterms;
     g.splits_total = p.splits_total;

@@ -28,8 +28,6 @@ template <>
 struct AccOf<double> { typedef double type; };
 
 constexpr int kProjThreads = 256;
-constexpr int kProjElems = 32768;  // output elements per workgroup, at most
-constexpr int kProjMinBlocks = 1536; // workgroups wanted (6 per compute unit) before runs grow
 constexpr int kProjU = 8;          // independent elements per thread per batch (general form)
 constexpr int kProjUV = 2;         // independent 16-byte chunks per thread per batch (vector form)
 
@@ -250,11 +248,11 @@ hipError_t pad_rows(const double *in, int64_t rows, int J, int ld, TO *out, hipS
 
 template <class TV, class TF, class TO>
 hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int ldF, int J, int ldT,
-                   int64_t nslots, TO *T, hipStream_t s) {
+                   int64_t nslots, TO *T, hipStream_t s, const Tune &tn) {
     if (nslots <= 0 || ldT <= 0) return hipSuccess;
     // runs of slots: large enough to amortise the staging, small enough that
     // the grid still fills the chip
-    int spw = (int)std::min<int64_t>(kProjElems / ldT, ceil_div(nslots, kProjMinBlocks));
+    int spw = (int)std::min<int64_t>(tn.proj_elems / ldT, ceil_div(nslots, tn.proj_min_blocks));
     if (spw < 1) spw = 1;
     if (spw > 4096) spw = 4096;
     // staged nonzeros: room for 4 per slot on average (at most 4096, so LDS
@@ -276,13 +274,13 @@ hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, cons
 }
 
 template hipError_t project<double, double, double>(const int32_t *, const int32_t *, const double *, const double *,
-                                                    int, int, int, int64_t, double *, hipStream_t);
+                                                    int, int, int, int64_t, double *, hipStream_t, const Tune &);
 template hipError_t project<float, float, float>(const int32_t *, const int32_t *, const float *, const float *, int,
-                                                 int, int, int64_t, float *, hipStream_t);
+                                                 int, int, int64_t, float *, hipStream_t, const Tune &);
 template hipError_t project<float, float, bf16>(const int32_t *, const int32_t *, const float *, const float *, int,
-                                                int, int, int64_t, bf16 *, hipStream_t);
+                                                int, int, int64_t, bf16 *, hipStream_t, const Tune &);
 template hipError_t project<float, bf16, bf16>(const int32_t *, const int32_t *, const float *, const bf16 *, int,
-                                               int, int, int64_t, bf16 *, hipStream_t);
+                                               int, int, int64_t, bf16 *, hipStream_t, const Tune &);
 template hipError_t pad_rows<double>(const double *, int64_t, int, int, double *, hipStream_t);
 template hipError_t pad_rows<bf16>(const double *, int64_t, int, int, bf16 *, hipStream_t);
 template hipError_t pad_rows<float>(const double *, int64_t, int, int, float *, hipStream_t);

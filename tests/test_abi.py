@@ -196,15 +196,21 @@ def test_batched_rejects_bad_arguments_on_host():
     J = (ctypes.c_int32 * 6)(3, 3, 3, 4, 4, 4)
     o = tk.default_opts()
     out = ctypes.c_size_t(0)
-    assert L.tucker_batched_workspace_bytes(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), ctypes.byref(out)) == 0
+    assert L.tucker_batched_workspace_bytes(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), None, ctypes.byref(out)) == 0
     b2 = _ws(c2, (4, 4, 4), o)[1]
     assert out.value == max(_ws(c1, (3, 3, 3), o)[1], b2)
-    assert L.tucker_batched_workspace_bytes(tk.ALGO_FIT, 2, arr, J, ctypes.byref(o), ctypes.byref(out)) == \
+    assert L.tucker_batched_workspace_bytes(tk.ALGO_FIT, 2, arr, J, ctypes.byref(o), None, ctypes.byref(out)) == \
         tk.TK_ERR_ARG
-    assert L.tucker_batched_workspace_bytes(tk.ALGO_MP, 0, arr, J, ctypes.byref(o), ctypes.byref(out)) == \
+    assert L.tucker_batched_workspace_bytes(tk.ALGO_MP, 0, arr, J, ctypes.byref(o), None, ctypes.byref(out)) == \
         tk.TK_ERR_ARG
     Jbad = (ctypes.c_int32 * 6)(3, 3, 3, 4, 40, 4)
-    assert L.tucker_batched_workspace_bytes(tk.ALGO_MP, 2, arr, Jbad, ctypes.byref(o), ctypes.byref(out)) == \
+    assert L.tucker_batched_workspace_bytes(tk.ALGO_MP, 2, arr, Jbad, ctypes.byref(o), None, ctypes.byref(out)) == \
+        tk.TK_ERR_ARG
+    # per-tensor launch choices: checked per tensor
+    tunes = (tk.tk_tune * 2)(tk.make_tune((4096, 256, 128, 2)), tk.make_tune((0, 0, 0, 0)))
+    assert L.tucker_batched_workspace_bytes(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), tunes, ctypes.byref(out)) == 0
+    tunes[1].gram_items = 5
+    assert L.tucker_batched_workspace_bytes(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), tunes, ctypes.byref(out)) == \
         tk.TK_ERR_ARG
     vp = ctypes.c_void_p
     cores = (vp * 2)(0x10, 0x20)
@@ -215,11 +221,61 @@ def test_batched_rejects_bad_arguments_on_host():
     ws = (vp * 2)(0x40, 0x50)
     st = (vp * 2)(None, None)
     for n in (0, 65):
-        assert L.tucker_batched(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), cores, facs, hist, done, stat, None, n, ws,
+        assert L.tucker_batched(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), cores, facs, hist, done, stat, None, None, n, ws,
                                 1 << 30, st) == tk.TK_ERR_ARG
-    assert L.tucker_batched(tk.ALGO_MP, 2, arr, Jbad, ctypes.byref(o), cores, facs, hist, done, stat, None, 2, ws,
+    assert L.tucker_batched(tk.ALGO_MP, 2, arr, Jbad, ctypes.byref(o), cores, facs, hist, done, stat, None, None,
+                            2, ws, 1 << 30, st) == tk.TK_ERR_ARG
+    assert L.tucker_batched(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), cores, facs, hist, done, stat, None, None, 2,
+                            ws, 16, st) == tk.TK_ERR_WORKSPACE
+    assert L.tucker_batched(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), None, facs, hist, done, stat, None, None, 2, ws,
                             1 << 30, st) == tk.TK_ERR_ARG
-    assert L.tucker_batched(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), cores, facs, hist, done, stat, None, 2, ws,
-                            16, st) == tk.TK_ERR_WORKSPACE
-    assert L.tucker_batched(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), None, facs, hist, done, stat, None, 2, ws,
-                            1 << 30, st) == tk.TK_ERR_ARG
+    assert L.tucker_batched(tk.ALGO_MP, 2, arr, J, ctypes.byref(o), cores, facs, hist, done, stat, None, tunes, 2,
+                            ws, 1 << 30, st) == tk.TK_ERR_ARG
+
+
+@pytest.mark.parametrize("field,bad,good", [("proj_elems", 512, 1024), ("proj_elems", 70000, 65536),
+                                            ("proj_min_blocks", 32, 64), ("proj_min_blocks", 20000, 16384),
+                                            ("gram_items", 63, 64), ("gram_items", 16385, 16384),
+                                            ("gram_min_stages", 65, 64), ("gram_min_stages", -1, 1)])
+def test_tune_ranges_checked_on_host(field, bad, good):
+    c, d = _coo()
+    for v, want in ((bad, tk.TK_ERR_ARG), (good, 0), (0, 0)):
+        o = tk._opts(tune={field: v})
+        st, b = _ws(c, (3, 3, 3), o)
+        assert st == want, (field, v, st)
+
+
+def test_tune_changes_no_workspace_rule():
+    """A launch choice may change the Gram's split scratch, never the
+    validation: every tune in range gives a positive workspace."""
+    c, d = _coo(dims=(300, 200, 100), nnz=5000)
+    for t in [(1024, 64, 64, 1), (65536, 16384, 16384, 64), (8192, 768, 512, 8)]:
+        st, b = _ws(c, (20, 10, 5), tk._opts(tune=t))
+        assert st == 0 and b > 0
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and field offsets of the option and statistics structs as a C
+    compiler lays them out, against the binding's ctypes mirrors."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"tk_opts": tk.tk_opts, "tk_stats": tk.tk_stats, "tk_tune": tk.tk_tune, "tk_coo": tk.tk_coo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tucker.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
