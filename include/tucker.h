@@ -111,9 +111,11 @@ typedef struct tk_opts {
                                with fit(0) = 0 (paper: 1e-4); tol <= 0 runs
                                exactly max_iters sweeps */
     int32_t eig_max_iters;  /* cap on filtered subspace iterations per eigensolve */
-    double  eig_tol;        /* relative change of the sum of the J leading Ritz values at
-                               which an eigensolve stops; 0 = by precision (1e-12 for
-                               FP64, 1e-8 for FP32, 1e-6 for mixed BF16) */
+    double  eig_tol;        /* relative accuracy of the sum of the J leading Ritz values
+                               at which an eigensolve stops (residual estimate, or
+                               change across a full-degree filter step); 0 = by
+                               precision (1e-12 for FP64, 1e-8 for FP32, 1e-6 for
+                               mixed BF16) */
     int32_t timing;         /* 1: record HIP events around the projection and
                                TTMc kernels and report their times in tk_stats */
     const float *model;     /* [dev] TK_INIT_LEARNED: the network parameters

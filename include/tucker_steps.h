@@ -27,9 +27,12 @@ int tucker_step_lead_eig_workspace(int32_t n, int32_t J, size_t *bytes);
                      each column positive
      theta    [dev]  J doubles (output): the eigenvalues (Ritz values)
      matvecs  [host] output: products with M used (1 for the direct solver)
-     tol      relative change of the sum of the J leading Ritz values at
-              which the iteration stops (used for n > 140; smaller
-              matrices are diagonalised directly)
+     tol      relative accuracy of the sum of the J leading Ritz values at
+              which the iteration stops: the residual estimate
+              sum_j r_j^2 / (theta_j - theta_b) (b = block width), or the
+              change of the sum across a full-degree filter step, at most
+              tol times the sum (used for n > 140; smaller matrices are
+              diagonalised directly)
      warm     nonzero: start from the block that the previous call with the
               same n, J and workspace left in the workspace (as the sweeps
               of HOOI and MP do); zero: pseudo-random start

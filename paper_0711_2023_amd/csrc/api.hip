@@ -136,6 +136,7 @@ struct Plan {
     int64_t Lpart_elems = 0;
     void *Leigw = nullptr;
     bool blk_ok[3] = {false, false, false};  // Xblk[n] holds a previous block
+    int sweep_solves[3] = {0, 0, 0};         // warm (sweep) eigensolves done per mode
 };
 
 static size_t elem_size(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
@@ -605,6 +606,12 @@ static int run_eig(Plan &p, int n, double *M, double *F, bool warm, const tk_opt
     // is resolved to 1e-8 and 1e-6 of itself respectively
     eo.tol = o->eig_tol > 0 ? o->eig_tol : (p.prec == P64 ? 1e-12 : (p.prec == P32 ? 1e-8 : 1e-6));
     eo.warm = warm && p.blk_ok[n];
+    // a block left by the previous sweep's solve of this mode is usually
+    // converged or nearly so: its filter starts at a low degree. Blocks from
+    // the start (HO-SVD of X_(n) X_(n)^T, or the learned start) belong to
+    // another matrix and get the full degree at once.
+    if (eo.warm && p.sweep_solves[n] == 0) eo.warm_degree = eo.degree;
+    if (warm) p.sweep_solves[n] += 1;
     eo.seed = 0x5eed0000ull + (uint64_t)n;
     int it = 0, nc = 0;
     ST(lead_eig(M, (int)p.I[n], p.J[n], p.Xblk[n], F, p.theta, p.eigw, eo, &it, &nc, s));

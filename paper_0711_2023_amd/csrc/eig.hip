@@ -15,8 +15,14 @@
 //   (mu = smallest Ritz value of the block) and amplifies the top;
 //   the filtered columns are re-orthogonalised against the locked ones and
 //   orthonormalised by shifted CholeskyQR (one shifted pass, one plain).
-// It stops when the sum of the J leading Ritz values changes by at most
-// tol (relative) between Rayleigh-Ritz steps, or when all J are locked.
+// It stops when a residual estimate of the error of the sum of the J
+// leading Ritz values, sum_j r_j^2 / (theta_j - mu) (the quadratic bound of
+// a Ritz value by its residual r_j and its distance to the rest of the
+// block's spectrum), is at most tol times the sum; when that sum changes by
+// at most tol (relative) across a filter of full degree; or when all J are
+// locked. A warm start (the previous sweep's factors) is often converged on
+// arrival, so its filter starts at a low degree that doubles per step up to
+// the full one.
 #include "common.h"
 
 #include <algorithm>
@@ -818,6 +824,8 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
     std::vector<double> h(2 * (size_t)b), thL;
     double Eold = -1.0;
     int matvecs = 0, Lk = 0;
+    int deg_cap = o.warm ? std::max(1, std::min(o.warm_degree, o.degree)) : o.degree;
+    bool full_step = false;  // the last filter had the full degree
     double *Xc = X;
     double *Md = M;  // deflated in place
     std::vector<double> tha;
@@ -854,7 +862,17 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
         for (double v : thL) E += v;
         for (int j = 0; j < J - Lk; ++j) E += tha[j];
         const double thmax = std::max(thL.empty() ? 0.0 : thL[0], tha[0]);
-        bool conv = (Eold >= 0 && std::fabs(E - Eold) <= o.tol * std::fabs(E)) || !(thmax > 0.0);
+        // residual estimate of the error of E (needs a gap below every
+        // wanted Ritz value inside the block)
+        double errE = 0.0;
+        bool est_ok = w > J - Lk;
+        for (int j = 0; est_ok && j < J - Lk; ++j) {
+            const double gap = tha[j] - tha[w - 1];
+            if (!(gap > 1e-12 * thmax)) est_ok = false;
+            else errE += res[j] * res[j] / gap;
+        }
+        bool conv = (est_ok && errE <= o.tol * std::fabs(E)) ||
+                    (full_step && Eold >= 0 && std::fabs(E - Eold) <= o.tol * std::fabs(E)) || !(thmax > 0.0);
         // newly converged leading pairs
         int newl = 0;
         const double lock_tol = 1e-11 * std::max(thmax, 1e-300);
@@ -905,6 +923,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
             TK_HIP(dgemm(n, wa, n, Md, n, false, Xf, b, Ya, b, 1.0 / std::max(top, 1e-300), 0.0, nullptr, 0.0,
                          nullptr, L.split, L.split_elems, s));
             ++matvecs;
+            full_step = true;
         } else {
             const double c = 0.5 * mu, e = 0.5 * mu, t = (top - c) / e;
             // The filter scales the block's top by T_d(t) relative to its
@@ -912,7 +931,8 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
             // by the same factor. Keeping T_d(t) <= 1e8 keeps the filtered
             // block well within what shifted CholeskyQR orthonormalises.
             const int dmax = (int)std::floor(std::acosh(1e8) / std::acosh(std::max(t, 1.0 + 1e-12)));
-            const int degree = std::max(1, std::min(o.degree, dmax));
+            const int degree = std::max(1, std::min(deg_cap, dmax));
+            full_step = deg_cap >= o.degree || degree == dmax;
             double sig = 1.0 / t;
             TK_HIP(dgemm(n, wa, n, Md, n, false, Xf, b, Ya, b, sig / e, -c * sig / e, Xf, 0.0, nullptr, L.split,
                          L.split_elems, s));
@@ -935,6 +955,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
                 sig = sig2;
             }
         }
+        deg_cap = std::min(o.degree, 2 * deg_cap);
         // orthonormalise against the locked vectors and among themselves
         TK_HIP(hipMemcpy2DAsync(Xf, sizeof(double) * b, cur, sizeof(double) * b, sizeof(double) * wa, n,
                                 hipMemcpyDeviceToDevice, s));
