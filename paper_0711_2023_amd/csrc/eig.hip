@@ -834,9 +834,13 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
     // inexact only among nearly tied Ritz pairs, and locking still requires
     // a true residual below its threshold); the step after the energy test
     // has passed diagonalises fully and provides the output.
+    // The full diagonalisation only needs the J - Lk leading active columns:
+    // the stop rule has judged exactly those (their residuals), and the
+    // extra columns of the block serve the filter alone.
     bool final_rr = false;
     for (int outer = 0;; ++outer) {
-        const int w = b - Lk;
+        if (final_rr && J == Lk) break;  // every wanted pair is locked
+        const int w = final_rr ? J - Lk : b - Lk;
         double *Xa = Xc + Lk, *Wa = L.W + Lk;
         // Rayleigh-Ritz on the active columns
         TK_HIP(dgemm(n, w, n, Md, n, false, Xa, b, Wa, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
