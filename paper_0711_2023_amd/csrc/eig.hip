@@ -193,6 +193,153 @@ __global__ void __launch_bounds__(1024) k_chol_inv(const double *S, int lds, int
     }
 }
 
+// Blocked form of the same factor and inverse for w <= kCholBlkMax, on the
+// matrix padded to W = 16 * ceil(w / 16) with an identity block (which stays
+// decoupled). Each step factors a 16 x 16 diagonal block in the registers of
+// one wave (lane i holds row i; column entries of other rows are fetched
+// with readlane, so the serial column chain has no LDS round trips) and
+// inverts it there, then the panel below (times the block inverse, transposed)
+// and the trailing lower tiles (L_ib L_jb^T subtracted) are FP64 MFMA
+// products. The inverse of L is completed by block forward substitution,
+// Li_ib,jb = -Li_ib,ib sum_kb L_ib,kb Li_kb,jb, one block row at a time, and
+// R^-1 = (L^-1)^T is written out. Same pivot clamping as k_chol_inv.
+constexpr int kCholBlkMax = 96;
+constexpr int kCholBlkThreads = 256;
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// x of lane l (l uniform across the wave)
+__device__ inline double read_lane(double x, int l) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)v, l);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__global__ void __launch_bounds__(kCholBlkThreads) k_chol_inv_blk(const double *S, int lds, int w, double shift,
+                                                                  double *Rinv) {
+    extern __shared__ double sm[];
+    const int W = (w + 15) & ~15, NB = W / 16;
+    double *A = sm;                   // W x W: lower factor L, built in place
+    double *Li = sm + (size_t)W * W;  // W x W: L^-1 (lower)
+    double *scr = Li + (size_t)W * W; // one 16 x 16 tile per wave
+    __shared__ double tr;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nw = kCholBlkThreads / 64;
+    const int l16 = lane & 15, l4 = lane >> 4;
+    for (int t = tid; t < W * W; t += kCholBlkThreads) {
+        const int i = t / W, j = t - i * W;
+        A[t] = (i < w && j < w) ? 0.5 * (S[(int64_t)i * lds + j] + S[(int64_t)j * lds + i]) : (i == j ? 1.0 : 0.0);
+        Li[t] = 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double sum = 0;
+        for (int i = 0; i < w; ++i) sum += A[i * W + i];
+        tr = sum;
+    }
+    __syncthreads();
+    const double add = shift * tr;
+    for (int i = tid; i < w; i += kCholBlkThreads) A[i * W + i] += add;
+    __syncthreads();
+    const double tiny = 1e-300 + 1e-30 * (tr > 0 ? tr : 1.0);
+    for (int kb = 0; kb < NB; ++kb) {
+        const int o = kb * 16;
+        if (wid == 0) {
+            double r[16], li[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) r[j] = lane < 16 ? A[(o + lane) * W + o + j] : 0.0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const double d = fmax(read_lane(r[c], c), tiny);
+                const double l = sqrt(d), rl = 1.0 / l;
+                r[c] = lane > c ? r[c] * rl : (lane == c ? l : r[c]);
+#pragma unroll
+                for (int j = c + 1; j < 16; ++j) {
+                    const double ljc = read_lane(r[c], j);
+                    if (lane >= j) r[j] -= r[c] * ljc;
+                }
+            }
+            // lane j builds column j of the block's inverse
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                double acc = lane == i ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = 0; k < i; ++k) acc -= read_lane(r[k], i) * li[k];
+                li[i] = lane <= i ? acc / read_lane(r[i], i) : 0.0;
+            }
+            if (lane < 16) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    if (j <= lane) A[(o + lane) * W + o + j] = r[j];
+                    Li[(o + j) * W + o + lane] = li[j];
+                }
+            }
+        }
+        __syncthreads();
+        // panel: L_ib,kb = A_ib,kb Li_kb,kb^T
+        for (int ib = kb + 1 + wid; ib < NB; ib += nw) {
+            doublex4 acc = {0, 0, 0, 0};
+            for (int kc = 0; kc < 4; ++kc) {
+                const double a = A[(ib * 16 + l16) * W + o + kc * 4 + l4];
+                const double b = Li[(o + l16) * W + o + kc * 4 + l4];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+            for (int v = 0; v < 4; ++v) A[(ib * 16 + 4 * v + l4) * W + o + l16] = acc[v];
+        }
+        __syncthreads();
+        // trailing lower tiles: A_ib,jb -= L_ib,kb L_jb,kb^T (kb < jb <= ib)
+        const int nt = NB - kb - 1;
+        for (int t = wid; t < nt * (nt + 1) / 2; t += nw) {
+            int x = t, rr = 0;
+            while (x > rr) {
+                x -= rr + 1;
+                ++rr;
+            }
+            const int ib = kb + 1 + rr, jb = kb + 1 + x;
+            doublex4 acc;
+            for (int v = 0; v < 4; ++v) acc[v] = A[(ib * 16 + 4 * v + l4) * W + jb * 16 + l16];
+            for (int kc = 0; kc < 4; ++kc) {
+                const double a = A[(ib * 16 + l16) * W + o + kc * 4 + l4];
+                const double b = A[(jb * 16 + l16) * W + o + kc * 4 + l4];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-a, b, acc, 0, 0, 0);
+            }
+            for (int v = 0; v < 4; ++v) A[(ib * 16 + 4 * v + l4) * W + jb * 16 + l16] = acc[v];
+        }
+        __syncthreads();
+    }
+    double *sc = scr + wid * 256;
+    for (int ib = 1; ib < NB; ++ib) {
+        for (int jb = wid; jb < ib; jb += nw) {
+            doublex4 acc = {0, 0, 0, 0};
+            for (int kb = jb; kb < ib; ++kb)
+                for (int kc = 0; kc < 4; ++kc) {
+                    const double a = A[(ib * 16 + l16) * W + kb * 16 + kc * 4 + l4];
+                    const double b = Li[(kb * 16 + kc * 4 + l4) * W + jb * 16 + l16];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                }
+            wave_sync();
+            for (int v = 0; v < 4; ++v) sc[(4 * v + l4) * 16 + l16] = acc[v];
+            wave_sync();
+            doublex4 acc2 = {0, 0, 0, 0};
+            for (int kc = 0; kc < 4; ++kc) {
+                const double a = Li[(ib * 16 + l16) * W + ib * 16 + kc * 4 + l4];
+                const double b = sc[(kc * 4 + l4) * 16 + l16];
+                acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc2, 0, 0, 0);
+            }
+            for (int v = 0; v < 4; ++v) Li[(ib * 16 + 4 * v + l4) * W + jb * 16 + l16] = -acc2[v];
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < w * w; t += kCholBlkThreads) {
+        const int i = t / w, j = t - i * w;
+        Rinv[t] = (i <= j) ? Li[j * W + i] : 0.0;
+    }
+}
+
 // Parallel cyclic Jacobi on the symmetric b x b matrix Hin (leading
 // dimension ldh). Outputs the eigenvalues in descending order (theta) and
 // the matching eigenvectors as columns of Vout (b x b row-major).
@@ -704,6 +851,21 @@ static hipError_t project_out(double *X, int64_t n, int b, int c0, int w, EigLay
 // against the columns [0, c0), which are orthonormal already: column
 // scaling (collapsed columns replaced by pseudo-random ones), then two
 // passes of (projection against [0, c0), CholeskyQR), the first shifted.
+hipError_t chol_inv_upper(const double *S, int w, double shift, double *Rinv, hipStream_t s) {
+    if (w <= kCholBlkMax) {
+        const int W = (w + 15) & ~15;
+        const size_t lds = sizeof(double) * (2 * (size_t)W * W + (kCholBlkThreads / 64) * 256);
+        hipFuncSetAttribute((const void *)k_chol_inv_blk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k_chol_inv_blk<<<1, kCholBlkThreads, lds, s>>>(S, w, w, shift, Rinv);
+    } else {
+        const size_t lds = sizeof(double) * ((size_t)w * w + w);
+        hipFuncSetAttribute((const void *)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        k_chol_inv<<<1, 1024, lds, s>>>(S, w, w, shift, Rinv);
+    }
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
 static hipError_t orthonormalise(double *X, int64_t n, int b, int c0, int w, EigLayout &L, uint64_t seed,
                                  hipStream_t s) {
     if (w <= 0) return hipSuccess;
@@ -718,10 +880,7 @@ static hipError_t orthonormalise(double *X, int64_t n, int b, int c0, int w, Eig
         double shift = pass == 0 ? 11.0 * ((double)n * w + (double)w * (w + 1)) * u / w : 0.0;
         TK_HIP(dgemm(w, w, (int)n, X + c0, b, true, X + c0, b, L.S, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split,
                      L.split_elems, s));
-        size_t lds = sizeof(double) * ((size_t)w * w + w);
-        hipFuncSetAttribute((const void *)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_chol_inv<<<1, 1024, lds, s>>>(L.S, w, w, shift, L.Rinv);
-        TK_LAUNCHED();
+        TK_HIP(chol_inv_upper(L.S, w, shift, L.Rinv, s));
         TK_HIP(dgemm((int)n, w, w, X + c0, b, false, L.Rinv, w, L.Y0, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split,
                      L.split_elems, s));
         TK_HIP(hipMemcpy2DAsync(X + c0, sizeof(double) * b, L.Y0, sizeof(double) * w, sizeof(double) * w, n,
@@ -766,13 +925,7 @@ hipError_t skinny_gemm(int M, int N, int K, const double *A, int64_t lda, bool a
 }
 int64_t skinny_part_bound(int max_n) { return (int64_t)512 * 16 * (ceil_div(max_n, 16) * 16); }
 
-hipError_t chol_inv_upper(const double *S, int w, double shift, double *Rinv, hipStream_t s) {
-    const size_t lds = sizeof(double) * ((size_t)w * w + w);
-    hipFuncSetAttribute((const void *)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_chol_inv<<<1, 1024, lds, s>>>(S, w, w, shift, Rinv);
-    TK_LAUNCHED();
-    return hipSuccess;
-}
+
 
 hipError_t canonical_cols(const double *X, int64_t n, int ldx, int J, double *F, hipStream_t s) {
     k_extract<<<J, 256, 0, s>>>(X, n, ldx, J, F, nullptr);
