@@ -146,7 +146,8 @@ def learned_leg(args):
 def batched_leg(tk, dev, sweeps):
     """64 tensors (mode sizes U{200..800}, density 0.5 %, cores U{10..40},
     U(0,1) values), MP with BF16 Grams, `sweeps` sweeps each: one call on 8
-    streams against the same call on one stream."""
+    streams against the same call on one stream, and the 8-stream call again
+    with the tuner's launch choices per shape bucket."""
     import numpy as np
     import torch
     import synth
@@ -173,6 +174,26 @@ def batched_leg(tk, dev, sweeps):
         out[f"swept_nnz_per_s_{ns}_streams"] = round(total * sweeps / wall, 1)
         log(f"batched: {ns} stream(s) {1000 * wall:.1f} ms for 64 tensors")
     out["speedup_8_over_1_stream"] = round(out["wall_ms_1_streams"] / out["wall_ms_8_streams"], 3)
+    # launch choices per shape bucket from the tuner (measured before the
+    # timed call; results within rounding of the built-in choices)
+    from paper_0711_2023_amd import autotune
+    t0 = time.perf_counter()
+    cache = autotune.TuneCache()
+    tunes = autotune.tune_batch(tk.ALGO_MP, tensors, cores, "mixed", cache, reps=1)
+    out["tune_s"] = round(time.perf_counter() - t0, 2)
+    out["tune_buckets"] = len(cache.entries)
+    out["tuned_choices"] = sorted({str(t.key()) for t in tunes})
+    streams = [torch.cuda.Stream(device=dev) for _ in range(8)]
+    tk.batched(tk.ALGO_MP, tensors[:8], cores[:8], streams=streams, tunes=tunes[:8], precision="mixed",
+               max_iters=2, tol=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tk.batched(tk.ALGO_MP, tensors, cores, streams=streams, tunes=tunes, precision="mixed", max_iters=sweeps,
+               tol=0.0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out["wall_ms_8_streams_tuned"] = round(1000 * wall, 1)
+    log(f"batched: 8 streams with tuned launch choices {1000 * wall:.1f} ms (tuning {out['tune_s']} s)")
     return out
 
 
