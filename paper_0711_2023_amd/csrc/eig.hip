@@ -689,6 +689,51 @@ __global__ void __launch_bounds__(256) k_skinny(SkinnyArgs g) {
     }
 }
 
+// Short K (<= kSkinnyWideMaxK): TPW adjacent 16 x 16 tiles of one 16-row strip
+// of C per workgroup of 16 waves, which interleave over K in steps of 4
+// (consecutive waves read consecutive K) and are summed in LDS in a fixed
+// order. No partial strips and no second launch.
+constexpr int kSkinnyWideMaxK = 2048;
+constexpr int kSkinnyWideWaves = 16;
+template <int TPW>
+__global__ void __launch_bounds__(64 * kSkinnyWideWaves) k_skinny_wide(SkinnyArgs g, int NG) {
+    extern __shared__ double red[];  // [waves][TPW][256]
+    const int strip = blockIdx.x / NG, t0 = (blockIdx.x - strip * NG) * TPW;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int i = strip * 16 + (l & 15), kq = l >> 4;
+    doublex4 acc[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) acc[u] = doublex4{0, 0, 0, 0};
+#pragma unroll 4
+    for (int k0 = 4 * wave; k0 < g.K; k0 += 4 * kSkinnyWideWaves) {
+        const int k = k0 + kq;
+        const bool kin = k < g.K;
+        double a = 0.0;
+        if (kin && i < g.M) a = g.at ? g.A[(int64_t)k * g.lda + i] : g.A[(int64_t)i * g.lda + k];
+        double bv[TPW];
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            const int j = (t0 + u) * 16 + (l & 15);
+            bv[u] = (kin && j < g.N) ? g.B[(int64_t)k * g.ldb + j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[u], acc[u], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < TPW; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(wave * TPW + u) * 256 + (4 * v + (l >> 4)) * 16 + (l & 15)] = acc[u][v];
+    __syncthreads();
+    for (int e = threadIdx.x; e < TPW * 256; e += 64 * kSkinnyWideWaves) {
+        const int u = e >> 8, q = e & 255, r = q >> 4, c = q & 15;
+        double sum = 0.0;
+        for (int w = 0; w < kSkinnyWideWaves; ++w) sum += red[(w * TPW + u) * 256 + q];
+        const int jj = (t0 + u) * 16 + c;
+        if (strip * 16 + r < g.M && jj < g.N) skinny_out(g, strip * 16 + r, jj, sum);
+    }
+}
+constexpr int kSkinnyTPW = 1;  // 2 and 4 (fewer re-reads of A, fewer workgroups) measured slower
+
 __global__ void k_skinny_reduce(SkinnyArgs g, int NC) {
     const int64_t total = (int64_t)g.M * g.N;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -735,6 +780,18 @@ static hipError_t skinny(SkinnyArgs g, double *part, int64_t part_elems, hipStre
         g.part = nullptr;
         const int64_t total = (int64_t)g.M * g.N;
         k_skinny_reduce<<<(unsigned)std::min<int64_t>(ceil_div(total, 256), 2048), 256, 0, s>>>(g, NT * 16);
+        TK_LAUNCHED();
+        return hipSuccess;
+    }
+    if (g.K <= kSkinnyWideMaxK) {
+        g.S = 1;
+        g.Kc = g.K;
+        g.part = nullptr;
+        const int NG = (NT + kSkinnyTPW - 1) / kSkinnyTPW;
+        const size_t lds = sizeof(double) * kSkinnyWideWaves * kSkinnyTPW * 256;
+        hipFuncSetAttribute((const void *)k_skinny_wide<kSkinnyTPW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+        k_skinny_wide<kSkinnyTPW><<<(unsigned)(((g.M + 15) / 16) * NG), 64 * kSkinnyWideWaves, lds, s>>>(g, NG);
         TK_LAUNCHED();
         return hipSuccess;
     }
