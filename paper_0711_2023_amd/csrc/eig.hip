@@ -353,13 +353,11 @@ __global__ void __launch_bounds__(512) k_jacobi(const double *Hin, int ldh, int 
     double *H = sm;
     double *V = V_LDS ? sm + (size_t)b * b : Vglob;
     const int m = b + (b & 1), half = m / 2;
-    double *cs = (V_LDS ? sm + 2 * (size_t)b * b : sm + (size_t)b * b);
-    double *sn = cs + half;
-    int *pp = reinterpret_cast<int *>(sn + half);
-    int *qq = pp + half;
+    __shared__ double cs[(kMaxBlock + 1) / 2], sn[(kMaxBlock + 1) / 2];
+    __shared__ int pp[(kMaxBlock + 1) / 2], qq[(kMaxBlock + 1) / 2];
     __shared__ double red[32];
     __shared__ double hmax;
-    __shared__ int done, any_rot, idle_pair;
+    __shared__ int done, any_rot;
     const int tid = threadIdx.x, nth = blockDim.x;
     for (int t = tid; t < b * b; t += nth) {
         int i = t / b, j = t - i * b;
@@ -383,8 +381,6 @@ __global__ void __launch_bounds__(512) k_jacobi(const double *Hin, int ldh, int 
         if (tid == 0) any_rot = 0;
         int nrot = 0;
         for (int r = 0; r < m - 1; ++r) {
-            if (tid == 0) idle_pair = -1;
-            __syncthreads();
             for (int k = tid; k < half; k += nth) {
                 int a, c;
                 if (k == 0) {
@@ -406,8 +402,6 @@ __global__ void __launch_bounds__(512) k_jacobi(const double *Hin, int ldh, int 
                         cc = 1.0 / sqrt(1.0 + t * t);
                         ss = t * cc;
                     }
-                } else {
-                    idle_pair = k;
                 }
                 cs[k] = cc;
                 sn[k] = ss;
@@ -415,7 +409,6 @@ __global__ void __launch_bounds__(512) k_jacobi(const double *Hin, int ldh, int 
                 qq[k] = q;
             }
             __syncthreads();
-            const int kd = idle_pair;
             // H <- G^T H G on 2x2 blocks (pair k1 rows, pair k2 columns)
             if (bact) {
                 const int k2 = bk2;
@@ -423,10 +416,10 @@ __global__ void __launch_bounds__(512) k_jacobi(const double *Hin, int ldh, int 
                 const double c2 = cs[k2], s2 = sn[k2];
                 for (int k1 = bk1; k1 < half; k1 += bstep) {
                     const int p1 = pp[k1], q1 = qq[k1];
-                    if (k1 == kd || k2 == kd) {
+                    if (q1 >= b || q2 >= b) {  // a pair with the padding index of odd b
                         // the idle real index x of the dummy pair meets the
                         // rotation of the other pair on one side only
-                        if (k1 == kd && k2 != kd) {
+                        if (q1 >= b && q2 < b) {
                             const int x = p1;
                             double hp = H[x * b + p2], hq = H[x * b + q2];
                             double np_ = c2 * hp - s2 * hq, nq = s2 * hp + c2 * hq;
@@ -466,7 +459,7 @@ __global__ void __launch_bounds__(512) k_jacobi(const double *Hin, int ldh, int 
                     H[q1 * b + q2] = zd;
                 }
                 // V <- V G: rows bk1, bk1 + bstep, ... of pair k2
-                if (k2 != kd) {
+                if (q2 < b) {
                     for (int row = bk1; row < b; row += bstep) {
                         double vp = V[row * b + p2], vq = V[row * b + q2];
                         V[row * b + p2] = c2 * vp - s2 * vq;
@@ -855,14 +848,12 @@ size_t eig_work_bytes(int n, int b) {
 // ------------------------------------------------------------------ host helpers
 static hipError_t jacobi(const double *H, int ldh, int b, double *theta, double *Vout, double *Vg, hipStream_t s,
                          int sweeps = 30) {
-    const int half = (b + 1) / 2;
-    size_t small = sizeof(double) * 2 * half + sizeof(int) * 2 * half;
     if (b <= kJacobiVLds) {
-        size_t lds = sizeof(double) * 2 * (size_t)b * b + small;
+        size_t lds = sizeof(double) * 2 * (size_t)b * b;
         hipFuncSetAttribute((const void *)k_jacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         k_jacobi<true><<<1, 512, lds, s>>>(H, ldh, b, sweeps, theta, Vout, Vg);
     } else {
-        size_t lds = sizeof(double) * (size_t)b * b + small;
+        size_t lds = sizeof(double) * (size_t)b * b;
         hipFuncSetAttribute((const void *)k_jacobi<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         k_jacobi<false><<<1, 512, lds, s>>>(H, ldh, b, sweeps, theta, Vout, Vg);
     }
