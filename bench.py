@@ -17,6 +17,8 @@ The JSON line reports:
 * roofline of the projection kernel, the metric's kernel (live HIP-event
   times on the library's stream x algorithmic bytes per launch), and of the
   Gram kernel beside it (algorithmic flops per launch);
+* parity_small: every precision form against the FP64 oracle's stored
+  numbers on the small workload (fit differences, factor subspace angles);
 * cpu_baseline: one sweep of the FP64 oracle on the host cores, same input.
 """
 import argparse
@@ -197,6 +199,47 @@ def batched_leg(tk, dev, sweeps):
     return out
 
 
+def parity_leg(tk, dev):
+    """Every precision form of MP and HOOI (10 sweeps, HO-SVD start) on two small
+    seeded tensors -- the uniform workload (100^3, 10,000 nonzeros, core 10^3)
+    and a planted Tucker model of that shape (100,000 entries, noise 0.1) --
+    against the FP64 oracle's numbers stored in tests/golden/small_reference.npz
+    (written by tests/golden/make_small_reference.py; the oracle is not run
+    here): the largest |fit difference| over the sweeps and the largest
+    principal angle between GPU and oracle factor subspaces over the modes."""
+    import numpy as np
+    import torch
+    import synth
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "small_reference.npz"), allow_pickle=False)
+
+    def angle(A, B):  # largest principal angle, arcsin form
+        R = B - A @ (A.T @ B)
+        return float(np.arcsin(min(1.0, np.linalg.norm(R, 2))))
+
+    out = {"reference": "FP64 oracle (stored)", "sweeps": 10, "start": "HO-SVD"}
+    for case in ("uniform", "planted"):
+        dims = tuple(int(x) for x in ref[f"{case}_dims"])
+        J = tuple(int(x) for x in ref[f"{case}_core"])
+        nnz, seed = int(ref[f"{case}_nnz"]), int(ref[f"{case}_seed"])
+        if case == "uniform":
+            idx, vals, dims = synth.uniform_sparse(dims, nnz, seed)
+        else:
+            idx, vals, dims = synth.planted_tucker(dims, J, nnz, float(ref["planted_noise"]), seed)
+        di = torch.from_numpy(idx.astype(np.int32)).to(dev)
+        dv = torch.from_numpy(vals).to(dev)
+        res = {"tensor": f"{dims[0]}x{dims[1]}x{dims[2]}, {nnz} nonzeros, core {J[0]}x{J[1]}x{J[2]}"}
+        for algo in ("mp", "hooi"):
+            fo = ref[f"{case}_{algo}_fits"]
+            for prec in ("fp64", "fp32", "mixed"):
+                r = getattr(tk, algo)(di, dv, dims, J, precision=prec, max_iters=len(fo), tol=0.0)
+                fg = np.array(r.fits)
+                ang = max(angle(ref[f"{case}_{algo}_{k}"], f.cpu().numpy()) for k, f in zip("ABC", r.factors))
+                res[f"{algo}_{prec}"] = {"max_abs_fit_diff": float(np.max(np.abs(fg - fo))),
+                                         "max_subspace_angle_rad": ang}
+        out[case] = res
+    return out
+
+
 def cpu_baseline(idx, vals, dims, J, sweeps=1):
     import numpy as np
     import oracle as O
@@ -233,6 +276,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the many-tensor leg")
     ap.add_argument("--learned-leg", action="store_true",
                     help="internal: train the learned start, time the mixed run from it, print one JSON line")
+    ap.add_argument("--no-parity", action="store_true", help="skip the small-workload comparison with the "
+                    "stored oracle reference")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
@@ -390,6 +435,10 @@ def main():
 
     if not args.no_batch:
         line["batched"] = batched_leg(tk, dev, args.sweeps)
+
+    if not args.no_parity:
+        line["parity_small"] = parity_leg(tk, dev)
+        log(f"parity against the stored FP64 oracle reference: {line['parity_small']}")
 
     if not args.no_cpu:
         log("timing the FP64 oracle (one sweep) on the host")

@@ -340,3 +340,19 @@ def test_core_entry_definition_matches_slicewise_core():
     G = O.core_from_slices(X, A, B, C)
     for p, q, r in [(0, 0, 0), (3, 2, 4), (1, 2, 3), (2, 0, 1)]:
         assert abs(O.core_entry(X, A, B, C, p, q, r) - G[p, q, r]) <= 1e-12 * max(1.0, np.abs(G).max())
+
+
+def test_small_reference_is_the_oracles():
+    """tests/golden/small_reference.npz (the benchmark's parity reference) is
+    what the oracle computes now."""
+    import importlib.util
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location("msr", os.path.join(here, "golden", "make_small_reference.py"))
+    msr = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(msr)
+    now = msr.compute()
+    stored = np.load(os.path.join(here, "golden", "small_reference.npz"), allow_pickle=False)
+    assert sorted(now) == sorted(stored.files)
+    for k in now:
+        np.testing.assert_allclose(stored[k], now[k], rtol=0, atol=1e-12, err_msg=k)
