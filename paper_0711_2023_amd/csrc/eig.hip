@@ -688,29 +688,48 @@ __global__ void __launch_bounds__(256) k_skinny(SkinnyArgs g) {
 // order. No partial strips and no second launch.
 constexpr int kSkinnyWideMaxK = 2048;
 constexpr int kSkinnyWideWaves = 16;
-template <int TPW>
+template <int TPW, bool AT>
 __global__ void __launch_bounds__(64 * kSkinnyWideWaves) k_skinny_wide(SkinnyArgs g, int NG) {
     extern __shared__ double red[];  // [waves][TPW][256]
+    constexpr int U = 4;             // K steps whose loads are in flight together
+    constexpr int STEP = 4 * kSkinnyWideWaves;
     const int strip = blockIdx.x / NG, t0 = (blockIdx.x - strip * NG) * TPW;
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int i = strip * 16 + (l & 15), kq = l >> 4;
+    // out-of-range rows, columns and K steps load from a valid address and are
+    // zeroed afterwards, so the loads carry no branches and can all be in flight
+    const bool iok = i < g.M;
+    const int ic = iok ? i : g.M - 1;
+    bool jok[TPW];
+    int jc[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int j = (t0 + u) * 16 + (l & 15);
+        jok[u] = j < g.N;
+        jc[u] = jok[u] ? j : g.N - 1;
+    }
     doublex4 acc[TPW];
 #pragma unroll
     for (int u = 0; u < TPW; ++u) acc[u] = doublex4{0, 0, 0, 0};
-#pragma unroll 4
-    for (int k0 = 4 * wave; k0 < g.K; k0 += 4 * kSkinnyWideWaves) {
-        const int k = k0 + kq;
-        const bool kin = k < g.K;
-        double a = 0.0;
-        if (kin && i < g.M) a = g.at ? g.A[(int64_t)k * g.lda + i] : g.A[(int64_t)i * g.lda + k];
-        double bv[TPW];
+    for (int k0 = 4 * wave; k0 < g.K; k0 += STEP * U) {
+        double a[U], bv[U][TPW];
 #pragma unroll
-        for (int u = 0; u < TPW; ++u) {
-            const int j = (t0 + u) * 16 + (l & 15);
-            bv[u] = (kin && j < g.N) ? g.B[(int64_t)k * g.ldb + j] : 0.0;
+        for (int q = 0; q < U; ++q) {
+            const int k = k0 + q * STEP + kq;
+            const bool kin = k < g.K;
+            const int kc = kin ? k : g.K - 1;
+            const double av = AT ? g.A[(int64_t)kc * g.lda + ic] : g.A[(int64_t)ic * g.lda + kc];
+            a[q] = av * ((kin && iok) ? 1.0 : 0.0);  // a product, not a select: keeps the load unpredicated
+#pragma unroll
+            for (int u = 0; u < TPW; ++u) {
+                const double b = g.B[(int64_t)kc * g.ldb + jc[u]];
+                bv[q][u] = b * ((kin && jok[u]) ? 1.0 : 0.0);
+            }
         }
 #pragma unroll
-        for (int u = 0; u < TPW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[u], acc[u], 0, 0, 0);
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int u = 0; u < TPW; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], bv[q][u], acc[u], 0, 0, 0);
     }
 #pragma unroll
     for (int u = 0; u < TPW; ++u)
@@ -782,9 +801,16 @@ static hipError_t skinny(SkinnyArgs g, double *part, int64_t part_elems, hipStre
         g.part = nullptr;
         const int NG = (NT + kSkinnyTPW - 1) / kSkinnyTPW;
         const size_t lds = sizeof(double) * kSkinnyWideWaves * kSkinnyTPW * 256;
-        hipFuncSetAttribute((const void *)k_skinny_wide<kSkinnyTPW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
-        k_skinny_wide<kSkinnyTPW><<<(unsigned)(((g.M + 15) / 16) * NG), 64 * kSkinnyWideWaves, lds, s>>>(g, NG);
+        const unsigned grid = (unsigned)(((g.M + 15) / 16) * NG);
+        if (g.at) {
+            hipFuncSetAttribute((const void *)k_skinny_wide<kSkinnyTPW, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            k_skinny_wide<kSkinnyTPW, true><<<grid, 64 * kSkinnyWideWaves, lds, s>>>(g, NG);
+        } else {
+            hipFuncSetAttribute((const void *)k_skinny_wide<kSkinnyTPW, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            k_skinny_wide<kSkinnyTPW, false><<<grid, 64 * kSkinnyWideWaves, lds, s>>>(g, NG);
+        }
         TK_LAUNCHED();
         return hipSuccess;
     }
