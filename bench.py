@@ -230,7 +230,7 @@ def parity_leg(tk, dev):
         res = {"tensor": f"{dims[0]}x{dims[1]}x{dims[2]}, {nnz} nonzeros, core {J[0]}x{J[1]}x{J[2]}"}
         for algo in ("mp", "hooi"):
             fo = ref[f"{case}_{algo}_fits"]
-            for prec in ("fp64", "fp32", "mixed"):
+            for prec in ("fp64", "fp32", "mixed") + (("bf16x3",) if algo == "mp" else ()):
                 r = getattr(tk, algo)(di, dv, dims, J, precision=prec, max_iters=len(fo), tol=0.0)
                 fg = np.array(r.fits)
                 ang = max(angle(ref[f"{case}_{algo}_{k}"], f.cpu().numpy()) for k, f in zip("ABC", r.factors))
@@ -305,7 +305,9 @@ def main():
     dv = torch.from_numpy(vals).to(dev)
     fn = tk.mp if args.algo == "mp" else tk.hooi
     algo_id = tk.ALGO_MP if args.algo == "mp" else tk.ALGO_HOOI
-    wsb = tk.workspace_bytes(algo_id, di, dv, dims, J, precision=args.precision)
+    # one workspace large enough for every precision the legs below run
+    precs = [args.precision, "fp32", "mixed"] + (["bf16x3"] if args.algo == "mp" else [])
+    wsb = max(tk.workspace_bytes(algo_id, di, dv, dims, J, precision=pr) for pr in precs)
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     log(f"workspace {wsb / 2**30:.2f} GiB")
 
@@ -400,7 +402,7 @@ def main():
 
     if not args.no_ttf:
         ttf = {}
-        for prec in ("fp32", "mixed"):
+        for prec in ("fp32", "mixed") + (("bf16x3",) if args.algo == "mp" else ()):
             runs = []
             for _ in range(3):
                 torch.cuda.synchronize()
@@ -415,6 +417,8 @@ def main():
             log(f"time-to-fit {prec}: {ttf[prec]}")
         ttf["speedup_plain_over_mixed"] = round(ttf["fp32"]["wall_ms"] / ttf["mixed"]["wall_ms"], 3)
         ttf["mixed_reaches_plain_fit"] = bool(ttf["mixed"]["fit"] >= ttf["fp32"]["fit"] - 1e-4)
+        if "bf16x3" in ttf:  # split-BF16 Grams: FP32-like accuracy
+            ttf["speedup_plain_over_bf16x3"] = round(ttf["fp32"]["wall_ms"] / ttf["bf16x3"]["wall_ms"], 3)
         if not args.no_learn:
             # in a child process with a time limit, so that this line is
             # printed whatever happens there

@@ -61,6 +61,11 @@ extern "C" {
 #define TK_FP32        1  /* FP32 projections, FP32 MFMA Grams; eigensolve, core, fit FP64 */
 #define TK_MIXED_BF16  2  /* BF16 projections for the Grams, BF16 MFMA with FP32
                              accumulation; eigensolve, core and fit FP64 */
+#define TK_MIXED_BF16X3 3 /* MP only: each projection for the Grams as a BF16 pair
+                             (rounded value + rounded remainder, from FP32 factors),
+                             Grams as hi hi^T + hi lo^T + lo hi^T on BF16 MFMA with
+                             FP32 accumulation (about FP32 accuracy, three times the
+                             MFMA work of TK_MIXED_BF16); TK_ERR_ARG for HOOI */
 
 /* ---- initialisation --------------------------------------------------- */
 #define TK_INIT_HOSVD  0  /* B, C from the leading eigenvectors of X_(n) X_(n)^T */
@@ -104,7 +109,7 @@ typedef struct tk_tune {
 
 /* Options; tucker_default_opts() fills the paper's values. */
 typedef struct tk_opts {
-    int32_t precision;      /* TK_FP64 | TK_FP32 | TK_MIXED_BF16 */
+    int32_t precision;      /* TK_FP64 | TK_FP32 | TK_MIXED_BF16 | TK_MIXED_BF16X3 */
     int32_t init;           /* TK_INIT_HOSVD | TK_INIT_GIVEN | TK_INIT_LEARNED */
     int32_t max_iters;      /* sweep cap; the paper uses 50 */
     double  tol;            /* stop after sweep t when fit(t) - fit(t-1) < tol,
@@ -114,8 +119,8 @@ typedef struct tk_opts {
     double  eig_tol;        /* relative accuracy of the sum of the J leading Ritz values
                                at which an eigensolve stops (residual estimate, or
                                change across a full-degree filter step); 0 = by
-                               precision (1e-12 for FP64, 1e-8 for FP32, 1e-6 for
-                               mixed BF16) */
+                               precision (1e-12 for FP64, 1e-8 for FP32 and split
+                               BF16, 1e-6 for mixed BF16) */
     int32_t timing;         /* 1: record HIP events around the projection and
                                TTMc kernels and report their times in tk_stats */
     const float *model;     /* [dev] TK_INIT_LEARNED: the network parameters

@@ -14,7 +14,7 @@ from dataclasses import dataclass
 
 __all__ = [
     "TuckerError", "lib", "hooi", "mp", "fit", "workspace_bytes", "default_opts",
-    "FP64", "FP32", "MIXED_BF16", "INIT_HOSVD", "INIT_GIVEN", "INIT_LEARNED",
+    "FP64", "FP32", "MIXED_BF16", "MIXED_BF16X3", "INIT_HOSVD", "INIT_GIVEN", "INIT_LEARNED",
     "Result", "LIB_PATH", "SYMBOLS", "lead_eig", "learn_param_count", "learn_sketch", "learn_forward",
     "learn_backward", "learn_align", "learn_adam", "learn_test_width", "batched",
 ]
@@ -24,10 +24,11 @@ LIB_PATH = os.path.join(HERE, "libtucker.so")
 
 TK_OK, TK_WARN_NOCONV = 0, 1
 TK_ERR_ARG, TK_ERR_INDEX, TK_ERR_VALUE, TK_ERR_EMPTY, TK_ERR_WORKSPACE, TK_ERR_DEVICE = -1, -2, -3, -4, -5, -6
-FP64, FP32, MIXED_BF16 = 0, 1, 2
+FP64, FP32, MIXED_BF16, MIXED_BF16X3 = 0, 1, 2, 3
 INIT_HOSVD, INIT_GIVEN, INIT_LEARNED = 0, 1, 2
 ALGO_HOOI, ALGO_MP, ALGO_FIT = 0, 1, 2
-_PREC = {"fp64": FP64, "fp32": FP32, "mixed": MIXED_BF16, "bf16": MIXED_BF16}
+_PREC = {"fp64": FP64, "fp32": FP32, "mixed": MIXED_BF16, "bf16": MIXED_BF16, "bf16x3": MIXED_BF16X3,
+         "mixed3": MIXED_BF16X3}
 
 # every function declared in include/*.h
 SYMBOLS = ["tucker_default_opts", "tucker_workspace_bytes", "tucker_hooi", "tucker_mp", "tucker_fit",

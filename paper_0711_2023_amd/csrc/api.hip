@@ -136,6 +136,8 @@ struct Plan {
     int64_t Lpart_elems = 0;
     void *Leigw = nullptr;
     bool blk_ok[3] = {false, false, false};  // Xblk[n] holds a previous block
+    bool split = false;                      // MP with split-BF16 Grams (hi and lo parts)
+    void *Tlo[3] = {nullptr, nullptr, nullptr};  // lo parts of the projections
     int sweep_solves[3] = {0, 0, 0};         // warm (sweep) eigensolves done per mode
 };
 
@@ -159,6 +161,26 @@ static GramTerm term_of(const Plan &p, int m, int n, const void *base) {
         t.s_chunk = Ilo * Jm;
     }
     return t;
+}
+
+// M_n from the projections T(ma), T(mb): two terms, or six for split-BF16
+// (hi hi^T + hi lo^T + lo hi^T of each; the dropped lo lo^T is below the
+// rounding of the others)
+static hipError_t mp_gram(Plan &p, int n, int ma, int mb, hipStream_t s) {
+    GramTerm g[kGramMaxTerms];
+    int nt = 0;
+    for (int m : {ma, mb}) {
+        g[nt++] = term_of(p, m, n, p.T[m]);
+        if (p.split) {
+            GramTerm hl = term_of(p, m, n, p.T[m]);
+            hl.base_b = p.Tlo[m];
+            GramTerm lh = term_of(p, m, n, p.Tlo[m]);
+            lh.base_b = p.T[m];
+            g[nt++] = hl;
+            g[nt++] = lh;
+        }
+    }
+    return gram((int)p.I[n], p.prec, nt, g, p.Mg, p.gram_scratch, s, p.tune);
 }
 
 static void carve(Plan &p, Arena &ar) {
@@ -196,6 +218,8 @@ static void carve(Plan &p, Arena &ar) {
     const size_t es = elem_size(prec);
     if (p.algo == TK_ALGO_MP) {
         for (int m = 0; m < 3; ++m) p.T[m] = ar.take<char>((int64_t)(p.nslots[m] * p.ldT[m] * es));
+        if (p.split)
+            for (int m = 0; m < 3; ++m) p.Tlo[m] = ar.take<char>((int64_t)(p.nslots[m] * p.ldT[m] * es));
         if (prec == PBF16) p.Tcore = ar.take<float>(p.nslots[2] * p.J[2]);
     } else if (p.algo == TK_ALGO_HOOI) {
         p.T[2] = ar.take<char>((int64_t)(p.nslots[2] * p.J[2] * es));
@@ -215,13 +239,17 @@ static void carve(Plan &p, Arena &ar) {
         p.Mg = ar.take<double>(maxI * maxI);
         size_t gs = 0;
         for (int n = 0; n < 3; ++n) {
-            int64_t K[2];
+            int64_t K[kGramMaxTerms];
             int gprec = prec;
             if (p.algo == TK_ALGO_MP) {
                 int m1 = (n + 1) % 3, m2 = (n + 2) % 3;
-                K[0] = p.nslots[m1] / p.I[n] * p.ldT[m1];
-                K[1] = p.nslots[m2] / p.I[n] * p.ldT[m2];
-                gs = std::max(gs, gram_scratch_bytes((int)p.I[n], gprec, 2, K, p.tune));
+                const int64_t K1 = p.nslots[m1] / p.I[n] * p.ldT[m1], K2 = p.nslots[m2] / p.I[n] * p.ldT[m2];
+                const int per = p.split ? 3 : 1;  // hi.hi (+ hi.lo, lo.hi)
+                for (int q = 0; q < per; ++q) {
+                    K[q] = K1;
+                    K[per + q] = K2;
+                }
+                gs = std::max(gs, gram_scratch_bytes((int)p.I[n], gprec, 2 * per, K, p.tune));
             } else {
                 K[0] = (int64_t)p.J[(n + 1) % 3] * p.J[(n + 2) % 3];
                 gprec = prec == P64 ? P64 : P32;
@@ -242,7 +270,11 @@ static void carve(Plan &p, Arena &ar) {
         for (int n = 0; n < 3; ++n) {
             p.F32[n] = prec != P64 ? ar.take<float>(p.I[n] * p.J[n]) : nullptr;
             p.F16[n] = prec == PBF16 ? ar.take<bf16>(p.I[n] * p.J[n]) : nullptr;
-            p.Fp[n] = p.algo == TK_ALGO_MP ? ar.take<char>(p.I[n] * p.ldT[n] * (int64_t)elem_size(prec)) : nullptr;
+            // padded factor rows for the projections (FP32 for split Grams:
+            // their lo parts need more than BF16 factors)
+            p.Fp[n] = p.algo == TK_ALGO_MP
+                          ? ar.take<char>(p.I[n] * p.ldT[n] * (int64_t)(p.split ? 4 : elem_size(prec)))
+                          : nullptr;
         }
     }
     const int64_t J0 = p.J[0], J1 = p.J[1], J2 = p.J[2];
@@ -288,9 +320,10 @@ static int check_coo(const tk_coo *X, const int32_t *J) {
     return TK_OK;
 }
 
-static int check_opts(const tk_opts *o, const tk_coo *X) {
+static int check_opts(const tk_opts *o, const tk_coo *X, int algo) {
     if (!o) return TK_ERR_ARG;
-    if (o->precision < 0 || o->precision > 2) return TK_ERR_ARG;
+    if (o->precision < 0 || o->precision > 3) return TK_ERR_ARG;
+    if (o->precision == TK_MIXED_BF16X3 && algo != TK_ALGO_MP) return TK_ERR_ARG;
     if (o->init != TK_INIT_HOSVD && o->init != TK_INIT_GIVEN && o->init != TK_INIT_LEARNED) return TK_ERR_ARG;
     if (o->init == TK_INIT_LEARNED && !o->model) return TK_ERR_ARG;
     if (o->tune) {
@@ -322,6 +355,8 @@ static Tune tune_of(const tk_tune *t) {
 static void plan_init(Plan &p, int algo, int prec, const tk_coo *X, const int32_t *J, int init = TK_INIT_HOSVD,
                       const tk_tune *tune = nullptr) {
     p.algo = algo;
+    p.split = prec == TK_MIXED_BF16X3;
+    if (p.split) prec = PBF16;  // BF16 storage, two parts
     p.prec = prec;
     p.init = init;
     p.tune = tune_of(tune);
@@ -377,7 +412,7 @@ int tucker_workspace_bytes(int32_t algo, const tk_coo *X, const int32_t *core_di
     if (algo != TK_ALGO_HOOI && algo != TK_ALGO_MP && algo != TK_ALGO_FIT) return TK_ERR_ARG;
     int prec = P64;
     if (algo != TK_ALGO_FIT) {
-        if ((st = check_opts(opt, X))) return st;
+        if ((st = check_opts(opt, X, algo))) return st;
         prec = opt->precision;
     }
     Plan p;
@@ -498,6 +533,9 @@ static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double
 static hipError_t project_m(Plan &p, int m, const double *F64, void *T, int out_prec, hipStream_t s, int ld = 0) {
     const int J = p.J[m];
     if (ld <= 0) ld = p.ldT[m];
+    if (p.split && T == p.T[m] && out_prec == PBF16 && ld == p.ldT[m])  // the Gram copy: hi and lo parts
+        return project_split(p.ptr[m], p.lidx[m], p.lval32[m], (const float *)p.Fp[m], ld, J, p.nslots[m],
+                             (bf16 *)T, (bf16 *)p.Tlo[m], s, p.tune);
     // the padded copy (rows of ldT, type of T) when T has that stride and
     // type, else rows of J
     const bool padded = p.Fp[m] && ld == p.ldT[m] && out_prec == p.prec;
@@ -528,7 +566,7 @@ static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s)
     if (p.Fp[n]) {
         if (p.prec == P64)
             TK_HIP(pad_rows<double>(F, p.I[n], p.J[n], p.ldT[n], (double *)p.Fp[n], s));
-        else if (p.prec == P32)
+        else if (p.prec == P32 || p.split)
             TK_HIP(pad_rows<float>(F, p.I[n], p.J[n], p.ldT[n], (float *)p.Fp[n], s));
         else
             TK_HIP(pad_rows<bf16>(F, p.I[n], p.J[n], p.ldT[n], (bf16 *)p.Fp[n], s));
@@ -604,7 +642,7 @@ static int run_eig(Plan &p, int n, double *M, double *F, bool warm, const tk_opt
     // FP32 projections limit the Gram to about 1e-7 relative, BF16 ones (8
     // significant bits) to about 1e-3, so the sum of the leading Ritz values
     // is resolved to 1e-8 and 1e-6 of itself respectively
-    eo.tol = o->eig_tol > 0 ? o->eig_tol : (p.prec == P64 ? 1e-12 : (p.prec == P32 ? 1e-8 : 1e-6));
+    eo.tol = o->eig_tol > 0 ? o->eig_tol : (p.prec == P64 ? 1e-12 : (p.prec == P32 || p.split ? 1e-8 : 1e-6));
     eo.warm = warm && p.blk_ok[n];
     // a block left by the previous sweep's solve of this mode is usually
     // converged or nearly so: its filter starts at a low degree. Blocks from
@@ -630,7 +668,7 @@ static int common_start(int algo, const tk_coo *X, const int32_t *J, const tk_op
                         Plan &p) {
     int st = check_coo(X, J);
     if (st) return st;
-    if ((st = check_opts(o, X))) return st;
+    if ((st = check_opts(o, X, algo))) return st;
     if (!core || !factors || !factors[0] || !factors[1] || !factors[2] || !iters_done) return TK_ERR_ARG;
     if (o->max_iters > 0 && !fit_history) return TK_ERR_ARG;
     if (X->nnz == 0) return TK_ERR_EMPTY;
@@ -756,15 +794,13 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     tm.begin(kProj);
     ST(project_m(p, 2, C, p.T[2], prec, s));
     tm.end();
-    const int gprec = prec;
     double prev = 0.0;
     int t = 0;
     *iters_done = 0;
     for (t = 1; t <= o->max_iters; ++t) {
         // M1 (mode 0) from T(1) and T(2)
-        GramTerm g0[2] = {term_of(p, 1, 0, p.T[1]), term_of(p, 2, 0, p.T[2])};
         tm.begin(kGram);
-        ST(gram((int)p.I[0], gprec, 2, g0, p.Mg, p.gram_scratch, s, p.tune));
+        ST(mp_gram(p, 0, 1, 2, s));
         tm.end();
         tm.begin(kEig);
         if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
@@ -773,9 +809,8 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         ST(project_m(p, 0, A, p.T[0], prec, s));
         tm.end();
         // M2 (mode 1) from T(0) and T(2)
-        GramTerm g1[2] = {term_of(p, 0, 1, p.T[0]), term_of(p, 2, 1, p.T[2])};
         tm.begin(kGram);
-        ST(gram((int)p.I[1], gprec, 2, g1, p.Mg, p.gram_scratch, s, p.tune));
+        ST(mp_gram(p, 1, 0, 2, s));
         tm.end();
         tm.begin(kEig);
         if ((st = run_eig(p, 1, p.Mg, B, true, o, stats, &noconv, s))) return st;
@@ -784,9 +819,8 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         ST(project_m(p, 1, B, p.T[1], prec, s));
         tm.end();
         // M3 (mode 2) from T(0) and T(1)
-        GramTerm g2[2] = {term_of(p, 0, 2, p.T[0]), term_of(p, 1, 2, p.T[1])};
         tm.begin(kGram);
-        ST(gram((int)p.I[2], gprec, 2, g2, p.Mg, p.gram_scratch, s, p.tune));
+        ST(mp_gram(p, 2, 0, 1, s));
         tm.end();
         tm.begin(kEig);
         if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
@@ -815,9 +849,8 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     }
     if (o->max_iters == 0) {
         // no sweep: A from the start factors, then the core
-        GramTerm g0[2] = {term_of(p, 1, 0, p.T[1]), term_of(p, 2, 0, p.T[2])};
         tm.begin(kGram);
-        ST(gram((int)p.I[0], gprec, 2, g0, p.Mg, p.gram_scratch, s, p.tune));
+        ST(mp_gram(p, 0, 1, 2, s));
         tm.end();
         tm.begin(kEig);
         if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;

@@ -122,20 +122,30 @@ template <class TV, class TF, class TO>
 hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int ldF, int J, int ldT,
                    int64_t nslots, TO *T, hipStream_t s, const Tune &tn = Tune());
 // out[i * ld + r] = in[i * J + r] for r < J, zero for J <= r < ld.
+// Projection into a BF16 pair (hi = rounded value, lo = rounded remainder)
+// from FP32 factor rows padded to ld (a multiple of 8), for split-BF16 Grams.
+hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *lval, const float *F, int ld, int J,
+                         int64_t nslots, bf16 *Thi, bf16 *Tlo, hipStream_t s, const Tune &tn = Tune());
 template <class TO>
 hipError_t pad_rows(const double *in, int64_t rows, int J, int ld, TO *out, hipStream_t s);
 
 // ---------------------------------------------------------------- mfma.hip
 // One operand of a Gram: row i, column k = (kc, kr) with kr < chunk_len,
 // element at base + i*s_row + kc*s_chunk + kr.
+// A term may pair two operands of the same layout: base_b (NULL = base) holds
+// the right-hand rows, for the cross products of split operands.
 struct GramTerm {
     const void *base;
     int64_t s_row;
     int64_t s_chunk;
     int64_t chunk_len;
     int64_t nchunks;
+    const void *base_b = nullptr;
 };
-// M (FP64, n x n, symmetric, full) = sum over terms of T_t T_t^T.
+constexpr int kGramMaxTerms = 6;
+// M (FP64, n x n, symmetric, full) = sum over terms of T_t U_t^T (U_t = T_t
+// unless base_b is set; the sum must be symmetric, as the lower triangle is
+// computed and mirrored). At most kGramMaxTerms terms.
 // Element type by precision: P64 double, P32 float, PBF16 bf16.
 size_t gram_scratch_bytes(int n, int prec, int nterms, const int64_t *K, const Tune &tn = Tune());
 hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, void *scratch, hipStream_t s,

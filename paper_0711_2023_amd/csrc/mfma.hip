@@ -99,13 +99,13 @@ __device__ inline bf16 cvt<bf16, double>(double x) { return (bf16)(float)x; }
 
 // ------------------------------------------------------------------ Gram
 struct GramTermK {
-    const void *base;
+    const void *base, *base_b;
     int64_t s_row, s_chunk, chunk_len, nchunks;
     int64_t kper;         // K elements per split (multiple of the stage depth)
     int32_t split_begin;  // first split index of this term
 };
 struct GramKArgs {
-    GramTermK t[2];
+    GramTermK t[kGramMaxTerms];
     int32_t nterms;
     int32_t splits_total;
     int32_t npairs;
@@ -207,16 +207,20 @@ __global__ void __launch_bounds__(256) k_gram(GramKArgs g, typename P::Acc *part
     const int rnd = gq / g.npairs, pair = gq - rnd * g.npairs;
     const int sidx = rnd * 8 + gx;
     if (sidx >= g.splits_total) return;
-    const int term = (g.nterms > 1 && sidx >= g.t[1].split_begin) ? 1 : 0;
+    int term = 0;
+    for (int q = 1; q < g.nterms; ++q)
+        if (sidx >= g.t[q].split_begin) term = q;
     const GramTermK t = g.t[term];
     const int split = sidx - t.split_begin;
     int ti, tj;
     pair_decode(pair, ti, tj);
-    const bool diag = ti == tj;
+    const E *base = reinterpret_cast<const E *>(t.base);
+    const E *base_b = reinterpret_cast<const E *>(t.base_b);
+    // a diagonal tile of a term with one operand reads its rows once
+    const bool diag = ti == tj && base_b == base;
     const int64_t K = t.chunk_len * t.nchunks;
     const int64_t kbeg = (int64_t)split * t.kper;
     const int64_t kend = kbeg + t.kper < K ? kbeg + t.kper : K;
-    const E *base = reinterpret_cast<const E *>(t.base);
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
     const int kv = tid % Cfg::TPR, rr = tid / Cfg::TPR;
@@ -232,7 +236,7 @@ __global__ void __launch_bounds__(256) k_gram(GramKArgs g, typename P::Acc *part
 
     StageRegs<Cfg, VEC> ra, rb;
     load_stage<Cfg, VEC>(ra, base, t, rowA0, g.n, k, kend, kc, kr, rr);
-    if (!diag) load_stage<Cfg, VEC>(rb, base, t, rowB0, g.n, k, kend, kc, kr, rr);
+    if (!diag) load_stage<Cfg, VEC>(rb, base_b, t, rowB0, g.n, k, kend, kc, kr, rr);
     const E *Bsrc = diag ? As : Bs;
     for (int64_t k0 = kbeg; k0 < kend; k0 += KS) {
         store_stage<Cfg, VEC>(ra, As, rr, kv);
@@ -247,7 +251,7 @@ __global__ void __launch_bounds__(256) k_gram(GramKArgs g, typename P::Acc *part
         }
         if (k0 + KS < kend) {
             load_stage<Cfg, VEC>(ra, base, t, rowA0, g.n, k, kend, kc, kr, rr);
-            if (!diag) load_stage<Cfg, VEC>(rb, base, t, rowB0, g.n, k, kend, kc, kr, rr);
+            if (!diag) load_stage<Cfg, VEC>(rb, base_b, t, rowB0, g.n, k, kend, kc, kr, rr);
         }
 #pragma unroll
         for (int q = 0; q < KS; q += P::KI)
@@ -294,8 +298,8 @@ __global__ void k_gram_reduce(const Acc *partials, int splits_total, int TBK, in
 
 struct GramPlan {
     int TBK, KS, npairs, splits_total;
-    int64_t kper[2];
-    int32_t split_begin[2];
+    int64_t kper[kGramMaxTerms];
+    int32_t split_begin[kGramMaxTerms];
     size_t acc_size;
 };
 
@@ -339,7 +343,8 @@ static hipError_t launch_gram(const GramKArgs &g, bool vec, unsigned blocks, Acc
 
 hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, void *scratch, hipStream_t s,
                 const Tune &tn) {
-    int64_t K[2] = {0, 0};
+    if (nterms < 1 || nterms > kGramMaxTerms) return hipErrorInvalidValue;
+    int64_t K[kGramMaxTerms] = {0, 0, 0, 0, 0, 0};
     for (int t = 0; t < nterms; ++t) K[t] = terms[t].chunk_len * terms[t].nchunks;
     GramPlan p = gram_plan(n, prec, nterms, K, tn);
     GramKArgs g{};
@@ -352,6 +357,7 @@ hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, v
     bool vec = true;
     for (int t = 0; t < nterms; ++t) {
         g.t[t].base = terms[t].base;
+        g.t[t].base_b = terms[t].base_b ? terms[t].base_b : terms[t].base;
         g.t[t].s_row = terms[t].s_row;
         g.t[t].s_chunk = terms[t].s_chunk;
         g.t[t].chunk_len = terms[t].chunk_len;
@@ -360,7 +366,8 @@ hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, v
         g.t[t].split_begin = p.split_begin[t];
         vec = vec && terms[t].chunk_len % vw == 0 && terms[t].s_row % vw == 0 &&
               (terms[t].nchunks == 1 || terms[t].s_chunk % vw == 0) &&
-              reinterpret_cast<uintptr_t>(terms[t].base) % 16 == 0;
+              reinterpret_cast<uintptr_t>(terms[t].base) % 16 == 0 &&
+              reinterpret_cast<uintptr_t>(g.t[t].base_b) % 16 == 0;
     }
     const unsigned blocks = (unsigned)(8 * p.npairs * ceil_div(p.splits_total, 8));
     const int64_t total = (int64_t)p.npairs * p.TBK * p.TBK;

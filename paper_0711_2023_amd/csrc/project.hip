@@ -135,13 +135,16 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const int32_t *__restr
 // Row strides of T and F equal and a multiple of 16 bytes, F's padding
 // columns zero: each thread produces whole 16-byte chunks of T, which never
 // cross a slot, from 16-byte loads of F rows and one vector store per chunk.
-template <class TV, class TF, class TO>
+// SPLIT: T receives each output rounded to TO and Tlo the rounded remainder
+// (the value minus its rounded part), so T + Tlo carries about twice the
+// significand bits of TO.
+template <class TV, class TF, class TO, bool SPLIT = false>
 __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__restrict__ ptr,
                                                               const int32_t *__restrict__ lidx,
                                                               const TV *__restrict__ lval,
                                                               const TF *__restrict__ F, int32_t J, int32_t ldT,
                                                               int32_t spw, int32_t cap, int64_t nslots,
-                                                              TO *__restrict__ T) {
+                                                              TO *__restrict__ T, TO *__restrict__ Tlo = nullptr) {
     typedef typename AccOf<TV>::type Acc;
     typedef typename Vec16<TF>::type FV;
     constexpr int V = 16 / sizeof(TO);            // outputs per chunk
@@ -216,6 +219,12 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
 #pragma unroll
                 for (int t = 0; t < V; ++t) o[t] = (TO)acc[u][t];
                 *reinterpret_cast<typename Vec16<TO>::type *>(out + (int64_t)c * V) = o;
+                if (SPLIT) {
+                    typename Vec16<TO>::type o2;
+#pragma unroll
+                    for (int t = 0; t < V; ++t) o2[t] = (TO)(acc[u][t] - (Acc)o[t]);
+                    *reinterpret_cast<typename Vec16<TO>::type *>(Tlo + s0 * ldT + (int64_t)c * V) = o2;
+                }
             }
         }
     }
@@ -269,6 +278,24 @@ hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, cons
     else
         k_project<TV, TF, TO><<<(unsigned)blocks, kProjThreads, lds, s>>>(ptr, lidx, lval, F, ldF, J, ldT, spw,
                                                                          cap, nslots, T);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
+hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *lval, const float *F, int ld, int J,
+                         int64_t nslots, bf16 *Thi, bf16 *Tlo, hipStream_t s, const Tune &tn) {
+    if (nslots <= 0 || ld <= 0) return hipSuccess;
+    if (ld % 8 != 0 || ((uintptr_t)F & 15) != 0 || ((uintptr_t)Thi & 15) != 0 || ((uintptr_t)Tlo & 15) != 0)
+        return hipErrorInvalidValue;
+    int spw = (int)std::min<int64_t>(tn.proj_elems / ld, ceil_div(nslots, tn.proj_min_blocks));
+    if (spw < 1) spw = 1;
+    if (spw > 4096) spw = 4096;
+    int cap = spw * 4 < 256 ? 256 : spw * 4;
+    if (cap > 4096) cap = 4096;
+    const size_t lds = sizeof(int32_t) * (((spw + 4) & ~3) + ((cap + 3) & ~3)) + sizeof(float) * cap;
+    const int64_t blocks = ceil_div(nslots, spw);
+    k_project_vec<float, float, bf16, true><<<(unsigned)blocks, kProjThreads, lds, s>>>(ptr, lidx, lval, F, J, ld,
+                                                                                       spw, cap, nslots, Thi, Tlo);
     TK_LAUNCHED();
     return hipSuccess;
 }

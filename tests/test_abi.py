@@ -279,3 +279,20 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[name]) == ctypes.sizeof(cls), name
         for f, _ in cls._fields_:
             assert int(got[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+
+
+def test_split_bf16_precision_is_mp_only():
+    c, d = _coo(dims=(40, 30, 20), nnz=500)
+    o = tk.default_opts()
+    o.precision = tk.MIXED_BF16X3
+    st, b3 = _ws(c, (5, 4, 3), o, tk.ALGO_MP)
+    assert st == 0
+    o.precision = tk.MIXED_BF16
+    st, b2 = _ws(c, (5, 4, 3), o, tk.ALGO_MP)
+    assert st == 0 and b3 > b2  # lo parts, FP32 factor rows, six-term Gram splits
+    o.precision = tk.MIXED_BF16X3
+    st, _ = _ws(c, (5, 4, 3), o, tk.ALGO_HOOI)
+    assert st == tk.TK_ERR_ARG
+    o.precision = 4
+    st, _ = _ws(c, (5, 4, 3), o, tk.ALGO_MP)
+    assert st == tk.TK_ERR_ARG
