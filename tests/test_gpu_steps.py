@@ -131,3 +131,28 @@ def test_lead_eig_warm_start_sequence(tk):
     need = tk.lib  # keep flake quiet
     F, th, it, st, ws = tk.lead_eig(torch.from_numpy(H2).cuda(), J[2], tol=1e-13)
     _check(tk, M2, J[2], tol=1e-13, warm=True, ws=ws)
+
+
+@pytest.mark.parametrize("n,J", [(150, 128), (300, 120), (1200, 60)])
+def test_lead_eig_wide_subspace_and_k_split(tk, n, J):
+    """J at the API cap (128) and near it, where the block (at most 140
+    columns) has few extra columns, and a larger n (1200: one-pass products
+    over 75 row strips), on a gapped spectrum."""
+    _say(f"lead_eig wide {n} {J}")
+    rng = np.random.default_rng(n + J)
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    lam = np.concatenate([np.linspace(200, 100, J), np.linspace(30, 0.01, n - J)])
+    M = (Q * lam) @ Q.T
+    _check(tk, M, J, angle=1e-8)
+
+
+def test_lead_eig_split_k_products(tk):
+    """n = 2500 > 2048: the eigensolver's products over n use split-K partial
+    strips summed in a fixed order by a second kernel."""
+    _say("lead_eig split-K 2500")
+    rng = np.random.default_rng(7)
+    n, J = 2500, 20
+    Y = rng.standard_normal((n, 60))
+    lam = np.concatenate([np.linspace(10, 5, J), np.linspace(1, 0.1, 40)])
+    M = (Y * lam) @ Y.T / n + 1e-3 * np.eye(n)
+    _check(tk, M, J, angle=1e-7)
