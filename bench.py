@@ -43,10 +43,14 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def project_bytes(nnz, nslots, J, I_m, out_bytes):
-    """Bytes one projection launch must move: leaf index + FP32 value per
-    nonzero, slot pointers, the dense projected tensor, the factor."""
-    return nnz * 8 + (nslots + 1) * 4 + nslots * J * out_bytes + I_m * J * 4
+def project_bytes(nnz, nslots, J, I_m, precision):
+    """Bytes one projection launch must move: leaf index + value per nonzero
+    (FP64 values for fp64, else FP32), slot pointers, the dense projected
+    tensor, the factor copy it reads (FP16 rows for mixed)."""
+    out_bytes = {"mixed": 2, "fp32": 4, "fp64": 8}[precision]
+    val_bytes = 8 if precision == "fp64" else 4
+    fac_bytes = {"mixed": 2, "fp32": 4, "fp64": 8}[precision]
+    return nnz * (4 + val_bytes) + (nslots + 1) * 4 + nslots * J * out_bytes + I_m * J * fac_bytes
 
 
 def gram_flops(I, J, n):
@@ -349,12 +353,11 @@ def main():
     value = statistics.median(rates)
     st = results[len(results) // 2].stats
     sweeps = results[0].iters
-    out_bytes = {"mixed": 2, "fp32": 4, "fp64": 8}[args.precision]
     # per-launch averages
     proj_ms = st["project_ms"] / max(1, st["project_calls"])
     gram_ms = st["gram_ms"] / max(1, st["gram_calls"])
     nslots = [dims[(m + 2) % 3] * dims[(m + 1) % 3] for m in range(3)]
-    pbytes = statistics.mean(project_bytes(nu, nslots[m], J[m], dims[m], out_bytes) for m in range(3))
+    pbytes = statistics.mean(project_bytes(nu, nslots[m], J[m], dims[m], args.precision) for m in range(3))
     proj_gbs = pbytes / (proj_ms / 1000.0) / 1e9
     gflops = statistics.mean(gram_flops(dims, J, n) for n in range(3))
     gram_tf = gflops / (gram_ms / 1000.0) / 1e12

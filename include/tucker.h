@@ -59,8 +59,9 @@ extern "C" {
 /* ---- precision of the projection / Gram / TTMc path ------------------- */
 #define TK_FP64        0  /* FP64 everywhere */
 #define TK_FP32        1  /* FP32 projections, FP32 MFMA Grams; eigensolve, core, fit FP64 */
-#define TK_MIXED_BF16  2  /* BF16 projections for the Grams, BF16 MFMA with FP32
-                             accumulation; eigensolve, core and fit FP64 */
+#define TK_MIXED_BF16  2  /* BF16 projections for the Grams (MP: FP32 sums of FP16
+                             factor rows), BF16 MFMA with FP32 accumulation;
+                             eigensolve, core and fit FP64 */
 #define TK_MIXED_BF16X3 3 /* MP only: each projection for the Grams as a BF16 pair
                              (rounded value + rounded remainder, from FP32 factors),
                              Grams as hi hi^T + hi lo^T + lo hi^T on BF16 MFMA with

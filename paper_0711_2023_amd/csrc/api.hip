@@ -122,7 +122,8 @@ struct Plan {
     double *theta;
     float *F32[3] = {nullptr, nullptr, nullptr};
     bf16 *F16[3] = {nullptr, nullptr, nullptr};
-    void *Fp[3] = {nullptr, nullptr, nullptr};  // MP: factor rows padded to ldT, zero padding, type of T
+    void *Fp[3] = {nullptr, nullptr, nullptr};  // MP: factor rows padded to ldT, zero padding
+                                                //     (FP64 / FP32; FP16 for BF16 T)
     double *Z, *Gp, *core_split;
     int64_t core_split_elems;
     double *Gx, *Pn[3], *W1, *W2;
@@ -270,8 +271,10 @@ static void carve(Plan &p, Arena &ar) {
         for (int n = 0; n < 3; ++n) {
             p.F32[n] = prec != P64 ? ar.take<float>(p.I[n] * p.J[n]) : nullptr;
             p.F16[n] = prec == PBF16 ? ar.take<bf16>(p.I[n] * p.J[n]) : nullptr;
-            // padded factor rows for the projections (FP32 for split Grams:
-            // their lo parts need more than BF16 factors)
+            // padded factor rows for the projections: FP16 for BF16 T (more
+            // significand than BF16 for entries of orthonormal columns, and
+            // the projection's FMA takes FP16 operands directly), FP32 for
+            // split Grams (their lo parts need more than 16-bit factors)
             p.Fp[n] = p.algo == TK_ALGO_MP
                           ? ar.take<char>(p.I[n] * p.ldT[n] * (int64_t)(p.split ? 4 : elem_size(prec)))
                           : nullptr;
@@ -460,6 +463,23 @@ struct Timer {
         (void)hipEventRecord(ev[used + 1], s);
         used += 2;
     }
+    // A pair for a single kernel that records them itself at its start and
+    // end (kernel time without the dispatch gap an event bracket includes).
+    KernelEvents kernel(int k) {
+        if (!on) return KernelEvents();
+        if (used + 2 > ev.size()) {
+            for (int i = 0; i < 2; ++i) {
+                hipEvent_t e;
+                (void)hipEventCreate(&e);
+                ev.push_back(e);
+            }
+        }
+        kind.resize(used / 2 + 1);
+        kind[used / 2] = k;
+        const KernelEvents ke{ev[used], ev[used + 1]};
+        used += 2;
+        return ke;
+    }
     // call after a stream synchronisation
     void collect() {
         if (!on) return;
@@ -530,33 +550,36 @@ static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double
 
 // T(m) = X x_m F^T for the given output precision. F64 is the FP64 factor;
 // its FP32 copy must be current for FP32 / BF16 outputs.
-static hipError_t project_m(Plan &p, int m, const double *F64, void *T, int out_prec, hipStream_t s, int ld = 0) {
+static hipError_t project_m(Plan &p, int m, const double *F64, void *T, int out_prec, hipStream_t s, int ld = 0,
+                            KernelEvents ke = KernelEvents()) {
     const int J = p.J[m];
     if (ld <= 0) ld = p.ldT[m];
+    const int32_t *ptr = p.ptr[m], *lidx = p.lidx[m];
+    const int64_t I = p.I[m], ns = p.nslots[m];
     if (p.split && T == p.T[m] && out_prec == PBF16 && ld == p.ldT[m])  // the Gram copy: hi and lo parts
-        return project_split(p.ptr[m], p.lidx[m], p.lval32[m], (const float *)p.Fp[m], ld, J, p.nslots[m],
-                             (bf16 *)T, (bf16 *)p.Tlo[m], s, p.tune);
-    // the padded copy (rows of ldT, type of T) when T has that stride and
-    // type, else rows of J
+        return project_split(ptr, lidx, p.lval32[m], (const float *)p.Fp[m], I, ld, J, ns, p.nnz, (bf16 *)T,
+                             (bf16 *)p.Tlo[m], s, p.tune, ke);
+    // the padded copy (rows of ldT) when T has that stride and type, else
+    // rows of J
     const bool padded = p.Fp[m] && ld == p.ldT[m] && out_prec == p.prec;
     if (padded) {
         if (out_prec == P64)
-            return project<double, double, double>(p.ptr[m], p.lidx[m], p.lval64[m], (const double *)p.Fp[m], ld, J,
-                                                   ld, p.nslots[m], (double *)T, s, p.tune);
+            return project<double, double, double>(ptr, lidx, p.lval64[m], (const double *)p.Fp[m], I, ld, J, ld, ns,
+                                                   p.nnz, (double *)T, s, p.tune, ke);
         if (out_prec == P32)
-            return project<float, float, float>(p.ptr[m], p.lidx[m], p.lval32[m], (const float *)p.Fp[m], ld, J, ld,
-                                                p.nslots[m], (float *)T, s, p.tune);
-        return project<float, bf16, bf16>(p.ptr[m], p.lidx[m], p.lval32[m], (const bf16 *)p.Fp[m], ld, J, ld,
-                                          p.nslots[m], (bf16 *)T, s, p.tune);
+            return project<float, float, float>(ptr, lidx, p.lval32[m], (const float *)p.Fp[m], I, ld, J, ld, ns,
+                                                p.nnz, (float *)T, s, p.tune, ke);
+        return project<float, f16, bf16>(ptr, lidx, p.lval32[m], (const f16 *)p.Fp[m], I, ld, J, ld, ns, p.nnz,
+                                         (bf16 *)T, s, p.tune, ke);
     }
     if (out_prec == P64)
-        return project<double, double, double>(p.ptr[m], p.lidx[m], p.lval64[m], F64, J, J, ld, p.nslots[m],
-                                               (double *)T, s, p.tune);
+        return project<double, double, double>(ptr, lidx, p.lval64[m], F64, I, J, J, ld, ns, p.nnz, (double *)T, s,
+                                               p.tune, ke);
     if (out_prec == P32)
-        return project<float, float, float>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, J, ld, p.nslots[m],
-                                            (float *)T, s, p.tune);
-    return project<float, float, bf16>(p.ptr[m], p.lidx[m], p.lval32[m], p.F32[m], J, J, ld, p.nslots[m], (bf16 *)T,
-                                       s, p.tune);
+        return project<float, float, float>(ptr, lidx, p.lval32[m], p.F32[m], I, J, J, ld, ns, p.nnz, (float *)T, s,
+                                            p.tune, ke);
+    return project<float, float, bf16>(ptr, lidx, p.lval32[m], p.F32[m], I, J, J, ld, ns, p.nnz, (bf16 *)T, s,
+                                       p.tune, ke);
 }
 
 static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s) {
@@ -569,7 +592,7 @@ static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s)
         else if (p.prec == P32 || p.split)
             TK_HIP(pad_rows<float>(F, p.I[n], p.J[n], p.ldT[n], (float *)p.Fp[n], s));
         else
-            TK_HIP(pad_rows<bf16>(F, p.I[n], p.J[n], p.ldT[n], (bf16 *)p.Fp[n], s));
+            TK_HIP(pad_rows<f16>(F, p.I[n], p.J[n], p.ldT[n], (f16 *)p.Fp[n], s));
     }
     return hipSuccess;
 }
@@ -788,12 +811,8 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     const int prec = p.prec;
     double *A = factors[0], *B = factors[1], *C = factors[2];
     // projections of the start: T(1)(B), T(2)(C)
-    tm.begin(kProj);
-    ST(project_m(p, 1, B, p.T[1], prec, s));
-    tm.end();
-    tm.begin(kProj);
-    ST(project_m(p, 2, C, p.T[2], prec, s));
-    tm.end();
+    ST(project_m(p, 1, B, p.T[1], prec, s, 0, tm.kernel(kProj)));
+    ST(project_m(p, 2, C, p.T[2], prec, s, 0, tm.kernel(kProj)));
     double prev = 0.0;
     int t = 0;
     *iters_done = 0;
@@ -805,9 +824,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         tm.begin(kEig);
         if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
         tm.end();
-        tm.begin(kProj);
-        ST(project_m(p, 0, A, p.T[0], prec, s));
-        tm.end();
+        ST(project_m(p, 0, A, p.T[0], prec, s, 0, tm.kernel(kProj)));
         // M2 (mode 1) from T(0) and T(2)
         tm.begin(kGram);
         ST(mp_gram(p, 1, 0, 2, s));
@@ -815,9 +832,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         tm.begin(kEig);
         if ((st = run_eig(p, 1, p.Mg, B, true, o, stats, &noconv, s))) return st;
         tm.end();
-        tm.begin(kProj);
-        ST(project_m(p, 1, B, p.T[1], prec, s));
-        tm.end();
+        ST(project_m(p, 1, B, p.T[1], prec, s, 0, tm.kernel(kProj)));
         // M3 (mode 2) from T(0) and T(1)
         tm.begin(kGram);
         ST(mp_gram(p, 2, 0, 1, s));
@@ -825,15 +840,13 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         tm.begin(kEig);
         if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
         tm.end();
-        tm.begin(kProj);
-        ST(project_m(p, 2, C, p.T[2], prec, s));
-        tm.end();
+        ST(project_m(p, 2, C, p.T[2], prec, s, 0, tm.kernel(kProj)));
         // core from T(2)(C) (FP64 or FP32, never BF16)
         const void *T2c = p.T[2];
         bool f64 = prec == P64;
         if (prec == PBF16) {
-            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.J[2], p.J[2], p.nslots[2],
-                                             p.Tcore, s)));
+            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.I[2], p.J[2], p.J[2],
+                                             p.J[2], p.nslots[2], p.nnz, p.Tcore, s)));
             T2c = p.Tcore;
         }
         tm.begin(kCore);
@@ -857,8 +870,8 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         tm.end();
         const void *T2c = p.T[2];
         if (prec == PBF16) {
-            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.J[2], p.J[2], p.J[2], p.nslots[2],
-                                             p.Tcore, s)));
+            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.I[2], p.J[2], p.J[2],
+                                             p.J[2], p.nslots[2], p.nnz, p.Tcore, s)));
             T2c = p.Tcore;
         }
         tm.begin(kCore);
@@ -934,9 +947,7 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
     int maxit = o->max_iters > 0 ? o->max_iters : 0;
     for (int t = 1; t <= std::max(maxit, 1); ++t) {
         const bool last_only = (maxit == 0);
-        tm.begin(kProj);
-        ST(project_m(p, 2, C, p.T[2], tprec, s));
-        tm.end();
+        ST(project_m(p, 2, C, p.T[2], tprec, s, 0, tm.kernel(kProj)));
         const void *Bop = prec == P64 ? (const void *)B : (prec == P32 ? (const void *)p.F32[1] : (const void *)p.F16[1]);
         // mode 0: Y0[q][i0][r2] = sum_i1 B[i1][q] T2[i1][i0][r2]
         tm.begin(kTtmc);
@@ -983,9 +994,7 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
         // mode 2 (and the core): T(0)(A) = [i2][i1][r0] in FP64 / FP32
         void *T0 = prec == PBF16 ? (void *)p.T0f : p.T[0];
         const int t0prec = prec == P64 ? P64 : P32;
-        tm.begin(kProj);
-        ST(project_m(p, 0, A, T0, t0prec, s));
-        tm.end();
+        ST(project_m(p, 0, A, T0, t0prec, s, 0, tm.kernel(kProj)));
         const void *Bop2 = prec == P64 ? (const void *)B : (const void *)p.F32[1];
         // Y2[i2][q][r0] = sum_i1 B[i1][q] T0[i2][i1][r0]
         tm.begin(kTtmc);
@@ -1078,8 +1087,8 @@ extern "C" int tucker_fit(const tk_coo *X, const int32_t *J, const double *core,
     const int J0 = J[0], J1 = J[1], J2 = J[2];
     const int64_t nJ = (int64_t)J0 * J1 * J2;
     // Gx = X x_n A(n)^T via T(2)(C) and the two contractions of the MP core
-    ST((project<double, double, double>(p.ptr[2], p.lidx[2], p.lval64[2], factors[2], J2, J2, J2, p.nslots[2],
-                                        (double *)p.T[2], s)));
+    ST((project<double, double, double>(p.ptr[2], p.lidx[2], p.lval64[2], factors[2], p.I[2], J2, J2, J2,
+                                        p.nslots[2], p.nnz, (double *)p.T[2], s)));
     ST(core_from_T2(p, p.T[2], J2, true, factors[0], factors[1], p.Gx, s));
     ST(dot(p.Gx, core, nJ, p.partials, p.scal + 3, s));
     // P_n = A(n)^T A(n)

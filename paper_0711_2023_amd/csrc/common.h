@@ -9,6 +9,7 @@
 namespace tk {
 
 typedef __bf16 bf16;
+typedef _Float16 f16;
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -113,19 +114,29 @@ struct Tune {
     int gram_min_stages = 4;    // K stages per Gram workgroup, at least
 };
 
+// Events a kernel launch records itself at the kernel's start and end (both
+// null: an ordinary launch).
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // ---------------------------------------------------------------- project.hip
 // T[slot * ldT + r] = sum over the slot's entries of lval * F[lidx * ldF + r]
 // for r < J, zero for J <= r < ldT; slots = I_hi * I_lo, dense and
-// zero-filled. With ldF == ldT, 16-byte rows and F's padding columns zero
-// (as pad_rows leaves them), whole 16-byte chunks are computed at once.
+// zero-filled; F has rowsF rows (the leaf mode's size) and the ordering at
+// most nnz nonzeros. With ldF == ldT,
+// 16-byte rows and F's padding columns zero (as pad_rows leaves them), whole
+// 16-byte chunks are computed at once.
 template <class TV, class TF, class TO>
-hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int ldF, int J, int ldT,
-                   int64_t nslots, TO *T, hipStream_t s, const Tune &tn = Tune());
-// out[i * ld + r] = in[i * J + r] for r < J, zero for J <= r < ld.
+hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int64_t rowsF, int ldF,
+                   int J, int ldT, int64_t nslots, int64_t nnz, TO *T, hipStream_t s, const Tune &tn = Tune(),
+                   KernelEvents ke = KernelEvents());
 // Projection into a BF16 pair (hi = rounded value, lo = rounded remainder)
 // from FP32 factor rows padded to ld (a multiple of 8), for split-BF16 Grams.
-hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *lval, const float *F, int ld, int J,
-                         int64_t nslots, bf16 *Thi, bf16 *Tlo, hipStream_t s, const Tune &tn = Tune());
+hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *lval, const float *F, int64_t rowsF,
+                         int ld, int J, int64_t nslots, int64_t nnz, bf16 *Thi, bf16 *Tlo, hipStream_t s,
+                         const Tune &tn = Tune(), KernelEvents ke = KernelEvents());
+// out[i * ld + r] = in[i * J + r] for r < J, zero for J <= r < ld.
 template <class TO>
 hipError_t pad_rows(const double *in, int64_t rows, int J, int ld, TO *out, hipStream_t s);
 

@@ -9,16 +9,26 @@
 // is written exactly once, empty fibres as zeros.
 //
 // The kernel is bound by HBM writes of T. A workgroup owns a contiguous run
-// of slots (about 8192 output elements). It first stages the run's slot
+// of slots (about 32768 output elements). It first stages the run's slot
 // pointers and its nonzeros (leaf index, value) in LDS with coalesced loads,
 // so the dependent chain pointer -> nonzero -> factor row costs two bulk
-// loads per workgroup instead of three trips to memory per element. Then
-// lanes cover consecutive output elements: lanes in the same slot read the
-// same staged nonzeros and consecutive entries of a factor row (coalesced,
-// served by L2), and stores write contiguous memory. Each thread takes its
-// elements in batches of 8 and issues the factor loads of a batch together. Nonzeros beyond the LDS
-// capacity (a run with very long fibres) are read from global memory.
+// loads per workgroup instead of three trips to memory per element.
+//
+// Vector form (padded rows): a thread owns one 16-byte column chunk of the
+// output for the whole run and walks the run's slots with a fixed stride, so
+// no index division remains in the loop; lanes of one slot read one factor
+// row (served by L2) and a wave stores 1 KiB of contiguous output. Factor
+// rows are read and T written through buffer descriptors with 32-bit
+// offsets, whose range check turns the load of an empty fibre into zeros.
+// The loop is bound by vector-ALU issue (a wave64 instruction takes four
+// cycles), so the per-nonzero work is kept to the address, the LDS read and
+// one fused multiply-add per output; with an FP16 factor copy the
+// multiply-add takes the FP16 operand directly (mixed FP16/FP32 FMA).
+// Nonzeros beyond the LDS capacity (a run with very long fibres) are read
+// from global memory.
 #include "common.h"
+
+#include <hip/hip_ext.h>
 
 namespace tk {
 
@@ -29,46 +39,42 @@ struct AccOf<double> { typedef double type; };
 
 constexpr int kProjThreads = 256;
 constexpr int kProjU = 8;          // independent elements per thread per batch (general form)
-constexpr int kProjUV = 2;         // independent 16-byte chunks per thread per batch (vector form)
 
-template <class TO>
-struct Vec16;
-template <>
-struct Vec16<double> { typedef double __attribute__((ext_vector_type(2))) type; };
-template <>
-struct Vec16<float> { typedef float __attribute__((ext_vector_type(4))) type; };
-template <>
-struct Vec16<bf16> { typedef bf16 __attribute__((ext_vector_type(8))) type; };
+template <class T>
+struct Vec16 { typedef T __attribute__((ext_vector_type(16 / sizeof(T)))) type; };
 
-// Stage the run's slot pointers and nonzeros into LDS: sptr[0..ns], then up to
-// cap nonzeros. Returns the number staged.
-template <class TV>
-__device__ inline int stage_run(const int32_t *__restrict__ ptr, const int32_t *__restrict__ lidx,
-                                const TV *__restrict__ lval, int64_t s0, int ns, int cap, int32_t *sptr,
-                                int32_t *sidx, TV *sval, int32_t &q0) {
-    const int tid = threadIdx.x;
-    for (int i = tid; i <= ns; i += kProjThreads) sptr[i] = ptr[s0 + i];
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Stage the run's slot pointers into LDS: sptr[0..ns]; returns the pointer of
+// the run's first nonzero.
+__device__ inline int32_t stage_ptr(const int32_t *__restrict__ ptr, int64_t s0, int ns, int32_t *sptr) {
+    for (int i = threadIdx.x; i <= ns; i += kProjThreads) sptr[i] = ptr[s0 + i];
     __syncthreads();
-    q0 = sptr[0];
-    const int nq = sptr[ns] - q0;
-    const int nst = nq < cap ? nq : cap;
-    for (int i = tid; i < nst; i += kProjThreads) {
-        sidx[i] = lidx[q0 + i];
-        sval[i] = lval[q0 + i];
-    }
-    __syncthreads();
-    return nst;
+    return sptr[0];
 }
 
+// Buffer descriptor over [base, base + bytes): a load at or past the end
+// returns zeros and a store there is dropped. The range check covers the
+// per-lane offset only, so every offset is passed in the per-lane operand.
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+constexpr uint32_t kOffNone = 0x80000000u;  // past every projection buffer (all are below 2 GiB)
+
+// Nonzero p of the run (p relative to the run's first): staged copy for
+// p < nst, else global memory. The LDS read is issued unconditionally at a
+// clamped index and the global read is a distinct (streaming) load, so that
+// the LDS read stays an LDS access (a read that may come from either space
+// would otherwise become one generic load through the vector memory path).
 template <class TV>
 __device__ inline void nz_at(int p, int nst, int32_t q0, const int32_t *sidx, const TV *sval,
                              const int32_t *__restrict__ lidx, const TV *__restrict__ lval, int32_t &id, TV &v) {
-    if (p < nst) {
-        id = sidx[p];
-        v = sval[p];
-    } else {
-        id = lidx[q0 + p];
-        v = lval[q0 + p];
+    const int ps = p < nst ? p : 0;
+    id = sidx[ps];
+    v = sval[ps];
+    if (p >= nst) {
+        id = __builtin_nontemporal_load(lidx + q0 + p);
+        v = __builtin_nontemporal_load(lval + q0 + p);
     }
 }
 
@@ -87,8 +93,14 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const int32_t *__restr
     const int tid = threadIdx.x;
     const int64_t s0 = (int64_t)blockIdx.x * spw;
     const int ns = (int)(s0 + spw <= nslots ? spw : nslots - s0);
-    int32_t q0;
-    const int nst = stage_run(ptr, lidx, lval, s0, ns, cap, sptr, sidx, sval, q0);
+    const int32_t q0 = stage_ptr(ptr, s0, ns, sptr);
+    const int nq = sptr[ns] - q0;
+    const int nst = nq < cap ? nq : cap;
+    for (int i = tid; i < nst; i += kProjThreads) {
+        sidx[i] = lidx[q0 + i];
+        sval[i] = lval[q0 + i];
+    }
+    __syncthreads();
     const int nel = ns * ldT;
     const float rld = 1.0f / (float)ldT;
     TO *out = T + s0 * ldT;
@@ -132,100 +144,134 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const int32_t *__restr
     }
 }
 
-// Row strides of T and F equal and a multiple of 16 bytes, F's padding
-// columns zero: each thread produces whole 16-byte chunks of T, which never
-// cross a slot, from 16-byte loads of F rows and one vector store per chunk.
-// SPLIT: T receives each output rounded to TO and Tlo the rounded remainder
-// (the value minus its rounded part), so T + Tlo carries about twice the
-// significand bits of TO.
+// A staged nonzero: leaf index and value side by side (one LDS read).
+template <class TV>
+struct NzPair;
+template <>
+struct NzPair<float> { int32_t i; float v; };
+template <>
+struct NzPair<double> { int32_t i; int32_t pad; double v; };
+
+// Unstaged nonzero p of the run, through descriptors over the run's index and
+// value arrays (a buffer load, which cannot merge with the LDS read of the
+// staged case).
+__device__ inline void nz_global(__amdgpu_buffer_rsrc_t ri, __amdgpu_buffer_rsrc_t rv, int p, NzPair<float> &e) {
+    e.i = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(ri, (uint32_t)p * 4u, 0, 0);
+    e.v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rv, (uint32_t)p * 4u, 0, 0));
+}
+__device__ inline void nz_global(__amdgpu_buffer_rsrc_t ri, __amdgpu_buffer_rsrc_t rv, int p, NzPair<double> &e) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    e.i = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(ri, (uint32_t)p * 4u, 0, 0);
+    e.v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rv, (uint32_t)p * 8u, 0, 0));
+}
+
+__device__ inline float fused(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fused(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// acc[t] (+)= v * F entry t of the 16-byte loads x (FP16 / BF16 / FP32 / FP64 rows).
+template <class TF, int NL, class Acc, bool FIRST>
+__device__ inline void fma_row(const u32x4 (&x)[NL], Acc v, Acc *acc) {
+    constexpr int FPV = 16 / sizeof(TF);
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+        const typename Vec16<TF>::type f = __builtin_bit_cast(typename Vec16<TF>::type, x[l]);
+#pragma unroll
+        for (int t = 0; t < FPV; ++t)  // the first as a fused product with zero: one mixed FMA for FP16 rows
+            acc[l * FPV + t] = fused(v, (Acc)f[t], FIRST ? (Acc)0 : acc[l * FPV + t]);
+    }
+}
+
+template <int NL>
+__device__ inline void load_row(__amdgpu_buffer_rsrc_t r, uint32_t off, u32x4 (&x)[NL]) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) x[l] = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16 * l, 0, 0);
+}
+
+// Row strides of T and F equal (ldT) and a multiple of 16 bytes of T, F's
+// padding columns zero, F below 2 GiB with fewer than 2^24 rows: each thread
+// produces whole 16-byte chunks of T. SPLIT: T receives each output rounded
+// to TO and Tlo the rounded remainder (the value minus its rounded part), so
+// T + Tlo carries about twice the significand bits of TO.
 template <class TV, class TF, class TO, bool SPLIT = false>
 __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__restrict__ ptr,
                                                               const int32_t *__restrict__ lidx,
                                                               const TV *__restrict__ lval,
-                                                              const TF *__restrict__ F, int32_t J, int32_t ldT,
-                                                              int32_t spw, int32_t cap, int64_t nslots,
+                                                              const TF *__restrict__ F, uint32_t Fbytes, int32_t J,
+                                                              int32_t ldT, int32_t spw, int32_t cap, int64_t nslots,
                                                               TO *__restrict__ T, TO *__restrict__ Tlo = nullptr) {
     typedef typename AccOf<TV>::type Acc;
-    typedef typename Vec16<TF>::type FV;
-    constexpr int V = 16 / sizeof(TO);            // outputs per chunk
-    constexpr int FPV = 16 / sizeof(TF);          // factor entries per 16-byte load
-    constexpr int NL = V / FPV;                   // loads per chunk
-    constexpr int U = kProjUV;
+    constexpr int V = 16 / sizeof(TO);              // outputs per chunk
+    constexpr int NL = V * (int)sizeof(TF) / 16;    // 16-byte factor loads per chunk
     extern __shared__ __attribute__((aligned(16))) int32_t smem[];
-    int32_t *sptr = smem, *sidx = smem + ((spw + 4) & ~3);
-    TV *sval = reinterpret_cast<TV *>(sidx + ((cap + 3) & ~3));
+    int32_t *sptr = smem;
+    NzPair<TV> *snz = reinterpret_cast<NzPair<TV> *>(smem + ((spw + 4) & ~3));
     const int tid = threadIdx.x;
     const int64_t s0 = (int64_t)blockIdx.x * spw;
     const int ns = (int)(s0 + spw <= nslots ? spw : nslots - s0);
-    int32_t q0;
-    const int nst = stage_run(ptr, lidx, lval, s0, ns, cap, sptr, sidx, sval, q0);
-    const int cps = ldT / V;  // chunks per slot
-    const int nch = ns * cps;
-    const float rcps = 1.0f / (float)cps;
-    TO *out = T + s0 * ldT;
-    for (int cb = tid; cb < nch; cb += kProjThreads * U) {
-        int r0[U], a[U], b[U], id[U];
-        TV v[U];
-        Acc acc[U][V];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int c = cb + u * kProjThreads;
-            int sl = (int)((float)c * rcps);
-            if (sl * cps > c) --sl;
-            if ((sl + 1) * cps <= c) ++sl;
-            r0[u] = (c - sl * cps) * V;
-            a[u] = 0;
-            b[u] = 0;
-            if (c < nch && r0[u] < J) {
-                a[u] = sptr[sl] - q0;
-                b[u] = sptr[sl + 1] - q0;
-            }
-            id[u] = 0;
-            v[u] = 0;
-            if (a[u] < b[u]) nz_at(a[u], nst, q0, sidx, sval, lidx, lval, id[u], v[u]);
+    // uniform across the workgroup (the descriptors below must be scalar)
+    const int32_t q0 = __builtin_amdgcn_readfirstlane(stage_ptr(ptr, s0, ns, sptr));
+    const int nq = __builtin_amdgcn_readfirstlane(sptr[ns] - q0);
+    const int nst = nq < cap ? nq : cap;
+    for (int i = tid; i < nst; i += kProjThreads) {
+        NzPair<TV> e{};
+        e.i = lidx[q0 + i];
+        e.v = lval[q0 + i];
+        snz[i] = e;
+    }
+    __syncthreads();
+    const int cps = ldT / V;            // chunks per slot
+    const int spi = kProjThreads / cps; // slots per pass of the workgroup
+    const int tsl = tid / cps, r = tid - tsl * cps;
+    if (tsl >= spi) return;
+    const bool col_on = r * V < J;
+    const uint32_t rowb = (uint32_t)ldT * sizeof(TF), coloff = (uint32_t)r * V * sizeof(TF);
+    const __amdgpu_buffer_rsrc_t fr = buf_rsrc(F, Fbytes);
+    const uint32_t outb = (uint32_t)ns * (uint32_t)ldT * sizeof(TO);
+    const __amdgpu_buffer_rsrc_t orr = buf_rsrc(T + s0 * ldT, outb);
+    const __amdgpu_buffer_rsrc_t ri = buf_rsrc(lidx + q0, (uint32_t)nq * 4u);
+    const __amdgpu_buffer_rsrc_t rv = buf_rsrc(lval + q0, (uint32_t)nq * (uint32_t)sizeof(TV));
+    for (int sl = tsl; sl < ns; sl += spi) {
+        int a = 0, b = 0;
+        if (col_on) {
+            a = sptr[sl] - q0;
+            b = sptr[sl + 1] - q0;
         }
-        FV f[U][NL];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int l = 0; l < NL; ++l)
-                f[u][l] = a[u] < b[u] ? *reinterpret_cast<const FV *>(F + (int64_t)id[u] * ldT + r0[u] + l * FPV)
-                                      : FV(0);
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int l = 0; l < NL; ++l)
-#pragma unroll
-                for (int t = 0; t < FPV; ++t) acc[u][l * FPV + t] = (Acc)v[u] * (Acc)f[u][l][t];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            for (int p = a[u] + 1; p < b[u]; ++p) {
-                int32_t i2;
-                TV v2;
-                nz_at(p, nst, q0, sidx, sval, lidx, lval, i2, v2);
-                const FV *row = reinterpret_cast<const FV *>(F + (int64_t)i2 * ldT + r0[u]);
-#pragma unroll
-                for (int l = 0; l < NL; ++l) {
-                    const FV g = row[l];
-#pragma unroll
-                    for (int t = 0; t < FPV; ++t) acc[u][l * FPV + t] += (Acc)v2 * (Acc)g[t];
-                }
+        // first nonzero; an empty fibre loads zeros from past the end of F
+        NzPair<TV> e = snz[a < nst ? a : 0];
+        if (a < b && a >= nst) nz_global(ri, rv, a, e);
+        Acc acc[V];
+        {
+            u32x4 x[NL];
+            load_row<NL>(fr, a < b ? __umul24((uint32_t)e.i, rowb) + coloff : kOffNone, x);
+            fma_row<TF, NL, Acc, true>(x, a < b ? (Acc)e.v : (Acc)0, acc);
+        }
+        if (b <= nst) {
+            for (int p = a + 1; p < b; ++p) {
+                const NzPair<TV> e2 = snz[p];
+                u32x4 x[NL];
+                load_row<NL>(fr, __umul24((uint32_t)e2.i, rowb) + coloff, x);
+                fma_row<TF, NL, Acc, false>(x, (Acc)e2.v, acc);
             }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int c = cb + u * kProjThreads;
-            if (c < nch) {
-                typename Vec16<TO>::type o;
-#pragma unroll
-                for (int t = 0; t < V; ++t) o[t] = (TO)acc[u][t];
-                *reinterpret_cast<typename Vec16<TO>::type *>(out + (int64_t)c * V) = o;
-                if (SPLIT) {
-                    typename Vec16<TO>::type o2;
-#pragma unroll
-                    for (int t = 0; t < V; ++t) o2[t] = (TO)(acc[u][t] - (Acc)o[t]);
-                    *reinterpret_cast<typename Vec16<TO>::type *>(Tlo + s0 * ldT + (int64_t)c * V) = o2;
-                }
+        } else {
+            for (int p = a + 1; p < b; ++p) {
+                NzPair<TV> e2 = snz[p < nst ? p : 0];
+                if (p >= nst) nz_global(ri, rv, p, e2);
+                u32x4 x[NL];
+                load_row<NL>(fr, __umul24((uint32_t)e2.i, rowb) + coloff, x);
+                fma_row<TF, NL, Acc, false>(x, (Acc)e2.v, acc);
             }
+        }
+        const uint32_t off = (uint32_t)(sl * cps + r) * 16u;
+        typename Vec16<TO>::type o;
+#pragma unroll
+        for (int t = 0; t < V; ++t) o[t] = (TO)acc[t];
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, o), orr, off, 0, 0);
+        if (SPLIT) {
+            typename Vec16<TO>::type o2;
+#pragma unroll
+            for (int t = 0; t < V; ++t) o2[t] = (TO)(acc[t] - (Acc)o[t]);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, o2), buf_rsrc(Tlo + s0 * ldT, outb), off,
+                                                   0, 0);
         }
     }
 }
@@ -255,61 +301,95 @@ hipError_t pad_rows(const double *in, int64_t rows, int J, int ld, TO *out, hipS
     return hipSuccess;
 }
 
-template <class TV, class TF, class TO>
-hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int ldF, int J, int ldT,
-                   int64_t nslots, TO *T, hipStream_t s, const Tune &tn) {
-    if (nslots <= 0 || ldT <= 0) return hipSuccess;
+// Run length and staging capacity of a projection launch.
+struct ProjShape {
+    int spw, cap;
+    int64_t blocks;
+};
+static ProjShape proj_shape(int64_t nslots, int ld, const Tune &tn, int cap_max) {
     // runs of slots: large enough to amortise the staging, small enough that
     // the grid still fills the chip
-    int spw = (int)std::min<int64_t>(tn.proj_elems / ldT, ceil_div(nslots, tn.proj_min_blocks));
-    if (spw < 1) spw = 1;
-    if (spw > 4096) spw = 4096;
-    // staged nonzeros: room for 4 per slot on average (at most 4096, so LDS
-    // stays under 64 KiB); longer runs read the rest from global memory
-    int cap = spw * 4 < 256 ? 256 : spw * 4;
-    if (cap > 4096) cap = 4096;
-    const size_t lds = sizeof(int32_t) * (((spw + 4) & ~3) + ((cap + 3) & ~3)) + sizeof(TV) * cap;
-    const int64_t blocks = ceil_div(nslots, spw);
-    const bool vec = ldF == ldT && ldT % (16 / (int)sizeof(TO)) == 0 && ((uintptr_t)F & 15) == 0 &&
-                     ((uintptr_t)T & 15) == 0;
-    if (vec)
-        k_project_vec<TV, TF, TO><<<(unsigned)blocks, kProjThreads, lds, s>>>(ptr, lidx, lval, F, J, ldT, spw, cap,
-                                                                             nslots, T);
-    else
-        k_project<TV, TF, TO><<<(unsigned)blocks, kProjThreads, lds, s>>>(ptr, lidx, lval, F, ldF, J, ldT, spw,
-                                                                         cap, nslots, T);
-    TK_LAUNCHED();
-    return hipSuccess;
-}
-
-hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *lval, const float *F, int ld, int J,
-                         int64_t nslots, bf16 *Thi, bf16 *Tlo, hipStream_t s, const Tune &tn) {
-    if (nslots <= 0 || ld <= 0) return hipSuccess;
-    if (ld % 8 != 0 || ((uintptr_t)F & 15) != 0 || ((uintptr_t)Thi & 15) != 0 || ((uintptr_t)Tlo & 15) != 0)
-        return hipErrorInvalidValue;
     int spw = (int)std::min<int64_t>(tn.proj_elems / ld, ceil_div(nslots, tn.proj_min_blocks));
     if (spw < 1) spw = 1;
     if (spw > 4096) spw = 4096;
+    // staged nonzeros: room for 4 per slot on average; longer runs read the
+    // rest from global memory
     int cap = spw * 4 < 256 ? 256 : spw * 4;
-    if (cap > 4096) cap = 4096;
-    const size_t lds = sizeof(int32_t) * (((spw + 4) & ~3) + ((cap + 3) & ~3)) + sizeof(float) * cap;
-    const int64_t blocks = ceil_div(nslots, spw);
-    k_project_vec<float, float, bf16, true><<<(unsigned)blocks, kProjThreads, lds, s>>>(ptr, lidx, lval, F, J, ld,
-                                                                                       spw, cap, nslots, Thi, Tlo);
+    if (cap > cap_max) cap = cap_max;
+    return {spw, cap, ceil_div(nslots, spw)};
+}
+
+// The vector form's conditions beyond equal, 16-byte padded rows: 32-bit
+// buffer offsets for F, the run's output and its nonzeros, 24-bit row
+// indices, and a chunk column per thread.
+template <class TV, class TF, class TO>
+static bool vec_ok(const TF *F, int64_t rowsF, int ld, const void *T, int spw, int64_t nnz) {
+    const int V = 16 / (int)sizeof(TO);
+    return ld % V == 0 && ld / V <= kProjThreads && ((uintptr_t)F & 15) == 0 && ((uintptr_t)T & 15) == 0 &&
+           rowsF < (int64_t(1) << 24) && rowsF * ld * (int64_t)sizeof(TF) < (int64_t(1) << 31) &&
+           (int64_t)spw * ld * (int64_t)sizeof(TO) < (int64_t(1) << 31) &&
+           nnz * (int64_t)sizeof(TV) < (int64_t(1) << 32);
+}
+
+// Launch on s, through the extended launch when the caller asked for the
+// kernel's own start / end events.
+template <class K, class... A>
+static void launch(K kernel, int64_t blocks, size_t lds, hipStream_t s, KernelEvents ke, A... args) {
+    if (ke.start && ke.stop)
+        hipExtLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kProjThreads), (uint32_t)lds, s, ke.start, ke.stop,
+                              0u, args...);
+    else
+        kernel<<<(unsigned)blocks, kProjThreads, lds, s>>>(args...);
+}
+
+template <class TV, class TF, class TO>
+hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int64_t rowsF, int ldF,
+                   int J, int ldT, int64_t nslots, int64_t nnz, TO *T, hipStream_t s, const Tune &tn,
+                   KernelEvents ke) {
+    if (nslots <= 0 || ldT <= 0) return hipSuccess;
+    if (ldF == ldT && vec_ok<TV, TF, TO>(F, rowsF, ldT, T, proj_shape(nslots, ldT, tn, 4096).spw, nnz)) {
+        // pairs of 16 bytes for FP64 values: at most 2048 staged (32 KiB)
+        const ProjShape sh = proj_shape(nslots, ldT, tn, sizeof(TV) == 8 ? 2048 : 4096);
+        const size_t lds = sizeof(int32_t) * ((sh.spw + 4) & ~3) + sizeof(NzPair<TV>) * (size_t)sh.cap;
+        launch(k_project_vec<TV, TF, TO, false>, sh.blocks, lds, s, ke, ptr, lidx, lval, F,
+               (uint32_t)(rowsF * ldT * (int64_t)sizeof(TF)), (int32_t)J, (int32_t)ldT, (int32_t)sh.spw,
+               (int32_t)sh.cap, nslots, T, (TO *)nullptr);
+    } else {
+        const ProjShape sh = proj_shape(nslots, ldT, tn, 4096);
+        const size_t lds = sizeof(int32_t) * (((sh.spw + 4) & ~3) + ((sh.cap + 3) & ~3)) + sizeof(TV) * sh.cap;
+        launch(k_project<TV, TF, TO>, sh.blocks, lds, s, ke, ptr, lidx, lval, F, (int32_t)ldF, (int32_t)J,
+               (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap, nslots, T);
+    }
     TK_LAUNCHED();
     return hipSuccess;
 }
 
-template hipError_t project<double, double, double>(const int32_t *, const int32_t *, const double *, const double *,
-                                                    int, int, int, int64_t, double *, hipStream_t, const Tune &);
-template hipError_t project<float, float, float>(const int32_t *, const int32_t *, const float *, const float *, int,
-                                                 int, int, int64_t, float *, hipStream_t, const Tune &);
-template hipError_t project<float, float, bf16>(const int32_t *, const int32_t *, const float *, const float *, int,
-                                                int, int, int64_t, bf16 *, hipStream_t, const Tune &);
-template hipError_t project<float, bf16, bf16>(const int32_t *, const int32_t *, const float *, const bf16 *, int,
-                                               int, int, int64_t, bf16 *, hipStream_t, const Tune &);
+hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *lval, const float *F, int64_t rowsF,
+                         int ld, int J, int64_t nslots, int64_t nnz, bf16 *Thi, bf16 *Tlo, hipStream_t s,
+                         const Tune &tn, KernelEvents ke) {
+    if (nslots <= 0 || ld <= 0) return hipSuccess;
+    const ProjShape sh = proj_shape(nslots, ld, tn, 4096);
+    if (!vec_ok<float, float, bf16>(F, rowsF, ld, Thi, sh.spw, nnz) || ((uintptr_t)Tlo & 15) != 0)
+        return hipErrorInvalidValue;
+    const size_t lds = sizeof(int32_t) * ((sh.spw + 4) & ~3) + sizeof(NzPair<float>) * (size_t)sh.cap;
+    launch(k_project_vec<float, float, bf16, true>, sh.blocks, lds, s, ke, ptr, lidx, lval, F,
+           (uint32_t)(rowsF * ld * (int64_t)sizeof(float)), (int32_t)J, (int32_t)ld, (int32_t)sh.spw,
+           (int32_t)sh.cap, nslots, Thi, Tlo);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
+#define TK_PROJECT(TV, TF, TO)                                                                                 \
+    template hipError_t project<TV, TF, TO>(const int32_t *, const int32_t *, const TV *, const TF *, int64_t, int, \
+                                            int, int, int64_t, int64_t, TO *, hipStream_t, const Tune &,       \
+                                            KernelEvents);
+TK_PROJECT(double, double, double)
+TK_PROJECT(float, float, float)
+TK_PROJECT(float, float, bf16)
+TK_PROJECT(float, f16, bf16)
+#undef TK_PROJECT
 template hipError_t pad_rows<double>(const double *, int64_t, int, int, double *, hipStream_t);
-template hipError_t pad_rows<bf16>(const double *, int64_t, int, int, bf16 *, hipStream_t);
+template hipError_t pad_rows<f16>(const double *, int64_t, int, int, f16 *, hipStream_t);
 template hipError_t pad_rows<float>(const double *, int64_t, int, int, float *, hipStream_t);
 
 }  // namespace tk
