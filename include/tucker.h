@@ -121,7 +121,8 @@ typedef struct tk_opts {
                                at which an eigensolve stops (residual estimate, or
                                change across a full-degree filter step); 0 = by
                                precision (1e-12 for FP64, 1e-8 for FP32 and split
-                               BF16, 1e-6 for mixed BF16) */
+                               BF16, 1e-4 for mixed BF16: a tenth of the relative
+                               accuracy of the Gram at that precision) */
     int32_t timing;         /* 1: record HIP events around the projection and
                                TTMc kernels and report their times in tk_stats */
     const float *model;     /* [dev] TK_INIT_LEARNED: the network parameters

@@ -664,8 +664,8 @@ static int run_eig(Plan &p, int n, double *M, double *F, bool warm, const tk_opt
     // 0 = by precision: FP64 follows the oracle's exact eigensolver closely;
     // FP32 projections limit the Gram to about 1e-7 relative, BF16 ones (8
     // significant bits) to about 1e-3, so the sum of the leading Ritz values
-    // is resolved to 1e-8 and 1e-6 of itself respectively
-    eo.tol = o->eig_tol > 0 ? o->eig_tol : (p.prec == P64 ? 1e-12 : (p.prec == P32 || p.split ? 1e-8 : 1e-6));
+    // is resolved to a tenth of that: 1e-8 and 1e-4 of itself respectively
+    eo.tol = o->eig_tol > 0 ? o->eig_tol : (p.prec == P64 ? 1e-12 : (p.prec == P32 || p.split ? 1e-8 : 1e-4));
     eo.warm = warm && p.blk_ok[n];
     // a block left by the previous sweep's solve of this mode is usually
     // converged or nearly so: its filter starts at a low degree. Blocks from
