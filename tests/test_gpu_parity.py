@@ -113,6 +113,38 @@ def test_mid_reduced_precision_mp(tk, mid, prec, tol):
     assert max(abs(a - b) for a, b in zip(r.fits, ref.fits)) <= tol
 
 
+# ------------------------------------------------------------ long fibres: more nonzeros per run than LDS stages
+@pytest.fixture(scope="module")
+def longfib():
+    # 120 mode-3 fibres of length 1500 at 25 % density (338-404 nonzeros each):
+    # a projection run along mode 3 holds one or two fibres, more nonzeros than
+    # its LDS stage (256), so the projection reads the rest from global memory
+    idx, vals, dims = synth.bernoulli_sparse((12, 10, 1500), 0.25, 31)
+    return idx, vals, dims, O.SparseTensor3(idx, vals, dims), (3, 4, 6)
+
+
+@pytest.mark.parametrize("algo", ["mp", "hooi"])
+def test_long_fibres_fp64(tk, longfib, algo):
+    idx, vals, dims, X, J = longfib
+    _say(f"long fibres fp64 {algo}")
+    ref = (O.mp if algo == "mp" else O.hooi)(X, J, 3, 0.0, fit="identity")
+    di, dv = _dev(idx, vals)
+    r = getattr(tk, algo)(di, dv, dims, J, precision="fp64", max_iters=3, tol=0.0, eig_tol=1e-13)
+    np.testing.assert_allclose(r.fits, ref.fits, rtol=0, atol=1e-7)
+    f_or = O.fit_slicewise(X, r.core.cpu().numpy(), *[f.cpu().numpy() for f in r.factors])
+    assert abs(f_or - r.fits[-1]) < 1e-9
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("mixed", 1e-4), ("bf16x3", 1e-6)])
+def test_long_fibres_reduced_precision_mp(tk, longfib, prec, tol):
+    idx, vals, dims, X, J = longfib
+    _say(f"long fibres {prec} mp")
+    ref = O.mp(X, J, 3, 0.0, fit="identity")
+    di, dv = _dev(idx, vals)
+    r = tk.mp(di, dv, dims, J, precision=prec, max_iters=3, tol=0.0)
+    assert max(abs(a - b) for a, b in zip(r.fits, ref.fits)) <= tol
+
+
 def test_stopping_rule_matches_oracle(tk, mid):
     idx, vals, dims, X, J = mid
     _say("mid stopping rule")
