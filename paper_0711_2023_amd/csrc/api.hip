@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 namespace tk {
@@ -116,6 +117,10 @@ struct Plan {
     void *Y;           // HOOI second-stage output for the Gram
     float *Y2f;        // mixed HOOI: FP32 Y2 (core input)
     double *Mg;        // Gram (max In^2)
+    // HO-SVD start: Gram, eigensolver workspace and Ritz values of mode 3,
+    // whose start solve runs beside mode 2's
+    double *Mg2 = nullptr, *theta2 = nullptr;
+    char *eigw2 = nullptr;
     void *gram_scratch;
     double *Xblk[3];
     void *eigw;
@@ -268,6 +273,11 @@ static void carve(Plan &p, Arena &ar) {
         }
         p.eigw = ar.take<char>((int64_t)ew);
         p.theta = ar.take<double>(std::max<int64_t>(bmax, maxI));
+        if (p.init == TK_INIT_HOSVD) {
+            p.Mg2 = ar.take<double>(p.I[2] * p.I[2]);
+            p.eigw2 = ar.take<char>((int64_t)eig_work_bytes((int)p.I[2], p.b[2]));
+            p.theta2 = ar.take<double>(std::max<int64_t>(p.b[2], p.I[2]));
+        }
         for (int n = 0; n < 3; ++n) {
             p.F32[n] = prec != P64 ? ar.take<float>(p.I[n] * p.J[n]) : nullptr;
             p.F16[n] = prec == PBF16 ? ar.take<bf16>(p.I[n] * p.J[n]) : nullptr;
@@ -658,7 +668,7 @@ static int finish_fit(Plan &p, const double *core, hipStream_t s, double *fit) {
 }
 
 static int run_eig(Plan &p, int n, double *M, double *F, bool warm, const tk_opts *o, tk_stats *st,
-                   int *noconv_any, hipStream_t s) {
+                   int *noconv_any, hipStream_t s, void *eigw = nullptr, double *theta = nullptr) {
     EigOpts eo;
     eo.max_iters = o->eig_max_iters;
     // 0 = by precision: FP64 follows the oracle's exact eigensolver closely;
@@ -675,7 +685,8 @@ static int run_eig(Plan &p, int n, double *M, double *F, bool warm, const tk_opt
     if (warm) p.sweep_solves[n] += 1;
     eo.seed = 0x5eed0000ull + (uint64_t)n;
     int it = 0, nc = 0;
-    ST(lead_eig(M, (int)p.I[n], p.J[n], p.Xblk[n], F, p.theta, p.eigw, eo, &it, &nc, s));
+    ST(lead_eig(M, (int)p.I[n], p.J[n], p.Xblk[n], F, theta ? theta : p.theta, eigw ? eigw : p.eigw, eo, &it, &nc,
+                s));
     if (st) {
         st->eig_iters += it;
         st->eig_noconv += nc;
@@ -746,6 +757,69 @@ static int learned_mode(Plan &p, int n, const tk_opts *o, double *F, double nx2,
     return full_rank && better ? 1 : 0;
 }
 
+// HO-SVD start of modes 2 and 3. Each comes from its own unfolding (Figure 1)
+// and does not depend on the other; an eigensolve is a chain of small
+// launches with host decisions between them, so mode 3's Gram and solve run
+// on a second stream driven by a second host thread, beside mode 2's on s.
+static int hosvd_start_pair(Plan &p, const tk_opts *o, double *const *factors, tk_stats *st, int *noconv,
+                            hipStream_t s) {
+    const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
+    int dev = 0;
+    ST(hipGetDevice(&dev));
+    hipStream_t s2 = nullptr;
+    hipEvent_t e1 = nullptr, e2 = nullptr;
+    int r = TK_OK;
+    if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&e2, hipEventDisableTiming) != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+        hipStreamWaitEvent(s2, e1, 0) != hipSuccess)
+        r = TK_ERR_DEVICE;
+    tk_stats st2{};
+    int nc2 = 0, r2 = TK_OK;
+    if (r == TK_OK) {
+        std::thread th([&] {
+            if (hipSetDevice(dev) != hipSuccess) {
+                r2 = TK_ERR_DEVICE;
+                return;
+            }
+            // ordering 0's slots are the mode-3 slices
+            const hipError_t e = hosvd_gram(2, dims, p.ptr[2], p.lidx[2], p.lval64[2], p.ptr[0], p.lidx[0],
+                                            p.lval64[0], p.Mg2, s2);
+            if (e != hipSuccess) {
+                set_hip_error(e, "hosvd_gram");
+                r2 = TK_ERR_DEVICE;
+                return;
+            }
+            r2 = run_eig(p, 2, p.Mg2, factors[2], false, o, st ? &st2 : nullptr, &nc2, s2, p.eigw2, p.theta2);
+        });
+        // mode 2 here (ordering 2's slots are its slices); no early return
+        // while the other thread runs
+        const hipError_t e = hosvd_gram(1, dims, p.ptr[1], p.lidx[1], p.lval64[1], p.ptr[2], p.lidx[2], p.lval64[2],
+                                        p.Mg, s);
+        if (e != hipSuccess) {
+            set_hip_error(e, "hosvd_gram");
+            r = TK_ERR_DEVICE;
+        } else {
+            r = run_eig(p, 1, p.Mg, factors[1], false, o, st, noconv, s);
+        }
+        th.join();
+        if (r == TK_OK) r = r2;
+        // the sweeps on s follow mode 3's work
+        if (hipEventRecord(e2, s2) != hipSuccess || hipStreamWaitEvent(s, e2, 0) != hipSuccess)
+            r = r ? r : TK_ERR_DEVICE;
+        if (hipStreamSynchronize(s2) != hipSuccess) r = r ? r : TK_ERR_DEVICE;
+    }
+    if (st) {
+        st->eig_iters += st2.eig_iters;
+        st->eig_noconv += st2.eig_noconv;
+    }
+    if (nc2) *noconv = 1;
+    if (e2) (void)hipEventDestroy(e2);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s2) (void)hipStreamDestroy(s2);
+    return r;
+}
+
 static int init_factors(Plan &p, const tk_opts *o, double *const *factors, tk_stats *st, int *noconv, double nx2,
                         hipStream_t s) {
     const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
@@ -760,6 +834,7 @@ static int init_factors(Plan &p, const tk_opts *o, double *const *factors, tk_st
             p.blk_ok[0] = true;
         }
     }
+    if (o->init == TK_INIT_HOSVD && p.Mg2) return hosvd_start_pair(p, o, factors, st, noconv, s);
     for (int n = 1; n < 3; ++n) {
         if (o->init == TK_INIT_GIVEN) {
             ST(refresh_copies(p, n, factors[n], s));
