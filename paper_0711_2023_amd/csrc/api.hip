@@ -28,6 +28,17 @@ void set_hip_error(hipError_t e, const char *where) {
 constexpr int kMaxJ = 128;
 constexpr int64_t kMaxHosvdDim = 8192;
 
+// Buffers of one learned start: features, norms, network output, FP64
+// leading columns / H U, K x K Gram and eigenvectors, eigenvalues, pivots,
+// skinny partial strips, eigensolver workspace.
+struct LearnBufs {
+    float *LF = nullptr, *Lrho = nullptr, *LR = nullptr;
+    double *LQ = nullptr, *LHQ = nullptr, *LC = nullptr, *LV = nullptr, *Ltheta = nullptr, *Lg = nullptr;
+    double *Lpart = nullptr;
+    int64_t Lpart_elems = 0;
+    void *Leigw = nullptr;
+};
+
 // ------------------------------------------------------------------ small kernels
 __global__ void k_fit(const double *normx2, const double *g2, const double *xhx, const double *xh2, double *fit,
                       int general) {
@@ -132,15 +143,9 @@ struct Plan {
     double *Z, *Gp, *core_split;
     int64_t core_split_elems;
     double *Gx, *Pn[3], *W1, *W2;
-    // learned start (modes 1 and 2, one at a time): features, norms, network
-    // output, FP64 leading columns / H U, J x J Gram and eigenvectors, eigen-
-    // values, skinny partial strips, eigensolver workspace, back-propagation
-    // scratch
-    float *LF = nullptr, *Lrho = nullptr, *LR = nullptr;
-    double *LQ = nullptr, *LHQ = nullptr, *LC = nullptr, *LV = nullptr, *Ltheta = nullptr, *Lg = nullptr;
-    double *Lpart = nullptr;
-    int64_t Lpart_elems = 0;
-    void *Leigw = nullptr;
+    // learned start: one buffer set per start slot (slot 1 serves mode 3,
+    // whose start runs beside mode 2's)
+    LearnBufs L[2];
     bool blk_ok[3] = {false, false, false};  // Xblk[n] holds a previous block
     bool split = false;                      // MP with split-BF16 Grams (hi and lo parts)
     void *Tlo[3] = {nullptr, nullptr, nullptr};  // lo parts of the projections
@@ -273,7 +278,7 @@ static void carve(Plan &p, Arena &ar) {
         }
         p.eigw = ar.take<char>((int64_t)ew);
         p.theta = ar.take<double>(std::max<int64_t>(bmax, maxI));
-        if (p.init == TK_INIT_HOSVD) {
+        if (p.init == TK_INIT_HOSVD || p.init == TK_INIT_LEARNED) {
             p.Mg2 = ar.take<double>(p.I[2] * p.I[2]);
             p.eigw2 = ar.take<char>((int64_t)eig_work_bytes((int)p.I[2], p.b[2]));
             p.theta2 = ar.take<double>(std::max<int64_t>(p.b[2], p.I[2]));
@@ -305,18 +310,23 @@ static void carve(Plan &p, Arena &ar) {
     if (p.init == TK_INIT_LEARNED && p.algo != TK_ALGO_FIT) {
         int64_t In = std::max({p.I[0], p.I[1], p.I[2]});
         int Km = learn_test_width(std::max({p.J[0], p.J[1], p.J[2]}));
-        p.LF = ar.take<float>(In * 64);
-        p.Lrho = ar.take<float>(In);
-        p.LR = ar.take<float>(In * 128);
-        p.LQ = ar.take<double>(In * Km);
-        p.LHQ = ar.take<double>(In * Km);
-        p.LC = ar.take<double>((int64_t)Km * Km);
-        p.LV = ar.take<double>((int64_t)Km * Km);
-        p.Ltheta = ar.take<double>(Km);
-        p.Lg = ar.take<double>(Km);
-        p.Lpart_elems = skinny_part_bound(Km);
-        p.Lpart = ar.take<double>(p.Lpart_elems);
-        p.Leigw = ar.take<char>((int64_t)eig_work_bytes(Km, Km));
+        for (int k = 0; k < 2; ++k) {
+            LearnBufs &b = p.L[k];
+            const int64_t Ik = k == 0 ? In : p.I[2];
+            const int Kk = k == 0 ? Km : learn_test_width(p.J[2]);
+            b.LF = ar.take<float>(Ik * 64);
+            b.Lrho = ar.take<float>(Ik);
+            b.LR = ar.take<float>(Ik * 128);
+            b.LQ = ar.take<double>(Ik * Kk);
+            b.LHQ = ar.take<double>(Ik * Kk);
+            b.LC = ar.take<double>((int64_t)Kk * Kk);
+            b.LV = ar.take<double>((int64_t)Kk * Kk);
+            b.Ltheta = ar.take<double>(Kk);
+            b.Lg = ar.take<double>(Kk);
+            b.Lpart_elems = skinny_part_bound(Kk);
+            b.Lpart = ar.take<double>(b.Lpart_elems);
+            b.Leigw = ar.take<char>((int64_t)eig_work_bytes(Kk, Kk));
+        }
     }
 }
 
@@ -721,24 +731,26 @@ static int common_start(int algo, const tk_coo *X, const int32_t *J, const tk_op
 // H_n on the span of the network's first K outputs. Returns 1 when the start
 // is accepted, 0 when the mode must fall back to HO-SVD (H_n is left in p.Mg
 // either way), or a negative status.
-static int learned_mode(Plan &p, int n, const tk_opts *o, double *F, double nx2, hipStream_t s) {
+static int learned_mode(Plan &p, int n, const tk_opts *o, double *F, double nx2, hipStream_t s, LearnBufs &lb,
+                        double *Mg) {
     const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
     const int64_t In = p.I[n];
     const int J = p.J[n], K = learn_test_width(J);
     const int sl = (n + 1) % 3;  // ordering whose slots are the mode-n slices
     if (p.lval32[sl])
-        ST(learn_sketch<float>(p.ptr[sl], p.lidx[sl], p.lval32[sl], In, p.I[lo_of(sl)], n, o->seed, p.LF, p.Lrho, s));
+        ST(learn_sketch<float>(p.ptr[sl], p.lidx[sl], p.lval32[sl], In, p.I[lo_of(sl)], n, o->seed, lb.LF, lb.Lrho,
+                               s));
     else
-        ST(learn_sketch<double>(p.ptr[sl], p.lidx[sl], p.lval64[sl], In, p.I[lo_of(sl)], n, o->seed, p.LF, p.Lrho,
-                                s));
-    ST(learn_forward(p.LF, p.Lrho, In, o->model, p.LR, nullptr, s));
-    ST(hosvd_gram(n, dims, p.ptr[n], p.lidx[n], p.lval64[n], p.ptr[sl], p.lidx[sl], p.lval64[sl], p.Mg, s));
+        ST(learn_sketch<double>(p.ptr[sl], p.lidx[sl], p.lval64[sl], In, p.I[lo_of(sl)], n, o->seed, lb.LF,
+                                lb.Lrho, s));
+    ST(learn_forward(lb.LF, lb.Lrho, In, o->model, lb.LR, nullptr, s));
+    ST(hosvd_gram(n, dims, p.ptr[n], p.lidx[n], p.lval64[n], p.ptr[sl], p.lidx[sl], p.lval64[sl], Mg, s));
     if (K > In) return 0;  // no room for a test subspace: HO-SVD
-    ST(learn_start(p.LR, In, J, p.Mg, F, p.Ltheta, p.Lg, p.LQ, p.LHQ, p.LC, p.LV, p.Leigw, p.Lpart, p.Lpart_elems,
-                   s));
+    ST(learn_start(lb.LR, In, J, Mg, F, lb.Ltheta, lb.Lg, lb.LQ, lb.LHQ, lb.LC, lb.LV, lb.Leigw, lb.Lpart,
+                   lb.Lpart_elems, s));
     std::vector<double> th(J), g(K);
-    ST(hipMemcpyAsync(th.data(), p.Ltheta, sizeof(double) * J, hipMemcpyDeviceToHost, s));
-    ST(hipMemcpyAsync(g.data(), p.Lg, sizeof(double) * K, hipMemcpyDeviceToHost, s));
+    ST(hipMemcpyAsync(th.data(), lb.Ltheta, sizeof(double) * J, hipMemcpyDeviceToHost, s));
+    ST(hipMemcpyAsync(g.data(), lb.Lg, sizeof(double) * K, hipMemcpyDeviceToHost, s));
     ST(hipStreamSynchronize(s));
     // the start's captured energy tr(F^T H_n F) = sum of the Ritz values,
     // against Jn/In of ||X||^2 (a random Jn-dimensional subspace's mean)
@@ -757,13 +769,39 @@ static int learned_mode(Plan &p, int n, const tk_opts *o, double *F, double nx2,
     return full_rank && better ? 1 : 0;
 }
 
-// HO-SVD start of modes 2 and 3. Each comes from its own unfolding (Figure 1)
-// and does not depend on the other; an eigensolve is a chain of small
-// launches with host decisions between them, so mode 3's Gram and solve run
-// on a second stream driven by a second host thread, beside mode 2's on s.
-static int hosvd_start_pair(Plan &p, const tk_opts *o, double *const *factors, tk_stats *st, int *noconv,
-                            hipStream_t s) {
+// Start of mode n (1 or 2) from slot k's buffers (0: p.Mg, p.eigw, p.theta,
+// p.L[0]; 1: the second set) on stream s: HO-SVD (the leading eigenvectors
+// of X_(n) X_(n)^T), or the learned start with HO-SVD as its fallback.
+static int start_mode(Plan &p, int n, int k, const tk_opts *o, double *const *factors, tk_stats *st, int *noconv,
+                      double nx2, hipStream_t s) {
+    double *Mg = k == 0 ? p.Mg : p.Mg2;
+    void *eigw = k == 0 ? p.eigw : (void *)p.eigw2;
+    double *theta = k == 0 ? p.theta : p.theta2;
+    if (o->init == TK_INIT_LEARNED) {
+        const int ok = learned_mode(p, n, o, factors[n], nx2, s, p.L[k], Mg);
+        if (ok < 0) return ok;
+        if (ok == 1) {
+            // the eigensolves of the sweeps start from this factor
+            ST(eig_seed_block(p.Xblk[n], (int)p.I[n], p.J[n], factors[n], eigw, 0x1ea7ull + n, s));
+            p.blk_ok[n] = true;
+            ST(refresh_copies(p, n, factors[n], s));
+            return TK_OK;
+        }
+        if (st) st->init_fallbacks += 1;
+        return run_eig(p, n, Mg, factors[n], false, o, st, noconv, s, eigw, theta);  // H_n is in Mg
+    }
     const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
+    const int sl = (n + 1) % 3;  // ordering whose slots are the mode-n slices
+    ST(hosvd_gram(n, dims, p.ptr[n], p.lidx[n], p.lval64[n], p.ptr[sl], p.lidx[sl], p.lval64[sl], Mg, s));
+    return run_eig(p, n, Mg, factors[n], false, o, st, noconv, s, eigw, theta);
+}
+
+// Starts of modes 2 and 3. Each comes from its own unfolding (Figure 1) and
+// does not depend on the other; an eigensolve is a chain of small launches
+// with host decisions between them, so mode 3's start runs on a second stream
+// driven by a second host thread, with its own buffers, beside mode 2's on s.
+static int start_pair(Plan &p, const tk_opts *o, double *const *factors, tk_stats *st, int *noconv, double nx2,
+                      hipStream_t s) {
     int dev = 0;
     ST(hipGetDevice(&dev));
     hipStream_t s2 = nullptr;
@@ -782,26 +820,10 @@ static int hosvd_start_pair(Plan &p, const tk_opts *o, double *const *factors, t
                 r2 = TK_ERR_DEVICE;
                 return;
             }
-            // ordering 0's slots are the mode-3 slices
-            const hipError_t e = hosvd_gram(2, dims, p.ptr[2], p.lidx[2], p.lval64[2], p.ptr[0], p.lidx[0],
-                                            p.lval64[0], p.Mg2, s2);
-            if (e != hipSuccess) {
-                set_hip_error(e, "hosvd_gram");
-                r2 = TK_ERR_DEVICE;
-                return;
-            }
-            r2 = run_eig(p, 2, p.Mg2, factors[2], false, o, st ? &st2 : nullptr, &nc2, s2, p.eigw2, p.theta2);
+            r2 = start_mode(p, 2, 1, o, factors, st ? &st2 : nullptr, &nc2, nx2, s2);
         });
-        // mode 2 here (ordering 2's slots are its slices); no early return
-        // while the other thread runs
-        const hipError_t e = hosvd_gram(1, dims, p.ptr[1], p.lidx[1], p.lval64[1], p.ptr[2], p.lidx[2], p.lval64[2],
-                                        p.Mg, s);
-        if (e != hipSuccess) {
-            set_hip_error(e, "hosvd_gram");
-            r = TK_ERR_DEVICE;
-        } else {
-            r = run_eig(p, 1, p.Mg, factors[1], false, o, st, noconv, s);
-        }
+        // mode 2 here; no early return while the other thread runs
+        r = start_mode(p, 1, 0, o, factors, st, noconv, nx2, s);
         th.join();
         if (r == TK_OK) r = r2;
         // the sweeps on s follow mode 3's work
@@ -812,6 +834,7 @@ static int hosvd_start_pair(Plan &p, const tk_opts *o, double *const *factors, t
     if (st) {
         st->eig_iters += st2.eig_iters;
         st->eig_noconv += st2.eig_noconv;
+        st->init_fallbacks += st2.init_fallbacks;
     }
     if (nc2) *noconv = 1;
     if (e2) (void)hipEventDestroy(e2);
@@ -822,42 +845,24 @@ static int hosvd_start_pair(Plan &p, const tk_opts *o, double *const *factors, t
 
 static int init_factors(Plan &p, const tk_opts *o, double *const *factors, tk_stats *st, int *noconv, double nx2,
                         hipStream_t s) {
-    const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
+    if (o->init == TK_INIT_GIVEN) {
+        for (int n = 1; n < 3; ++n) ST(refresh_copies(p, n, factors[n], s));
+        return TK_OK;
+    }
     if (o->init == TK_INIT_LEARNED) {
         // mode 1 has no start in HOOI and MP (Figures 3 and 7), but its first
         // eigensolve can start from a learned block instead of a random one
         // (factors[0] is only scratch here; the first sweep overwrites it)
-        const int ok = learned_mode(p, 0, o, factors[0], nx2, s);
+        const int ok = learned_mode(p, 0, o, factors[0], nx2, s, p.L[0], p.Mg);
         if (ok < 0) return ok;
         if (ok == 1) {
             ST(eig_seed_block(p.Xblk[0], (int)p.I[0], p.J[0], factors[0], p.eigw, 0x1ea7ull, s));
             p.blk_ok[0] = true;
         }
     }
-    if (o->init == TK_INIT_HOSVD && p.Mg2) return hosvd_start_pair(p, o, factors, st, noconv, s);
+    if (p.Mg2) return start_pair(p, o, factors, st, noconv, nx2, s);
     for (int n = 1; n < 3; ++n) {
-        if (o->init == TK_INIT_GIVEN) {
-            ST(refresh_copies(p, n, factors[n], s));
-            continue;
-        }
-        if (o->init == TK_INIT_LEARNED) {
-            const int ok = learned_mode(p, n, o, factors[n], nx2, s);
-            if (ok < 0) return ok;
-            if (ok == 1) {
-                // the eigensolves of the sweeps start from this factor
-                ST(eig_seed_block(p.Xblk[n], (int)p.I[n], p.J[n], factors[n], p.eigw, 0x1ea7ull + n, s));
-                p.blk_ok[n] = true;
-                ST(refresh_copies(p, n, factors[n], s));
-                continue;
-            }
-            if (st) st->init_fallbacks += 1;
-            int r = run_eig(p, n, p.Mg, factors[n], false, o, st, noconv, s);  // H_n is in p.Mg
-            if (r) return r;
-            continue;
-        }
-        const int sl = (n + 1) % 3;  // ordering whose slots are the mode-n slices
-        ST(hosvd_gram(n, dims, p.ptr[n], p.lidx[n], p.lval64[n], p.ptr[sl], p.lidx[sl], p.lval64[sl], p.Mg, s));
-        int r = run_eig(p, n, p.Mg, factors[n], false, o, st, noconv, s);
+        const int r = start_mode(p, n, 0, o, factors, st, noconv, nx2, s);
         if (r) return r;
     }
     return TK_OK;
