@@ -123,7 +123,9 @@ struct Plan {
     double *lval64[3];
     float *lval32[3];
     void *T[3];        // projections for the Grams (type by precision)
-    float *Tcore;      // mixed MP: FP32 copy of the last projection, for the core
+    float *Tcore;      // mixed MP: FP32 copy of the last projection, for the core (rows of ldc)
+    float *Fc = nullptr;  // mixed MP: mode-3 factor rows in FP32 padded to ldc, for that projection
+    int ldc = 0;
     float *T0f;        // mixed HOOI: FP32 T(0) for mode 3 and the core
     void *Y;           // HOOI second-stage output for the Gram
     float *Y2f;        // mixed HOOI: FP32 Y2 (core input)
@@ -231,7 +233,11 @@ static void carve(Plan &p, Arena &ar) {
         for (int m = 0; m < 3; ++m) p.T[m] = ar.take<char>((int64_t)(p.nslots[m] * p.ldT[m] * es));
         if (p.split)
             for (int m = 0; m < 3; ++m) p.Tlo[m] = ar.take<char>((int64_t)(p.nslots[m] * p.ldT[m] * es));
-        if (prec == PBF16) p.Tcore = ar.take<float>(p.nslots[2] * p.J[2]);
+        if (prec == PBF16) {
+            p.ldc = (int)ceil_div(p.J[2], 4) * 4;  // 16-byte rows: the vector projection
+            p.Tcore = ar.take<float>(p.nslots[2] * p.ldc);
+            p.Fc = ar.take<float>(p.I[2] * p.ldc);
+        }
     } else if (p.algo == TK_ALGO_HOOI) {
         p.T[2] = ar.take<char>((int64_t)(p.nslots[2] * p.J[2] * es));
         if (prec == PBF16)
@@ -606,6 +612,7 @@ static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s)
     const int64_t cnt = p.I[n] * p.J[n];
     if (p.F32[n]) TK_HIP(convert_f64<float>(F, p.F32[n], cnt, s));
     if (p.F16[n]) TK_HIP(convert_f64<bf16>(F, p.F16[n], cnt, s));
+    if (p.Fc && n == 2) TK_HIP(pad_rows<float>(F, p.I[2], p.J[2], p.ldc, p.Fc, s));
     if (p.Fp[n]) {
         if (p.prec == P64)
             TK_HIP(pad_rows<double>(F, p.I[n], p.J[n], p.ldT[n], (double *)p.Fp[n], s));
@@ -815,16 +822,24 @@ static int start_pair(Plan &p, const tk_opts *o, double *const *factors, tk_stat
     tk_stats st2{};
     int nc2 = 0, r2 = TK_OK;
     if (r == TK_OK) {
-        std::thread th([&] {
+        auto second = [&] {
             if (hipSetDevice(dev) != hipSuccess) {
                 r2 = TK_ERR_DEVICE;
                 return;
             }
             r2 = start_mode(p, 2, 1, o, factors, st ? &st2 : nullptr, &nc2, nx2, s2);
-        });
+        };
+        std::thread th;
+        try {
+            th = std::thread(second);
+        } catch (...) {  // no thread to be had: mode 3 after mode 2, from this thread
+        }
         // mode 2 here; no early return while the other thread runs
         r = start_mode(p, 1, 0, o, factors, st, noconv, nx2, s);
-        th.join();
+        if (th.joinable())
+            th.join();
+        else
+            second();
         if (r == TK_OK) r = r2;
         // the sweeps on s follow mode 3's work
         if (hipEventRecord(e2, s2) != hipSuccess || hipStreamWaitEvent(s, e2, 0) != hipSuccess)
@@ -925,12 +940,12 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         const void *T2c = p.T[2];
         bool f64 = prec == P64;
         if (prec == PBF16) {
-            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.I[2], p.J[2], p.J[2],
-                                             p.J[2], p.nslots[2], p.nnz, p.Tcore, s)));
+            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.Fc, p.I[2], p.ldc, p.J[2], p.ldc,
+                                             p.nslots[2], p.nnz, p.Tcore, s)));
             T2c = p.Tcore;
         }
         tm.begin(kCore);
-        ST(core_from_T2(p, T2c, prec == PBF16 ? p.J[2] : p.ldT[2], f64, A, B, core, s));
+        ST(core_from_T2(p, T2c, prec == PBF16 ? p.ldc : p.ldT[2], f64, A, B, core, s));
         tm.end();
         double fit = 0;
         if ((st = finish_fit(p, core, s, &fit))) return st;
@@ -950,12 +965,12 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         tm.end();
         const void *T2c = p.T[2];
         if (prec == PBF16) {
-            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.F32[2], p.I[2], p.J[2], p.J[2],
-                                             p.J[2], p.nslots[2], p.nnz, p.Tcore, s)));
+            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.Fc, p.I[2], p.ldc, p.J[2], p.ldc,
+                                             p.nslots[2], p.nnz, p.Tcore, s)));
             T2c = p.Tcore;
         }
         tm.begin(kCore);
-        ST(core_from_T2(p, T2c, prec == PBF16 ? p.J[2] : p.ldT[2], prec == P64, A, B, core, s));
+        ST(core_from_T2(p, T2c, prec == PBF16 ? p.ldc : p.ldT[2], prec == P64, A, B, core, s));
         tm.end();
         ST(hipStreamSynchronize(s));
     }
