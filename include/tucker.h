@@ -20,7 +20,11 @@
  * Stream:  `stream` is a hipStream_t passed as void* (NULL = the null
  *          stream). Work is enqueued on it; every entry point returns after
  *          its results are complete and visible to the host (the sweep loops
- *          read one fit value per sweep back to the host).
+ *          read one fit value per sweep back to the host). With an HO-SVD or
+ *          learned start, the start of mode 3 runs on a second stream that
+ *          the call creates (default priority) and drives from a second host
+ *          thread, beside mode 2's on `stream`; `stream` waits for it, and
+ *          the stream is destroyed, before the sweeps begin.
  * Indices: 0-based int32 coordinates, structure of arrays: idx[n][p] is the
  *          mode-n coordinate of nonzero p. Duplicate coordinates are summed;
  *          explicit zeros are allowed.
