@@ -193,7 +193,7 @@ struct EigOpts {
     int max_iters = 400;
     double tol = 1e-10;
     int degree = 60;
-    int warm_degree = 8;  // first filter degree of a warm start (doubles per step)
+    int warm_degree = 16;  // first filter degree of a warm start (doubles per step)
     bool warm = false;
     uint64_t seed = 1234;
     int direct_sweeps = 30;  // Jacobi sweep cap when the matrix is diagonalised directly
