@@ -351,9 +351,14 @@ __global__ void __launch_bounds__(kCholBlkThreads) k_chol_inv_blk(const double *
 // barriers, and 1024 threads give a 62 x 62 sweep in 100 us where 512 took
 // 119 us (same rotations, same bits). Outputs the eigenvalues in descending order (theta) and
 // the matching eigenvectors as columns of Vout (b x b row-major).
+// With max_sweeps > 1 the matrix counts as diagonal, and no further sweep is
+// made, once its off-diagonal squares sum to at most off2 times all squares;
+// the test comes before each sweep, so an input that is already diagonal
+// enough costs none. A single-sweep call makes no test.
 template <bool V_LDS>
 __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double *Hin, int ldh, int b, int max_sweeps,
-                                                           double *theta, double *Vout, double *Vglob) {
+                                                           double off2, double *theta, double *Vout,
+                                                           double *Vglob) {
     extern __shared__ double sm[];
     double *H = sm;
     double *V = V_LDS ? sm + (size_t)b * b : Vglob;
@@ -383,6 +388,36 @@ __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double *Hin, in
     // V rows: pair k = tid % half fixed, row = tid / half + s*bstep
     __syncthreads();
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        if (max_sweeps > 1) {
+            double off = 0, dia = 0;
+            for (int t = tid; t < b * b; t += nth) {
+                int i = t / b, j = t - i * b;
+                double v = H[t] * H[t];
+                if (i == j)
+                    dia += v;
+                else
+                    off += v;
+            }
+            for (int d = 32; d >= 1; d >>= 1) {
+                off += __shfl_xor(off, d, 64);
+                dia += __shfl_xor(dia, d, 64);
+            }
+            if ((tid & 63) == 0) {
+                red[tid >> 6] = off;
+                red[16 + (tid >> 6)] = dia;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double o = 0, dd = 0;
+                for (int i = 0; i < (nth >> 6); ++i) {
+                    o += red[i];
+                    dd += red[16 + i];
+                }
+                done = (o <= off2 * (o + dd)) || (dd == 0.0);
+            }
+            __syncthreads();
+            if (done) break;
+        }
         if (tid == 0) any_rot = 0;
         int nrot = 0;
         for (int r = 0; r < m - 1; ++r) {
@@ -477,34 +512,6 @@ __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double *Hin, in
         if (nrot) any_rot = 1;
         __syncthreads();
         if (!any_rot) break;
-        double off = 0, dia = 0;
-        for (int t = tid; t < b * b; t += nth) {
-            int i = t / b, j = t - i * b;
-            double v = H[t] * H[t];
-            if (i == j)
-                dia += v;
-            else
-                off += v;
-        }
-        for (int d = 32; d >= 1; d >>= 1) {
-            off += __shfl_xor(off, d, 64);
-            dia += __shfl_xor(dia, d, 64);
-        }
-        if ((tid & 63) == 0) {
-            red[tid >> 6] = off;
-            red[16 + (tid >> 6)] = dia;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double o = 0, dd = 0;
-            for (int i = 0; i < (nth >> 6); ++i) {
-                o += red[i];
-                dd += red[16 + i];
-            }
-            done = (o <= 1e-26 * (o + dd)) || (dd == 0.0);
-        }
-        __syncthreads();
-        if (done) break;
     }
     // sort by eigenvalue, descending (ties by index)
     for (int i = tid; i < b; i += nth) {
@@ -878,15 +885,15 @@ size_t eig_work_bytes(int n, int b) {
 
 // ------------------------------------------------------------------ host helpers
 static hipError_t jacobi(const double *H, int ldh, int b, double *theta, double *Vout, double *Vg, hipStream_t s,
-                         int sweeps = 30) {
+                         int sweeps = 30, double off2 = 1e-26) {
     if (b <= kJacobiVLds) {
         size_t lds = sizeof(double) * 2 * (size_t)b * b;
         hipFuncSetAttribute((const void *)k_jacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_jacobi<true><<<1, kJacobiThreads, lds, s>>>(H, ldh, b, sweeps, theta, Vout, Vg);
+        k_jacobi<true><<<1, kJacobiThreads, lds, s>>>(H, ldh, b, sweeps, off2, theta, Vout, Vg);
     } else {
         size_t lds = sizeof(double) * (size_t)b * b;
         hipFuncSetAttribute((const void *)k_jacobi<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        k_jacobi<false><<<1, kJacobiThreads, lds, s>>>(H, ldh, b, sweeps, theta, Vout, Vg);
+        k_jacobi<false><<<1, kJacobiThreads, lds, s>>>(H, ldh, b, sweeps, off2, theta, Vout, Vg);
     }
     TK_LAUNCHED();
     return hipSuccess;
@@ -1080,6 +1087,13 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
     // the stop rule has judged exactly those (their residuals), and the
     // extra columns of the block serve the filter alone.
     bool final_rr = false;
+    // The closing step rotates only inside the wanted columns: the span it
+    // returns, and the fit that depends on it alone, are fixed before it, and
+    // the trace of its Ritz values is exact at any rotation. Each Ritz value
+    // moves by about the square of the remaining off-diagonal over its gap, so
+    // an off-diagonal norm of 1e-4 tol relative to the whole (squared: off2)
+    // suffices; FP64 solves keep the rounding-level limit.
+    const double jt = 1e-4 * o.tol, final_off2 = std::max(1e-26, jt * jt);
     for (int outer = 0;; ++outer) {
         if (final_rr && J == Lk) break;  // every wanted pair is locked
         const int w = final_rr ? J - Lk : b - Lk;
@@ -1088,7 +1102,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
         TK_HIP(dgemm(n, w, n, Md, n, false, Xa, b, Wa, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
         ++matvecs;
         TK_HIP(dgemm(w, w, n, Xa, b, true, Wa, b, L.S, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
-        TK_HIP(jacobi(L.S, w, w, L.theta, L.V, L.Vg, s, final_rr ? 30 : 1));
+        TK_HIP(jacobi(L.S, w, w, L.theta, L.V, L.Vg, s, final_rr ? 30 : 1, final_off2));
         TK_HIP(dgemm(n, w, w, Xa, b, false, L.V, w, L.Y0, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
                      s));
         TK_HIP(dgemm(n, w, w, Wa, b, false, L.V, w, L.Y1, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
