@@ -1122,12 +1122,15 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
         for (double v : thL) E += v;
         for (int j = 0; j < J - Lk; ++j) E += tha[j];
         const double thmax = std::max(thL.empty() ? 0.0 : thL[0], tha[0]);
-        // residual estimate of the error of E (needs a gap below every
-        // wanted Ritz value inside the block)
+        // residual estimate of the error of E: each wanted Ritz value is off
+        // by about its squared residual over its distance to the unwanted
+        // spectrum, whose top is estimated by the first unwanted Ritz value
+        // (not the block's last one, which can sit far lower and understate
+        // the error tenfold on clustered spectra)
         double errE = 0.0;
         bool est_ok = w > J - Lk;
         for (int j = 0; est_ok && j < J - Lk; ++j) {
-            const double gap = tha[j] - tha[w - 1];
+            const double gap = tha[j] - tha[J - Lk];
             if (!(gap > 1e-12 * thmax)) est_ok = false;
             else errE += res[j] * res[j] / gap;
         }

@@ -156,3 +156,42 @@ def test_lead_eig_split_k_products(tk):
     lam = np.concatenate([np.linspace(10, 5, J), np.linspace(1, 0.1, 40)])
     M = (Y * lam) @ Y.T / n + 1e-3 * np.eye(n)
     _check(tk, M, J, angle=1e-7)
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-8])
+@pytest.mark.parametrize("case", ["gapped", "mp0"])
+def test_lead_eig_loose_tolerance(tk, mid_grams, case, tol):
+    """The tolerances of the reduced-precision forms (1e-4 mixed, 1e-8 FP32):
+    the sum E of the J leading Ritz values within tol * E of LAPACK's (the
+    stop rule), each returned value the diagonal entry of F^T M F, and the
+    closing Rayleigh-Ritz step's Jacobi stopped at an off-diagonal norm of
+    at most 1e-4 tol relative to the whole of F^T M F; F orthonormal with
+    the sign convention at any tolerance."""
+    _say(f"lead_eig loose {case} {tol}")
+    if case == "gapped":
+        rng = np.random.default_rng(11)
+        n, J = 400, 30
+        Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+        lam = np.concatenate([np.linspace(100, 50, J), np.linspace(20, 0.1, n - J)])
+        M = (Q * lam) @ Q.T
+    else:
+        M, J = mid_grams["mp0"]
+    F, th, it, st, _ = tk.lead_eig(torch.from_numpy(M).cuda(), J, tol=tol)
+    F = F.cpu().numpy()
+    th = th.cpu().numpy()
+    assert np.all(np.isfinite(F)) and np.all(np.isfinite(th))
+    assert np.abs(F.T @ F - np.eye(J)).max() < 1e-12
+    w = np.linalg.eigvalsh(0.5 * (M + M.T))[::-1]
+    scale = abs(w[0])
+    e_ref = w[:J].sum()
+    H = F.T @ M @ F
+    assert abs(np.trace(H) - e_ref) <= tol * abs(e_ref), (np.trace(H), e_ref)
+    np.testing.assert_allclose(th, np.diag(H), rtol=0, atol=1e-11 * scale)
+    assert np.all(np.diff(th) <= 1e-12 * scale)
+    assert np.all(th <= w[:J] + 1e-11 * scale)  # Ritz values never exceed the eigenvalues
+    # locked columns (residual at most 1e-11 of the top value) couple to the
+    # rest at that level, outside the closing step's block
+    off = np.sqrt(max(0.0, (H * H).sum() - (np.diag(H) ** 2).sum()))
+    assert off <= 2e-4 * tol * np.linalg.norm(H) + 1e-9 * scale, off
+    for c in range(J):
+        assert F[np.argmax(np.abs(F[:, c])), c] > 0
