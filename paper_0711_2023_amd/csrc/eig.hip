@@ -38,10 +38,10 @@ constexpr int kJacobiThreads = 1024;
 
 // p extra columns: a wider block converges in fewer filter steps but each
 // Rayleigh-Ritz and CholeskyQR step costs more; on flat spectra (uniform
-// data, n = 1000, J = 50) J / 4 took the least time of J/2 .. J/8.
+// data, n = 1000, J = 50) six took the least time of 4, 6, 8, 12, 16 and 25.
 int eig_block_width(int n, int J) {
     if (n <= kDirectMax) return n;
-    int p = std::min(32, std::max(8, J / 4));
+    int p = std::min(32, std::max(6, J / 8));
     int b = std::min(J + p, kMaxBlock);
     b = std::min(b, n);
     return std::max(b, J);
