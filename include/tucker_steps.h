@@ -29,7 +29,8 @@ int tucker_step_lead_eig_workspace(int32_t n, int32_t J, size_t *bytes);
      matvecs  [host] output: products with M used (1 for the direct solver)
      tol      relative accuracy of the sum of the J leading Ritz values at
               which the iteration stops: the residual estimate
-              sum_j r_j^2 / (theta_j - theta_b) (b = block width), or the
+              sum_j r_j^2 / (theta_j - theta_{J+1}) (theta_{J+1}: the first
+              Ritz value outside the J leading ones), or the
               change of the sum across a full-degree filter step, at most
               tol times the sum (used for n > 140; smaller matrices are
               diagonalised directly)
