@@ -1,7 +1,8 @@
 """Step-level parity on the GPU: the leading-eigenvector solver against LAPACK
 (numpy.linalg.eigh) on the Grams the oracle builds for HOOI and MP, and on
 synthetic matrices with known spectra (gapped, one dominant eigenvalue over a
-clustered bulk, rank-deficient)."""
+clustered bulk, rank-deficient), at the oracle-level tolerance and at the looser
+ones of the reduced-precision forms."""
 import sys
 
 import numpy as np
