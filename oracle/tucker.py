@@ -72,6 +72,7 @@ __all__ = [
     "sp_algorithm",
     "Decomposition",
     "subspace_angle",
+    "random_start",
 ]
 
 
@@ -523,3 +524,21 @@ def subspace_angle(A: np.ndarray, B: np.ndarray) -> float:
     R = B - A @ (A.T @ B)
     s = np.linalg.norm(R, 2)
     return float(np.arcsin(min(1.0, s)))
+
+
+# --------------------------------------------------------------------------
+# Random start (Figure 5: a random matrix with uniform entries on [0, 1],
+# columns normalised to unit length)
+# --------------------------------------------------------------------------
+def random_start(I: int, J: int, n: int, seed: int) -> np.ndarray:
+    """The I x J start of mode n drawn from SplitMix64 (Steele, Lea and
+    Flood, OOPSLA 2014): entry (i, r) is the top 53 bits of output number
+    (n * 2^40 + i * J + r) as a double in [0, 1); then every column is
+    divided by its Euclidean norm, as Figure 5 prescribes for C."""
+    from .learn import splitmix64_at
+    base = n << 40
+    U = np.empty((I, J))
+    for i in range(I):
+        for r in range(J):
+            U[i, r] = (splitmix64_at(seed, base + i * J + r) >> 11) * 2.0 ** -53
+    return U / np.linalg.norm(U, axis=0, keepdims=True)

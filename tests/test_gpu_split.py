@@ -42,8 +42,7 @@ def tk():
 
 
 def _angle(A, B):
-    R = B - A @ (A.T @ B)
-    return float(np.arcsin(min(1.0, np.linalg.norm(R, 2))))
+    return O.subspace_angle(A, B)
 
 
 @pytest.mark.parametrize("case", ["uniform", "planted"])

@@ -356,3 +356,76 @@ def test_small_reference_is_the_oracles():
     assert sorted(now) == sorted(stored.files)
     for k in now:
         np.testing.assert_allclose(stored[k], now[k], rtol=0, atol=1e-12, err_msg=k)
+
+
+def _rot(n, pairs, thetas):
+    """Orthonormal columns: column c is cos(t) e_a + sin(t) e_b for
+    (a, b), t in zip(pairs, thetas)."""
+    B = np.zeros((n, len(pairs)))
+    for c, ((a, b), t) in enumerate(zip(pairs, thetas)):
+        B[a, c] = np.cos(t)
+        B[b, c] = np.sin(t)
+    return B
+
+
+@pytest.mark.parametrize("theta", [0.0, 1e-12, 1e-9, 1e-6, 1e-3, 0.1, 0.7, 1.2, np.pi / 2])
+def test_subspace_angle_known_angles(theta):
+    """span{e1} against span{cos(t) e1 + sin(t) e2} is at angle t exactly,
+    including the small-angle regime where arccos of the cosine loses it."""
+    n = 7
+    A = np.eye(n)[:, :1]
+    B = _rot(n, [(0, 1)], [theta])
+    got = O.subspace_angle(A, B)
+    assert abs(got - theta) <= 1e-15 + 1e-12 * theta, (got, theta)
+    # the largest of several principal angles, whatever the column order
+    A3 = np.eye(n)[:, :3]
+    B3 = _rot(n, [(0, 3), (1, 4), (2, 5)], [theta / 3, theta, theta / 2])
+    assert abs(O.subspace_angle(A3, B3) - theta) <= 1e-15 + 1e-12 * theta
+    assert abs(O.subspace_angle(A3, B3[:, ::-1]) - theta) <= 1e-15 + 1e-12 * theta
+
+
+def test_subspace_angle_basis_invariance_and_symmetry():
+    """The angle depends on the spans only: any orthonormal basis of either
+    gives the same value, and for equal dimensions it is symmetric."""
+    rng = np.random.default_rng(3)
+    n, k = 40, 5
+    A = np.linalg.qr(rng.standard_normal((n, k)))[0]
+    B = np.linalg.qr(A + 0.05 * rng.standard_normal((n, k)))[0]
+    a = O.subspace_angle(A, B)
+    assert a > 1e-3
+    Q = np.linalg.qr(rng.standard_normal((k, k)))[0]
+    assert abs(O.subspace_angle(A @ Q, B) - a) < 1e-13
+    assert abs(O.subspace_angle(A, B @ Q) - a) < 1e-13
+    assert abs(O.subspace_angle(B, A) - a) < 1e-13
+    # against the principal angles from the singular values of A^T B
+    # (Bjorck and Golub), accurate at this size
+    s = np.linalg.svd(A.T @ B, compute_uv=False)
+    assert abs(np.arccos(np.clip(s.min(), -1, 1)) - a) < 1e-8
+    # a span and itself
+    assert O.subspace_angle(A, A @ Q) < 1e-14
+
+
+def test_bench_angle_is_the_oracles():
+    """The benchmark's own copy of the comparison (it may not import the
+    oracle outside its CPU-baseline leg) equals the oracle's function."""
+    import bench
+    rng = np.random.default_rng(5)
+    for k in (1, 4, 9):
+        A = np.linalg.qr(rng.standard_normal((30, k)))[0]
+        B = np.linalg.qr(A + 0.1 * rng.standard_normal((30, k)))[0]
+        assert bench.subspace_angle(A, B) == O.subspace_angle(A, B)
+
+
+def test_random_start_columns():
+    """SP's start (Figure 5): entries uniform on [0, 1) from SplitMix64
+    before normalisation (mean 1/2, second moment 1/3), unit columns, and the
+    draw of entry (i, r) fixed by (mode, i, r, seed) alone."""
+    from oracle.learn import splitmix64_at
+    C = O.random_start(300, 4, 2, 77)
+    assert np.allclose(np.linalg.norm(C, axis=0), 1.0, atol=1e-15)
+    raw = np.array([[(splitmix64_at(77, (2 << 40) + i * 4 + r) >> 11) * 2.0 ** -53 for r in range(4)]
+                    for i in range(300)])
+    assert raw.min() >= 0.0 and raw.max() < 1.0
+    assert abs(raw.mean() - 0.5) < 0.03 and abs((raw ** 2).mean() - 1 / 3) < 0.03
+    assert np.allclose(C * np.linalg.norm(raw, axis=0), raw, rtol=1e-15, atol=0)
+    assert not np.allclose(O.random_start(300, 4, 1, 77), C)
