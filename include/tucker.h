@@ -37,6 +37,19 @@
  *          work is enqueued, and then no output is written. TK_ERR_INDEX and
  *          TK_ERR_VALUE are detected by the first kernels, before any output
  *          is written. tucker_strerror() gives a text.
+ * Limits:  besides the conditions of the problem (Jn <= In), the library
+ *          rejects with TK_ERR_ARG, before any device work:
+ *          - Jn > 128 (the eigensolver keeps its Rayleigh-Ritz matrix of
+ *            Jn + max(6, Jn/8) columns in one workgroup's LDS);
+ *          - nnz >= 2^31 - 1, or any In >= 2^31 (32-bit coordinates);
+ *          - I_a * I_b >= 2^31 for any pair of modes (the fibres of the third
+ *            mode are the slots of a dense, 32-bit indexed layout);
+ *          - with an HO-SVD start (TK_INIT_HOSVD, also as the fallback of
+ *            TK_INIT_LEARNED, and opts.hosvd_fit), In > 8192 for a mode that
+ *            needs its start Gram X_(n) X_(n)^T (modes 2 and 3; all three for
+ *            tucker_hosvd and opts.hosvd_fit): one Gram row is kept in a
+ *            workgroup's LDS. TK_INIT_GIVEN and TK_INIT_RANDOM have no such
+ *            limit.
  */
 #ifndef TUCKER_H
 #define TUCKER_H
@@ -79,11 +92,20 @@ extern "C" {
                              opts.seed); a mode whose start is rank-deficient or
                              captures no more of ||X||^2 than a random subspace
                              would on average (Jn/In of it) falls back to HO-SVD */
+#define TK_INIT_RANDOM  3 /* Slice Projection's start (Section 4.3, Figure 5): a
+                             random matrix with entries uniform on [0, 1) and
+                             columns normalised to unit length, for C (SP) or B
+                             and C (HOOI, MP). Entry (i, r) of mode n (0-based n)
+                             is the top 53 bits, scaled by 2^-53, of output number
+                             n * 2^40 + i * Jn + r of SplitMix64 (Steele, Lea and
+                             Flood, OOPSLA 2014) seeded with opts.seed. */
 
 /* ---- algorithm selector of the workspace query ------------------------ */
 #define TK_ALGO_HOOI   0
 #define TK_ALGO_MP     1
 #define TK_ALGO_FIT    2
+#define TK_ALGO_SP     3
+#define TK_ALGO_HOSVD  4
 
 /* Sparse third-order tensor in coordinate form. */
 typedef struct tk_coo {
@@ -132,8 +154,19 @@ typedef struct tk_opts {
     const float *model;     /* [dev] TK_INIT_LEARNED: the network parameters
                                (tucker_learn_param_count() floats, layout in
                                tucker_learn.h); NULL otherwise */
-    uint64_t seed;          /* TK_INIT_LEARNED: seed of the sketch generator */
+    uint64_t seed;          /* TK_INIT_LEARNED: seed of the sketch generator;
+                               TK_INIT_RANDOM: seed of the start */
     const tk_tune *tune;    /* [host] launch choices, or NULL for the built-in ones */
+    int32_t hosvd_fit;      /* 1: HOOI, MP and SP also compute the fit of the HO-SVD
+                               (Figure 1: all three factors from X_(n) X_(n)^T, then
+                               the core) before the sweeps and report it in
+                               stats.hosvd_fit; costs the mode-1 start Gram and
+                               eigensolve (and modes 2, 3 for SP or a non-HO-SVD
+                               start), one FP64 projection and the core. The
+                               decomposition itself is unchanged. Only with
+                               TK_INIT_HOSVD or TK_INIT_RANDOM (TK_ERR_ARG
+                               otherwise): the report uses the factor buffers
+                               as scratch before the sweeps. */
 } tk_opts;
 
 /* Optional statistics (pass NULL to skip). Times in milliseconds. */
@@ -155,17 +188,23 @@ typedef struct tk_stats {
     int32_t eig_noconv;     /* eigensolves that hit eig_max_iters */
     double  norm_x;         /* ||X||_F */
     int32_t init_fallbacks; /* TK_INIT_LEARNED: modes that fell back to HO-SVD */
+    double  hosvd_fit;      /* opts.hosvd_fit = 1 (and tucker_hosvd): the HO-SVD fit;
+                               otherwise 0 */
+    double  core_norm;      /* ||G||_F of the returned core */
+    double  ttmc_sweep_ms[64]; /* opts.timing = 1: the TTMc phase's time in sweep t
+                               (t < 64; its share of ttmc_ms), 0 beyond */
 } tk_stats;
 
 /* Fill *opt with: FP32, HO-SVD init, 50 sweeps, tol 1e-4, eig cap 400
    products, eig tol 0 (by precision), no timing, no model, seed 0x5eed,
-   built-in launch choices. */
+   built-in launch choices, no HO-SVD fit. */
 void tucker_default_opts(tk_opts *opt);
 
 /* Bytes of device workspace that tucker_hooi (algo TK_ALGO_HOOI),
-   tucker_mp (TK_ALGO_MP) or tucker_fit (TK_ALGO_FIT) needs for this tensor
-   shape, nnz, core size and precision. Host only; enqueues nothing. Returns
-   TK_OK and writes *bytes, or TK_ERR_ARG. */
+   tucker_mp (TK_ALGO_MP), tucker_sp (TK_ALGO_SP), tucker_hosvd
+   (TK_ALGO_HOSVD) or tucker_fit (TK_ALGO_FIT) needs for this tensor shape,
+   nnz, core size and options. Host only; enqueues nothing. Returns TK_OK
+   and writes *bytes, or TK_ERR_ARG. */
 int tucker_workspace_bytes(int32_t algo, const tk_coo *X, const int32_t *core_dims,
                            const tk_opts *opt, size_t *bytes);
 
@@ -195,6 +234,35 @@ int tucker_mp(const tk_coo *X, const int32_t *core_dims, const tk_opts *opt,
               double *core, double *const *factors, double *fit_history,
               int32_t *iters_done, tk_stats *stats,
               void *workspace, size_t workspace_bytes, void *stream);
+
+/* Slice Projection (Section 4.3, Figure 5): C from the start (TK_INIT_RANDOM,
+   the paper's; TK_INIT_GIVEN reads factors[2]; TK_INIT_HOSVD; columns are
+   normalised to unit length either way), then per sweep
+     M13 = sum_j X_:j: C C^T X_:j:^T -> A
+     M21 = sum_k X_::k^T A A^T X_::k -> B
+     M32 = sum_i X_i::^T B B^T X_i:: -> C
+   (leading eigenvectors; each Gram uses one other factor), the core and
+   Delta_G(t) = 1 - ||G(t-1)|| / ||G(t)|| with ||G(0)|| = 0: stop after sweep
+   t when Delta_G(t) < tol (tol <= 0: exactly max_iters sweeps).
+   fit_history holds the fit after every sweep (as for HOOI and MP).
+   TK_INIT_LEARNED is rejected (TK_ERR_ARG). Arguments as tucker_hooi. */
+int tucker_sp(const tk_coo *X, const int32_t *core_dims, const tk_opts *opt,
+              double *core, double *const *factors, double *fit_history,
+              int32_t *iters_done, tk_stats *stats,
+              void *workspace, size_t workspace_bytes, void *stream);
+
+/* HO-SVD (Section 4.1, Figure 1): A(n) = Jn leading eigenvectors of
+   X_(n) X_(n)^T for n = 1, 2, 3 (FP64 Grams; the eigensolver's tolerance
+   follows opt->precision as for the other algorithms), then
+   G = [[X; A^T, B^T, C^T]] from an FP64 projection and the fit.
+   opt->init, max_iters and tol are not used.
+     core    [dev]  J1*J2*J3 doubles (output)
+     factors [host] array of 3 [dev] pointers to In x Jn doubles (output)
+     fit     [host] output
+     stats   [host] optional                                                 */
+int tucker_hosvd(const tk_coo *X, const int32_t *core_dims, const tk_opts *opt,
+                 double *core, double *const *factors, double *fit, tk_stats *stats,
+                 void *workspace, size_t workspace_bytes, void *stream);
 
 /* fit(X, Xhat) = 1 - ||X - Xhat||_F / ||X||_F (Section 3, fit equation) of
    Xhat = [[G; A(1), A(2), A(3)]] for ANY core and factors (orthonormality

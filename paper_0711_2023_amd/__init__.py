@@ -13,8 +13,8 @@ import os
 from dataclasses import dataclass
 
 __all__ = [
-    "TuckerError", "lib", "hooi", "mp", "fit", "workspace_bytes", "default_opts",
-    "FP64", "FP32", "MIXED_BF16", "MIXED_BF16X3", "INIT_HOSVD", "INIT_GIVEN", "INIT_LEARNED",
+    "TuckerError", "lib", "hooi", "mp", "sp", "hosvd", "fit", "workspace_bytes", "default_opts",
+    "FP64", "FP32", "MIXED_BF16", "MIXED_BF16X3", "INIT_HOSVD", "INIT_GIVEN", "INIT_LEARNED", "INIT_RANDOM",
     "Result", "LIB_PATH", "SYMBOLS", "lead_eig", "learn_param_count", "learn_sketch", "learn_forward",
     "learn_backward", "learn_align", "learn_adam", "learn_test_width", "batched",
 ]
@@ -25,13 +25,14 @@ LIB_PATH = os.path.join(HERE, "libtucker.so")
 TK_OK, TK_WARN_NOCONV = 0, 1
 TK_ERR_ARG, TK_ERR_INDEX, TK_ERR_VALUE, TK_ERR_EMPTY, TK_ERR_WORKSPACE, TK_ERR_DEVICE = -1, -2, -3, -4, -5, -6
 FP64, FP32, MIXED_BF16, MIXED_BF16X3 = 0, 1, 2, 3
-INIT_HOSVD, INIT_GIVEN, INIT_LEARNED = 0, 1, 2
-ALGO_HOOI, ALGO_MP, ALGO_FIT = 0, 1, 2
+INIT_HOSVD, INIT_GIVEN, INIT_LEARNED, INIT_RANDOM = 0, 1, 2, 3
+ALGO_HOOI, ALGO_MP, ALGO_FIT, ALGO_SP, ALGO_HOSVD = 0, 1, 2, 3, 4
 _PREC = {"fp64": FP64, "fp32": FP32, "mixed": MIXED_BF16, "bf16": MIXED_BF16, "bf16x3": MIXED_BF16X3,
          "mixed3": MIXED_BF16X3}
 
 # every function declared in include/*.h
-SYMBOLS = ["tucker_default_opts", "tucker_workspace_bytes", "tucker_hooi", "tucker_mp", "tucker_fit",
+SYMBOLS = ["tucker_default_opts", "tucker_workspace_bytes", "tucker_hooi", "tucker_mp", "tucker_sp", "tucker_hosvd",
+           "tucker_fit",
            "tucker_strerror", "tucker_step_lead_eig_workspace", "tucker_step_lead_eig",
            "tucker_learn_param_count", "tucker_learn_sketch_workspace", "tucker_learn_sketch",
            "tucker_learn_forward", "tucker_learn_backward_workspace", "tucker_learn_backward",
@@ -48,7 +49,7 @@ class tk_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("init", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("eig_max_iters", ctypes.c_int32), ("eig_tol", ctypes.c_double),
                 ("timing", ctypes.c_int32), ("model", ctypes.c_void_p), ("seed", ctypes.c_uint64),
-                ("tune", ctypes.c_void_p)]
+                ("tune", ctypes.c_void_p), ("hosvd_fit", ctypes.c_int32)]
 
 
 class tk_tune(ctypes.Structure):
@@ -79,7 +80,8 @@ class tk_stats(ctypes.Structure):
                 ("gram_ms", ctypes.c_double), ("gram_calls", ctypes.c_int64), ("eig_ms", ctypes.c_double),
                 ("core_ms", ctypes.c_double),
                 ("nnz_unique", ctypes.c_int64), ("eig_iters", ctypes.c_int32), ("eig_noconv", ctypes.c_int32),
-                ("norm_x", ctypes.c_double), ("init_fallbacks", ctypes.c_int32)]
+                ("norm_x", ctypes.c_double), ("init_fallbacks", ctypes.c_int32), ("hosvd_fit", ctypes.c_double),
+                ("core_norm", ctypes.c_double), ("ttmc_sweep_ms", ctypes.c_double * 64)]
 
 
 class TuckerError(RuntimeError):
@@ -106,10 +108,13 @@ def lib():
         L.tucker_workspace_bytes.restype = ctypes.c_int
         sig = [P(tk_coo), P(ctypes.c_int32), P(tk_opts), ctypes.c_void_p, P(ctypes.c_void_p), P(ctypes.c_double),
                P(ctypes.c_int32), P(tk_stats), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
-        for name in ("tucker_hooi", "tucker_mp"):
+        for name in ("tucker_hooi", "tucker_mp", "tucker_sp"):
             f = getattr(L, name)
             f.argtypes = sig
             f.restype = ctypes.c_int
+        L.tucker_hosvd.argtypes = [P(tk_coo), P(ctypes.c_int32), P(tk_opts), ctypes.c_void_p, P(ctypes.c_void_p),
+                                   P(ctypes.c_double), P(tk_stats), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.tucker_hosvd.restype = ctypes.c_int
         L.tucker_fit.argtypes = [P(tk_coo), P(ctypes.c_int32), ctypes.c_void_p, P(ctypes.c_void_p),
                                  P(ctypes.c_double), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.tucker_fit.restype = ctypes.c_int
@@ -161,8 +166,9 @@ def default_opts() -> tk_opts:
 
 
 def _opts(precision="fp32", init=INIT_HOSVD, max_iters=50, tol=1e-4, eig_max_iters=None, eig_tol=None,
-          timing=False, model=None, seed=None, tune=None) -> tk_opts:
+          timing=False, model=None, seed=None, tune=None, hosvd_fit=False) -> tk_opts:
     o = default_opts()
+    o.hosvd_fit = 1 if hosvd_fit else 0
     if model is not None:
         o.model = model.data_ptr()
     if seed is not None:
@@ -223,12 +229,14 @@ class Result:
 
 
 def _stats_dict(s: tk_stats) -> dict:
-    return {name: getattr(s, name) for name, _ in s._fields_}
+    d = {name: getattr(s, name) for name, _ in s._fields_}
+    d["ttmc_sweep_ms"] = list(s.ttmc_sweep_ms)
+    return d
 
 
 def _run(fn_name: str, algo: int, idx, vals, dims, core_dims, *, precision="fp32", init=INIT_HOSVD,
          max_iters=50, tol=1e-4, eig_max_iters=None, eig_tol=None, timing=False, factors=None, workspace=None,
-         stream=None, model=None, seed=None, tune=None) -> Result:
+         stream=None, model=None, seed=None, tune=None, hosvd_fit=False) -> Result:
     """`model`: float32 tensor of learn_param_count() parameters on the GPU,
     used with init=INIT_LEARNED. `tune`: launch choices (see make_tune)."""
     import torch
@@ -236,7 +244,7 @@ def _run(fn_name: str, algo: int, idx, vals, dims, core_dims, *, precision="fp32
     coo = _Coo(idx, vals, dims)
     if model is not None and (model.dtype != torch.float32 or not model.is_cuda or not model.is_contiguous()):
         raise TypeError("model must be a contiguous float32 tensor on the GPU")
-    o = _opts(precision, init, max_iters, tol, eig_max_iters, eig_tol, timing, model, seed, tune)
+    o = _opts(precision, init, max_iters, tol, eig_max_iters, eig_tol, timing, model, seed, tune, hosvd_fit)
     J = [int(j) for j in core_dims]
     Jc = (ctypes.c_int32 * 3)(*J)
     need = ctypes.c_size_t(0)
@@ -268,6 +276,38 @@ def hooi(idx, vals, dims, core_dims, **kw) -> Result:
 def mp(idx, vals, dims, core_dims, **kw) -> Result:
     """Multislice Projection (Figure 7). Same arguments as ``hooi``."""
     return _run("tucker_mp", ALGO_MP, idx, vals, dims, core_dims, **kw)
+
+
+def sp(idx, vals, dims, core_dims, **kw) -> Result:
+    """Slice Projection (Figure 5); stops on the core growth Delta_G. The
+    paper's random start is init=INIT_RANDOM (the default here)."""
+    kw.setdefault("init", INIT_RANDOM)
+    return _run("tucker_sp", ALGO_SP, idx, vals, dims, core_dims, **kw)
+
+
+def hosvd(idx, vals, dims, core_dims, precision="fp64", eig_tol=None, workspace=None, stream=None) -> Result:
+    """HO-SVD (Figure 1): every factor from its unfolding Gram, then the
+    core; Result.fits holds the one fit."""
+    import torch
+    dev = vals.device
+    coo = _Coo(idx, vals, dims)
+    o = _opts(precision, eig_tol=eig_tol)
+    J = [int(j) for j in core_dims]
+    Jc = (ctypes.c_int32 * 3)(*J)
+    need = ctypes.c_size_t(0)
+    _check(lib().tucker_workspace_bytes(ALGO_HOSVD, ctypes.byref(coo.c), Jc, ctypes.byref(o), ctypes.byref(need)))
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
+    G = torch.empty(J, dtype=torch.float64, device=dev)
+    facs = [torch.empty((int(dims[n]), J[n]), dtype=torch.float64, device=dev) for n in range(3)]
+    fptrs = (ctypes.c_void_p * 3)(*[f.data_ptr() for f in facs])
+    out = ctypes.c_double(0)
+    st = tk_stats()
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    status = _check(lib().tucker_hosvd(ctypes.byref(coo.c), Jc, ctypes.byref(o), G.data_ptr(), fptrs,
+                                       ctypes.byref(out), ctypes.byref(st), workspace.data_ptr(),
+                                       int(workspace.numel()), ctypes.c_void_p(s.cuda_stream)))
+    return Result(G, facs, [float(out.value)], 0, _stats_dict(st), status)
 
 
 def lead_eig(M, J, tol=1e-10, warm=False, workspace=None, stream=None):

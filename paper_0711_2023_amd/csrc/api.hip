@@ -8,6 +8,7 @@
 // per sweep.
 #include "../../include/tucker.h"
 #include "common.h"
+#include "guards.h"
 
 #include <chrono>
 #include <cmath>
@@ -106,6 +107,8 @@ static inline int lo_of(int m) { return (m + 1) % 3; }
 
 struct Plan {
     int algo, prec, init = TK_INIT_HOSVD;
+    int eprec = P64;    // precision whose accuracy sets the eigensolver tolerance
+    bool hfit = false;  // also the HO-SVD fit (opts.hosvd_fit): FP64 projection buffer Th
     Tune tune;
     int64_t I[3], nnz;
     int J[3];
@@ -142,6 +145,7 @@ struct Plan {
     bf16 *F16[3] = {nullptr, nullptr, nullptr};
     void *Fp[3] = {nullptr, nullptr, nullptr};  // MP: factor rows padded to ldT, zero padding
                                                 //     (FP64 / FP32; FP16 for BF16 T)
+    double *Th = nullptr;  // FP64 T(2) = X x_3 C^T (J3 columns) for the HO-SVD core
     double *Z, *Gp, *core_split;
     int64_t core_split_elems;
     double *Gx, *Pn[3], *W1, *W2;
@@ -155,6 +159,9 @@ struct Plan {
 };
 
 static size_t elem_size(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
+
+// MP and SP share their buffers (three projections with padded rows).
+static inline bool slice_algo(int algo) { return algo == TK_ALGO_MP || algo == TK_ALGO_SP; }
 
 static GramTerm term_of(const Plan &p, int m, int n, const void *base) {
     // T(m) is [i_hi][i_lo][r < ldT]; rows of the mode-n unfolding are i_n.
@@ -229,7 +236,7 @@ static void carve(Plan &p, Arena &ar) {
     p.Y2f = nullptr;
     for (int m = 0; m < 3; ++m) p.T[m] = nullptr;
     const size_t es = elem_size(prec);
-    if (p.algo == TK_ALGO_MP) {
+    if (slice_algo(p.algo)) {
         for (int m = 0; m < 3; ++m) p.T[m] = ar.take<char>((int64_t)(p.nslots[m] * p.ldT[m] * es));
         if (p.split)
             for (int m = 0; m < 3; ++m) p.Tlo[m] = ar.take<char>((int64_t)(p.nslots[m] * p.ldT[m] * es));
@@ -249,16 +256,24 @@ static void carve(Plan &p, Arena &ar) {
             ymax = std::max(ymax, p.I[n] * (int64_t)p.J[(n + 1) % 3] * p.J[(n + 2) % 3]);
         p.Y = ar.take<char>(ymax * (prec == P64 ? 8 : 4));
         if (prec == PBF16) p.Y2f = nullptr;
-    } else {  // fit
+    } else {  // fit, HO-SVD: FP64 T(2) for the core
         p.T[2] = ar.take<double>(p.nslots[2] * p.J[2]);
     }
+    p.Th = p.algo == TK_ALGO_FIT || p.algo == TK_ALGO_HOSVD ? (double *)p.T[2]
+           : p.hfit ? ar.take<double>(p.nslots[2] * p.J[2]) : nullptr;
     if (p.algo != TK_ALGO_FIT) {
         p.Mg = ar.take<double>(maxI * maxI);
         size_t gs = 0;
-        for (int n = 0; n < 3; ++n) {
+        for (int n = 0; n < 3 && p.algo != TK_ALGO_HOSVD; ++n) {
             int64_t K[kGramMaxTerms];
             int gprec = prec;
-            if (p.algo == TK_ALGO_MP) {
+            if (p.algo == TK_ALGO_SP) {
+                // SP: one projection per Gram, T((n+2)%3) (Figure 5)
+                const int m = (n + 2) % 3;
+                const int per = p.split ? 3 : 1;
+                for (int q = 0; q < per; ++q) K[q] = p.nslots[m] / p.I[n] * p.ldT[m];
+                gs = std::max(gs, gram_scratch_bytes((int)p.I[n], gprec, per, K, p.tune));
+            } else if (slice_algo(p.algo)) {
                 int m1 = (n + 1) % 3, m2 = (n + 2) % 3;
                 const int64_t K1 = p.nslots[m1] / p.I[n] * p.ldT[m1], K2 = p.nslots[m2] / p.I[n] * p.ldT[m2];
                 const int per = p.split ? 3 : 1;  // hi.hi (+ hi.lo, lo.hi)
@@ -267,7 +282,7 @@ static void carve(Plan &p, Arena &ar) {
                     K[per + q] = K2;
                 }
                 gs = std::max(gs, gram_scratch_bytes((int)p.I[n], gprec, 2 * per, K, p.tune));
-            } else {
+            } else if (p.algo == TK_ALGO_HOOI) {
                 K[0] = (int64_t)p.J[(n + 1) % 3] * p.J[(n + 2) % 3];
                 gprec = prec == P64 ? P64 : P32;
                 gs = std::max(gs, gram_scratch_bytes((int)p.I[n], gprec, 1, K, p.tune));
@@ -296,7 +311,7 @@ static void carve(Plan &p, Arena &ar) {
             // significand than BF16 for entries of orthonormal columns, and
             // the projection's FMA takes FP16 operands directly), FP32 for
             // split Grams (their lo parts need more than 16-bit factors)
-            p.Fp[n] = p.algo == TK_ALGO_MP
+            p.Fp[n] = slice_algo(p.algo)
                           ? ar.take<char>(p.I[n] * p.ldT[n] * (int64_t)(p.split ? 4 : elem_size(prec)))
                           : nullptr;
         }
@@ -313,7 +328,7 @@ static void carve(Plan &p, Arena &ar) {
         p.W1 = ar.take<double>(J0 * J1 * J2);
         p.W2 = ar.take<double>(J0 * J1 * J2);
     }
-    if (p.init == TK_INIT_LEARNED && p.algo != TK_ALGO_FIT) {
+    if (p.init == TK_INIT_LEARNED && p.algo != TK_ALGO_FIT && p.algo != TK_ALGO_HOSVD) {
         int64_t In = std::max({p.I[0], p.I[1], p.I[2]});
         int Km = learn_test_width(std::max({p.J[0], p.J[1], p.J[2]}));
         for (int k = 0; k < 2; ++k) {
@@ -352,9 +367,21 @@ static int check_coo(const tk_coo *X, const int32_t *J) {
 static int check_opts(const tk_opts *o, const tk_coo *X, int algo) {
     if (!o) return TK_ERR_ARG;
     if (o->precision < 0 || o->precision > 3) return TK_ERR_ARG;
-    if (o->precision == TK_MIXED_BF16X3 && algo != TK_ALGO_MP) return TK_ERR_ARG;
-    if (o->init != TK_INIT_HOSVD && o->init != TK_INIT_GIVEN && o->init != TK_INIT_LEARNED) return TK_ERR_ARG;
-    if (o->init == TK_INIT_LEARNED && !o->model) return TK_ERR_ARG;
+    if (o->precision == TK_MIXED_BF16X3 && !slice_algo(algo)) return TK_ERR_ARG;
+    if (algo == TK_ALGO_HOSVD) {
+        if (o->eig_max_iters < 1 || !(o->eig_tol >= 0.0)) return TK_ERR_ARG;
+        for (int n = 0; n < 3; ++n)
+            if (X->dims[n] > kMaxHosvdDim) return TK_ERR_ARG;
+        return TK_OK;
+    }
+    if (o->init != TK_INIT_HOSVD && o->init != TK_INIT_GIVEN && o->init != TK_INIT_LEARNED &&
+        o->init != TK_INIT_RANDOM)
+        return TK_ERR_ARG;
+    if (o->init == TK_INIT_LEARNED && (!o->model || algo == TK_ALGO_SP)) return TK_ERR_ARG;
+    if (o->hosvd_fit != 0 && o->hosvd_fit != 1) return TK_ERR_ARG;
+    // the report uses the factor buffers as scratch: not with a start read
+    // from them or one that replaces the HO-SVD
+    if (o->hosvd_fit && (o->init == TK_INIT_GIVEN || o->init == TK_INIT_LEARNED)) return TK_ERR_ARG;
     if (o->tune) {
         const tk_tune *t = o->tune;
         auto in = [](int32_t v, int32_t lo, int32_t hi) { return v == 0 || (v >= lo && v <= hi); };
@@ -364,9 +391,14 @@ static int check_opts(const tk_opts *o, const tk_coo *X, int algo) {
     }
     if (o->max_iters < 0 || o->eig_max_iters < 1) return TK_ERR_ARG;
     if (!(o->eig_tol >= 0.0) || std::isnan(o->tol)) return TK_ERR_ARG;
-    if (o->init != TK_INIT_GIVEN)  // HO-SVD, or its fallback for the learned start
-        for (int n = 1; n < 3; ++n)
-            if (X->dims[n] > kMaxHosvdDim) return TK_ERR_ARG;
+    // start Grams X_(n) X_(n)^T: modes 2 and 3 for an HO-SVD start (or the
+    // learned start's fallback), mode 3 alone for SP's; all three for the
+    // HO-SVD fit
+    const bool hs = o->init == TK_INIT_HOSVD || o->init == TK_INIT_LEARNED;
+    for (int n = 0; n < 3; ++n) {
+        const bool needs = o->hosvd_fit || (hs && (algo == TK_ALGO_SP ? n == 2 : n >= 1));
+        if (needs && X->dims[n] > kMaxHosvdDim) return TK_ERR_ARG;
+    }
     return TK_OK;
 }
 
@@ -382,9 +414,11 @@ static Tune tune_of(const tk_tune *t) {
 }
 
 static void plan_init(Plan &p, int algo, int prec, const tk_coo *X, const int32_t *J, int init = TK_INIT_HOSVD,
-                      const tk_tune *tune = nullptr) {
+                      const tk_tune *tune = nullptr, bool hfit = false) {
     p.algo = algo;
+    p.hfit = hfit && algo != TK_ALGO_FIT && algo != TK_ALGO_HOSVD;
     p.split = prec == TK_MIXED_BF16X3;
+    p.eprec = p.split ? P32 : prec;
     if (p.split) prec = PBF16;  // BF16 storage, two parts
     p.prec = prec;
     p.init = init;
@@ -396,7 +430,7 @@ static void plan_init(Plan &p, int algo, int prec, const tk_coo *X, const int32_
     }
     for (int m = 0; m < 3; ++m) p.nslots[m] = p.I[hi_of(m)] * p.I[lo_of(m)];
     const int vec = prec == P64 ? 2 : (prec == P32 ? 4 : 8);  // elements per 16 bytes
-    for (int m = 0; m < 3; ++m) p.ldT[m] = algo == TK_ALGO_MP ? (int)ceil_div(p.J[m], vec) * vec : p.J[m];
+    for (int m = 0; m < 3; ++m) p.ldT[m] = slice_algo(algo) ? (int)ceil_div(p.J[m], vec) * vec : p.J[m];
 }
 
 }  // namespace tk
@@ -417,6 +451,7 @@ void tucker_default_opts(tk_opts *o) {
     o->model = nullptr;
     o->seed = 0x5eedull;
     o->tune = nullptr;
+    o->hosvd_fit = 0;
 }
 
 const char *tucker_strerror(int st) {
@@ -438,15 +473,16 @@ int tucker_workspace_bytes(int32_t algo, const tk_coo *X, const int32_t *core_di
     if (!bytes) return TK_ERR_ARG;
     int st = check_coo(X, core_dims);
     if (st) return st;
-    if (algo != TK_ALGO_HOOI && algo != TK_ALGO_MP && algo != TK_ALGO_FIT) return TK_ERR_ARG;
+    if (algo < TK_ALGO_HOOI || algo > TK_ALGO_HOSVD) return TK_ERR_ARG;
     int prec = P64;
     if (algo != TK_ALGO_FIT) {
         if ((st = check_opts(opt, X, algo))) return st;
-        prec = opt->precision;
+        prec = algo == TK_ALGO_HOSVD ? P64 : opt->precision;
     }
+    const bool dec = algo != TK_ALGO_FIT && algo != TK_ALGO_HOSVD;
     Plan p;
-    plan_init(p, algo, prec, X, core_dims, algo != TK_ALGO_FIT ? opt->init : TK_INIT_HOSVD,
-              algo != TK_ALGO_FIT ? opt->tune : nullptr);
+    plan_init(p, algo, prec, X, core_dims, dec ? opt->init : TK_INIT_HOSVD, dec ? opt->tune : nullptr,
+              dec && opt->hosvd_fit);
     Arena ar;
     carve(p, ar);
     *bytes = ar.used + 256;
@@ -467,6 +503,8 @@ struct Timer {
     size_t used = 0;
     double ms[5] = {0, 0, 0, 0, 0};
     int64_t calls[5] = {0, 0, 0, 0, 0};
+    double sweep_ttmc[64] = {};  // TTMc time (projections + second stage) per collect() = per sweep
+    int sweeps = 0;
     Timer(bool on_, hipStream_t s_) : on(on_), s(s_) {}
     ~Timer() {
         for (auto e : ev) (void)hipEventDestroy(e);
@@ -509,12 +547,16 @@ struct Timer {
     // call after a stream synchronisation
     void collect() {
         if (!on) return;
+        double ttmc = 0.0;
         for (size_t i = 0; i + 1 < used; i += 2) {
             float t = 0;
             (void)hipEventElapsedTime(&t, ev[i], ev[i + 1]);
             ms[kind[i / 2]] += t;
             calls[kind[i / 2]] += 1;
+            if (kind[i / 2] == kProj || kind[i / 2] == kTtmc) ttmc += t;
         }
+        if (sweeps < 64) sweep_ttmc[sweeps] = ttmc;
+        ++sweeps;
         used = 0;
     }
     void report(tk_stats *st) const {
@@ -526,6 +568,7 @@ struct Timer {
         st->gram_calls = calls[kGram];
         st->eig_ms = ms[kEig];
         st->core_ms = ms[kCore];
+        for (int t = 0; t < 64; ++t) st->ttmc_sweep_ms[t] = t < sweeps ? sweep_ttmc[t] : 0.0;
     }
 };
 
@@ -542,6 +585,14 @@ static double now_ms() {
         }                                 \
     } while (0)
 
+// An ordering failed its range checks (guards.h): nothing was written out
+// of bounds, but the decomposition cannot go on.
+static int order_failed(int r) {
+    if (r == TK_ERR_DEVICE && !g_err[0])
+        snprintf(g_err, sizeof(g_err), "fibre ordering failed its range checks (scan total or slot position)");
+    return r;
+}
+
 // Validation, duplicate summing, orderings, ||X||^2.
 static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double *normx2_out) {
     const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
@@ -549,10 +600,14 @@ static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double
     int32_t flags = 0;
     ST(hipMemcpyAsync(&flags, p.flags, 4, hipMemcpyDeviceToHost, s));
     ST(hipStreamSynchronize(s));
-    if (flags & 1) return TK_ERR_INDEX;
-    if (flags & 2) return TK_ERR_VALUE;
+    if (int r = prep_status(flags)) return r;
     OrderScratch sc{p.counts, p.cursor, p.tmp, p.scan};
-    ST(build_order(X->idx, p.nnz, dims, 2, p.ptr[2], p.perm, sc, s));
+    ST(build_order(X->idx, p.nnz, dims, 2, p.ptr[2], p.perm, sc, p.flags, s));
+    // the duplicate pass reads through perm: the ordering must have passed
+    // its range checks first
+    ST(hipMemcpyAsync(&flags, p.flags, 4, hipMemcpyDeviceToHost, s));
+    ST(hipStreamSynchronize(s));
+    if (int r = prep_status(flags)) return order_failed(r);
     int32_t *cidx[3] = {p.cidx[0], p.cidx[1], p.cidx[2]};
     ST(dedup(X->idx, X->vals, p.nnz, p.perm, p.heads, p.pos, p.scan, cidx, p.cval, p.nu, s));
     int32_t nu = 0;
@@ -561,13 +616,16 @@ static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double
     ST(sumsq(p.cval, nu, p.partials, p.scal + 0, s));
     const int32_t *cid[3] = {p.cidx[0], p.cidx[1], p.cidx[2]};
     for (int m = 0; m < 3; ++m) {
-        ST(build_order(cid, nu, dims, m, p.ptr[m], p.perm, sc, s));
-        ST(gather_leaf<double>(p.cidx[m], p.cval, p.perm, nu, p.lidx[m], p.lval64[m], s));
-        if (p.lval32[m]) ST(gather_leaf<float>(p.cidx[m], p.cval, p.perm, nu, p.lidx[m], p.lval32[m], s));
+        ST(build_order(cid, nu, dims, m, p.ptr[m], p.perm, sc, p.flags, s));
+        ST(gather_leaf<double>(p.cidx[m], p.cval, p.perm, nu, p.lidx[m], p.lval64[m], p.flags, s));
+        if (p.lval32[m])
+            ST(gather_leaf<float>(p.cidx[m], p.cval, p.perm, nu, p.lidx[m], p.lval32[m], p.flags, s));
     }
     double nx2 = 0;
     ST(hipMemcpyAsync(&nx2, p.scal + 0, 8, hipMemcpyDeviceToHost, s));
+    ST(hipMemcpyAsync(&flags, p.flags, 4, hipMemcpyDeviceToHost, s));
     ST(hipStreamSynchronize(s));
+    if (int r = prep_status(flags)) return order_failed(r);
     *nu_out = nu;
     *normx2_out = nx2;
     if (!(nx2 > 0.0)) return TK_ERR_EMPTY;
@@ -674,13 +732,18 @@ static hipError_t core_from_T2(Plan &p, const void *T2, int ldt, bool t2_is_f64,
     return hipSuccess;
 }
 
-static int finish_fit(Plan &p, const double *core, hipStream_t s, double *fit) {
+// fit = 1 - sqrt(||X||^2 - ||G||^2) / ||X|| (the identity for orthonormal
+// factors and G = X x_n A(n)^T); *g2 (optional) receives ||G||^2.
+static int finish_fit(Plan &p, const double *core, hipStream_t s, double *fit, double *g2 = nullptr) {
     const int64_t nJ = (int64_t)p.J[0] * p.J[1] * p.J[2];
     ST(sumsq(core, nJ, p.partials, p.scal + 1, s));
     k_fit<<<1, 1, 0, s>>>(p.scal + 0, p.scal + 1, nullptr, nullptr, p.scal + 2, 0);
     ST(hipGetLastError());
-    ST(hipMemcpyAsync(fit, p.scal + 2, 8, hipMemcpyDeviceToHost, s));
+    double gf[2];  // ||G||^2, fit
+    ST(hipMemcpyAsync(gf, p.scal + 1, 16, hipMemcpyDeviceToHost, s));
     ST(hipStreamSynchronize(s));
+    *fit = gf[1];
+    if (g2) *g2 = gf[0];
     return TK_OK;
 }
 
@@ -692,7 +755,7 @@ static int run_eig(Plan &p, int n, double *M, double *F, bool warm, const tk_opt
     // FP32 projections limit the Gram to about 1e-7 relative, BF16 ones (8
     // significant bits) to about 1e-3, so the sum of the leading Ritz values
     // is resolved to a tenth of that: 1e-8 and 1e-4 of itself respectively
-    eo.tol = o->eig_tol > 0 ? o->eig_tol : (p.prec == P64 ? 1e-12 : (p.prec == P32 || p.split ? 1e-8 : 1e-4));
+    eo.tol = o->eig_tol > 0 ? o->eig_tol : (p.eprec == P64 ? 1e-12 : (p.eprec == P32 ? 1e-8 : 1e-4));
     eo.warm = warm && p.blk_ok[n];
     // a block left by the previous sweep's solve of this mode is usually
     // converged or nearly so: its filter starts at a low degree. Blocks from
@@ -723,7 +786,7 @@ static int common_start(int algo, const tk_coo *X, const int32_t *J, const tk_op
     if (!core || !factors || !factors[0] || !factors[1] || !factors[2] || !iters_done) return TK_ERR_ARG;
     if (o->max_iters > 0 && !fit_history) return TK_ERR_ARG;
     if (X->nnz == 0) return TK_ERR_EMPTY;
-    plan_init(p, algo, o->precision, X, J, o->init, o->tune);
+    plan_init(p, algo, o->precision, X, J, o->init, o->tune, o->hosvd_fit != 0);
     Arena ar;
     carve(p, ar);
     if (!ws || wsb < ar.used + 256) return TK_ERR_WORKSPACE;
@@ -858,10 +921,70 @@ static int start_pair(Plan &p, const tk_opts *o, double *const *factors, tk_stat
     return r;
 }
 
+// ------------------------------------------------------------------ random start
+// Output number k of SplitMix64 seeded with `seed` (the state advances by the
+// golden gamma before each output, then the variant-13 finaliser).
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// One workgroup per column r of the I x J start of mode n: entries uniform
+// on [0, 1) from SplitMix64 output n * 2^40 + i * J + r, then the column
+// divided by its norm (sum of squares in a fixed order).
+__global__ void __launch_bounds__(256) k_random_start(double *F, int64_t I, int J, int n, uint64_t seed) {
+    const int r = blockIdx.x;
+    const uint64_t base = ((uint64_t)n << 40) + (uint64_t)r;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < I; i += blockDim.x) {
+        const double u = (double)(splitmix64_at(seed, base + (uint64_t)i * J) >> 11) * 0x1.0p-53;
+        F[i * J + r] = u;
+        acc += u * u;
+    }
+    __shared__ double ws[4];
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    const double nrm = sqrt(ws[0] + ws[1] + ws[2] + ws[3]);
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int64_t i = threadIdx.x; i < I; i += blockDim.x) F[i * J + r] *= inv;
+}
+
+// Columns of F (I x J) divided by their norms, in place (the given start of SP).
+__global__ void __launch_bounds__(256) k_normalise_cols(double *F, int64_t I, int J) {
+    const int r = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < I; i += blockDim.x) {
+        const double v = F[i * J + r];
+        acc += v * v;
+    }
+    __shared__ double ws[4];
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    const double nrm = sqrt(ws[0] + ws[1] + ws[2] + ws[3]);
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int64_t i = threadIdx.x; i < I; i += blockDim.x) F[i * J + r] *= inv;
+}
+
+static int random_mode(Plan &p, int n, double *F, uint64_t seed, hipStream_t s) {
+    k_random_start<<<p.J[n], 256, 0, s>>>(F, p.I[n], p.J[n], n, seed);
+    ST(hipGetLastError());
+    ST(refresh_copies(p, n, F, s));
+    return TK_OK;
+}
+
 static int init_factors(Plan &p, const tk_opts *o, double *const *factors, tk_stats *st, int *noconv, double nx2,
                         hipStream_t s) {
     if (o->init == TK_INIT_GIVEN) {
         for (int n = 1; n < 3; ++n) ST(refresh_copies(p, n, factors[n], s));
+        return TK_OK;
+    }
+    if (o->init == TK_INIT_RANDOM) {
+        for (int n = 1; n < 3; ++n)
+            if (int r = random_mode(p, n, factors[n], o->seed, s)) return r;
         return TK_OK;
     }
     if (o->init == TK_INIT_LEARNED) {
@@ -883,6 +1006,75 @@ static int init_factors(Plan &p, const tk_opts *o, double *const *factors, tk_st
     return TK_OK;
 }
 
+
+// ------------------------------------------------------------------ HO-SVD core and fit
+// G = [[X; A^T, B^T, C^T]] from an FP64 projection T(2) = X x_3 C^T (rows
+// of J3) and its fit; the core goes to `core`.
+static int hosvd_core_fit(Plan &p, const double *A, const double *B, const double *C, double *core, hipStream_t s,
+                          double *fit) {
+    ST((project<double, double, double>(p.ptr[2], p.lidx[2], p.lval64[2], C, p.I[2], p.J[2], p.J[2], p.J[2],
+                                        p.nslots[2], p.nnz, p.Th, s)));
+    ST(core_from_T2(p, p.Th, p.J[2], true, A, B, core, s));
+    return finish_fit(p, core, s, fit);
+}
+
+// The HO-SVD fit of Figure 1 reported beside a decomposition. The HO-SVD
+// factors of the modes in `todo` (those the start has not computed already)
+// go to the caller's factor buffers as scratch and the core to `core`; the
+// start and the sweeps overwrite both afterwards. Called after an HO-SVD
+// start (todo = the modes it lacks) or before a random start (all three).
+// The eigensolver blocks these solves leave are discarded, so the
+// decomposition runs exactly as it would without the report.
+static int report_hosvd_fit(Plan &p, const tk_opts *o, const bool todo[3], double *core, double *const *factors,
+                            tk_stats *st, int *noconv, hipStream_t s) {
+    const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
+    for (int n = 0; n < 3; ++n) {
+        if (!todo[n]) continue;
+        const int sl = (n + 1) % 3;
+        ST(hosvd_gram(n, dims, p.ptr[n], p.lidx[n], p.lval64[n], p.ptr[sl], p.lidx[sl], p.lval64[sl], p.Mg, s));
+        const int r = run_eig(p, n, p.Mg, factors[n], false, o, nullptr, noconv, s);
+        if (r) return r;
+        p.blk_ok[n] = false;
+    }
+    double fit = 0.0;
+    if (int r = hosvd_core_fit(p, factors[0], factors[1], factors[2], core, s, &fit)) return r;
+    if (st) st->hosvd_fit = fit;
+    return TK_OK;
+}
+
+
+// Start of B and C with the HO-SVD fit report around it when asked for:
+// before a random start (it needs all three HO-SVD factors), after an
+// HO-SVD start (it needs only A's).
+static int hosvd_report_around_start(Plan &p, const tk_opts *o, double *core, double *const *factors,
+                                     tk_stats *st, int *noconv, double nx2, hipStream_t s) {
+    if (p.hfit && o->init == TK_INIT_RANDOM) {
+        const bool all[3] = {true, true, true};
+        if (int r = report_hosvd_fit(p, o, all, core, factors, st, noconv, s)) return r;
+    }
+    if (int r = init_factors(p, o, factors, st, noconv, nx2, s)) return r;
+    if (p.hfit && o->init == TK_INIT_HOSVD) {
+        const bool a_only[3] = {true, false, false};
+        if (int r = report_hosvd_fit(p, o, a_only, core, factors, st, noconv, s)) return r;
+    }
+    return TK_OK;
+}
+
+// MP and SP core from T(2)(C): the projection itself when it is FP64 or
+// FP32, else (BF16 Grams) an FP32 projection with rows of ldc for it.
+static hipError_t slice_core(Plan &p, const double *A, const double *B, double *core, hipStream_t s, Timer &tm) {
+    const void *T2c = p.T[2];
+    if (p.prec == PBF16) {
+        TK_HIP((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.Fc, p.I[2], p.ldc, p.J[2], p.ldc,
+                                             p.nslots[2], p.nnz, p.Tcore, s, p.tune, tm.kernel(kProj))));
+        T2c = p.Tcore;
+    }
+    tm.begin(kCore);
+    TK_HIP(core_from_T2(p, T2c, p.prec == PBF16 ? p.ldc : p.ldT[2], p.prec == P64, A, B, core, s));
+    tm.end();
+    return hipSuccess;
+}
+
 }  // namespace tk
 
 extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, double *core, double *const *factors,
@@ -900,14 +1092,16 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     if ((st = prep(p, X, s, &nu, &nx2))) return st;
     double t1 = now_ms();
     int noconv = 0;
-    if ((st = init_factors(p, o, factors, stats, &noconv, nx2, s))) return st;
+    if ((st = hosvd_report_around_start(p, o, core, factors, stats, &noconv, nx2, s))) return st;
     ST(hipStreamSynchronize(s));
     double t2 = now_ms();
     const int prec = p.prec;
     double *A = factors[0], *B = factors[1], *C = factors[2];
+    double g2 = 0.0;
     // projections of the start: T(1)(B), T(2)(C)
-    ST(project_m(p, 1, B, p.T[1], prec, s, 0, tm.kernel(kProj)));
-    ST(project_m(p, 2, C, p.T[2], prec, s, 0, tm.kernel(kProj)));
+    // (part of the start, not of a sweep's TTMc phase: untimed)
+    ST(project_m(p, 1, B, p.T[1], prec, s));
+    ST(project_m(p, 2, C, p.T[2], prec, s));
     double prev = 0.0;
     int t = 0;
     *iters_done = 0;
@@ -937,18 +1131,9 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         tm.end();
         ST(project_m(p, 2, C, p.T[2], prec, s, 0, tm.kernel(kProj)));
         // core from T(2)(C) (FP64 or FP32, never BF16)
-        const void *T2c = p.T[2];
-        bool f64 = prec == P64;
-        if (prec == PBF16) {
-            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.Fc, p.I[2], p.ldc, p.J[2], p.ldc,
-                                             p.nslots[2], p.nnz, p.Tcore, s)));
-            T2c = p.Tcore;
-        }
-        tm.begin(kCore);
-        ST(core_from_T2(p, T2c, prec == PBF16 ? p.ldc : p.ldT[2], f64, A, B, core, s));
-        tm.end();
+        ST(slice_core(p, A, B, core, s, tm));
         double fit = 0;
-        if ((st = finish_fit(p, core, s, &fit))) return st;
+        if ((st = finish_fit(p, core, s, &fit, &g2))) return st;
         tm.collect();
         fit_history[t - 1] = fit;
         *iters_done = t;
@@ -963,16 +1148,9 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         tm.begin(kEig);
         if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
         tm.end();
-        const void *T2c = p.T[2];
-        if (prec == PBF16) {
-            ST((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.Fc, p.I[2], p.ldc, p.J[2], p.ldc,
-                                             p.nslots[2], p.nnz, p.Tcore, s)));
-            T2c = p.Tcore;
-        }
-        tm.begin(kCore);
-        ST(core_from_T2(p, T2c, prec == PBF16 ? p.ldc : p.ldT[2], prec == P64, A, B, core, s));
-        tm.end();
-        ST(hipStreamSynchronize(s));
+        ST(slice_core(p, A, B, core, s, tm));
+        double fit = 0;
+        if ((st = finish_fit(p, core, s, &fit, &g2))) return st;
     }
     double t3 = now_ms();
     if (stats) {
@@ -982,6 +1160,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         tm.report(stats);
         stats->nnz_unique = nu;
         stats->norm_x = std::sqrt(nx2);
+        stats->core_norm = std::sqrt(g2);
     }
     return noconv ? TK_WARN_NOCONV : TK_OK;
 }
@@ -1025,9 +1204,10 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
     if ((st = prep(p, X, s, &nu, &nx2))) return st;
     double t1 = now_ms();
     int noconv = 0;
-    if ((st = init_factors(p, o, factors, stats, &noconv, nx2, s))) return st;
+    if ((st = hosvd_report_around_start(p, o, core, factors, stats, &noconv, nx2, s))) return st;
     ST(hipStreamSynchronize(s));
     double t2 = now_ms();
+    double g2 = 0.0;
     const int prec = p.prec;
     const int64_t I0 = p.I[0], I1 = p.I[1], I2 = p.I[2];
     const int J0 = p.J[0], J1 = p.J[1], J2 = p.J[2];
@@ -1137,11 +1317,12 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
             ST(hipGetLastError());
         }
         if (last_only) {
-            ST(hipStreamSynchronize(s));
+            double fit = 0;
+            if ((st = finish_fit(p, core, s, &fit, &g2))) return st;
             break;
         }
         double fit = 0;
-        if ((st = finish_fit(p, core, s, &fit))) return st;
+        if ((st = finish_fit(p, core, s, &fit, &g2))) return st;
         tm.collect();
         fit_history[t - 1] = fit;
         *iters_done = t;
@@ -1156,6 +1337,170 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
         tm.report(stats);
         stats->nnz_unique = nu;
         stats->norm_x = std::sqrt(nx2);
+        stats->core_norm = std::sqrt(g2);
+    }
+    return noconv ? TK_WARN_NOCONV : TK_OK;
+}
+
+
+namespace tk {
+// SP's Gram of mode n from the single projection T(m): one term, or three
+// for split-BF16 (hi hi^T + hi lo^T + lo hi^T).
+static hipError_t sp_gram(Plan &p, int n, int m, hipStream_t s) {
+    GramTerm g[3];
+    int nt = 0;
+    g[nt++] = term_of(p, m, n, p.T[m]);
+    if (p.split) {
+        GramTerm hl = term_of(p, m, n, p.T[m]);
+        hl.base_b = p.Tlo[m];
+        GramTerm lh = term_of(p, m, n, p.Tlo[m]);
+        lh.base_b = p.T[m];
+        g[nt++] = hl;
+        g[nt++] = lh;
+    }
+    return gram((int)p.I[n], p.prec, nt, g, p.Mg, p.gram_scratch, s, p.tune);
+}
+}  // namespace tk
+
+extern "C" int tucker_sp(const tk_coo *X, const int32_t *J, const tk_opts *o, double *core, double *const *factors,
+                         double *fit_history, int32_t *iters_done, tk_stats *stats, void *ws, size_t wsb,
+                         void *stream) {
+    Plan p;
+    int st = common_start(TK_ALGO_SP, X, J, o, core, factors, fit_history, iters_done, ws, wsb, p);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    Timer tm(o->timing != 0, s);
+    double t0 = now_ms();
+    int64_t nu = 0;
+    double nx2 = 0;
+    if ((st = prep(p, X, s, &nu, &nx2))) return st;
+    double t1 = now_ms();
+    int noconv = 0;
+    double *A = factors[0], *B = factors[1], *C = factors[2];
+    // the start of C (Figure 5): random (the paper's), given, or HO-SVD;
+    // columns of unit length. The HO-SVD fit report, when asked for, comes
+    // before a random start and after an HO-SVD one.
+    if (p.hfit && o->init == TK_INIT_RANDOM) {
+        const bool all[3] = {true, true, true};
+        if ((st = report_hosvd_fit(p, o, all, core, factors, stats, &noconv, s))) return st;
+    }
+    if (o->init == TK_INIT_RANDOM) {
+        if ((st = random_mode(p, 2, C, o->seed, s))) return st;
+    } else if (o->init == TK_INIT_GIVEN) {
+        k_normalise_cols<<<p.J[2], 256, 0, s>>>(C, p.I[2], p.J[2]);
+        ST(hipGetLastError());
+        ST(refresh_copies(p, 2, C, s));
+    } else {
+        if ((st = start_mode(p, 2, 0, o, factors, stats, &noconv, nx2, s))) return st;
+        if (p.hfit) {
+            const bool ab[3] = {true, true, false};
+            if ((st = report_hosvd_fit(p, o, ab, core, factors, stats, &noconv, s))) return st;
+        }
+    }
+    ST(hipStreamSynchronize(s));
+    double t2 = now_ms();
+    const int prec = p.prec;
+    ST(project_m(p, 2, C, p.T[2], prec, s));  // part of the start: untimed
+    double prev_norm = 0.0, g2 = 0.0;
+    *iters_done = 0;
+    const int maxit = std::max(o->max_iters, 1);
+    for (int t = 1; t <= maxit; ++t) {
+        // M13 = sum_j X_:j: C C^T X_:j:^T: Gram of T(2) = X x_3 C^T on mode 1
+        tm.begin(kGram);
+        ST(sp_gram(p, 0, 2, s));
+        tm.end();
+        tm.begin(kEig);
+        if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
+        tm.end();
+        // M21 = sum_k X_::k^T A A^T X_::k: Gram of T(0) = X x_1 A^T on mode 2
+        ST(project_m(p, 0, A, p.T[0], prec, s, 0, tm.kernel(kProj)));
+        tm.begin(kGram);
+        ST(sp_gram(p, 1, 0, s));
+        tm.end();
+        tm.begin(kEig);
+        if ((st = run_eig(p, 1, p.Mg, B, true, o, stats, &noconv, s))) return st;
+        tm.end();
+        // M32 = sum_i X_i::^T B B^T X_i::: Gram of T(1) = X x_2 B^T on mode 3
+        ST(project_m(p, 1, B, p.T[1], prec, s, 0, tm.kernel(kProj)));
+        tm.begin(kGram);
+        ST(sp_gram(p, 2, 1, s));
+        tm.end();
+        tm.begin(kEig);
+        if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
+        tm.end();
+        // T(2)(C): the core now, mode 1's Gram in the next sweep
+        ST(project_m(p, 2, C, p.T[2], prec, s, 0, tm.kernel(kProj)));
+        ST(slice_core(p, A, B, core, s, tm));
+        double fit = 0;
+        if ((st = finish_fit(p, core, s, &fit, &g2))) return st;
+        tm.collect();
+        const double gn = std::sqrt(g2);
+        // Delta_G(t) = 1 - ||G(t-1)|| / ||G(t)||, ||G(0)|| = 0 (Section 4.3)
+        const double dG = gn > 0.0 ? 1.0 - prev_norm / gn : 0.0;
+        if (o->max_iters > 0) {
+            fit_history[t - 1] = fit;
+            *iters_done = t;
+        }
+        if (o->max_iters == 0 || (o->tol > 0 && dG < o->tol)) break;
+        prev_norm = gn;
+    }
+    double t3 = now_ms();
+    if (stats) {
+        stats->prep_ms = t1 - t0;
+        stats->init_ms = t2 - t1;
+        stats->sweeps_ms = t3 - t2;
+        tm.report(stats);
+        stats->nnz_unique = nu;
+        stats->norm_x = std::sqrt(nx2);
+        stats->core_norm = std::sqrt(g2);
+    }
+    return noconv ? TK_WARN_NOCONV : TK_OK;
+}
+
+extern "C" int tucker_hosvd(const tk_coo *X, const int32_t *J, const tk_opts *o, double *core, double *const *factors,
+                            double *fit, tk_stats *stats, void *ws, size_t wsb, void *stream) {
+    int st = check_coo(X, J);
+    if (st) return st;
+    if ((st = check_opts(o, X, TK_ALGO_HOSVD))) return st;
+    if (!core || !factors || !factors[0] || !factors[1] || !factors[2] || !fit) return TK_ERR_ARG;
+    if (X->nnz == 0) return TK_ERR_EMPTY;
+    Plan p;
+    plan_init(p, TK_ALGO_HOSVD, P64, X, J);
+    p.eprec = o->precision == TK_MIXED_BF16X3 ? P32 : o->precision;
+    tk_opts oh = *o;  // the starts below are HO-SVD ones whatever opt->init says
+    oh.init = TK_INIT_HOSVD;
+    o = &oh;
+    Arena ar;
+    carve(p, ar);
+    if (!ws || wsb < ar.used + 256) return TK_ERR_WORKSPACE;
+    ar.base = reinterpret_cast<char *>(align_up(reinterpret_cast<uintptr_t>(ws), 256));
+    ar.used = 0;
+    carve(p, ar);
+    g_err[0] = 0;
+    hipStream_t s = (hipStream_t)stream;
+    if (stats) memset(stats, 0, sizeof(*stats));
+    double t0 = now_ms();
+    int64_t nu = 0;
+    double nx2 = 0;
+    if ((st = prep(p, X, s, &nu, &nx2))) return st;
+    double t1 = now_ms();
+    int noconv = 0;
+    // Figure 1: every factor from its own unfolding Gram; modes 2 and 3
+    // side by side (as the starts of HOOI and MP), then mode 1
+    if ((st = start_pair(p, o, factors, stats, &noconv, nx2, s))) return st;
+    if ((st = start_mode(p, 0, 0, o, factors, stats, &noconv, nx2, s))) return st;
+    if ((st = hosvd_core_fit(p, factors[0], factors[1], factors[2], core, s, fit))) return st;
+    double t2 = now_ms();
+    if (stats) {
+        stats->prep_ms = t1 - t0;
+        stats->init_ms = t2 - t1;
+        stats->nnz_unique = nu;
+        stats->norm_x = std::sqrt(nx2);
+        stats->hosvd_fit = *fit;
+        // ||G||^2 = ||X||^2 (1 - (1 - fit)^2) by the fit identity
+        const double r = 1.0 - *fit;
+        stats->core_norm = std::sqrt(std::max(0.0, nx2 * (1.0 - r * r)));
     }
     return noconv ? TK_WARN_NOCONV : TK_OK;
 }

@@ -74,8 +74,10 @@ struct OrderScratch {
     int32_t *tmp;      // nnz
     int32_t *scan;     // scan_scratch_ints(nslots)
 };
+// Positions are range-checked (guards.h): a failed check sets
+// kFlagOrderCheck in *flags and leaves perm unwritten.
 hipError_t build_order(const int32_t *const idx[3], int64_t nnz, const int64_t dims[3], int m,
-                       int32_t *ptr, int32_t *perm, OrderScratch sc, hipStream_t s);
+                       int32_t *ptr, int32_t *perm, OrderScratch sc, int32_t *flags, hipStream_t s);
 
 // Validation: flags |= 1 (index out of range), 2 (non-finite value).
 hipError_t validate(const int32_t *const idx[3], const double *vals, int64_t nnz, const int64_t dims[3],
@@ -89,10 +91,10 @@ hipError_t dedup(const int32_t *const idx[3], const double *vals, int64_t nnz, c
                  int32_t *nu_dev, hipStream_t s);
 
 // Gather the leaf index and value of an ordering: lidx[q] = idx_m[perm[q]],
-// lval[q] = (T)vals[perm[q]].
+// lval[q] = (T)vals[perm[q]]; nothing when *flags has kFlagOrderCheck.
 template <class T>
 hipError_t gather_leaf(const int32_t *idx_m, const double *vals, const int32_t *perm, int64_t n, int32_t *lidx,
-                       T *lval, hipStream_t s);
+                       T *lval, const int32_t *flags, hipStream_t s);
 
 // Deterministic sum of squares (FP64) into *out.
 hipError_t sumsq(const double *v, int64_t n, double *partials, double *out, hipStream_t s);

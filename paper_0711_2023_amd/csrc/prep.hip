@@ -8,6 +8,7 @@
 // Every reduction here is deterministic: integer atomics only count, and
 // floating-point sums run in an order fixed by the data.
 #include "common.h"
+#include "guards.h"
 
 #include <cmath>
 
@@ -176,19 +177,35 @@ __global__ void k_slot_hist(const int32_t *ihi, const int32_t *ilo, int64_t nnz,
         atomicAdd(&counts[ihi[p] * Ilo + ilo[p]], 1);
 }
 
-__global__ void k_slot_scatter(const int32_t *ihi, const int32_t *ilo, int64_t nnz, int32_t Ilo, const int32_t *ptr,
-                               int32_t *cursor, int32_t *tmp) {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
-        int32_t slot = ihi[p] * Ilo + ilo[p];
-        int32_t pos = ptr[slot] + atomicAdd(&cursor[slot], 1);
-        tmp[pos] = (int32_t)p;
+// Entry p goes to ptr[slot] + (its arrival rank in the slot). A position
+// outside the slot's range (which a wrong scan would produce) is not
+// written; it raises kFlagOrderCheck, as does a scan total other than nnz.
+__global__ void k_slot_scatter(const int32_t *ihi, const int32_t *ilo, int64_t nnz, int32_t Ilo, int64_t nslots,
+                               const int32_t *ptr, int32_t *cursor, int32_t *tmp, int32_t *flags) {
+    const bool total_ok = order_total_ok(ptr[nslots], nnz);
+    int bad = total_ok ? 0 : 1;
+    if (total_ok) {
+        for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz;
+             p += (int64_t)gridDim.x * blockDim.x) {
+            int32_t slot = ihi[p] * Ilo + ilo[p];
+            int32_t b = ptr[slot], e = ptr[slot + 1];
+            int64_t pos = (int64_t)b + atomicAdd(&cursor[slot], 1);
+            if (order_pos_ok(pos, b, e, nnz))
+                tmp[pos] = (int32_t)p;
+            else
+                bad = 1;
+        }
     }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flags, kFlagOrderCheck);
 }
 
 // The order inside a slot is fixed by the key (i_m, input position), which
 // is unique, so the result does not depend on the atomic order above.
+// Skipped entirely when the scatter raised kFlagOrderCheck (tmp is then not
+// a permutation).
 __global__ void k_slot_rank(const int32_t *ihi, const int32_t *ilo, const int32_t *im, int64_t nnz, int32_t Ilo,
-                            const int32_t *ptr, const int32_t *tmp, int32_t *perm) {
+                            const int32_t *ptr, const int32_t *tmp, int32_t *perm, const int32_t *flags) {
+    if (*flags & kFlagOrderCheck) return;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * blockDim.x) {
         int32_t p = tmp[q];
         int32_t slot = ihi[p] * Ilo + ilo[p];
@@ -205,7 +222,7 @@ __global__ void k_slot_rank(const int32_t *ihi, const int32_t *ilo, const int32_
 }
 
 hipError_t build_order(const int32_t *const idx[3], int64_t nnz, const int64_t dims[3], int m, int32_t *ptr,
-                       int32_t *perm, OrderScratch sc, hipStream_t s) {
+                       int32_t *perm, OrderScratch sc, int32_t *flags, hipStream_t s) {
     const int hi = (m + 2) % 3, lo = (m + 1) % 3;
     const int64_t nslots = dims[hi] * dims[lo];
     const int32_t Ilo = (int32_t)dims[lo];
@@ -217,9 +234,10 @@ hipError_t build_order(const int32_t *const idx[3], int64_t nnz, const int64_t d
     }
     TK_HIP(scan_exclusive(sc.counts, ptr, nslots, sc.scan, s));
     if (nnz > 0) {
-        k_slot_scatter<<<grid_for(nnz), 256, 0, s>>>(idx[hi], idx[lo], nnz, Ilo, ptr, sc.cursor, sc.tmp);
+        k_slot_scatter<<<grid_for(nnz), 256, 0, s>>>(idx[hi], idx[lo], nnz, Ilo, nslots, ptr, sc.cursor, sc.tmp,
+                                                     flags);
         TK_LAUNCHED();
-        k_slot_rank<<<grid_for(nnz), 256, 0, s>>>(idx[hi], idx[lo], idx[m], nnz, Ilo, ptr, sc.tmp, perm);
+        k_slot_rank<<<grid_for(nnz), 256, 0, s>>>(idx[hi], idx[lo], idx[m], nnz, Ilo, ptr, sc.tmp, perm, flags);
         TK_LAUNCHED();
     }
     return hipSuccess;
@@ -272,9 +290,11 @@ hipError_t dedup(const int32_t *const idx[3], const double *vals, int64_t nnz, c
 }
 
 // ------------------------------------------------------------------ leaf gather
+// Skipped when the ordering failed its checks (perm is then not written).
 template <class T>
 __global__ void k_gather_leaf(const int32_t *idx_m, const double *vals, const int32_t *perm, int64_t n, int32_t *lidx,
-                              T *lval) {
+                              T *lval, const int32_t *flags) {
+    if (*flags & kFlagOrderCheck) return;
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
         int32_t p = perm[q];
         lidx[q] = idx_m[p];
@@ -283,16 +303,16 @@ __global__ void k_gather_leaf(const int32_t *idx_m, const double *vals, const in
 }
 template <class T>
 hipError_t gather_leaf(const int32_t *idx_m, const double *vals, const int32_t *perm, int64_t n, int32_t *lidx,
-                       T *lval, hipStream_t s) {
+                       T *lval, const int32_t *flags, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_gather_leaf<T><<<grid_for(n), 256, 0, s>>>(idx_m, vals, perm, n, lidx, lval);
+    k_gather_leaf<T><<<grid_for(n), 256, 0, s>>>(idx_m, vals, perm, n, lidx, lval, flags);
     TK_LAUNCHED();
     return hipSuccess;
 }
 template hipError_t gather_leaf<double>(const int32_t *, const double *, const int32_t *, int64_t, int32_t *,
-                                        double *, hipStream_t);
+                                        double *, const int32_t *, hipStream_t);
 template hipError_t gather_leaf<float>(const int32_t *, const double *, const int32_t *, int64_t, int32_t *, float *,
-                                       hipStream_t);
+                                       const int32_t *, hipStream_t);
 
 // ------------------------------------------------------------------ sum of squares
 __device__ inline double block_sum_f64(double x) {

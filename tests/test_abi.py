@@ -296,3 +296,92 @@ def test_split_bf16_precision_is_mp_only():
     o.precision = 4
     st, _ = _ws(c, (5, 4, 3), o, tk.ALGO_MP)
     assert st == tk.TK_ERR_ARG
+
+
+def test_sp_and_hosvd_entry_points_reject_before_device_work():
+    L = tk.lib()
+    c, d = _coo()
+    facs = (ctypes.c_void_p * 3)(0x10, 0x20, 0x30)
+    hist = (ctypes.c_double * 50)()
+    done = ctypes.c_int32(0)
+    out = ctypes.c_double(0)
+    o = tk.default_opts()
+    o.init = tk.INIT_RANDOM
+    bad = (ctypes.c_int32 * 3)(3, 10, 3)  # J2 > I2
+    assert L.tucker_sp(ctypes.byref(c), bad, ctypes.byref(o), 0x40, facs, hist, ctypes.byref(done), None, 0x50,
+                       1 << 30, None) == tk.TK_ERR_ARG
+    assert L.tucker_hosvd(ctypes.byref(c), bad, ctypes.byref(o), 0x40, facs, ctypes.byref(out), None, 0x50, 1 << 30,
+                          None) == tk.TK_ERR_ARG
+    J = (ctypes.c_int32 * 3)(3, 3, 3)
+    assert L.tucker_sp(ctypes.byref(c), J, ctypes.byref(o), 0x40, facs, hist, ctypes.byref(done), None, 0x50, 16,
+                       None) == tk.TK_ERR_WORKSPACE
+    assert L.tucker_hosvd(ctypes.byref(c), J, ctypes.byref(o), 0x40, facs, ctypes.byref(out), None, 0x50, 16,
+                          None) == tk.TK_ERR_WORKSPACE
+    assert L.tucker_hosvd(ctypes.byref(c), J, ctypes.byref(o), 0x40, facs, None, None, 0x50, 1 << 30,
+                          None) == tk.TK_ERR_ARG
+    # SP has no learned start
+    o.init = tk.INIT_LEARNED
+    o.model = 0x60
+    assert L.tucker_sp(ctypes.byref(c), J, ctypes.byref(o), 0x40, facs, hist, ctypes.byref(done), None, 0x50,
+                       1 << 30, None) == tk.TK_ERR_ARG
+    c0, d0 = _coo(nnz=0)
+    o = tk.default_opts()
+    o.init = tk.INIT_RANDOM
+    assert L.tucker_sp(ctypes.byref(c0), J, ctypes.byref(o), 0x40, facs, hist, ctypes.byref(done), None, 0x50,
+                       1 << 30, None) == tk.TK_ERR_EMPTY
+
+
+def test_random_start_and_hosvd_fit_options():
+    c, d = _coo(dims=(40, 30, 20), nnz=500)
+    for algo in (tk.ALGO_HOOI, tk.ALGO_MP, tk.ALGO_SP):
+        o = tk.default_opts()
+        o.init = tk.INIT_RANDOM
+        st, b0 = _ws(c, (5, 4, 3), o, algo)
+        assert st == 0 and b0 > 0
+        o.hosvd_fit = 1  # one more FP64 projection buffer
+        st, b1 = _ws(c, (5, 4, 3), o, algo)
+        assert st == 0 and b1 > b0
+        o.init = tk.INIT_GIVEN  # the report needs the factor buffers as scratch
+        assert _ws(c, (5, 4, 3), o, algo)[0] == tk.TK_ERR_ARG
+        o.init = tk.INIT_HOSVD
+        o.hosvd_fit = 2
+        assert _ws(c, (5, 4, 3), o, algo)[0] == tk.TK_ERR_ARG
+        o.init = 4
+        o.hosvd_fit = 0
+        assert _ws(c, (5, 4, 3), o, algo)[0] == tk.TK_ERR_ARG
+    st, b = _ws(c, (5, 4, 3), tk.default_opts(), tk.ALGO_HOSVD)
+    assert st == 0 and b > 0
+    assert _ws(c, (5, 4, 3), tk.default_opts(), 5)[0] == tk.TK_ERR_ARG
+
+
+@pytest.mark.parametrize("case", ["J_over_128", "hosvd_dim", "slot_product"])
+def test_documented_limits(case):
+    """The limits listed in tucker.h, each at its edge: accepted on one side,
+    TK_ERR_ARG on the other."""
+    o = tk.default_opts()
+    if case == "J_over_128":
+        c, d = _coo(dims=(300, 200, 200), nnz=100)
+        assert _ws(c, (128, 5, 5), o)[0] == 0
+        assert _ws(c, (129, 5, 5), o)[0] == tk.TK_ERR_ARG
+    elif case == "hosvd_dim":
+        # modes 2 and 3 need their start Gram with an HO-SVD start; mode 1 does not
+        c, d = _coo(dims=(9000, 10, 8192), nnz=100)
+        assert _ws(c, (3, 3, 3), o)[0] == 0
+        c, d = _coo(dims=(10, 8193, 10), nnz=100)
+        assert _ws(c, (3, 3, 3), o)[0] == tk.TK_ERR_ARG
+        for init in (tk.INIT_GIVEN, tk.INIT_RANDOM):
+            o.init = init
+            assert _ws(c, (3, 3, 3), o)[0] == 0
+        o.init = tk.INIT_RANDOM
+        o.hosvd_fit = 1
+        assert _ws(c, (3, 3, 3), o)[0] == tk.TK_ERR_ARG
+        o.hosvd_fit = 0
+        c, d = _coo(dims=(8193, 10, 10), nnz=100)
+        assert _ws(c, (3, 3, 3), tk.default_opts(), tk.ALGO_HOSVD)[0] == tk.TK_ERR_ARG
+    else:
+        # I_a * I_b < 2^31 for every pair of modes
+        o.init = tk.INIT_GIVEN
+        c, d = _coo(dims=(46340, 46340, 2), nnz=10)
+        assert _ws(c, (1, 1, 1), o)[0] == 0
+        c, d = _coo(dims=(46341, 46341, 2), nnz=10)
+        assert _ws(c, (1, 1, 1), o)[0] == tk.TK_ERR_ARG
