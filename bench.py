@@ -43,28 +43,6 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def project_bytes(nnz, nslots, J, I_m, precision):
-    """Bytes one projection launch must move: leaf index + value per nonzero
-    (FP64 values for fp64, else FP32), slot pointers, the dense projected
-    tensor, the factor copy it reads (FP16 rows for mixed)."""
-    out_bytes = {"mixed": 2, "fp32": 4, "fp64": 8}[precision]
-    val_bytes = 8 if precision == "fp64" else 4
-    fac_bytes = {"mixed": 2, "fp32": 4, "fp64": 8}[precision]
-    return nnz * (4 + val_bytes) + (nslots + 1) * 4 + nslots * J * out_bytes + I_m * J * fac_bytes
-
-
-def gram_flops(I, J, n):
-    """Useful flops of the MP Gram of mode n: both projected terms, lower
-    triangle with diagonal, multiply+add = 2 flops."""
-    total = 0
-    for m in range(3):
-        if m == n:
-            continue
-        K = (I[0] * I[1] * I[2] // (I[n] * I[m])) * J[m]
-        total += I[n] * (I[n] + 1) * K
-    return total
-
-
 def traffic_from_profile(kernel_file):
     """HBM bytes per launch of the projection kernel measured by rocprofv3
     counters, if the committed measurement matches the current source."""
@@ -159,6 +137,70 @@ def learned_leg(args):
     return 0
 
 
+def c5_leg(args):
+    """Learned start against the HO-SVD start at 4000 x 4000 x 4000 with
+    10,000,000 nonzeros of a planted Tucker model (random orthonormal factors,
+    core 100^3 N(0,1), values at the sampled coordinates scaled to unit RMS
+    plus N(0, 0.1^2) noise), core 100^3: plain FP32 from the HO-SVD start,
+    mixed from the HO-SVD start and mixed from the learned start (network
+    trained first, untimed), each until the paper's Delta-fit < 1e-4 (at most
+    50 sweeps). The returned factors of the mixed runs are checked after the
+    fact by the FP64 oracle (core slice by slice, fit by the identity). One
+    JSON line."""
+    import numpy as np
+    import torch
+    import paper_0711_2023_amd as tk
+    import synth
+    import oracle as O
+    tk.lib()
+    dev = torch.device("cuda:0")
+    w = synth.WORKLOADS["cube4000_nnz10m_planted"]
+    dims, J, nnz = tuple(w["dims"]), tuple(w["core"]), int(w["nnz"])
+    t0 = time.perf_counter()
+    idx, vals, dims = synth.planted_tucker(dims, J, nnz, 0.1, w["seed"])
+    log(f"c5 leg: generated {dims} / {nnz} in {time.perf_counter() - t0:.1f} s")
+    di = torch.from_numpy(idx).to(dev)
+    dv = torch.from_numpy(vals).to(dev)
+    model, info = learned_model(tk, dev)
+    log(f"c5 leg: trained {info}")
+    out = {"workload": f"sparse {dims[0]}x{dims[1]}x{dims[2]}, {nnz} nonzeros of a planted Tucker model "
+                       f"(core {J[0]}x{J[1]}x{J[2]} N(0,1), random orthonormal factors, unit RMS + N(0,0.1^2)), "
+                       f"core {J[0]}x{J[1]}x{J[2]}, MP, stop at Delta-fit < 1e-4 (cap 50)", "training": info}
+    runs = {}
+    for name, prec, kw in (("fp32_hosvd", "fp32", {}), ("mixed_hosvd", "mixed", {}),
+                           ("mixed_learned", "mixed", {"init": tk.INIT_LEARNED, "model": model})):
+        tk.mp(di, dv, dims, J, precision=prec, max_iters=1, tol=0.0, **kw)  # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = tk.mp(di, dv, dims, J, precision=prec, max_iters=50, tol=1e-4, timing=True, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        runs[name] = r
+        out[name] = {"wall_ms": round(1000 * wall, 1), "sweeps": r.iters, "fit": r.fits[-1], "fits": r.fits,
+                     "init_ms": round(r.stats["init_ms"], 2), "sweeps_ms": round(r.stats["sweeps_ms"], 2),
+                     "init_fallbacks": r.stats["init_fallbacks"]}
+        log(f"c5 leg: {name} {out[name]}")
+    out["speedup_plain_over_mixed_hosvd"] = round(out["fp32_hosvd"]["wall_ms"] / out["mixed_hosvd"]["wall_ms"], 3)
+    out["speedup_plain_over_mixed_learned"] = round(out["fp32_hosvd"]["wall_ms"] / out["mixed_learned"]["wall_ms"],
+                                                    3)
+    out["learned_over_hosvd_start_wall"] = round(out["mixed_hosvd"]["wall_ms"] / out["mixed_learned"]["wall_ms"], 3)
+    # post-hoc oracle check of the returned factors
+    t2 = time.perf_counter()
+    X = O.SparseTensor3(idx, vals, dims)
+    nx2 = X.norm2()
+    for name in ("mixed_hosvd", "mixed_learned"):
+        A, B, C = (f.cpu().numpy() for f in runs[name].factors)
+        G = O.core_from_slices(X, A, B, C)
+        fo = O.fit_identity(nx2, G)
+        out[name]["oracle_fit_of_returned_factors"] = fo
+        out[name]["abs_fit_diff_vs_oracle"] = abs(fo - runs[name].fits[-1])
+        out[name]["orthonormality_err"] = max(float(np.abs(F.T @ F - np.eye(F.shape[1])).max()) for F in (A, B, C))
+    out["oracle_check_s"] = round(time.perf_counter() - t2, 1)
+    log(f"c5 leg: oracle check done in {out['oracle_check_s']} s")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def batched_leg(tk, dev, sweeps):
     """64 tensors (mode sizes U{200..800}, density 0.5 %, cores U{10..40},
     U(0,1) values), MP with BF16 Grams, `sweeps` sweeps each: one call on 8
@@ -250,7 +292,12 @@ def parity_leg(tk, dev):
     return out
 
 
-def cpu_baseline(idx, vals, dims, J, sweeps=1):
+def cpu_baseline(idx, vals, dims, J, budget_s=12.0):
+    """The FP64 oracle on the host cores, same input: its projections
+    T(m) = X x_m A(m)^T for m = 1, 2, 3 (one TTMc sweep's worth of projected
+    nonzeros, by the matricized n-mode product), repeated for about
+    `budget_s` seconds; and separately one whole MP sweep of the oracle
+    (slice-wise Grams, eigendecomposition of M M^T, slice-wise core and fit)."""
     import numpy as np
     import oracle as O
     try:
@@ -260,15 +307,164 @@ def cpu_baseline(idx, vals, dims, J, sweeps=1):
         cores = os.cpu_count() or 1
     X = O.SparseTensor3(idx, vals, dims)
     rng = np.random.default_rng(11)
-    B0 = np.linalg.qr(rng.standard_normal((dims[1], J[1])))[0]
-    C0 = np.linalg.qr(rng.standard_normal((dims[2], J[2])))[0]
+    F = [np.linalg.qr(rng.standard_normal((dims[n], J[n])))[0] for n in range(3)]
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        for m in range(3):
+            O.project_sparse(X, F[m], m)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s:
+            break
+    proj = {"value": 3 * X.nnz * reps / dt, "unit": "nnz/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{reps} repetition(s) of the oracle's three projections X x_m A(m)^T (m = 1, 2, 3) of the "
+                      f"same tensor with random orthonormal factors of the same shapes; 3*nnz*reps / wall time; "
+                      f"{dt:.1f} s"}
     t0 = time.perf_counter()
-    O.mp(X, J, sweeps, 0.0, init=(None, B0, C0))
+    O.mp(X, J, 1, 0.0, init=(None, F[1], F[2]))
     dt = time.perf_counter() - t0
-    return {"value": 3 * X.nnz * sweeps / dt, "unit": "nnz/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{sweeps} full sweep(s) of the FP64 oracle's Multislice Projection (slice-wise Grams, "
-                      f"eigendecomposition of M M^T, slice-wise core and fit) on the same input; "
-                      f"3*nnz*sweeps / wall time; {dt:.1f} s"}
+    whole = {"value": 3 * X.nnz / dt, "unit": "nnz/s", "cores": int(cores), "kind": "oracle",
+             "sample": f"one whole MP sweep of the oracle on the same tensor; 3*nnz / wall time; {dt:.1f} s; "
+                       f"compare with whole_sweep_nnz_per_s"}
+    return proj, whole
+
+
+def fibre_counts(idx, dims):
+    """Number of non-empty mode-m fibres F_m for m = 1, 2, 3 (distinct pairs of
+    the two other coordinates)."""
+    import numpy as np
+    out = []
+    for m in range(3):
+        a, b = [n for n in range(3) if n != m]
+        out.append(int(np.unique(idx[a].astype(np.int64) * dims[b] + idx[b]).size))
+    return out
+
+
+ELEM = {0: 8, 1: 4, 2: 2}      # bytes of an output element by TK_FP64, TK_FP32, TK_MIXED_BF16
+PREC_NAME = {0: "fp64", 1: "fp32", 2: "bf16"}
+
+
+def ld_of(J, s):
+    """Row stride of an MP projection: J rounded up to whole 16 bytes."""
+    v = 16 // s
+    return (J + v - 1) // v * v
+
+
+def proj_min_bytes(nnz, F, J, s, fp64):
+    """Method-minimal bytes of one projection: leaf index and value per nonzero
+    (FP64 values in FP64 mode, else FP32) + the projected non-empty fibres."""
+    return nnz * (12 if fp64 else 8) + F * J * s
+
+
+def proj_exec_bytes(nnz, F, J, s, fp64, I_m, fs, ld):
+    """Bytes the fibre-list projection moves: nonzeros, fibre pointers and
+    slots, rows of ld elements of the non-empty fibres, the padded factor copy
+    (fs bytes per element)."""
+    return nnz * (12 if fp64 else 8) + (2 * F + 1) * 4 + F * ld * s + I_m * ld * fs
+
+
+def events(r, phase, first_sweep=2):
+    return [e for e in r.stats["trace"] if e["phase"] == phase and e["sweep"] >= first_sweep]
+
+
+def ttmc_rates(results, nu, first_sweep=2):
+    """Projected nnz/s of the TTMc phase (projection launches + HOOI second
+    stage) per sweep from first_sweep on, median per decomposition, then the
+    median over decompositions."""
+    meds = []
+    for r in results:
+        per = {}
+        for e in r.stats["trace"]:
+            if e["sweep"] >= first_sweep and e["phase"] in ("project", "ttmc2"):
+                per[e["sweep"]] = per.get(e["sweep"], 0.0) + e["ms"]
+        meds.append(statistics.median(3 * nu / (ms / 1000.0) for ms in per.values()))
+    return statistics.median(meds)
+
+
+def proj_roofline(results, dims, J, nu, F, prec, fp64, fs, kernel, core_only=False):
+    """Roofline of the projection launches of one output precision: ratio of
+    the summed algorithmic (method-minimal) bytes to the summed launch time."""
+    byt, ms, exe, n = 0.0, 0.0, 0.0, 0
+    for r in results:
+        for e in events(r, "project"):
+            if e["precision"] != prec or (core_only and e["mode"] != 2):
+                continue
+            m, s = e["mode"], ELEM[prec]
+            ld = ld_of(J[m], 4) if core_only else ld_of(J[m], s)
+            byt += proj_min_bytes(nu, F[m], J[m], s, fp64)
+            exe += proj_exec_bytes(nu, F[m], J[m], s, fp64, dims[m], fs, ld)
+            ms += e["ms"]
+            n += 1
+    if n == 0:
+        return None
+    gbs = byt / (ms / 1000.0) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "algorithmic_bytes_per_launch": int(byt / n),
+            "executed_bytes_per_launch": int(exe / n), "avg_launch_ms": round(ms / n, 5), "launches": n}
+
+
+def gram_roofline(results, dims, J, occ, prec, algo="mp"):
+    """Gram launches: useful dense flops (lower triangle with diagonal, the
+    unpadded J) and the occupancy-minimal count (only pairs of non-empty
+    fibres: occ_m^2 of a term's dense count) per launch, against the MFMA peak
+    of the operand type."""
+    dense, minimal, ms, n = 0.0, 0.0, 0.0, 0
+    for r in results:
+        for e in events(r, "gram"):
+            k = e["mode"]
+            if algo == "mp":
+                for m in range(3):
+                    if m == k:
+                        continue
+                    o = 3 - k - m
+                    d = dims[k] * (dims[k] + 1) * dims[o] * J[m]
+                    dense += d
+                    minimal += d * occ[m] ** 2
+            else:  # HOOI: Y_(n) Y_(n)^T with K = J_a J_b
+                a, b = [m for m in range(3) if m != k]
+                d = dims[k] * (dims[k] + 1) * J[a] * J[b]
+                dense += d
+                minimal += d
+            ms += e["ms"]
+            n += 1
+    if n == 0:
+        return None
+    peak = PEAK_TFLOPS[PREC_NAME[prec]]
+    tf = dense / (ms / 1000.0) / 1e12
+    tfm = minimal / (ms / 1000.0) / 1e12
+    return {"kernel": "k_gram", "bound": "mfma", "operands": PREC_NAME[prec], "achieved": round(tf, 2),
+            "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+            "achieved_minimal_flops": round(tfm, 2), "frac_minimal_flops": round(tfm / peak, 4),
+            "dense_flops_per_launch": int(dense / n), "minimal_flops_per_launch": int(minimal / n),
+            "avg_launch_ms": round(ms / n, 5), "launches": n}
+
+
+def stage_b_roofline(results, dims, J, occ):
+    """HOOI second-stage products per mode: dense flops 2 I_n I_o J_m J_o of the
+    product and the minimal 2 F_m J_m J_o (occupancy of the projection it
+    reads), against the MFMA peak of the operand type."""
+    I0, I1, I2 = dims
+    J0, J1, J2 = J
+    # (dense flops, occupancy of the projection read) per second-stage mode
+    spec = {0: (2 * J1 * I0 * J2 * I1, occ[2]), 1: (2 * J0 * J2 * I0 * I1, occ[2]), 2: (2 * J1 * J0 * I1 * I2, occ[0])}
+    out = {}
+    for mode in range(3):
+        ms, n, prec = 0.0, 0, None
+        for r in results:
+            for e in events(r, "ttmc2"):
+                if e["mode"] == mode:
+                    ms += e["ms"]
+                    n += 1
+                    prec = e["precision"]
+        if n == 0:
+            continue
+        d, oc = spec[mode]
+        peak = PEAK_TFLOPS[PREC_NAME[prec]]
+        tf = d / (ms / n / 1000.0) / 1e12
+        out[f"mode{mode + 1}"] = {"operands": PREC_NAME[prec], "achieved": round(tf, 2), "peak": peak,
+                                  "unit": "TFLOP/s", "frac": round(tf / peak, 4), "dense_flops": int(d),
+                                  "minimal_flops": int(d * oc), "avg_launch_ms": round(ms / n, 5)}
+    return out
 
 
 def main():
@@ -284,15 +480,22 @@ def main():
     ap.add_argument("--no-ttf", action="store_true", help="skip the time-to-fit runs")
     ap.add_argument("--no-learn", action="store_true", help="skip the learned-start leg of the time-to-fit runs")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-tensor leg")
+    ap.add_argument("--no-forms", action="store_true", help="skip the other precision forms and the HOOI leg")
+    ap.add_argument("--no-unbal", action="store_true", help="skip the 2000 x 1000 x 500 MP-vs-HOOI leg")
     ap.add_argument("--learned-leg", action="store_true",
                     help="internal: train the learned start, time the mixed run from it, print one JSON line")
     ap.add_argument("--no-parity", action="store_true", help="skip the small-workload comparison with the "
                     "stored oracle reference")
+    ap.add_argument("--no-c5", action="store_true", help="skip the learned-start leg at 4000^3 / 10M nonzeros")
+    ap.add_argument("--c5-leg", action="store_true", help="internal: run the 4000^3 learned-start leg, print one "
+                    "JSON line")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     args = ap.parse_args()
     if args.learned_leg:
         return learned_leg(args)
+    if args.c5_leg:
+        return c5_leg(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this benchmark measures one GPU; runs on several GPUs are not supported",
@@ -310,14 +513,17 @@ def main():
     dims, J, nnz = tuple(w["dims"]), tuple(w["core"]), int(w["nnz"])
     log(f"generating {args.workload}: dims {dims} nnz {nnz} core {J}")
     idx, vals, dims = synth.uniform_sparse(dims, nnz, w["seed"])
+    F = fibre_counts(idx, dims)
+    occ = [F[m] / (dims[(m + 1) % 3] * dims[(m + 2) % 3]) for m in range(3)]
     dev = torch.device("cuda:0")
     di = torch.from_numpy(idx).to(dev)
     dv = torch.from_numpy(vals).to(dev)
     fn = tk.mp if args.algo == "mp" else tk.hooi
     algo_id = tk.ALGO_MP if args.algo == "mp" else tk.ALGO_HOOI
     # one workspace large enough for every precision the legs below run
-    precs = [args.precision, "fp32", "mixed"] + (["bf16x3"] if args.algo == "mp" else [])
-    wsb = max(tk.workspace_bytes(algo_id, di, dv, dims, J, precision=pr) for pr in precs)
+    precs = [args.precision, "fp32", "mixed", "fp64"] + (["bf16x3"] if args.algo == "mp" else [])
+    wsb = max([tk.workspace_bytes(algo_id, di, dv, dims, J, precision=pr) for pr in precs] +
+              [tk.workspace_bytes(tk.ALGO_HOOI, di, dv, dims, J, precision=pr) for pr in ("mixed", "fp32")])
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     log(f"workspace {wsb / 2**30:.2f} GiB")
 
@@ -329,17 +535,17 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration done (3 x 1 GiB)")
 
-    def step(prec, sweeps, tol):
-        return fn(di, dv, dims, J, precision=prec, max_iters=sweeps, tol=tol, timing=True, workspace=ws)
+    def step(f, prec, sweeps, tol):
+        return f(di, dv, dims, J, precision=prec, max_iters=sweeps, tol=tol, timing=True, workspace=ws, trace=4096)
 
     for i in range(args.warmup):
-        r = step(args.precision, args.sweeps, 0.0)
+        r = step(fn, args.precision, args.sweeps, 0.0)
         log(f"warmup {i}: fits {r.fits[-1]:.6e} sweeps_ms {r.stats['sweeps_ms']:.1f}")
     torch.cuda.synchronize()
     results = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        r = step(args.precision, args.sweeps, 0.0)
+        r = step(fn, args.precision, args.sweeps, 0.0)
         results.append(r)
         log(f"step {i}: fit {r.fits[-1]:.6e} prep {r.stats['prep_ms']:.1f} init {r.stats['init_ms']:.1f} "
             f"sweeps {r.stats['sweeps_ms']:.1f} ms (proj {r.stats['project_ms']:.2f}, gram {r.stats['gram_ms']:.2f}, "
@@ -349,36 +555,18 @@ def main():
     ms_per_step = 1000.0 * wall / max(1, args.steps)
 
     nu = results[0].stats["nnz_unique"]
-    if args.algo == "mp":
-        # every MP projection launch projects all nonzeros onto one factor
-        rates = [r.stats["project_calls"] * nu / (r.stats["ttmc_ms"] / 1000.0) for r in results]
-    else:
-        # a HOOI sweep projects the nonzeros onto all three factors (two
-        # projections plus three second-stage GEMMs)
-        rates = [3 * nu * r.iters / (r.stats["ttmc_ms"] / 1000.0) for r in results]
-    value = statistics.median(rates)
+    value = ttmc_rates(results, nu)
     st = results[len(results) // 2].stats
     sweeps = results[0].iters
-    # per-launch averages
-    proj_ms = st["project_ms"] / max(1, st["project_calls"])
-    gram_ms = st["gram_ms"] / max(1, st["gram_calls"])
-    nslots = [dims[(m + 2) % 3] * dims[(m + 1) % 3] for m in range(3)]
-    pbytes = statistics.mean(project_bytes(nu, nslots[m], J[m], dims[m], args.precision) for m in range(3))
-    proj_gbs = pbytes / (proj_ms / 1000.0) / 1e9
-    gflops = statistics.mean(gram_flops(dims, J, n) for n in range(3))
-    gram_tf = gflops / (gram_ms / 1000.0) / 1e12
-    gpeak = PEAK_TFLOPS["bf16" if args.precision == "mixed" else args.precision]
+    pcode = {"mixed": 2, "fp32": 1, "fp64": 0}[args.precision]
+    fs = {"mixed": 2, "fp32": 4, "fp64": 8}[args.precision]  # factor copy: FP16 rows for mixed
+    kname = {"mixed": "k_project_vec<float, f16, bf16> (fibre list)", "fp32": "k_project_vec<float, float, float> "
+             "(fibre list)", "fp64": "k_project_vec<double, double, double> (fibre list)"}[args.precision]
+    roof_proj = proj_roofline(results, dims, J, nu, F, pcode, args.precision == "fp64", fs, kname)
     kfile = os.path.join(ROOT, "paper_0711_2023_amd", "csrc", "project.hip")
-    traffic = traffic_from_profile(kfile)
-    roof_proj = {"kernel": "k_project", "bound": "hbm", "achieved": round(proj_gbs, 1), "peak": PEAK_HBM_GBS,
-                 "unit": "GB/s", "frac": round(proj_gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
-                 "algorithmic_bytes_per_launch": int(pbytes), "avg_launch_ms": round(proj_ms, 5)}
-    roof_gram = {"kernel": "k_gram", "bound": "mfma", "achieved": round(gram_tf, 2), "peak": gpeak,
-                 "unit": "TFLOP/s", "frac": round(gram_tf / gpeak, 4), "traffic": None,
-                 "algorithmic_flops_per_launch": int(gflops), "avg_launch_ms": round(gram_ms, 5)}
-    # the roofline line is the kernel of the metric (the projection); the
-    # Gram's MFMA fraction goes beside it
-    dominant, other = roof_proj, (roof_gram if args.algo == "mp" else None)
+    roof_proj["traffic"] = traffic_from_profile(kfile)
+    roof_proj["fibres_per_mode"] = F
+    roof_proj["occupancy_per_mode"] = [round(o, 4) for o in occ]
 
     line = {
         "metric": METRIC,
@@ -391,14 +579,17 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"mixed": "bf16(gram)+fp32(proj,acc)+fp64(eig,core,fit)", "fp32": "fp32+fp64(eig,core,fit)",
-                  "fp64": "fp64"}[args.precision],
+        "dtype": {"mixed": "bf16(gram,proj-out)+fp16(factor rows)+fp32(proj-acc,core-proj)+fp64(eig,core,fit)",
+                  "fp32": "fp32+fp64(eig,core,fit)", "fp64": "fp64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"sparse {dims[0]}x{dims[1]}x{dims[2]}, {nnz} uniform distinct nonzeros, U(0,1) "
                                f"values, core {J[0]}x{J[1]}x{J[2]}, {args.algo.upper()}, {args.sweeps} sweeps",
                    "dims": list(dims), "nnz": nnz, "core": list(J), "algo": args.algo,
                    "precision": args.precision, "sweeps": sweeps, "seed": w["seed"]},
-        "roofline": dominant,
+        "value_definition": "3*nnz / (summed HIP-event time of every projection launch of the sweep, including "
+                            "the FP32 projection for the core, plus HOOI second-stage products), median over sweeps "
+                            "2..10, median over steps",
+        "roofline": roof_proj,
         "phase_ms_per_sweep": {k: round(st[k] / max(1, sweeps), 4) for k in
                                ("project_ms", "ttmc_ms", "gram_ms", "eig_ms", "core_ms")},
         "whole_sweep_nnz_per_s": 3 * nu / (st["sweeps_ms"] / 1000.0 / max(1, sweeps)),
@@ -406,8 +597,44 @@ def main():
         "init_ms": round(st["init_ms"], 3),
         "fit": results[0].fits[-1],
     }
-    if other is not None:
-        line["roofline_other"] = other
+    forms = {}
+    if args.algo == "mp":
+        if args.precision == "mixed":
+            # the FP32 projection of mode 3 that feeds the core (the fourth launch of a sweep)
+            forms["core_projection_fp32"] = proj_roofline(
+                results, dims, J, nu, F, 1, False, 4, "k_project_vec<float, float, float> (fibre list, core input)",
+                core_only=True)
+        forms[f"gram_{args.precision}"] = gram_roofline(results, dims, J, occ, pcode)
+    line["roofline_forms"] = forms
+
+    if not args.no_forms and args.algo == "mp":
+        # the other precision forms of the same decomposition: projection and
+        # Gram rooflines, TTMc rate
+        for prec, pc, fsz in (("fp32", 1, 4), ("fp64", 0, 8)):
+            if prec == args.precision:
+                continue
+            step(fn, prec, args.sweeps, 0.0)
+            rs = [step(fn, prec, args.sweeps, 0.0) for _ in range(2)]
+            forms[f"projection_{prec}"] = proj_roofline(rs, dims, J, nu, F, pc, prec == "fp64", fsz,
+                                                        f"k_project_vec ({prec}, fibre list)")
+            forms[f"projection_{prec}"]["ttmc_nnz_per_s"] = ttmc_rates(rs, nu)
+            forms[f"gram_{prec}"] = gram_roofline(rs, dims, J, occ, pc)
+            log(f"form {prec}: projection {forms[f'projection_{prec}']}")
+        # HOOI on the same tensor: TTMc rate (two projections + three
+        # second-stage products per sweep), stage-B rooflines, Gram
+        hooi = {}
+        for prec in ("mixed", "fp32"):
+            step(tk.hooi, prec, args.sweeps, 0.0)
+            rs = [step(tk.hooi, prec, args.sweeps, 0.0) for _ in range(2)]
+            pc = {"mixed": 2, "fp32": 1}[prec]
+            hooi[prec] = {"ttmc_nnz_per_s": ttmc_rates(rs, nu),
+                          "fit_after_sweeps": rs[0].fits[-1],
+                          "stage_b": stage_b_roofline(rs, dims, J, occ),
+                          "gram": gram_roofline(rs, dims, J, occ, 1, algo="hooi"),
+                          "ms_per_decomposition": round(statistics.median(
+                              r.stats["prep_ms"] + r.stats["init_ms"] + r.stats["sweeps_ms"] for r in rs), 3)}
+            log(f"hooi {prec}: {hooi[prec]['ttmc_nnz_per_s']:.3e} nnz/s")
+        line["hooi"] = hooi
 
     if not args.no_ttf:
         ttf = {}
@@ -426,6 +653,7 @@ def main():
             log(f"time-to-fit {prec}: {ttf[prec]}")
         ttf["speedup_plain_over_mixed"] = round(ttf["fp32"]["wall_ms"] / ttf["mixed"]["wall_ms"], 3)
         ttf["mixed_reaches_plain_fit"] = bool(ttf["mixed"]["fit"] >= ttf["fp32"]["fit"] - 1e-4)
+        ttf["relative_fit_gap_mixed_vs_plain"] = (ttf["fp32"]["fit"] - ttf["mixed"]["fit"]) / ttf["fp32"]["fit"]
         if "bf16x3" in ttf:  # split-BF16 Grams: FP32-like accuracy
             ttf["speedup_plain_over_bf16x3"] = round(ttf["fp32"]["wall_ms"] / ttf["bf16x3"]["wall_ms"], 3)
         if not args.no_learn:
@@ -446,6 +674,19 @@ def main():
                 ttf["mixed_learned_reaches_plain_fit"] = bool(leg["fit"] >= ttf["fp32"]["fit"] - 1e-4)
         line["time_to_fit"] = ttf
 
+    if not args.no_unbal:
+        line["unbalanced"] = unbalanced_leg(tk, dev, args.sweeps)
+
+    if not args.no_c5:
+        # in a child process with a time limit (own device memory, about 40 GB)
+        cmd = [sys.executable, os.path.abspath(__file__), "--c5-leg"]
+        try:
+            r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
+            line["learned_start_4000cube"] = json.loads(r.stdout.strip().splitlines()[-1]) \
+                if r.returncode == 0 and r.stdout.strip() else {"error": f"exit {r.returncode}"}
+        except subprocess.TimeoutExpired:
+            line["learned_start_4000cube"] = {"error": "timed out after 900 s"}
+
     if not args.no_batch:
         line["batched"] = batched_leg(tk, dev, args.sweeps)
 
@@ -454,9 +695,53 @@ def main():
         log(f"parity against the stored FP64 oracle reference: {line['parity_small']}")
 
     if not args.no_cpu:
-        log("timing the FP64 oracle (one sweep) on the host")
-        line["cpu_baseline"] = cpu_baseline(idx, vals, dims, J, 1)
+        log("timing the FP64 oracle on the host")
+        line["cpu_baseline"], line["cpu_whole_sweep"] = cpu_baseline(idx, vals, dims, J)
     print(json.dumps(line), flush=True)
+
+
+def unbalanced_leg(tk, dev, sweeps):
+    """2000 x 1000 x 500 with 2,000,000 uniform nonzeros, cores (100, 20, 5)
+    and (10, 50, 100): MP and HOOI with BF16 Grams / TTMc, `sweeps` sweeps
+    from the HO-SVD start, their fits beside the FP64 oracle's stored
+    trajectories (tests/golden/fullsize_reference.json, written by
+    tests/golden/make_fullsize_reference.py from the oracle alone)."""
+    import numpy as np
+    import torch
+    import synth
+    path = os.path.join(ROOT, "tests", "golden", "fullsize_reference.json")
+    ref = json.load(open(path))["cases"] if os.path.exists(path) else {}
+    out = {}
+    first = True
+    for name in ("unbal_2000x1000x500_core100x20x5", "unbal_2000x1000x500_core10x50x100"):
+        w = synth.WORKLOADS[name]
+        if first:
+            idx, vals, dims = synth.uniform_sparse(tuple(w["dims"]), int(w["nnz"]), w["seed"])
+            di = torch.from_numpy(idx).to(dev)
+            dv = torch.from_numpy(vals).to(dev)
+            first = False
+        J = tuple(w["core"])
+        res = {}
+        for algo in ("mp", "hooi"):
+            getattr(tk, algo)(di, dv, dims, J, precision="mixed", max_iters=sweeps, tol=0.0)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = getattr(tk, algo)(di, dv, dims, J, precision="mixed", max_iters=sweeps, tol=0.0, timing=True)
+            torch.cuda.synchronize()
+            e = {"fit": r.fits[-1], "wall_ms": round(1000 * (time.perf_counter() - t1), 2),
+                 "ttmc_nnz_per_s": 3 * r.stats["nnz_unique"] * r.iters / (r.stats["ttmc_ms"] / 1000.0)}
+            rc = ref.get(name, {})
+            if f"{algo}_fits" in rc and len(rc[f"{algo}_fits"]) == len(r.fits):
+                o = np.array(rc[f"{algo}_fits"])
+                d = np.abs(np.array(r.fits) - o)
+                e["oracle_fit"] = float(o[-1])
+                e["max_abs_fit_diff_vs_oracle"] = float(d.max())
+                e["max_rel_fit_diff_vs_oracle"] = float((d / o).max())
+            res[algo] = e
+            log(f"unbalanced {name} {algo}: {e}")
+        res["hooi_minus_mp_fit"] = res["hooi"]["fit"] - res["mp"]["fit"]
+        out[name] = res
+    return out
 
 
 if __name__ == "__main__":

@@ -116,6 +116,31 @@ typedef struct tk_coo {
     const double  *vals;    /* [dev] nnz values */
 } tk_coo;
 
+/* Per-launch trace (opts.trace): one event per timed kernel or phase of the
+   sweeps, measured with HIP events on the call's stream. */
+#define TK_PHASE_PROJECT 0  /* a projection T(m) = X x_m A(m)^T (one kernel) */
+#define TK_PHASE_TTMC2   1  /* a HOOI second-stage product Y = T x_o A(o)^T */
+#define TK_PHASE_GRAM    2  /* a Gram (SYRK kernel and its FP64 partial-sum pass) */
+#define TK_PHASE_EIG     3  /* one leading-eigenvector solve (with its host round trips) */
+#define TK_PHASE_CORE    4  /* the core contractions of a sweep */
+typedef struct tk_event {
+    int32_t phase;      /* TK_PHASE_* */
+    int32_t mode;       /* 0-based: the leaf mode m of a projection T(m), the mode
+                           n a Gram or eigensolve serves, the mode of the Gram a
+                           second-stage product feeds; -1 for the core */
+    int32_t precision;  /* element type of the output (projection) or of the
+                           operands (products, Grams): TK_FP64, TK_FP32,
+                           TK_MIXED_BF16; the eigensolve is always TK_FP64 */
+    int32_t sweep;      /* 1-based sweep it belongs to */
+    double  ms;         /* duration in milliseconds */
+} tk_event;
+typedef struct tk_trace {
+    tk_event *events;   /* [host] room for `capacity` events, filled in launch order */
+    int32_t   capacity;
+    int32_t   count;    /* out: events written; the caller sets it to 0 first */
+    int64_t   dropped;  /* out: events that did not fit; the caller sets it to 0 first */
+} tk_trace;
+
 /* Launch choices: 0 in a field = the built-in choice. The projection's
    choices change no result bit (each output sums its nonzeros in the same
    order whatever the run length). The Gram's choices set its split over the
@@ -149,8 +174,8 @@ typedef struct tk_opts {
                                precision (1e-12 for FP64, 1e-8 for FP32 and split
                                BF16, 1e-4 for mixed BF16: a tenth of the relative
                                accuracy of the Gram at that precision) */
-    int32_t timing;         /* 1: record HIP events around the projection and
-                               TTMc kernels and report their times in tk_stats */
+    int32_t timing;         /* 1: record HIP events around the kernels and phases of
+                               the sweeps and report their sums in tk_stats */
     const float *model;     /* [dev] TK_INIT_LEARNED: the network parameters
                                (tucker_learn_param_count() floats, layout in
                                tucker_learn.h); NULL otherwise */
@@ -167,6 +192,8 @@ typedef struct tk_opts {
                                TK_INIT_HOSVD or TK_INIT_RANDOM (TK_ERR_ARG
                                otherwise): the report uses the factor buffers
                                as scratch before the sweeps. */
+    tk_trace *trace;        /* [host] per-launch trace of the sweeps, or NULL; a
+                               trace implies timing = 1 */
 } tk_opts;
 
 /* Optional statistics (pass NULL to skip). Times in milliseconds. */
@@ -197,7 +224,7 @@ typedef struct tk_stats {
 
 /* Fill *opt with: FP32, HO-SVD init, 50 sweeps, tol 1e-4, eig cap 400
    products, eig tol 0 (by precision), no timing, no model, seed 0x5eed,
-   built-in launch choices, no HO-SVD fit. */
+   built-in launch choices, no HO-SVD fit, no trace. */
 void tucker_default_opts(tk_opts *opt);
 
 /* Bytes of device workspace that tucker_hooi (algo TK_ALGO_HOOI),

@@ -37,8 +37,9 @@ int tucker_batched_workspace_bytes(int32_t algo, int32_t count, const tk_coo *X,
      nstreams     1..64 streams; workspaces[s] (bytes each) serves streams[s]
    Returns TK_OK when every tensor succeeded, TK_WARN_NOCONV if one only
    warned, else the first (lowest index) error status; TK_ERR_ARG (before
-   any device work) for a bad count, nstreams, pointer array, or any
-   tensor that tucker_workspace_bytes would reject. The device of the calling
+   any device work) for a bad count, nstreams, pointer array, opt->trace
+   set (one trace cannot take the events of concurrent decompositions), or
+   any tensor that tucker_workspace_bytes would reject. The device of the calling
    thread is used by every worker. */
 int tucker_batched(int32_t algo, int32_t count, const tk_coo *X, const int32_t *core_dims, const tk_opts *opt,
                    double *const *cores, double *const *factors, double *fit_history, int32_t *iters_done,

@@ -56,6 +56,7 @@ __all__ = [
     "unfold_dense",
     "tucker_dense",
     "project_dense",
+    "project_sparse",
     "core_from_slices",
     "core_entry",
     "fit_slicewise",
@@ -190,6 +191,17 @@ def project_dense(X: np.ndarray, A: np.ndarray, m: int) -> np.ndarray:
     two modes and r indexes the columns of A."""
     T = mode_product_dense(X, A.T, m)
     return np.moveaxis(T, m, 2)
+
+
+def project_sparse(X: "SparseTensor3", A: np.ndarray, m: int) -> np.ndarray:
+    """T = X x_m A^T for the sparse X, laid out [i_a][i_b][r] as
+    ``project_dense`` (a < b the other two modes): by the matricized form of
+    the n-mode product (Section 3), T_(m) = A^T X_(m), one sparse product of
+    the unfolding, then the columns (i_a fastest) folded back."""
+    others = [n for n in range(3) if n != m]
+    Ia, Ib = X.dims[others[0]], X.dims[others[1]]
+    Tm = np.asarray((X.unfolding(m).T @ A))             # (Ib * Ia) x J, column index ia + Ia * ib
+    return Tm.reshape(Ib, Ia, A.shape[1]).transpose(1, 0, 2)
 
 
 # --------------------------------------------------------------------------

@@ -49,7 +49,20 @@ class tk_opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("init", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("eig_max_iters", ctypes.c_int32), ("eig_tol", ctypes.c_double),
                 ("timing", ctypes.c_int32), ("model", ctypes.c_void_p), ("seed", ctypes.c_uint64),
-                ("tune", ctypes.c_void_p), ("hosvd_fit", ctypes.c_int32)]
+                ("tune", ctypes.c_void_p), ("hosvd_fit", ctypes.c_int32), ("trace", ctypes.c_void_p)]
+
+
+PHASES = ("project", "ttmc2", "gram", "eig", "core")  # TK_PHASE_* in order
+
+
+class tk_event(ctypes.Structure):
+    _fields_ = [("phase", ctypes.c_int32), ("mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("sweep", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
+class tk_trace(ctypes.Structure):
+    _fields_ = [("events", ctypes.c_void_p), ("capacity", ctypes.c_int32), ("count", ctypes.c_int32),
+                ("dropped", ctypes.c_int64)]
 
 
 class tk_tune(ctypes.Structure):
@@ -236,15 +249,25 @@ def _stats_dict(s: tk_stats) -> dict:
 
 def _run(fn_name: str, algo: int, idx, vals, dims, core_dims, *, precision="fp32", init=INIT_HOSVD,
          max_iters=50, tol=1e-4, eig_max_iters=None, eig_tol=None, timing=False, factors=None, workspace=None,
-         stream=None, model=None, seed=None, tune=None, hosvd_fit=False) -> Result:
+         stream=None, model=None, seed=None, tune=None, hosvd_fit=False, trace=0) -> Result:
     """`model`: float32 tensor of learn_param_count() parameters on the GPU,
-    used with init=INIT_LEARNED. `tune`: launch choices (see make_tune)."""
+    used with init=INIT_LEARNED. `tune`: launch choices (see make_tune).
+    `trace`: room for that many per-launch events (0 = no trace); they are
+    returned in Result.stats["trace"] as dicts."""
     import torch
     dev = vals.device
     coo = _Coo(idx, vals, dims)
     if model is not None and (model.dtype != torch.float32 or not model.is_cuda or not model.is_contiguous()):
         raise TypeError("model must be a contiguous float32 tensor on the GPU")
     o = _opts(precision, init, max_iters, tol, eig_max_iters, eig_tol, timing, model, seed, tune, hosvd_fit)
+    tr = None
+    if trace:
+        evs = (tk_event * int(trace))()
+        tr = tk_trace()
+        tr.events = ctypes.cast(evs, ctypes.c_void_p)
+        tr.capacity = int(trace)
+        tr._evs = evs  # kept alive with the trace
+        o.trace = ctypes.addressof(tr)
     J = [int(j) for j in core_dims]
     Jc = (ctypes.c_int32 * 3)(*J)
     need = ctypes.c_size_t(0)
@@ -265,7 +288,12 @@ def _run(fn_name: str, algo: int, idx, vals, dims, core_dims, *, precision="fp32
                                      ctypes.byref(done), ctypes.byref(st), workspace.data_ptr(),
                                      int(workspace.numel()), ctypes.c_void_p(s.cuda_stream))
     _check(status)
-    return Result(G, facs, [hist[i] for i in range(done.value)], int(done.value), _stats_dict(st), status)
+    sd = _stats_dict(st)
+    if tr is not None:
+        sd["trace"] = [{"phase": PHASES[e.phase], "mode": e.mode, "precision": e.precision, "sweep": e.sweep,
+                        "ms": e.ms} for e in tr._evs[:tr.count]]
+        sd["trace_dropped"] = int(tr.dropped)
+    return Result(G, facs, [hist[i] for i in range(done.value)], int(done.value), sd, status)
 
 
 def hooi(idx, vals, dims, core_dims, **kw) -> Result:

@@ -156,6 +156,11 @@ struct Plan {
     bool split = false;                      // MP with split-BF16 Grams (hi and lo parts)
     void *Tlo[3] = {nullptr, nullptr, nullptr};  // lo parts of the projections
     int sweep_solves[3] = {0, 0, 0};         // warm (sweep) eigensolves done per mode
+    // MP / SP: the non-empty fibres of each ordering; the projections for
+    // the Grams (and the core's FP32 one) write only their rows, into
+    // buffers zeroed once per call (zero_projections)
+    int32_t *fib[3] = {nullptr, nullptr, nullptr}, *fptr[3] = {nullptr, nullptr, nullptr};
+    int64_t nfib[3] = {0, 0, 0};
 };
 
 static size_t elem_size(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
@@ -220,7 +225,7 @@ static void carve(Plan &p, Arena &ar) {
     p.heads = ar.take<int32_t>(nnz + 1);
     p.pos = ar.take<int32_t>(nnz + 1);
     p.counts = ar.take<int32_t>(maxslots);
-    p.cursor = ar.take<int32_t>(maxslots);
+    p.cursor = ar.take<int32_t>(maxslots + 1);
     p.scan = ar.take<int32_t>(std::max(scan_scratch_ints(maxslots), scan_scratch_ints(nnz + 1)));
     for (int n = 0; n < 3; ++n) p.cidx[n] = ar.take<int32_t>(nnz);
     p.cval = ar.take<double>(nnz);
@@ -237,6 +242,11 @@ static void carve(Plan &p, Arena &ar) {
     for (int m = 0; m < 3; ++m) p.T[m] = nullptr;
     const size_t es = elem_size(prec);
     if (slice_algo(p.algo)) {
+        for (int m = 0; m < 3; ++m) {
+            const int64_t cap = std::min(p.nslots[m], nnz);
+            p.fib[m] = ar.take<int32_t>(cap);
+            p.fptr[m] = ar.take<int32_t>(cap + 1);
+        }
         for (int m = 0; m < 3; ++m) p.T[m] = ar.take<char>((int64_t)(p.nslots[m] * p.ldT[m] * es));
         if (p.split)
             for (int m = 0; m < 3; ++m) p.Tlo[m] = ar.take<char>((int64_t)(p.nslots[m] * p.ldT[m] * es));
@@ -452,6 +462,7 @@ void tucker_default_opts(tk_opts *o) {
     o->seed = 0x5eedull;
     o->tune = nullptr;
     o->hosvd_fit = 0;
+    o->trace = nullptr;
 }
 
 const char *tucker_strerror(int st) {
@@ -493,24 +504,31 @@ int tucker_workspace_bytes(int32_t algo, const tk_coo *X, const int32_t *core_di
 
 namespace tk {
 
-// HIP events around the phases of a sweep, on the call's stream.
-enum TimedKind { kProj = 0, kTtmc = 1, kGram = 2, kEig = 3, kCore = 4 };
+// HIP events around the phases of a sweep, on the call's stream. Each pair
+// carries its phase, the mode it serves and its element type; collect()
+// (after a stream synchronisation, once per sweep) sums them per phase and
+// appends them to the caller's trace when one is given.
+enum TimedKind { kProj = TK_PHASE_PROJECT, kTtmc = TK_PHASE_TTMC2, kGram = TK_PHASE_GRAM, kEig = TK_PHASE_EIG,
+                 kCore = TK_PHASE_CORE };
 struct Timer {
     bool on;
     hipStream_t s;
+    tk_trace *tr;
     std::vector<hipEvent_t> ev;
-    std::vector<int> kind;
+    struct Tag {
+        int kind, mode, prec;
+    };
+    std::vector<Tag> tag;
     size_t used = 0;
     double ms[5] = {0, 0, 0, 0, 0};
     int64_t calls[5] = {0, 0, 0, 0, 0};
     double sweep_ttmc[64] = {};  // TTMc time (projections + second stage) per collect() = per sweep
     int sweeps = 0;
-    Timer(bool on_, hipStream_t s_) : on(on_), s(s_) {}
+    Timer(const tk_opts *o, hipStream_t s_) : on(o->timing != 0 || o->trace), s(s_), tr(o->trace) {}
     ~Timer() {
         for (auto e : ev) (void)hipEventDestroy(e);
     }
-    void begin(int k) {
-        if (!on) return;
+    void reserve_pair(int k, int mode, int prec) {
         if (used + 2 > ev.size()) {
             for (int i = 0; i < 2; ++i) {
                 hipEvent_t e;
@@ -518,9 +536,13 @@ struct Timer {
                 ev.push_back(e);
             }
         }
+        tag.resize(used / 2 + 1);
+        tag[used / 2] = Tag{k, mode, prec};
+    }
+    void begin(int k, int mode = -1, int prec = -1) {
+        if (!on) return;
+        reserve_pair(k, mode, prec);
         (void)hipEventRecord(ev[used], s);
-        kind.resize(used / 2 + 1);
-        kind[used / 2] = k;
     }
     void end() {
         if (!on) return;
@@ -529,17 +551,9 @@ struct Timer {
     }
     // A pair for a single kernel that records them itself at its start and
     // end (kernel time without the dispatch gap an event bracket includes).
-    KernelEvents kernel(int k) {
+    KernelEvents kernel(int k, int mode = -1, int prec = -1) {
         if (!on) return KernelEvents();
-        if (used + 2 > ev.size()) {
-            for (int i = 0; i < 2; ++i) {
-                hipEvent_t e;
-                (void)hipEventCreate(&e);
-                ev.push_back(e);
-            }
-        }
-        kind.resize(used / 2 + 1);
-        kind[used / 2] = k;
+        reserve_pair(k, mode, prec);
         const KernelEvents ke{ev[used], ev[used + 1]};
         used += 2;
         return ke;
@@ -551,9 +565,16 @@ struct Timer {
         for (size_t i = 0; i + 1 < used; i += 2) {
             float t = 0;
             (void)hipEventElapsedTime(&t, ev[i], ev[i + 1]);
-            ms[kind[i / 2]] += t;
-            calls[kind[i / 2]] += 1;
-            if (kind[i / 2] == kProj || kind[i / 2] == kTtmc) ttmc += t;
+            const Tag &g = tag[i / 2];
+            ms[g.kind] += t;
+            calls[g.kind] += 1;
+            if (g.kind == kProj || g.kind == kTtmc) ttmc += t;
+            if (tr && tr->events) {
+                if (tr->count < tr->capacity)
+                    tr->events[tr->count++] = tk_event{g.kind, g.mode, g.prec, sweeps + 1, (double)t};
+                else
+                    tr->dropped++;
+            }
         }
         if (sweeps < 64) sweep_ttmc[sweeps] = ttmc;
         ++sweeps;
@@ -593,6 +614,32 @@ static int order_failed(int r) {
     return r;
 }
 
+// The fibre list of ordering m when it exists and `zeroed_target` (the
+// projection goes to a buffer zeroed by zero_projections), else none.
+static FibreList fibres_of(const Plan &p, int m, bool zeroed_target) {
+    FibreList fl;
+    if (p.fib[m] && zeroed_target) {
+        fl.fib = p.fib[m];
+        fl.fptr = p.fptr[m];
+        fl.n = p.nfib[m];
+    }
+    return fl;
+}
+
+// Zero the buffers whose empty-fibre rows the fibre-list projections leave
+// untouched: T(m) (and their lo parts) and the core's FP32 projection.
+static hipError_t zero_projections(Plan &p, hipStream_t s) {
+    if (!p.fib[0]) return hipSuccess;
+    const size_t es = elem_size(p.prec);
+    for (int m = 0; m < 3; ++m) {
+        const int64_t words = p.nslots[m] * p.ldT[m] * (int64_t)es / 4;  // rows are whole 16-byte chunks
+        TK_HIP(fill_i32((int32_t *)p.T[m], words, 0, s));
+        if (p.Tlo[m]) TK_HIP(fill_i32((int32_t *)p.Tlo[m], words, 0, s));
+    }
+    if (p.Tcore) TK_HIP(fill_i32((int32_t *)p.Tcore, p.nslots[2] * (int64_t)p.ldc, 0, s));
+    return hipSuccess;
+}
+
 // Validation, duplicate summing, orderings, ||X||^2.
 static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double *normx2_out) {
     const int64_t dims[3] = {p.I[0], p.I[1], p.I[2]};
@@ -621,14 +668,24 @@ static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double
         if (p.lval32[m])
             ST(gather_leaf<float>(p.cidx[m], p.cval, p.perm, nu, p.lidx[m], p.lval32[m], p.flags, s));
     }
+    // MP / SP: non-empty fibre lists of the three orderings
+    int32_t nfib[3] = {0, 0, 0};
+    if (p.fib[0])
+        for (int m = 0; m < 3; ++m) {
+            ST(fibre_list(p.ptr[m], p.nslots[m], std::min<int64_t>(p.nslots[m], std::max<int64_t>(p.nnz, 1)),
+                          p.fib[m], p.fptr[m], p.counts, p.cursor, p.scan, p.flags, s));
+            ST(hipMemcpyAsync(&nfib[m], p.cursor + p.nslots[m], 4, hipMemcpyDeviceToHost, s));
+        }
     double nx2 = 0;
     ST(hipMemcpyAsync(&nx2, p.scal + 0, 8, hipMemcpyDeviceToHost, s));
     ST(hipMemcpyAsync(&flags, p.flags, 4, hipMemcpyDeviceToHost, s));
     ST(hipStreamSynchronize(s));
     if (int r = prep_status(flags)) return order_failed(r);
+    for (int m = 0; m < 3; ++m) p.nfib[m] = nfib[m];
     *nu_out = nu;
     *normx2_out = nx2;
     if (!(nx2 > 0.0)) return TK_ERR_EMPTY;
+    ST(zero_projections(p, s));
     return TK_OK;
 }
 
@@ -640,21 +697,24 @@ static hipError_t project_m(Plan &p, int m, const double *F64, void *T, int out_
     if (ld <= 0) ld = p.ldT[m];
     const int32_t *ptr = p.ptr[m], *lidx = p.lidx[m];
     const int64_t I = p.I[m], ns = p.nslots[m];
+    // the Gram buffers T(m) were zeroed once (zero_projections): only the
+    // rows of non-empty fibres are written
+    const FibreList fl = fibres_of(p, m, T == p.T[m] && ld == p.ldT[m]);
     if (p.split && T == p.T[m] && out_prec == PBF16 && ld == p.ldT[m])  // the Gram copy: hi and lo parts
         return project_split(ptr, lidx, p.lval32[m], (const float *)p.Fp[m], I, ld, J, ns, p.nnz, (bf16 *)T,
-                             (bf16 *)p.Tlo[m], s, p.tune, ke);
+                             (bf16 *)p.Tlo[m], s, p.tune, ke, fl);
     // the padded copy (rows of ldT) when T has that stride and type, else
     // rows of J
     const bool padded = p.Fp[m] && ld == p.ldT[m] && out_prec == p.prec;
     if (padded) {
         if (out_prec == P64)
             return project<double, double, double>(ptr, lidx, p.lval64[m], (const double *)p.Fp[m], I, ld, J, ld, ns,
-                                                   p.nnz, (double *)T, s, p.tune, ke);
+                                                   p.nnz, (double *)T, s, p.tune, ke, fl);
         if (out_prec == P32)
             return project<float, float, float>(ptr, lidx, p.lval32[m], (const float *)p.Fp[m], I, ld, J, ld, ns,
-                                                p.nnz, (float *)T, s, p.tune, ke);
+                                                p.nnz, (float *)T, s, p.tune, ke, fl);
         return project<float, f16, bf16>(ptr, lidx, p.lval32[m], (const f16 *)p.Fp[m], I, ld, J, ld, ns, p.nnz,
-                                         (bf16 *)T, s, p.tune, ke);
+                                         (bf16 *)T, s, p.tune, ke, fl);
     }
     if (out_prec == P64)
         return project<double, double, double>(ptr, lidx, p.lval64[m], F64, I, J, J, ld, ns, p.nnz, (double *)T, s,
@@ -1066,10 +1126,11 @@ static hipError_t slice_core(Plan &p, const double *A, const double *B, double *
     const void *T2c = p.T[2];
     if (p.prec == PBF16) {
         TK_HIP((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.Fc, p.I[2], p.ldc, p.J[2], p.ldc,
-                                             p.nslots[2], p.nnz, p.Tcore, s, p.tune, tm.kernel(kProj))));
+                                             p.nslots[2], p.nnz, p.Tcore, s, p.tune, tm.kernel(kProj, 2, P32),
+                                             fibres_of(p, 2, true))));
         T2c = p.Tcore;
     }
-    tm.begin(kCore);
+    tm.begin(kCore, -1, p.prec == P64 ? P64 : P32);
     TK_HIP(core_from_T2(p, T2c, p.prec == PBF16 ? p.ldc : p.ldT[2], p.prec == P64, A, B, core, s));
     tm.end();
     return hipSuccess;
@@ -1085,7 +1146,7 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     if (stats) memset(stats, 0, sizeof(*stats));
-    Timer tm(o->timing != 0, s);
+    Timer tm(o, s);
     double t0 = now_ms();
     int64_t nu = 0;
     double nx2 = 0;
@@ -1107,29 +1168,29 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     *iters_done = 0;
     for (t = 1; t <= o->max_iters; ++t) {
         // M1 (mode 0) from T(1) and T(2)
-        tm.begin(kGram);
+        tm.begin(kGram, 0, p.prec);
         ST(mp_gram(p, 0, 1, 2, s));
         tm.end();
-        tm.begin(kEig);
+        tm.begin(kEig, 0, P64);
         if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
         tm.end();
-        ST(project_m(p, 0, A, p.T[0], prec, s, 0, tm.kernel(kProj)));
+        ST(project_m(p, 0, A, p.T[0], prec, s, 0, tm.kernel(kProj, 0, prec)));
         // M2 (mode 1) from T(0) and T(2)
-        tm.begin(kGram);
+        tm.begin(kGram, 1, p.prec);
         ST(mp_gram(p, 1, 0, 2, s));
         tm.end();
-        tm.begin(kEig);
+        tm.begin(kEig, 1, P64);
         if ((st = run_eig(p, 1, p.Mg, B, true, o, stats, &noconv, s))) return st;
         tm.end();
-        ST(project_m(p, 1, B, p.T[1], prec, s, 0, tm.kernel(kProj)));
+        ST(project_m(p, 1, B, p.T[1], prec, s, 0, tm.kernel(kProj, 1, prec)));
         // M3 (mode 2) from T(0) and T(1)
-        tm.begin(kGram);
+        tm.begin(kGram, 2, p.prec);
         ST(mp_gram(p, 2, 0, 1, s));
         tm.end();
-        tm.begin(kEig);
+        tm.begin(kEig, 2, P64);
         if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
         tm.end();
-        ST(project_m(p, 2, C, p.T[2], prec, s, 0, tm.kernel(kProj)));
+        ST(project_m(p, 2, C, p.T[2], prec, s, 0, tm.kernel(kProj, 2, prec)));
         // core from T(2)(C) (FP64 or FP32, never BF16)
         ST(slice_core(p, A, B, core, s, tm));
         double fit = 0;
@@ -1142,10 +1203,10 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     }
     if (o->max_iters == 0) {
         // no sweep: A from the start factors, then the core
-        tm.begin(kGram);
+        tm.begin(kGram, 0, p.prec);
         ST(mp_gram(p, 0, 1, 2, s));
         tm.end();
-        tm.begin(kEig);
+        tm.begin(kEig, 0, P64);
         if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
         tm.end();
         ST(slice_core(p, A, B, core, s, tm));
@@ -1197,7 +1258,7 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     if (stats) memset(stats, 0, sizeof(*stats));
-    Timer tm(o->timing != 0, s);
+    Timer tm(o, s);
     double t0 = now_ms();
     int64_t nu = 0;
     double nx2 = 0;
@@ -1222,10 +1283,10 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
     int maxit = o->max_iters > 0 ? o->max_iters : 0;
     for (int t = 1; t <= std::max(maxit, 1); ++t) {
         const bool last_only = (maxit == 0);
-        ST(project_m(p, 2, C, p.T[2], tprec, s, 0, tm.kernel(kProj)));
+        ST(project_m(p, 2, C, p.T[2], tprec, s, 0, tm.kernel(kProj, 2, tprec)));
         const void *Bop = prec == P64 ? (const void *)B : (prec == P32 ? (const void *)p.F32[1] : (const void *)p.F16[1]);
         // mode 0: Y0[q][i0][r2] = sum_i1 B[i1][q] T2[i1][i0][r2]
-        tm.begin(kTtmc);
+        tm.begin(kTtmc, 0, kprec01);
         ST(ttm(J1, (int)(I0 * J2), (int)I1, 1, Bop, J1, p.T[2], I0 * J2, 0, p.Y, I0 * J2, 0, kprec01,
                yprec == P64 ? P64 : P32, s));
         tm.end();
@@ -1236,11 +1297,11 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
             g.chunk_len = J2;
             g.nchunks = J1;
             g.s_chunk = I0 * J2;
-            tm.begin(kGram);
+            tm.begin(kGram, 0, yprec);
             ST(gram((int)I0, yprec, 1, &g, p.Mg, p.gram_scratch, s, p.tune));
             tm.end();
         }
-        tm.begin(kEig);
+        tm.begin(kEig, 0, P64);
         if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
         tm.end();
         if (last_only) {
@@ -1249,7 +1310,7 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
         const void *Aop = prec == P64 ? (const void *)A : (prec == P32 ? (const void *)p.F32[0] : (const void *)p.F16[0]);
         // mode 1: Y1[i1][p][r2] = sum_i0 A[i0][p] T2[i1][i0][r2]
         if (!last_only) {
-            tm.begin(kTtmc);
+            tm.begin(kTtmc, 1, kprec01);
             ST(ttm(J0, J2, (int)I0, (int)I1, Aop, J0, p.T[2], J2, I0 * J2, p.Y, J2, (int64_t)J0 * J2, kprec01,
                    yprec == P64 ? P64 : P32, s));
             tm.end();
@@ -1259,20 +1320,20 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
             g.chunk_len = (int64_t)J0 * J2;
             g.nchunks = 1;
             g.s_chunk = 0;
-            tm.begin(kGram);
+            tm.begin(kGram, 1, yprec);
             ST(gram((int)I1, yprec, 1, &g, p.Mg, p.gram_scratch, s, p.tune));
             tm.end();
-            tm.begin(kEig);
+            tm.begin(kEig, 1, P64);
             if ((st = run_eig(p, 1, p.Mg, B, true, o, stats, &noconv, s))) return st;
             tm.end();
         }
         // mode 2 (and the core): T(0)(A) = [i2][i1][r0] in FP64 / FP32
         void *T0 = prec == PBF16 ? (void *)p.T0f : p.T[0];
         const int t0prec = prec == P64 ? P64 : P32;
-        ST(project_m(p, 0, A, T0, t0prec, s, 0, tm.kernel(kProj)));
+        ST(project_m(p, 0, A, T0, t0prec, s, 0, tm.kernel(kProj, 0, t0prec)));
         const void *Bop2 = prec == P64 ? (const void *)B : (const void *)p.F32[1];
         // Y2[i2][q][r0] = sum_i1 B[i1][q] T0[i2][i1][r0]
-        tm.begin(kTtmc);
+        tm.begin(kTtmc, 2, t0prec);
         ST(ttm(J1, J0, (int)I1, (int)I2, Bop2, J1, T0, J0, I1 * J0, p.Y, J0, (int64_t)J1 * J0, t0prec,
                yprec == P64 ? P64 : P32, s));
         tm.end();
@@ -1283,10 +1344,10 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
             g.chunk_len = (int64_t)J1 * J0;
             g.nchunks = 1;
             g.s_chunk = 0;
-            tm.begin(kGram);
+            tm.begin(kGram, 2, yprec);
             ST(gram((int)I2, yprec, 1, &g, p.Mg, p.gram_scratch, s, p.tune));
             tm.end();
-            tm.begin(kEig);
+            tm.begin(kEig, 2, P64);
             if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
             tm.end();
         }
@@ -1370,7 +1431,7 @@ extern "C" int tucker_sp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     if (stats) memset(stats, 0, sizeof(*stats));
-    Timer tm(o->timing != 0, s);
+    Timer tm(o, s);
     double t0 = now_ms();
     int64_t nu = 0;
     double nx2 = 0;
@@ -1407,30 +1468,30 @@ extern "C" int tucker_sp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
     const int maxit = std::max(o->max_iters, 1);
     for (int t = 1; t <= maxit; ++t) {
         // M13 = sum_j X_:j: C C^T X_:j:^T: Gram of T(2) = X x_3 C^T on mode 1
-        tm.begin(kGram);
+        tm.begin(kGram, 0, p.prec);
         ST(sp_gram(p, 0, 2, s));
         tm.end();
-        tm.begin(kEig);
+        tm.begin(kEig, 0, P64);
         if ((st = run_eig(p, 0, p.Mg, A, true, o, stats, &noconv, s))) return st;
         tm.end();
         // M21 = sum_k X_::k^T A A^T X_::k: Gram of T(0) = X x_1 A^T on mode 2
-        ST(project_m(p, 0, A, p.T[0], prec, s, 0, tm.kernel(kProj)));
-        tm.begin(kGram);
+        ST(project_m(p, 0, A, p.T[0], prec, s, 0, tm.kernel(kProj, 0, prec)));
+        tm.begin(kGram, 1, p.prec);
         ST(sp_gram(p, 1, 0, s));
         tm.end();
-        tm.begin(kEig);
+        tm.begin(kEig, 1, P64);
         if ((st = run_eig(p, 1, p.Mg, B, true, o, stats, &noconv, s))) return st;
         tm.end();
         // M32 = sum_i X_i::^T B B^T X_i::: Gram of T(1) = X x_2 B^T on mode 3
-        ST(project_m(p, 1, B, p.T[1], prec, s, 0, tm.kernel(kProj)));
-        tm.begin(kGram);
+        ST(project_m(p, 1, B, p.T[1], prec, s, 0, tm.kernel(kProj, 1, prec)));
+        tm.begin(kGram, 2, p.prec);
         ST(sp_gram(p, 2, 1, s));
         tm.end();
-        tm.begin(kEig);
+        tm.begin(kEig, 2, P64);
         if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
         tm.end();
         // T(2)(C): the core now, mode 1's Gram in the next sweep
-        ST(project_m(p, 2, C, p.T[2], prec, s, 0, tm.kernel(kProj)));
+        ST(project_m(p, 2, C, p.T[2], prec, s, 0, tm.kernel(kProj, 2, prec)));
         ST(slice_core(p, A, B, core, s, tm));
         double fit = 0;
         if ((st = finish_fit(p, core, s, &fit, &g2))) return st;
@@ -1786,6 +1847,7 @@ extern "C" int tucker_batched_workspace_bytes(int32_t algo, int32_t count, const
                                               const tk_opts *opt, const tk_tune *tunes, size_t *bytes) {
     if (!bytes || !X || !core_dims || !opt || count < 1) return TK_ERR_ARG;
     if (algo != TK_ALGO_HOOI && algo != TK_ALGO_MP) return TK_ERR_ARG;
+    if (opt->trace) return TK_ERR_ARG;  // one trace cannot serve concurrent decompositions
     size_t best = 0;
     for (int32_t t = 0; t < count; ++t) {
         size_t b = 0;

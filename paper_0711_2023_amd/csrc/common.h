@@ -79,6 +79,15 @@ struct OrderScratch {
 hipError_t build_order(const int32_t *const idx[3], int64_t nnz, const int64_t dims[3], int m,
                        int32_t *ptr, int32_t *perm, OrderScratch sc, int32_t *flags, hipStream_t s);
 
+// The non-empty fibres of an ordering with slot pointers ptr[0..nslots]:
+// fib[f] = slot of the f-th non-empty fibre (ascending), fptr[f] = its first
+// entry, fptr[F] = ptr[nslots], where F = pos_tmp[nslots] (device) is their
+// number. fib has room for cap entries, fptr for cap + 1; a count beyond cap
+// sets kFlagOrderCheck in *flags and writes nothing out of range.
+// flag_tmp: nslots ints; pos_tmp: nslots + 1 ints; scan_scratch as scan.
+hipError_t fibre_list(const int32_t *ptr, int64_t nslots, int64_t cap, int32_t *fib, int32_t *fptr, int32_t *flag_tmp,
+                      int32_t *pos_tmp, int32_t *scan_scratch, int32_t *flags, hipStream_t s);
+
 // Validation: flags |= 1 (index out of range), 2 (non-finite value).
 hipError_t validate(const int32_t *const idx[3], const double *vals, int64_t nnz, const int64_t dims[3],
                     int32_t *flags, hipStream_t s);
@@ -123,21 +132,32 @@ struct KernelEvents {
 };
 
 // ---------------------------------------------------------------- project.hip
+// The non-empty fibres of an ordering (fibre_list): n fibres, fib[f] their
+// slots, fptr[f] their first entries. Empty (fib == nullptr) = not given.
+struct FibreList {
+    const int32_t *fib = nullptr, *fptr = nullptr;
+    int64_t n = 0;
+};
 // T[slot * ldT + r] = sum over the slot's entries of lval * F[lidx * ldF + r]
 // for r < J, zero for J <= r < ldT; slots = I_hi * I_lo, dense and
 // zero-filled; F has rowsF rows (the leaf mode's size) and the ordering at
 // most nnz nonzeros. With ldF == ldT,
 // 16-byte rows and F's padding columns zero (as pad_rows leaves them), whole
-// 16-byte chunks are computed at once.
+// 16-byte chunks are computed at once. With a fibre list as well (and the
+// whole output below 2 GiB), only the rows of non-empty fibres are written:
+// the rows of empty fibres must hold zeros already (the caller zeroes the
+// buffer once before the first such projection into it); the values written
+// are bitwise those of the dense form.
 template <class TV, class TF, class TO>
 hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int64_t rowsF, int ldF,
                    int J, int ldT, int64_t nslots, int64_t nnz, TO *T, hipStream_t s, const Tune &tn = Tune(),
-                   KernelEvents ke = KernelEvents());
+                   KernelEvents ke = KernelEvents(), FibreList fl = FibreList());
 // Projection into a BF16 pair (hi = rounded value, lo = rounded remainder)
-// from FP32 factor rows padded to ld (a multiple of 8), for split-BF16 Grams.
+// from FP32 factor rows padded to ld (a multiple of 8), for split-BF16 Grams;
+// a fibre list as for project.
 hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *lval, const float *F, int64_t rowsF,
                          int ld, int J, int64_t nslots, int64_t nnz, bf16 *Thi, bf16 *Tlo, hipStream_t s,
-                         const Tune &tn = Tune(), KernelEvents ke = KernelEvents());
+                         const Tune &tn = Tune(), KernelEvents ke = KernelEvents(), FibreList fl = FibreList());
 // out[i * ld + r] = in[i * J + r] for r < J, zero for J <= r < ld.
 template <class TO>
 hipError_t pad_rows(const double *in, int64_t rows, int J, int ld, TO *out, hipStream_t s);

@@ -148,6 +148,49 @@ hipError_t scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *s
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------- fibre lists
+// The non-empty fibres of an ordering (slots holding at least one entry), in
+// slot order: fib[f] = slot, fptr[f] = its first entry, fptr[F] = the total.
+__global__ void k_fibre_flags(const int32_t *__restrict__ ptr, int64_t nslots, int32_t *__restrict__ flag) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nslots; q += (int64_t)gridDim.x * blockDim.x)
+        flag[q] = ptr[q + 1] > ptr[q] ? 1 : 0;
+}
+
+__global__ void k_fibre_scatter(const int32_t *__restrict__ ptr, const int32_t *__restrict__ pos, int64_t nslots,
+                                int64_t cap, int32_t *__restrict__ fib, int32_t *__restrict__ fptr,
+                                int32_t *__restrict__ flags) {
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t q = tid; q < nslots; q += (int64_t)gridDim.x * blockDim.x) {
+        if (ptr[q + 1] > ptr[q]) {
+            const int32_t f = pos[q];
+            if (f >= 0 && (int64_t)f < cap) {
+                fib[f] = (int32_t)q;
+                fptr[f] = ptr[q];
+            } else {
+                atomicOr(flags, kFlagOrderCheck);
+            }
+        }
+    }
+    if (tid == 0) {
+        const int32_t total = pos[nslots];
+        if (total >= 0 && (int64_t)total <= cap)
+            fptr[total] = ptr[nslots];
+        else
+            atomicOr(flags, kFlagOrderCheck);
+    }
+}
+
+hipError_t fibre_list(const int32_t *ptr, int64_t nslots, int64_t cap, int32_t *fib, int32_t *fptr, int32_t *flag_tmp,
+                      int32_t *pos_tmp, int32_t *scan_scratch, int32_t *flags, hipStream_t s) {
+    if (nslots <= 0) return fill_i32(pos_tmp, 1, 0, s);
+    k_fibre_flags<<<grid_for(nslots), 256, 0, s>>>(ptr, nslots, flag_tmp);
+    TK_LAUNCHED();
+    TK_HIP(scan_exclusive(flag_tmp, pos_tmp, nslots, scan_scratch, s));
+    k_fibre_scatter<<<grid_for(nslots), 256, 0, s>>>(ptr, pos_tmp, nslots, cap, fib, fptr, flags);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
 // ------------------------------------------------------------------ validation
 __global__ void k_validate(const int32_t *i0, const int32_t *i1, const int32_t *i2, const double *v, int64_t nnz,
                            int32_t I0, int32_t I1, int32_t I2, int32_t *flags) {

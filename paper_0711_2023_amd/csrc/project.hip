@@ -192,8 +192,14 @@ __device__ inline void load_row(__amdgpu_buffer_rsrc_t r, uint32_t off, u32x4 (&
 // produces whole 16-byte chunks of T. SPLIT: T receives each output rounded
 // to TO and Tlo the rounded remainder (the value minus its rounded part), so
 // T + Tlo carries about twice the significand bits of TO.
-template <class TV, class TF, class TO, bool SPLIT = false>
+// FIB: the units of a run are the non-empty fibres of the ordering (ptr is
+// the fibre pointer list, fib[f] the slot of fibre f, nslots their number)
+// and only their rows are written; the rows of empty fibres keep what the
+// buffer holds (zeros written once before the first such projection). Else
+// the units are all slots and empty ones are written as zeros.
+template <class TV, class TF, class TO, bool SPLIT = false, bool FIB = false>
 __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__restrict__ ptr,
+                                                              const int32_t *__restrict__ fib,
                                                               const int32_t *__restrict__ lidx,
                                                               const TV *__restrict__ lval,
                                                               const TF *__restrict__ F, uint32_t Fbytes, int32_t J,
@@ -204,7 +210,8 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
     constexpr int NL = V * (int)sizeof(TF) / 16;    // 16-byte factor loads per chunk
     extern __shared__ __attribute__((aligned(16))) int32_t smem[];
     int32_t *sptr = smem;
-    NzPair<TV> *snz = reinterpret_cast<NzPair<TV> *>(smem + ((spw + 4) & ~3));
+    int32_t *sfib = smem + ((spw + 4) & ~3);  // FIB: slots of the run's fibres
+    NzPair<TV> *snz = reinterpret_cast<NzPair<TV> *>(smem + ((spw + 4) & ~3) + (FIB ? ((spw + 3) & ~3) : 0));
     const int tid = threadIdx.x;
     const int64_t s0 = (int64_t)blockIdx.x * spw;
     const int ns = (int)(s0 + spw <= nslots ? spw : nslots - s0);
@@ -218,6 +225,8 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
         e.v = lval[q0 + i];
         snz[i] = e;
     }
+    if (FIB)
+        for (int i = tid; i < ns; i += kProjThreads) sfib[i] = fib[s0 + i];
     __syncthreads();
     const int cps = ldT / V;            // chunks per slot
     const int spi = kProjThreads / cps; // slots per pass of the workgroup
@@ -226,8 +235,12 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
     const bool col_on = r * V < J;
     const uint32_t rowb = (uint32_t)ldT * sizeof(TF), coloff = (uint32_t)r * V * sizeof(TF);
     const __amdgpu_buffer_rsrc_t fr = buf_rsrc(F, Fbytes);
-    const uint32_t outb = (uint32_t)ns * (uint32_t)ldT * sizeof(TO);
-    const __amdgpu_buffer_rsrc_t orr = buf_rsrc(T + s0 * ldT, outb);
+    // output rows of the run: slots [row0, row0 + nrows); under FIB the span
+    // of the run's fibres, whose 32-bit byte size the host has checked
+    const int64_t row0 = FIB ? (int64_t)__builtin_amdgcn_readfirstlane(sfib[0]) : s0;
+    const int64_t nrows = FIB ? (int64_t)__builtin_amdgcn_readfirstlane(sfib[ns - 1]) + 1 - row0 : ns;
+    const uint32_t outb = (uint32_t)nrows * (uint32_t)ldT * sizeof(TO);
+    const __amdgpu_buffer_rsrc_t orr = buf_rsrc(T + row0 * ldT, outb);
     const __amdgpu_buffer_rsrc_t ri = buf_rsrc(lidx + q0, (uint32_t)nq * 4u);
     const __amdgpu_buffer_rsrc_t rv = buf_rsrc(lval + q0, (uint32_t)nq * (uint32_t)sizeof(TV));
     for (int sl = tsl; sl < ns; sl += spi) {
@@ -261,7 +274,8 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
                 fma_row<TF, NL, Acc, false>(x, (Acc)e2.v, acc);
             }
         }
-        const uint32_t off = (uint32_t)(sl * cps + r) * 16u;
+        const int orow = FIB ? (int)(sfib[sl] - row0) : sl;
+        const uint32_t off = (uint32_t)(orow * cps + r) * 16u;
         typename Vec16<TO>::type o;
 #pragma unroll
         for (int t = 0; t < V; ++t) o[t] = (TO)acc[t];
@@ -270,7 +284,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
             typename Vec16<TO>::type o2;
 #pragma unroll
             for (int t = 0; t < V; ++t) o2[t] = (TO)(acc[t] - (Acc)o[t]);
-            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, o2), buf_rsrc(Tlo + s0 * ldT, outb), off,
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, o2), buf_rsrc(Tlo + row0 * ldT, outb), off,
                                                    0, 0);
         }
     }
@@ -342,18 +356,41 @@ static void launch(K kernel, int64_t blocks, size_t lds, hipStream_t s, KernelEv
         kernel<<<(unsigned)blocks, kProjThreads, lds, s>>>(args...);
 }
 
+// A fibre list is usable when the whole output fits 32-bit buffer offsets
+// (a run's rows may then span any part of it).
+template <class TO>
+static bool fib_ok(const FibreList &fl, int64_t nslots, int ld) {
+    return fl.fib && fl.fptr && nslots * (int64_t)ld * (int64_t)sizeof(TO) < (int64_t(1) << 31);
+}
+
+// LDS bytes of a vector launch: staged pointers (and fibre slots), nonzeros.
+template <class TV>
+static size_t vec_lds(const ProjShape &sh, bool fib) {
+    return sizeof(int32_t) * (((sh.spw + 4) & ~3) + (fib ? ((sh.spw + 3) & ~3) : 0)) +
+           sizeof(NzPair<TV>) * (size_t)sh.cap;
+}
+
 template <class TV, class TF, class TO>
 hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, const TF *F, int64_t rowsF, int ldF,
                    int J, int ldT, int64_t nslots, int64_t nnz, TO *T, hipStream_t s, const Tune &tn,
-                   KernelEvents ke) {
+                   KernelEvents ke, FibreList fl) {
     if (nslots <= 0 || ldT <= 0) return hipSuccess;
     if (ldF == ldT && vec_ok<TV, TF, TO>(F, rowsF, ldT, T, proj_shape(nslots, ldT, tn, 4096).spw, nnz)) {
         // pairs of 16 bytes for FP64 values: at most 2048 staged (32 KiB)
-        const ProjShape sh = proj_shape(nslots, ldT, tn, sizeof(TV) == 8 ? 2048 : 4096);
-        const size_t lds = sizeof(int32_t) * ((sh.spw + 4) & ~3) + sizeof(NzPair<TV>) * (size_t)sh.cap;
-        launch(k_project_vec<TV, TF, TO, false>, sh.blocks, lds, s, ke, ptr, lidx, lval, F,
-               (uint32_t)(rowsF * ldT * (int64_t)sizeof(TF)), (int32_t)J, (int32_t)ldT, (int32_t)sh.spw,
-               (int32_t)sh.cap, nslots, T, (TO *)nullptr);
+        const int cap_max = sizeof(TV) == 8 ? 2048 : 4096;
+        const uint32_t Fb = (uint32_t)(rowsF * ldT * (int64_t)sizeof(TF));
+        if (fib_ok<TO>(fl, nslots, ldT)) {
+            if (fl.n <= 0) return hipSuccess;  // no nonzeros: every row keeps its zeros
+            const ProjShape sh = proj_shape(fl.n, ldT, tn, cap_max);
+            launch(k_project_vec<TV, TF, TO, false, true>, sh.blocks, vec_lds<TV>(sh, true), s, ke, fl.fptr, fl.fib,
+                   lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap, fl.n, T,
+                   (TO *)nullptr);
+        } else {
+            const ProjShape sh = proj_shape(nslots, ldT, tn, cap_max);
+            launch(k_project_vec<TV, TF, TO, false, false>, sh.blocks, vec_lds<TV>(sh, false), s, ke, ptr,
+                   (const int32_t *)nullptr, lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw,
+                   (int32_t)sh.cap, nslots, T, (TO *)nullptr);
+        }
     } else {
         const ProjShape sh = proj_shape(nslots, ldT, tn, 4096);
         const size_t lds = sizeof(int32_t) * (((sh.spw + 4) & ~3) + ((sh.cap + 3) & ~3)) + sizeof(TV) * sh.cap;
@@ -366,15 +403,23 @@ hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, cons
 
 hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *lval, const float *F, int64_t rowsF,
                          int ld, int J, int64_t nslots, int64_t nnz, bf16 *Thi, bf16 *Tlo, hipStream_t s,
-                         const Tune &tn, KernelEvents ke) {
+                         const Tune &tn, KernelEvents ke, FibreList fl) {
     if (nslots <= 0 || ld <= 0) return hipSuccess;
-    const ProjShape sh = proj_shape(nslots, ld, tn, 4096);
-    if (!vec_ok<float, float, bf16>(F, rowsF, ld, Thi, sh.spw, nnz) || ((uintptr_t)Tlo & 15) != 0)
+    if (!vec_ok<float, float, bf16>(F, rowsF, ld, Thi, proj_shape(nslots, ld, tn, 4096).spw, nnz) ||
+        ((uintptr_t)Tlo & 15) != 0)
         return hipErrorInvalidValue;
-    const size_t lds = sizeof(int32_t) * ((sh.spw + 4) & ~3) + sizeof(NzPair<float>) * (size_t)sh.cap;
-    launch(k_project_vec<float, float, bf16, true>, sh.blocks, lds, s, ke, ptr, lidx, lval, F,
-           (uint32_t)(rowsF * ld * (int64_t)sizeof(float)), (int32_t)J, (int32_t)ld, (int32_t)sh.spw,
-           (int32_t)sh.cap, nslots, Thi, Tlo);
+    const uint32_t Fb = (uint32_t)(rowsF * ld * (int64_t)sizeof(float));
+    if (fib_ok<bf16>(fl, nslots, ld)) {
+        if (fl.n <= 0) return hipSuccess;
+        const ProjShape sh = proj_shape(fl.n, ld, tn, 4096);
+        launch(k_project_vec<float, float, bf16, true, true>, sh.blocks, vec_lds<float>(sh, true), s, ke, fl.fptr,
+               fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw, (int32_t)sh.cap, fl.n, Thi, Tlo);
+    } else {
+        const ProjShape sh = proj_shape(nslots, ld, tn, 4096);
+        launch(k_project_vec<float, float, bf16, true, false>, sh.blocks, vec_lds<float>(sh, false), s, ke, ptr,
+               (const int32_t *)nullptr, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw,
+               (int32_t)sh.cap, nslots, Thi, Tlo);
+    }
     TK_LAUNCHED();
     return hipSuccess;
 }
@@ -382,7 +427,7 @@ hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *l
 #define TK_PROJECT(TV, TF, TO)                                                                                 \
     template hipError_t project<TV, TF, TO>(const int32_t *, const int32_t *, const TV *, const TF *, int64_t, int, \
                                             int, int, int64_t, int64_t, TO *, hipStream_t, const Tune &,       \
-                                            KernelEvents);
+                                            KernelEvents, FibreList);
 TK_PROJECT(double, double, double)
 TK_PROJECT(float, float, float)
 TK_PROJECT(float, float, bf16)

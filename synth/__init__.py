@@ -143,7 +143,7 @@ def planted_tucker(dims, core, nnz: int, noise: float, seed: int):
         h = (fac[0][i] @ g1).reshape(core[1], core[2])          # core slice for row i
         bj = fac[1][idx[1][sel]]                                # rows of B
         ck = fac[2][idx[2][sel]]                                # rows of C
-        vals[sel] = np.einsum("nq,qr,nr->n", bj, h, ck)
+        vals[sel] = ((bj @ h) * ck).sum(axis=1)                # b_j^T H_i c_k per nonzero
     vals /= np.sqrt(np.mean(vals * vals))
     vals += noise * rng.standard_normal(vals.size)
     return idx, vals, dims

@@ -262,7 +262,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    structs = {"tk_opts": tk.tk_opts, "tk_stats": tk.tk_stats, "tk_tune": tk.tk_tune, "tk_coo": tk.tk_coo}
+    structs = {"tk_opts": tk.tk_opts, "tk_stats": tk.tk_stats, "tk_tune": tk.tk_tune, "tk_coo": tk.tk_coo,
+               "tk_event": tk.tk_event, "tk_trace": tk.tk_trace}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tucker.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
@@ -385,3 +386,4 @@ def test_documented_limits(case):
         assert _ws(c, (1, 1, 1), o)[0] == 0
         c, d = _coo(dims=(46341, 46341, 2), nnz=10)
         assert _ws(c, (1, 1, 1), o)[0] == tk.TK_ERR_ARG
+

@@ -316,3 +316,41 @@ def test_learned_start_falls_back_to_hosvd(tk, trained):
     H = tk.hooi(di, dv, r["dims"], r["core"], precision="fp64", max_iters=3, tol=0.0)
     assert L.stats["init_fallbacks"] == 2
     np.testing.assert_allclose(L.fits, H.fits, rtol=0, atol=1e-12)
+
+
+def test_learned_start_wide_core(tk, trained):
+    """Core 100^3, so the network's test span is K = min(128, 2 Jn) = 128
+    columns (the width the 4000^3 benchmark workload uses): the start that MP
+    returns after no sweep against the oracle's Rayleigh-Ritz start on the
+    same sketch, network and H_n (captured energy within 1e-3 below the exact
+    step, orthonormal columns), and the decomposition from it against the
+    HO-SVD-started one (same final fit within 1e-4, no fallback)."""
+    _say("wide core: generating 400x350x300 planted, core 100^3")
+    idx, vals, dims = synth.planted_tucker((400, 350, 300), (100, 100, 100), 1_500_000, 0.1, 4242)
+    di, dv = _dev(idx, vals)
+    J = (100, 100, 100)
+    th = trained["params"].cpu().numpy()
+    _say("wide core: start only (fp64)")
+    res = tk.mp(di, dv, dims, J, precision="fp64", max_iters=0, tol=0.0, init=tk.INIT_LEARNED,
+                model=trained["params"], seed=SEED)
+    assert res.stats["init_fallbacks"] == 0
+    X = O.SparseTensor3(idx, vals, dims)
+    for n in (1, 2):
+        S = OL.sketch(idx, vals, dims, n, SEED)
+        Fo, rho = OL.row_features(S)
+        Ro, _ = OL.mlp_forward(Fo, rho, OL.round_weights(th))
+        H = O.unfolding_gram(X, n)
+        Uo, tho, _ = OL.start_factor(Ro, H, J[n])
+        U = res.factors[n].cpu().numpy()
+        e_gpu, e_or = np.trace(U.T @ H @ U), tho.sum()
+        _say(f"wide core: mode {n} K={tk.learn_test_width(J[n])} energy gpu {e_gpu:.6e} oracle {e_or:.6e}")
+        assert np.abs(U.T @ U - np.eye(U.shape[1])).max() < 1e-10
+        assert e_gpu <= e_or * (1 + 1e-9) and e_gpu >= e_or * (1 - 1e-3), (n, e_gpu, e_or)
+    kw = dict(precision="mixed", max_iters=8, tol=0.0)
+    _say("wide core: mixed from the learned start")
+    L = tk.mp(di, dv, dims, J, init=tk.INIT_LEARNED, model=trained["params"], seed=SEED, **kw)
+    _say("wide core: mixed from the HO-SVD start")
+    Hh = tk.mp(di, dv, dims, J, **kw)
+    _say(f"wide core: fits learned {L.fits[-1]:.6f} hosvd {Hh.fits[-1]:.6f}")
+    assert L.stats["init_fallbacks"] == 0
+    assert abs(L.fits[-1] - Hh.fits[-1]) <= 1e-4

@@ -134,6 +134,18 @@ def test_project_dense_layout():
     np.testing.assert_allclose(O.project_dense(D, A, 0), np.einsum("ijk,ip->jkp", D, A), rtol=1e-13, atol=1e-14)
 
 
+def test_project_sparse_matches_the_definition():
+    """The sparse projection against the n-mode product written out as
+    einsum on the densified tensor, every mode, ragged sizes (a transposed
+    fold or a swapped pair of other modes would fail here)."""
+    X = _tiny()
+    D = X.dense()
+    subs = {0: "ijk,ip->jkp", 1: "ijk,jq->ikq", 2: "ijk,kr->ijr"}
+    for m in range(3):
+        A = _orth(D.shape[m], 3, 10 + m)
+        np.testing.assert_allclose(O.project_sparse(X, A, m), np.einsum(subs[m], D, A), rtol=1e-13, atol=1e-14)
+
+
 # ---------------------------------------------------------------- core / fit
 def test_core_matches_einsum():
     X = _tiny()
