@@ -72,6 +72,8 @@ extern "C" {
 #define TK_ERR_EMPTY      -4  /* ||X|| = 0: the fit is undefined */
 #define TK_ERR_WORKSPACE  -5  /* workspace NULL or smaller than tucker_workspace_bytes() */
 #define TK_ERR_DEVICE     -6  /* a HIP call failed; tucker_strerror() has the HIP text */
+#define TK_ERR_SIZE       -7  /* tucker_fit_static: the problem needs more scratch than
+                                 TK_STATIC_SCRATCH_BYTES */
 
 /* ---- precision of the projection / Gram / TTMc path ------------------- */
 #define TK_FP64        0  /* FP64 everywhere */
@@ -302,6 +304,34 @@ int tucker_hosvd(const tk_coo *X, const int32_t *core_dims, const tk_opts *opt,
 int tucker_fit(const tk_coo *X, const int32_t *core_dims, const double *core,
                const double *const *factors, double *fit,
                void *workspace, size_t workspace_bytes, void *stream);
+
+/* The fit of tucker_fit for callers that cannot allocate device memory
+   (code under stream capture, serving loops that must not call the
+   allocator): the same arguments and result, without a workspace. Its scratch
+   space is a static device array of TK_STATIC_SCRATCH_BYTES (64 MiB) inside
+   the library, of which every device the library runs on holds one copy from
+   the library's load until the process ends. The first call on a device,
+   with that device current, looks up the array's device address once
+   (hipGetSymbolAddress); no call allocates or frees device memory.
+   Limit: TK_ERR_SIZE, before any device work, when the problem needs more
+   than TK_STATIC_SCRATCH_BYTES, i.e. when tucker_workspace_bytes(TK_ALGO_FIT,
+   ...) exceeds it (about 72 bytes per nonzero, 4 bytes per fibre slot of each
+   mode (I2*I3 + I3*I1 + I1*I2 slots) plus 8 per slot of the largest family,
+   8*J3 bytes per mode-3 fibre slot (I1*I2 of them, the FP64 projection), and
+   terms of the core's size). Other errors as tucker_fit.
+   Every call on one device shares that device's array: calls that overlap on
+   one device (from several host threads, or on several streams without
+   ordering between them) race and give wrong results; calls in sequence on
+   one stream, or on streams the caller orders, are safe. The call returns
+   after the fit has been read back (host-blocking, as tucker_fit).
+     core    [dev]  J1*J2*J3 doubles, row-major
+     factors [host] array of 3 [dev] pointers, In x Jn row-major doubles
+     fit     [host] output
+     stream  hipStream_t as void* (NULL = the null stream) of the current
+             device                                                        */
+#define TK_STATIC_SCRATCH_BYTES (64u << 20)
+int tucker_fit_static(const tk_coo *X, const int32_t *core_dims, const double *core,
+                      const double *const *factors, double *fit, void *stream);
 
 /* Static text for a status code (for TK_ERR_DEVICE, the last HIP error text
    seen by the calling thread). */

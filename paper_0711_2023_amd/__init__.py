@@ -15,7 +15,7 @@ from dataclasses import dataclass
 __all__ = [
     "TuckerError", "lib", "hooi", "mp", "sp", "hosvd", "fit", "workspace_bytes", "default_opts",
     "FP64", "FP32", "MIXED_BF16", "MIXED_BF16X3", "INIT_HOSVD", "INIT_GIVEN", "INIT_LEARNED", "INIT_RANDOM",
-    "Result", "LIB_PATH", "SYMBOLS", "lead_eig", "learn_param_count", "learn_sketch", "learn_forward",
+    "Result", "LIB_PATH", "fit_static", "SYMBOLS", "lead_eig", "learn_param_count", "learn_sketch", "learn_forward",
     "learn_backward", "learn_align", "learn_adam", "learn_test_width", "batched",
 ]
 
@@ -24,6 +24,8 @@ LIB_PATH = os.path.join(HERE, "libtucker.so")
 
 TK_OK, TK_WARN_NOCONV = 0, 1
 TK_ERR_ARG, TK_ERR_INDEX, TK_ERR_VALUE, TK_ERR_EMPTY, TK_ERR_WORKSPACE, TK_ERR_DEVICE = -1, -2, -3, -4, -5, -6
+TK_ERR_SIZE = -7
+STATIC_SCRATCH_BYTES = 64 << 20  # TK_STATIC_SCRATCH_BYTES of tucker.h
 FP64, FP32, MIXED_BF16, MIXED_BF16X3 = 0, 1, 2, 3
 INIT_HOSVD, INIT_GIVEN, INIT_LEARNED, INIT_RANDOM = 0, 1, 2, 3
 ALGO_HOOI, ALGO_MP, ALGO_FIT, ALGO_SP, ALGO_HOSVD = 0, 1, 2, 3, 4
@@ -32,7 +34,7 @@ _PREC = {"fp64": FP64, "fp32": FP32, "mixed": MIXED_BF16, "bf16": MIXED_BF16, "b
 
 # every function declared in include/*.h
 SYMBOLS = ["tucker_default_opts", "tucker_workspace_bytes", "tucker_hooi", "tucker_mp", "tucker_sp", "tucker_hosvd",
-           "tucker_fit",
+           "tucker_fit", "tucker_fit_static",
            "tucker_strerror", "tucker_step_lead_eig_workspace", "tucker_step_lead_eig",
            "tucker_learn_param_count", "tucker_learn_sketch_workspace", "tucker_learn_sketch",
            "tucker_learn_forward", "tucker_learn_backward_workspace", "tucker_learn_backward",
@@ -131,6 +133,9 @@ def lib():
         L.tucker_fit.argtypes = [P(tk_coo), P(ctypes.c_int32), ctypes.c_void_p, P(ctypes.c_void_p),
                                  P(ctypes.c_double), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.tucker_fit.restype = ctypes.c_int
+        L.tucker_fit_static.argtypes = [P(tk_coo), P(ctypes.c_int32), ctypes.c_void_p, P(ctypes.c_void_p),
+                                        P(ctypes.c_double), ctypes.c_void_p]
+        L.tucker_fit_static.restype = ctypes.c_int
         L.tucker_step_lead_eig_workspace.argtypes = [ctypes.c_int32, ctypes.c_int32, P(ctypes.c_size_t)]
         L.tucker_step_lead_eig_workspace.restype = ctypes.c_int
         L.tucker_step_lead_eig.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
@@ -380,6 +385,25 @@ def fit(idx, vals, dims, core, factors, workspace=None, stream=None) -> float:
     s = stream if stream is not None else torch.cuda.current_stream(dev)
     _check(lib().tucker_fit(ctypes.byref(coo.c), Jc, G.data_ptr(), fptrs, ctypes.byref(out), workspace.data_ptr(),
                             int(workspace.numel()), ctypes.c_void_p(s.cuda_stream)))
+    return float(out.value)
+
+
+def fit_static(idx, vals, dims, core, factors, stream=None) -> float:
+    """``fit`` without a workspace: the library's static device scratch
+    (TK_STATIC_SCRATCH_BYTES per device) serves it. Calls that overlap on one
+    device race; TuckerError(TK_ERR_SIZE) when the problem does not fit."""
+    import torch
+    dev = vals.device
+    coo = _Coo(idx, vals, dims)
+    J = list(core.shape)
+    Jc = (ctypes.c_int32 * 3)(*J)
+    G = core.to(device=dev, dtype=torch.float64).contiguous()
+    facs = [f.to(device=dev, dtype=torch.float64).contiguous() for f in factors]
+    fptrs = (ctypes.c_void_p * 3)(*[f.data_ptr() for f in facs])
+    out = ctypes.c_double(0)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(lib().tucker_fit_static(ctypes.byref(coo.c), Jc, G.data_ptr(), fptrs, ctypes.byref(out),
+                                   ctypes.c_void_p(s.cuda_stream)))
     return float(out.value)
 
 

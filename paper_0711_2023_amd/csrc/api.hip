@@ -475,6 +475,9 @@ const char *tucker_strerror(int st) {
         case TK_ERR_EMPTY: return "the tensor has zero norm; the fit is undefined";
         case TK_ERR_WORKSPACE: return "workspace missing or too small";
         case TK_ERR_DEVICE: return g_err[0] ? g_err : "HIP error";
+        case TK_ERR_SIZE:
+            return "the problem needs more scratch than the static buffer of tucker_fit_static holds "
+                   "(TK_STATIC_SCRATCH_BYTES)";
         default: return "unknown status";
     }
 }

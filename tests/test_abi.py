@@ -39,7 +39,7 @@ def test_default_opts_are_the_papers():
 
 
 def test_strerror_texts():
-    for st in (0, 1, -1, -2, -3, -4, -5, -6):
+    for st in (0, 1, -1, -2, -3, -4, -5, -6, -7):
         assert len(tk.strerror(st)) > 0
     assert "unknown" in tk.strerror(99)
 
@@ -387,3 +387,26 @@ def test_documented_limits(case):
         c, d = _coo(dims=(46341, 46341, 2), nnz=10)
         assert _ws(c, (1, 1, 1), o)[0] == tk.TK_ERR_ARG
 
+
+def test_fit_static_rejects_before_device_work():
+    """The workspace-free fit checks its arguments and its size limit on the
+    host, before it looks up the static scratch on a device."""
+    L = tk.lib()
+    facs = (ctypes.c_void_p * 3)(0x10, 0x20, 0x30)
+    out = ctypes.c_double(0)
+    c, d = _coo()
+    bad = (ctypes.c_int32 * 3)(3, 10, 3)  # J2 > I2
+    assert L.tucker_fit_static(ctypes.byref(c), bad, 0x40, facs, ctypes.byref(out), None) == tk.TK_ERR_ARG
+    J = (ctypes.c_int32 * 3)(3, 3, 3)
+    assert L.tucker_fit_static(ctypes.byref(c), J, None, facs, ctypes.byref(out), None) == tk.TK_ERR_ARG
+    assert L.tucker_fit_static(ctypes.byref(c), J, 0x40, facs, None, None) == tk.TK_ERR_ARG
+    # 2000 x 2000 x 100 with J3 = 50: the FP64 projection alone is 1.6 GB
+    big, dbig = _coo(dims=(2000, 2000, 100), nnz=1000)
+    J50 = (ctypes.c_int32 * 3)(50, 50, 50)
+    st, need = _ws(big, (50, 50, 50), algo=tk.ALGO_FIT)
+    assert st == 0 and need > tk.STATIC_SCRATCH_BYTES
+    assert L.tucker_fit_static(ctypes.byref(big), J50, 0x40, facs, ctypes.byref(out), None) == tk.TK_ERR_SIZE
+    assert "static" in tk.strerror(tk.TK_ERR_SIZE)
+    # a small problem fits the static scratch
+    st, need = _ws(c, (3, 3, 3), algo=tk.ALGO_FIT)
+    assert st == 0 and need <= tk.STATIC_SCRATCH_BYTES
