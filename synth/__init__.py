@@ -4,9 +4,10 @@ This module only draws inputs. It holds none of the decomposition's arithmetic,
 and both the FP64 oracle and the GPU library are fed from it. Every generator
 returns host arrays:
 
-* ``idx``  int32 array of shape (3, nnz), 0-based coordinates (i, j, k);
+* ``idx``  int32 array of shape (N, nnz), 0-based coordinates (N = 3, or 4
+  for the fourth-order generators and shapes);
 * ``vals`` float64 array of shape (nnz,);
-* ``dims`` tuple of three ints (I1, I2, I3).
+* ``dims`` tuple of N ints.
 
 The workload family is the paper's: random sparse third-order tensors whose
 nonzero values are uniform on [0, 1) (Section 5, "Varying Tensor Sizes"; the
@@ -22,6 +23,7 @@ __all__ = [
     "uniform_sparse",
     "bernoulli_sparse",
     "exact_tucker_block",
+    "exact_tucker_block_n",
     "superdiagonal",
     "matrix_as_tensor",
     "planted_tucker",
@@ -32,8 +34,7 @@ __all__ = [
 
 
 def _unravel(lin: np.ndarray, dims) -> np.ndarray:
-    i, j, k = np.unravel_index(lin, dims)
-    return np.stack([i, j, k]).astype(np.int32)
+    return np.stack(np.unravel_index(lin, dims)).astype(np.int32)
 
 
 def _distinct_linear(total: int, nnz: int, rng: np.random.Generator) -> np.ndarray:
@@ -52,7 +53,8 @@ def _distinct_linear(total: int, nnz: int, rng: np.random.Generator) -> np.ndarr
 
 
 def uniform_sparse(dims, nnz: int, seed: int):
-    """nnz distinct uniformly random coordinates with U(0,1) values."""
+    """nnz distinct uniformly random coordinates with U(0,1) values (any
+    number of modes: idx has one row per mode)."""
     dims = tuple(int(d) for d in dims)
     rng = np.random.Generator(np.random.PCG64(seed))
     lin = _distinct_linear(int(np.prod(dims, dtype=np.int64)), int(nnz), rng)
@@ -61,7 +63,8 @@ def uniform_sparse(dims, nnz: int, seed: int):
 
 
 def bernoulli_sparse(dims, density: float, seed: int):
-    """Each cell is nonzero with probability ``density``; values U(0,1).
+    """Each cell is nonzero with probability ``density``; values U(0,1) (any
+    number of modes).
 
     This is the appendix generator's distribution (a cell mask drawn by
     comparing a uniform number with the density, then a uniform value).
@@ -79,6 +82,24 @@ def bernoulli_sparse(dims, density: float, seed: int):
     vals = rng.random(lin.size)
     perm = rng.permutation(lin.size)
     return _unravel(lin[perm], dims), vals[perm], dims
+
+
+def exact_tucker_block_n(dims, block, rank, seed: int):
+    """Any order: zero except on a random index block, where it equals a dense
+    Tucker tensor of multilinear rank ``rank``."""
+    dims = tuple(int(d) for d in dims)
+    N = len(dims)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rows = [np.sort(rng.choice(dims[n], size=block[n], replace=False)) for n in range(N)]
+    dense = rng.standard_normal(rank)
+    for n in range(N):
+        f = _orthonormal(block[n], rank[n], rng)
+        dense = np.moveaxis(np.tensordot(f, np.moveaxis(dense, n, 0), axes=(1, 0)), 0, n)
+    grids = np.meshgrid(*rows, indexing="ij")
+    idx = np.stack([g.ravel() for g in grids]).astype(np.int32)
+    vals = dense.ravel().copy()
+    perm = rng.permutation(vals.size)
+    return idx[:, perm], vals[perm], dims
 
 
 def _orthonormal(n: int, r: int, rng: np.random.Generator) -> np.ndarray:
@@ -179,4 +200,6 @@ WORKLOADS = {
     "unbal_2000x1000x500_core100x20x5": {"dims": (2000, 1000, 500), "nnz": 2_000_000, "core": (100, 20, 5), "seed": 2},
     "unbal_2000x1000x500_core10x50x100": {"dims": (2000, 1000, 500), "nnz": 2_000_000, "core": (10, 50, 100), "seed": 2},
     "cube4000_nnz10m_planted": {"dims": (4000, 4000, 4000), "nnz": 10_000_000, "core": (100, 100, 100), "seed": 4},
+    # fourth order, the paper's shape (Table 5): 100^4 at 10 % density, cores 10^4 .. 90^4
+    "hyper100_nnz10m": {"dims": (100, 100, 100, 100), "nnz": 10_000_000, "core": (50, 50, 50, 50), "seed": 6},
 }
