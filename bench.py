@@ -143,8 +143,8 @@ def c5_leg(args):
     core 100^3 N(0,1), values at the sampled coordinates scaled to unit RMS
     plus N(0, 0.1^2) noise), core 100^3: plain FP32 from the HO-SVD start,
     mixed from the HO-SVD start and mixed from the learned start (network
-    trained first, untimed), each until the paper's Delta-fit < 1e-4 (at most
-    50 sweeps). The returned factors of the mixed runs are checked after the
+    trained first, untimed), 15 sweeps each, with the sweeps and time until
+    the fit gain drops below 1e-4 of the fit. The returned factors of the mixed runs are checked after the
     fact by the FP64 oracle (core slice by slice, fit by the identity). One
     JSON line."""
     import numpy as np
@@ -165,25 +165,39 @@ def c5_leg(args):
     log(f"c5 leg: trained {info}")
     out = {"workload": f"sparse {dims[0]}x{dims[1]}x{dims[2]}, {nnz} nonzeros of a planted Tucker model "
                        f"(core {J[0]}x{J[1]}x{J[2]} N(0,1), random orthonormal factors, unit RMS + N(0,0.1^2)), "
-                       f"core {J[0]}x{J[1]}x{J[2]}, MP, stop at Delta-fit < 1e-4 (cap 50)", "training": info}
+                       f"core {J[0]}x{J[1]}x{J[2]}, MP, 15 sweeps", "training": info}
+    # The fits of this tensor stay below 1e-4 (the planted signal is faint
+    # against the sampling noise at this density), so the paper's rule
+    # (Delta-fit < 1e-4 with fit(0) = 0) stops every run after its first
+    # sweep. Each form therefore runs a fixed 15 sweeps; reported beside the
+    # trajectories: the first sweep whose fit gain is below 1e-4 of the fit
+    # itself (the paper's threshold taken relative) and the time to it.
+    SW = 15
     runs = {}
     for name, prec, kw in (("fp32_hosvd", "fp32", {}), ("mixed_hosvd", "mixed", {}),
                            ("mixed_learned", "mixed", {"init": tk.INIT_LEARNED, "model": model})):
         tk.mp(di, dv, dims, J, precision=prec, max_iters=1, tol=0.0, **kw)  # warm-up
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r = tk.mp(di, dv, dims, J, precision=prec, max_iters=50, tol=1e-4, timing=True, **kw)
+        r = tk.mp(di, dv, dims, J, precision=prec, max_iters=SW, tol=0.0, timing=True, **kw)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t1
         runs[name] = r
-        out[name] = {"wall_ms": round(1000 * wall, 1), "sweeps": r.iters, "fit": r.fits[-1], "fits": r.fits,
-                     "init_ms": round(r.stats["init_ms"], 2), "sweeps_ms": round(r.stats["sweeps_ms"], 2),
-                     "init_fallbacks": r.stats["init_fallbacks"]}
+        f = r.fits
+        t_rel = next((t for t in range(2, len(f) + 1) if f[t - 1] - f[t - 2] < 1e-4 * f[t - 1]), len(f))
+        per = r.stats["sweeps_ms"] / max(1, r.iters)
+        out[name] = {"wall_ms_15_sweeps": round(1000 * wall, 1), "fits": f, "init_ms": round(r.stats["init_ms"], 2),
+                     "prep_ms": round(r.stats["prep_ms"], 2), "ms_per_sweep": round(per, 2),
+                     "init_fallbacks": r.stats["init_fallbacks"], "paper_rule_sweeps": 1 if f[0] < 1e-4 else None,
+                     "sweeps_to_relative_rule": t_rel,
+                     "ms_to_relative_rule": round(r.stats["prep_ms"] + r.stats["init_ms"] + t_rel * per, 1)}
         log(f"c5 leg: {name} {out[name]}")
-    out["speedup_plain_over_mixed_hosvd"] = round(out["fp32_hosvd"]["wall_ms"] / out["mixed_hosvd"]["wall_ms"], 3)
-    out["speedup_plain_over_mixed_learned"] = round(out["fp32_hosvd"]["wall_ms"] / out["mixed_learned"]["wall_ms"],
-                                                    3)
-    out["learned_over_hosvd_start_wall"] = round(out["mixed_hosvd"]["wall_ms"] / out["mixed_learned"]["wall_ms"], 3)
+    for k in ("mixed_hosvd", "mixed_learned"):
+        out[f"speedup_plain_over_{k}_relative_rule"] = round(out["fp32_hosvd"]["ms_to_relative_rule"] /
+                                                             out[k]["ms_to_relative_rule"], 3)
+    out["learned_over_hosvd_start_relative_rule"] = round(out["mixed_hosvd"]["ms_to_relative_rule"] /
+                                                          out["mixed_learned"]["ms_to_relative_rule"], 3)
+    out["fit_gap_learned_vs_hosvd_after_15"] = runs["mixed_learned"].fits[-1] - runs["mixed_hosvd"].fits[-1]
     # post-hoc oracle check of the returned factors
     t2 = time.perf_counter()
     X = O.SparseTensor3(idx, vals, dims)
@@ -487,6 +501,7 @@ def main():
     ap.add_argument("--no-parity", action="store_true", help="skip the small-workload comparison with the "
                     "stored oracle reference")
     ap.add_argument("--no-c5", action="store_true", help="skip the learned-start leg at 4000^3 / 10M nonzeros")
+    ap.add_argument("--no-order4", action="store_true", help="skip the fourth-order leg (100^4)")
     ap.add_argument("--c5-leg", action="store_true", help="internal: run the 4000^3 learned-start leg, print one "
                     "JSON line")
     ap.add_argument("--copy-calib", action="store_true",
@@ -677,6 +692,9 @@ def main():
     if not args.no_unbal:
         line["unbalanced"] = unbalanced_leg(tk, dev, args.sweeps)
 
+    if not args.no_order4:
+        line["fourth_order"] = fourth_order_leg(tk, dev)
+
     if not args.no_c5:
         # in a child process with a time limit (own device memory, about 40 GB)
         cmd = [sys.executable, os.path.abspath(__file__), "--c5-leg"]
@@ -698,6 +716,50 @@ def main():
         log("timing the FP64 oracle on the host")
         line["cpu_baseline"], line["cpu_whole_sweep"] = cpu_baseline(idx, vals, dims, J)
     print(json.dumps(line), flush=True)
+
+
+def fourth_order_leg(tk, dev):
+    """The paper's fourth-order shape (Table 5): 100^4 with each cell nonzero
+    with probability 0.1 and U(0,1) values (the appendix generator's
+    distribution, about 10M nonzeros), core 50^4. HO-SVD, and HOOI and MP
+    (mixed and plain FP32) until the paper's Delta-fit < 1e-4 rule stops them
+    (cap 50): fits beside the ones Table 6 prints for this shape (another
+    draw, another machine: context), wall times, projected nnz/s of the
+    sweeps."""
+    import numpy as np
+    import torch
+    import synth
+    t0 = time.perf_counter()
+    idx, vals, dims = synth.bernoulli_sparse((100, 100, 100, 100), 0.1, 6)
+    log(f"fourth order: generated {vals.size} nonzeros in {time.perf_counter() - t0:.1f} s")
+    di = torch.from_numpy(idx).to(dev)
+    dv = torch.from_numpy(vals).to(dev)
+    J = (50, 50, 50, 50)
+    out = {"workload": f"sparse 100^4, Bernoulli(0.1) cells ({vals.size} nonzeros), U(0,1) values, core 50^4",
+           "paper_fit_percent": {"hosvd": 6.988, "hooi": 7.135, "mp": 7.057}}
+    tk.hosvd(di, dv, dims, J)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    h = tk.hosvd(di, dv, dims, J)
+    torch.cuda.synchronize()
+    out["hosvd"] = {"fit_percent": 100 * h.fits[0], "wall_ms": round(1000 * (time.perf_counter() - t1), 2)}
+    nnz = vals.size
+    for algo in ("hooi", "mp"):
+        for prec in ("mixed", "fp32"):
+            getattr(tk, algo)(di, dv, dims, J, precision=prec, max_iters=1, tol=0.0)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = getattr(tk, algo)(di, dv, dims, J, precision=prec, max_iters=50, tol=1e-4, timing=True)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t1
+            e = {"fit_percent": 100 * r.fits[-1], "sweeps": r.iters, "wall_ms": round(1000 * wall, 2),
+                 "sweeps_ms": round(r.stats["sweeps_ms"], 2),
+                 "ttmc_nnz_per_s": 4 * r.stats["nnz_unique"] * r.iters / (r.stats["ttmc_ms"] / 1000.0),
+                 "whole_sweep_nnz_per_s": 4 * r.stats["nnz_unique"] * r.iters / (r.stats["sweeps_ms"] / 1000.0)}
+            out[f"{algo}_{prec}"] = e
+            log(f"fourth order {algo} {prec}: {e}")
+    out["nnz"] = int(nnz)
+    return out
 
 
 def unbalanced_leg(tk, dev, sweeps):

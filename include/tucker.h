@@ -109,12 +109,16 @@ extern "C" {
 #define TK_ALGO_SP     3
 #define TK_ALGO_HOSVD  4
 
-/* Sparse third-order tensor in coordinate form. */
+/* Sparse tensor in coordinate form: third order everywhere; fourth order
+   for tucker_hooi, tucker_mp, tucker_hosvd and their workspace query
+   (TK_ERR_ARG elsewhere). */
+#define TK_MAX_ORDER 4
 typedef struct tk_coo {
-    int32_t        order;   /* must be 3 */
+    int32_t        order;   /* 3, or 4 (see above) */
     int64_t        nnz;     /* number of listed entries, 0 <= nnz < 2^31 */
-    const int64_t *dims;    /* [host] order entries: I1, I2, I3 (each >= 1, < 2^31) */
-    const int32_t *idx[3];  /* [dev] nnz coordinates per mode, 0-based */
+    const int64_t *dims;    /* [host] order entries: I1, ..., IN (each >= 1, < 2^31) */
+    const int32_t *idx[TK_MAX_ORDER];  /* [dev] nnz coordinates per mode, 0-based; the
+                                          first `order` are read */
     const double  *vals;    /* [dev] nnz values */
 } tk_coo;
 

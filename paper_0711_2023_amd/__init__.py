@@ -44,7 +44,7 @@ SYMBOLS = ["tucker_default_opts", "tucker_workspace_bytes", "tucker_hooi", "tuck
 
 class tk_coo(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("nnz", ctypes.c_int64), ("dims", ctypes.POINTER(ctypes.c_int64)),
-                ("idx", ctypes.c_void_p * 3), ("vals", ctypes.c_void_p)]
+                ("idx", ctypes.c_void_p * 4), ("vals", ctypes.c_void_p)]
 
 
 class tk_opts(ctypes.Structure):
@@ -212,24 +212,27 @@ class _Coo:
     def __init__(self, idx, vals, dims):
         import torch
         if idx.dtype != torch.int32 or vals.dtype != torch.float64:
-            raise TypeError("idx must be int32 [3, nnz], vals float64 [nnz]")
+            raise TypeError("idx must be int32 [N, nnz], vals float64 [nnz]")
         if not (idx.is_cuda and vals.is_cuda):
             raise TypeError("idx and vals must be on the GPU")
-        self.idx = [idx[n].contiguous() for n in range(3)]
+        self.order = len(dims)
+        if self.order not in (3, 4) or idx.shape[0] != self.order:
+            raise TypeError("idx must have one row per mode (3 or 4)")
+        self.idx = [idx[n].contiguous() for n in range(self.order)]
         self.vals = vals.contiguous()
-        self.dims = (ctypes.c_int64 * 3)(*[int(d) for d in dims])
+        self.dims = (ctypes.c_int64 * self.order)(*[int(d) for d in dims])
         self.c = tk_coo()
-        self.c.order = 3
+        self.c.order = self.order
         self.c.nnz = int(vals.numel())
         self.c.dims = self.dims
-        for n in range(3):
+        for n in range(self.order):
             self.c.idx[n] = self.idx[n].data_ptr()
         self.c.vals = self.vals.data_ptr()
 
 
 def workspace_bytes(algo: int, idx, vals, dims, core, **opts) -> int:
     coo = _Coo(idx, vals, dims)
-    J = (ctypes.c_int32 * 3)(*[int(j) for j in core])
+    J = (ctypes.c_int32 * len(core))(*[int(j) for j in core])
     o = _opts(**opts)
     out = ctypes.c_size_t(0)
     _check(lib().tucker_workspace_bytes(int(algo), ctypes.byref(coo.c), J, ctypes.byref(o), ctypes.byref(out)))
@@ -274,17 +277,18 @@ def _run(fn_name: str, algo: int, idx, vals, dims, core_dims, *, precision="fp32
         tr._evs = evs  # kept alive with the trace
         o.trace = ctypes.addressof(tr)
     J = [int(j) for j in core_dims]
-    Jc = (ctypes.c_int32 * 3)(*J)
+    N = len(J)
+    Jc = (ctypes.c_int32 * N)(*J)
     need = ctypes.c_size_t(0)
     _check(lib().tucker_workspace_bytes(algo, ctypes.byref(coo.c), Jc, ctypes.byref(o), ctypes.byref(need)))
     if workspace is None or workspace.numel() < need.value:
         workspace = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
     G = torch.empty(J, dtype=torch.float64, device=dev)
     if factors is None:
-        facs = [torch.empty((int(dims[n]), J[n]), dtype=torch.float64, device=dev) for n in range(3)]
+        facs = [torch.empty((int(dims[n]), J[n]), dtype=torch.float64, device=dev) for n in range(N)]
     else:
         facs = [f.to(device=dev, dtype=torch.float64).contiguous().clone() for f in factors]
-    fptrs = (ctypes.c_void_p * 3)(*[f.data_ptr() for f in facs])
+    fptrs = (ctypes.c_void_p * N)(*[f.data_ptr() for f in facs])
     hist = (ctypes.c_double * max(1, int(max_iters)))()
     done = ctypes.c_int32(0)
     st = tk_stats()
@@ -302,12 +306,14 @@ def _run(fn_name: str, algo: int, idx, vals, dims, core_dims, *, precision="fp32
 
 
 def hooi(idx, vals, dims, core_dims, **kw) -> Result:
-    """HOOI (Figure 3). idx: int32 [3, nnz] and vals: float64 [nnz] on the GPU."""
+    """HOOI (Figure 3; Figure 4 for a fourth-order tensor). idx: int32
+    [N, nnz] (N = 3 or 4) and vals: float64 [nnz] on the GPU."""
     return _run("tucker_hooi", ALGO_HOOI, idx, vals, dims, core_dims, **kw)
 
 
 def mp(idx, vals, dims, core_dims, **kw) -> Result:
-    """Multislice Projection (Figure 7). Same arguments as ``hooi``."""
+    """Multislice Projection (Figure 7; Figure 8 for a fourth-order tensor).
+    Same arguments as ``hooi``."""
     return _run("tucker_mp", ALGO_MP, idx, vals, dims, core_dims, **kw)
 
 
@@ -326,14 +332,15 @@ def hosvd(idx, vals, dims, core_dims, precision="fp64", eig_tol=None, workspace=
     coo = _Coo(idx, vals, dims)
     o = _opts(precision, eig_tol=eig_tol)
     J = [int(j) for j in core_dims]
-    Jc = (ctypes.c_int32 * 3)(*J)
+    N = len(J)
+    Jc = (ctypes.c_int32 * N)(*J)
     need = ctypes.c_size_t(0)
     _check(lib().tucker_workspace_bytes(ALGO_HOSVD, ctypes.byref(coo.c), Jc, ctypes.byref(o), ctypes.byref(need)))
     if workspace is None or workspace.numel() < need.value:
         workspace = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
     G = torch.empty(J, dtype=torch.float64, device=dev)
-    facs = [torch.empty((int(dims[n]), J[n]), dtype=torch.float64, device=dev) for n in range(3)]
-    fptrs = (ctypes.c_void_p * 3)(*[f.data_ptr() for f in facs])
+    facs = [torch.empty((int(dims[n]), J[n]), dtype=torch.float64, device=dev) for n in range(N)]
+    fptrs = (ctypes.c_void_p * N)(*[f.data_ptr() for f in facs])
     out = ctypes.c_double(0)
     st = tk_stats()
     s = stream if stream is not None else torch.cuda.current_stream(dev)

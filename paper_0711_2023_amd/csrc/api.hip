@@ -9,6 +9,7 @@
 #include "../../include/tucker.h"
 #include "common.h"
 #include "guards.h"
+#include "timer.h"
 
 #include <chrono>
 #include <cmath>
@@ -485,6 +486,14 @@ const char *tucker_strerror(int st) {
 int tucker_workspace_bytes(int32_t algo, const tk_coo *X, const int32_t *core_dims, const tk_opts *opt,
                            size_t *bytes) {
     if (!bytes) return TK_ERR_ARG;
+    if (X && X->order == 4) {  // fourth order: HOOI, MP, HO-SVD
+        if (algo != TK_ALGO_HOOI && algo != TK_ALGO_MP && algo != TK_ALGO_HOSVD) return TK_ERR_ARG;
+        int st4 = TK_OK;
+        const size_t b = order_n_workspace(algo, X, core_dims, opt, &st4);
+        if (st4) return st4;
+        *bytes = b;
+        return TK_OK;
+    }
     int st = check_coo(X, core_dims);
     if (st) return st;
     if (algo < TK_ALGO_HOOI || algo > TK_ALGO_HOSVD) return TK_ERR_ARG;
@@ -506,95 +515,6 @@ int tucker_workspace_bytes(int32_t algo, const tk_coo *X, const int32_t *core_di
 }  // extern "C"
 
 namespace tk {
-
-// HIP events around the phases of a sweep, on the call's stream. Each pair
-// carries its phase, the mode it serves and its element type; collect()
-// (after a stream synchronisation, once per sweep) sums them per phase and
-// appends them to the caller's trace when one is given.
-enum TimedKind { kProj = TK_PHASE_PROJECT, kTtmc = TK_PHASE_TTMC2, kGram = TK_PHASE_GRAM, kEig = TK_PHASE_EIG,
-                 kCore = TK_PHASE_CORE };
-struct Timer {
-    bool on;
-    hipStream_t s;
-    tk_trace *tr;
-    std::vector<hipEvent_t> ev;
-    struct Tag {
-        int kind, mode, prec;
-    };
-    std::vector<Tag> tag;
-    size_t used = 0;
-    double ms[5] = {0, 0, 0, 0, 0};
-    int64_t calls[5] = {0, 0, 0, 0, 0};
-    double sweep_ttmc[64] = {};  // TTMc time (projections + second stage) per collect() = per sweep
-    int sweeps = 0;
-    Timer(const tk_opts *o, hipStream_t s_) : on(o->timing != 0 || o->trace), s(s_), tr(o->trace) {}
-    ~Timer() {
-        for (auto e : ev) (void)hipEventDestroy(e);
-    }
-    void reserve_pair(int k, int mode, int prec) {
-        if (used + 2 > ev.size()) {
-            for (int i = 0; i < 2; ++i) {
-                hipEvent_t e;
-                (void)hipEventCreate(&e);
-                ev.push_back(e);
-            }
-        }
-        tag.resize(used / 2 + 1);
-        tag[used / 2] = Tag{k, mode, prec};
-    }
-    void begin(int k, int mode = -1, int prec = -1) {
-        if (!on) return;
-        reserve_pair(k, mode, prec);
-        (void)hipEventRecord(ev[used], s);
-    }
-    void end() {
-        if (!on) return;
-        (void)hipEventRecord(ev[used + 1], s);
-        used += 2;
-    }
-    // A pair for a single kernel that records them itself at its start and
-    // end (kernel time without the dispatch gap an event bracket includes).
-    KernelEvents kernel(int k, int mode = -1, int prec = -1) {
-        if (!on) return KernelEvents();
-        reserve_pair(k, mode, prec);
-        const KernelEvents ke{ev[used], ev[used + 1]};
-        used += 2;
-        return ke;
-    }
-    // call after a stream synchronisation
-    void collect() {
-        if (!on) return;
-        double ttmc = 0.0;
-        for (size_t i = 0; i + 1 < used; i += 2) {
-            float t = 0;
-            (void)hipEventElapsedTime(&t, ev[i], ev[i + 1]);
-            const Tag &g = tag[i / 2];
-            ms[g.kind] += t;
-            calls[g.kind] += 1;
-            if (g.kind == kProj || g.kind == kTtmc) ttmc += t;
-            if (tr && tr->events) {
-                if (tr->count < tr->capacity)
-                    tr->events[tr->count++] = tk_event{g.kind, g.mode, g.prec, sweeps + 1, (double)t};
-                else
-                    tr->dropped++;
-            }
-        }
-        if (sweeps < 64) sweep_ttmc[sweeps] = ttmc;
-        ++sweeps;
-        used = 0;
-    }
-    void report(tk_stats *st) const {
-        if (!st) return;
-        st->project_ms = ms[kProj];
-        st->project_calls = calls[kProj];
-        st->ttmc_ms = ms[kProj] + ms[kTtmc];
-        st->gram_ms = ms[kGram];
-        st->gram_calls = calls[kGram];
-        st->eig_ms = ms[kEig];
-        st->core_ms = ms[kCore];
-        for (int t = 0; t < 64; ++t) st->ttmc_sweep_ms[t] = t < sweeps ? sweep_ttmc[t] : 0.0;
-    }
-};
 
 static double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -1144,6 +1064,8 @@ static hipError_t slice_core(Plan &p, const double *A, const double *B, double *
 extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, double *core, double *const *factors,
                          double *fit_history, int32_t *iters_done, tk_stats *stats, void *ws, size_t wsb,
                          void *stream) {
+    if (X && X->order == 4)
+        return order_n_mp(X, J, o, core, factors, fit_history, iters_done, stats, ws, wsb, stream);
     Plan p;
     int st = common_start(TK_ALGO_MP, X, J, o, core, factors, fit_history, iters_done, ws, wsb, p);
     if (st) return st;
@@ -1256,6 +1178,8 @@ static hipError_t ttm(int M, int N, int K, int batch, const void *A, int64_t lda
 extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, double *core, double *const *factors,
                            double *fit_history, int32_t *iters_done, tk_stats *stats, void *ws, size_t wsb,
                            void *stream) {
+    if (X && X->order == 4)
+        return order_n_hooi(X, J, o, core, factors, fit_history, iters_done, stats, ws, wsb, stream);
     Plan p;
     int st = common_start(TK_ALGO_HOOI, X, J, o, core, factors, fit_history, iters_done, ws, wsb, p);
     if (st) return st;
@@ -1524,6 +1448,7 @@ extern "C" int tucker_sp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
 
 extern "C" int tucker_hosvd(const tk_coo *X, const int32_t *J, const tk_opts *o, double *core, double *const *factors,
                             double *fit, tk_stats *stats, void *ws, size_t wsb, void *stream) {
+    if (X && X->order == 4) return order_n_hosvd(X, J, o, core, factors, fit, stats, ws, wsb, stream);
     int st = check_coo(X, J);
     if (st) return st;
     if ((st = check_opts(o, X, TK_ALGO_HOSVD))) return st;

@@ -6,6 +6,10 @@
 #include <cstddef>
 #include <cstdint>
 
+struct tk_coo;
+struct tk_opts;
+struct tk_stats;
+
 namespace tk {
 
 typedef __bf16 bf16;
@@ -88,6 +92,31 @@ hipError_t build_order(const int32_t *const idx[3], int64_t nnz, const int64_t d
 hipError_t fibre_list(const int32_t *ptr, int64_t nslots, int64_t cap, int32_t *fib, int32_t *fptr, int32_t *flag_tmp,
                       int32_t *pos_tmp, int32_t *scan_scratch, int32_t *flags, hipStream_t s);
 
+// The counting sort of build_order on explicit key digits: slot =
+// ihi[p] * Ilo + ilo[p] (nslots of them), within a slot by (im[p], p).
+hipError_t build_order_keys(const int32_t *ihi, const int32_t *ilo, const int32_t *im, int64_t nnz, int32_t Ilo,
+                            int64_t nslots, int32_t *ptr, int32_t *perm, OrderScratch sc, int32_t *flags,
+                            hipStream_t s);
+
+// ---- tensors of order N (at most 4 modes)
+constexpr int kMaxOrder = 4;
+struct CoordsN {
+    const int32_t *i[kMaxOrder];
+    int32_t dim[kMaxOrder];
+    int n;
+};
+struct CoordsOut {
+    int32_t *i[kMaxOrder];
+};
+// out[p] = a[p] * Ib + b[p] (two coordinates merged into one key digit).
+hipError_t merge_keys(const int32_t *a, const int32_t *b, int64_t nnz, int32_t Ib, int32_t *out, hipStream_t s);
+// flags |= 1 (a coordinate outside its mode), 2 (a non-finite value).
+hipError_t validate_n(CoordsN c, const double *vals, int64_t nnz, int32_t *flags, hipStream_t s);
+// Duplicate summing over an ordering whose sort key is the full coordinate
+// (perm), as dedup.
+hipError_t dedup_n(CoordsN c, const double *vals, int64_t nnz, const int32_t *perm, int32_t *heads, int32_t *pos,
+                   int32_t *scan_scratch, CoordsOut out, double *cval, int32_t *nu_dev, hipStream_t s);
+
 // Validation: flags |= 1 (index out of range), 2 (non-finite value).
 hipError_t validate(const int32_t *const idx[3], const double *vals, int64_t nnz, const int64_t dims[3],
                     int32_t *flags, hipStream_t s);
@@ -114,6 +143,13 @@ constexpr int kReduceBlocks = 512;
 hipError_t hosvd_gram(int n, const int64_t dims[3], const int32_t *ptr_n, const int32_t *lidx_n,
                       const double *lval_n, const int32_t *ptr_s, const int32_t *lidx_s, const double *lval_s,
                       double *H, hipStream_t s);
+// The same with explicit sizes, for any order: In = I_n rows; the slice of
+// row i is slots [i * In2, (i + 1) * In2) of ordering s (leaf index i_{n+1});
+// the entry at sub-slot j with leaf index k lies on fibre j * In1 + k of
+// ordering n (In1 = I_{n+1}).
+hipError_t hosvd_gram_sized(int32_t In, int32_t In1, int32_t In2, const int32_t *ptr_n, const int32_t *lidx_n,
+                            const double *lval_n, const int32_t *ptr_s, const int32_t *lidx_s, const double *lval_s,
+                            double *H, hipStream_t s);
 
 // Launch choices that do not change results (run lengths of the projection,
 // split-K items of the Gram); the defaults are the built-in ones, a tuned
@@ -267,5 +303,16 @@ int learn_test_width(int J);
 hipError_t learn_start(const float *R, int64_t rows, int J, const double *H, double *F, double *theta, double *gC,
                        double *Q, double *HQ, double *C, double *V, void *eigw, double *part, int64_t part_elems,
                        hipStream_t s);
+
+// ---------------------------------------------------------------- order_n.hip
+// Fourth-order HO-SVD, HOOI and MP behind tucker_hosvd, tucker_hooi and
+// tucker_mp (tk_coo.order == 4); the same arguments as those entry points.
+size_t order_n_workspace(int algo, const tk_coo *X, const int32_t *J, const tk_opts *o, int *status);
+int order_n_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, double *core, double *const *F, double *hist,
+               int32_t *iters_done, tk_stats *stats, void *ws, size_t wsb, void *stream);
+int order_n_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, double *core, double *const *F, double *hist,
+                 int32_t *iters_done, tk_stats *stats, void *ws, size_t wsb, void *stream);
+int order_n_hosvd(const tk_coo *X, const int32_t *J, const tk_opts *o, double *core, double *const *F, double *fit,
+                  tk_stats *stats, void *ws, size_t wsb, void *stream);
 
 }  // namespace tk

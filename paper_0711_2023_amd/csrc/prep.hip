@@ -264,27 +264,32 @@ __global__ void k_slot_rank(const int32_t *ihi, const int32_t *ilo, const int32_
     }
 }
 
-hipError_t build_order(const int32_t *const idx[3], int64_t nnz, const int64_t dims[3], int m, int32_t *ptr,
-                       int32_t *perm, OrderScratch sc, int32_t *flags, hipStream_t s) {
-    const int hi = (m + 2) % 3, lo = (m + 1) % 3;
-    const int64_t nslots = dims[hi] * dims[lo];
-    const int32_t Ilo = (int32_t)dims[lo];
+hipError_t build_order_keys(const int32_t *ihi, const int32_t *ilo, const int32_t *im, int64_t nnz, int32_t Ilo,
+                            int64_t nslots, int32_t *ptr, int32_t *perm, OrderScratch sc, int32_t *flags,
+                            hipStream_t s) {
     TK_HIP(fill_i32(sc.counts, nslots, 0, s));
     TK_HIP(fill_i32(sc.cursor, nslots, 0, s));
     if (nnz > 0) {
-        k_slot_hist<<<grid_for(nnz), 256, 0, s>>>(idx[hi], idx[lo], nnz, Ilo, sc.counts);
+        k_slot_hist<<<grid_for(nnz), 256, 0, s>>>(ihi, ilo, nnz, Ilo, sc.counts);
         TK_LAUNCHED();
     }
     TK_HIP(scan_exclusive(sc.counts, ptr, nslots, sc.scan, s));
     if (nnz > 0) {
-        k_slot_scatter<<<grid_for(nnz), 256, 0, s>>>(idx[hi], idx[lo], nnz, Ilo, nslots, ptr, sc.cursor, sc.tmp,
-                                                     flags);
+        k_slot_scatter<<<grid_for(nnz), 256, 0, s>>>(ihi, ilo, nnz, Ilo, nslots, ptr, sc.cursor, sc.tmp, flags);
         TK_LAUNCHED();
-        k_slot_rank<<<grid_for(nnz), 256, 0, s>>>(idx[hi], idx[lo], idx[m], nnz, Ilo, ptr, sc.tmp, perm, flags);
+        k_slot_rank<<<grid_for(nnz), 256, 0, s>>>(ihi, ilo, im, nnz, Ilo, ptr, sc.tmp, perm, flags);
         TK_LAUNCHED();
     }
     return hipSuccess;
 }
+
+hipError_t build_order(const int32_t *const idx[3], int64_t nnz, const int64_t dims[3], int m, int32_t *ptr,
+                       int32_t *perm, OrderScratch sc, int32_t *flags, hipStream_t s) {
+    const int hi = (m + 2) % 3, lo = (m + 1) % 3;
+    return build_order_keys(idx[hi], idx[lo], idx[m], nnz, (int32_t)dims[lo], dims[hi] * dims[lo], ptr, perm, sc,
+                            flags, s);
+}
+
 
 // ------------------------------------------------------------------ duplicates
 __global__ void k_heads(const int32_t *i0, const int32_t *i1, const int32_t *i2, const int32_t *perm, int64_t nnz,
@@ -326,6 +331,77 @@ hipError_t dedup(const int32_t *const idx[3], const double *vals, int64_t nnz, c
     TK_HIP(scan_exclusive(heads, pos, nnz, scan_scratch, s));
     k_dedup_write<<<grid_for(nnz), 256, 0, s>>>(idx[0], idx[1], idx[2], vals, perm, heads, pos, nnz, cidx[0], cidx[1],
                                                 cidx[2], cval);
+    TK_LAUNCHED();
+    k_copy_i32<<<1, 1, 0, s>>>(pos + nnz, nu_dev);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------ order N
+// out[p] = a[p] * Ib + b[p]: two coordinates merged into one key digit.
+__global__ void k_merge_keys(const int32_t *a, const int32_t *b, int64_t nnz, int32_t Ib, int32_t *out) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+        out[p] = a[p] * Ib + b[p];
+}
+
+hipError_t merge_keys(const int32_t *a, const int32_t *b, int64_t nnz, int32_t Ib, int32_t *out, hipStream_t s) {
+    if (nnz <= 0) return hipSuccess;
+    k_merge_keys<<<grid_for(nnz), 256, 0, s>>>(a, b, nnz, Ib, out);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
+__global__ void k_validate_n(CoordsN c, const double *v, int64_t nnz, int32_t *flags) {
+    int bad = 0;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
+        for (int k = 0; k < c.n; ++k)
+            if ((uint32_t)c.i[k][p] >= (uint32_t)c.dim[k]) bad |= 1;
+        if (!isfinite(v[p])) bad |= 2;
+    }
+    uint64_t any1 = __ballot(bad & 1), any2 = __ballot(bad & 2);
+    if ((threadIdx.x & 63) == 0 && (any1 | any2)) atomicOr(flags, (any1 ? 1 : 0) | (any2 ? 2 : 0));
+}
+
+hipError_t validate_n(CoordsN c, const double *vals, int64_t nnz, int32_t *flags, hipStream_t s) {
+    TK_HIP(fill_i32(flags, 1, 0, s));
+    if (nnz == 0) return hipSuccess;
+    k_validate_n<<<grid_for(nnz), 256, 0, s>>>(c, vals, nnz, flags);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
+__global__ void k_heads_n(CoordsN c, const int32_t *perm, int64_t nnz, int32_t *heads) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * blockDim.x) {
+        int32_t h = 1;
+        if (q > 0) {
+            const int32_t p = perm[q], r = perm[q - 1];
+            h = 0;
+            for (int k = 0; k < c.n; ++k) h |= c.i[k][p] != c.i[k][r];
+        }
+        heads[q] = h;
+    }
+}
+
+__global__ void k_dedup_write_n(CoordsN c, const double *vals, const int32_t *perm, const int32_t *heads,
+                                const int32_t *pos, int64_t nnz, CoordsOut out, double *cval) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * blockDim.x) {
+        if (!heads[q]) continue;
+        const int32_t p = perm[q];
+        double sum = vals[p];
+        for (int64_t r = q + 1; r < nnz && !heads[r]; ++r) sum += vals[perm[r]];
+        const int32_t u = pos[q];
+        for (int k = 0; k < c.n; ++k) out.i[k][u] = c.i[k][p];
+        cval[u] = sum;
+    }
+}
+
+hipError_t dedup_n(CoordsN c, const double *vals, int64_t nnz, const int32_t *perm, int32_t *heads, int32_t *pos,
+                   int32_t *scan_scratch, CoordsOut out, double *cval, int32_t *nu_dev, hipStream_t s) {
+    if (nnz == 0) return fill_i32(nu_dev, 1, 0, s);
+    k_heads_n<<<grid_for(nnz), 256, 0, s>>>(c, perm, nnz, heads);
+    TK_LAUNCHED();
+    TK_HIP(scan_exclusive(heads, pos, nnz, scan_scratch, s));
+    k_dedup_write_n<<<grid_for(nnz), 256, 0, s>>>(c, vals, perm, heads, pos, nnz, out, cval);
     TK_LAUNCHED();
     k_copy_i32<<<1, 1, 0, s>>>(pos + nnz, nu_dev);
     TK_LAUNCHED();
@@ -477,7 +553,13 @@ __global__ void k_symmetrize(double *H, int64_t n) {
 hipError_t hosvd_gram(int n, const int64_t dims[3], const int32_t *ptr_n, const int32_t *lidx_n,
                       const double *lval_n, const int32_t *ptr_s, const int32_t *lidx_s, const double *lval_s,
                       double *H, hipStream_t s) {
-    const int32_t In = (int32_t)dims[n], In1 = (int32_t)dims[(n + 1) % 3], In2 = (int32_t)dims[(n + 2) % 3];
+    return hosvd_gram_sized((int32_t)dims[n], (int32_t)dims[(n + 1) % 3], (int32_t)dims[(n + 2) % 3], ptr_n, lidx_n,
+                            lval_n, ptr_s, lidx_s, lval_s, H, s);
+}
+
+hipError_t hosvd_gram_sized(int32_t In, int32_t In1, int32_t In2, const int32_t *ptr_n, const int32_t *lidx_n,
+                            const double *lval_n, const int32_t *ptr_s, const int32_t *lidx_s, const double *lval_s,
+                            double *H, hipStream_t s) {
     size_t lds = sizeof(double) * (size_t)In;
     k_hosvd_gram<<<In, 64, lds, s>>>(In, In1, In2, ptr_n, lidx_n, lval_n, ptr_s, lidx_s, lval_s, H);
     TK_LAUNCHED();

@@ -82,7 +82,7 @@ def test_invalid_arguments_rejected_on_host(case):
     dims, J, order, nnz, null_idx, algo = (10, 9, 8), (3, 3, 3), 3, 5, False, tk.ALGO_MP
     o = tk.default_opts()
     if case == "order":
-        order = 4
+        order = 5
     elif case == "neg_nnz":
         nnz = -1
     elif case == "J_gt_I":
@@ -410,3 +410,55 @@ def test_fit_static_rejects_before_device_work():
     # a small problem fits the static scratch
     st, need = _ws(c, (3, 3, 3), algo=tk.ALGO_FIT)
     assert st == 0 and need <= tk.STATIC_SCRATCH_BYTES
+
+
+def _coo4(dims=(10, 9, 8, 7), nnz=5):
+    c = tk.tk_coo()
+    c.order = 4
+    c.nnz = nnz
+    d = (ctypes.c_int64 * 4)(*dims)
+    c.dims = d
+    for n in range(4):
+        c.idx[n] = 0x1000
+    c.vals = 0x2000
+    return c, d
+
+
+def test_fourth_order_options_checked_on_host():
+    """Order 4 is accepted by HOOI, MP and HO-SVD (workspace query) and
+    rejected by SP and the general fit; within MP and HOOI the options the
+    fourth-order path does not offer are rejected before any device work."""
+    c, d = _coo4()
+    J = (ctypes.c_int32 * 4)(3, 3, 2, 2)
+    out = ctypes.c_size_t(0)
+    L = tk.lib()
+    for algo in (tk.ALGO_HOOI, tk.ALGO_MP, tk.ALGO_HOSVD):
+        o = tk.default_opts()
+        assert L.tucker_workspace_bytes(algo, ctypes.byref(c), J, ctypes.byref(o), ctypes.byref(out)) == 0
+        assert out.value > 0
+    for algo in (tk.ALGO_SP, tk.ALGO_FIT):
+        o = tk.default_opts()
+        assert L.tucker_workspace_bytes(algo, ctypes.byref(c), J, ctypes.byref(o), ctypes.byref(out)) == tk.TK_ERR_ARG
+    bad = []
+    for field, value in (("precision", tk.MIXED_BF16X3), ("init", tk.INIT_LEARNED), ("init", tk.INIT_RANDOM),
+                         ("max_iters", 0), ("hosvd_fit", 1)):
+        o = tk.default_opts()
+        setattr(o, field, value)
+        bad.append(L.tucker_workspace_bytes(tk.ALGO_MP, ctypes.byref(c), J, ctypes.byref(o), ctypes.byref(out)))
+    assert all(b == tk.TK_ERR_ARG for b in bad), bad
+    # J > I, J > 128, slots beyond 32 bits
+    o = tk.default_opts()
+    Jbad = (ctypes.c_int32 * 4)(3, 3, 9, 2)
+    assert L.tucker_workspace_bytes(tk.ALGO_MP, ctypes.byref(c), Jbad, ctypes.byref(o), ctypes.byref(out)) == \
+        tk.TK_ERR_ARG
+    cb, db = _coo4(dims=(2000, 2000, 1000, 10))
+    assert L.tucker_workspace_bytes(tk.ALGO_MP, ctypes.byref(cb), J, ctypes.byref(o), ctypes.byref(out)) == \
+        tk.TK_ERR_ARG
+    # the drivers reject before device work too (null core)
+    facs = (ctypes.c_void_p * 4)(0x10, 0x20, 0x30, 0x40)
+    hist = (ctypes.c_double * 50)()
+    done = ctypes.c_int32(0)
+    assert L.tucker_mp(ctypes.byref(c), J, ctypes.byref(o), None, facs, hist, ctypes.byref(done), None, 0x50,
+                       1 << 30, None) == tk.TK_ERR_ARG
+    assert L.tucker_hooi(ctypes.byref(c), J, ctypes.byref(o), 0x40, facs, hist, ctypes.byref(done), None, 0x50, 16,
+                         None) == tk.TK_ERR_WORKSPACE
