@@ -5,8 +5,11 @@
 // the first stage of the HOOI tensor-times-matrix chain (Figure 3: U, V, W).
 //
 // Output layout: T[slot][r] with slot = i_hi * I_lo + i_lo (the two other
-// modes), r < ldT contiguous; r in [J, ldT) is zero padding; every element
-// is written exactly once, empty fibres as zeros.
+// modes; the other three for a fourth-order tensor), r < ldT contiguous; r in
+// [J, ldT) is zero padding. The slot form writes every element exactly once,
+// empty fibres as zeros; the fibre-list form (the sweeps of MP and SP) walks
+// only the non-empty fibres and writes only their rows, into a buffer whose
+// other rows were zeroed once.
 //
 // The kernel is bound by HBM writes of T. A workgroup owns a contiguous run
 // of slots (about 32768 output elements). It first stages the run's slot
@@ -243,7 +246,25 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
     const __amdgpu_buffer_rsrc_t orr = buf_rsrc(T + row0 * ldT, outb);
     const __amdgpu_buffer_rsrc_t ri = buf_rsrc(lidx + q0, (uint32_t)nq * 4u);
     const __amdgpu_buffer_rsrc_t rv = buf_rsrc(lval + q0, (uint32_t)nq * (uint32_t)sizeof(TV));
-    for (int sl = tsl; sl < ns; sl += spi) {
+    // the output chunk of unit sl (slot or fibre)
+    auto store = [&](int sl, const Acc *acc) {
+        const int orow = FIB ? (int)(sfib[sl] - row0) : sl;
+        const uint32_t off = (uint32_t)(orow * cps + r) * 16u;
+        typename Vec16<TO>::type o;
+#pragma unroll
+        for (int t = 0; t < V; ++t) o[t] = (TO)acc[t];
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, o), orr, off, 0, 0);
+        if (SPLIT) {
+            typename Vec16<TO>::type o2;
+#pragma unroll
+            for (int t = 0; t < V; ++t) o2[t] = (TO)(acc[t] - (Acc)o[t]);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, o2), buf_rsrc(Tlo + row0 * ldT, outb), off,
+                                                   0, 0);
+        }
+    };
+    // one unit of the run, with any of its nonzeros read from global memory
+    // when they lie beyond the staged ones
+    auto one = [&](int sl) {
         int a = 0, b = 0;
         if (col_on) {
             a = sptr[sl] - q0;
@@ -274,20 +295,9 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
                 fma_row<TF, NL, Acc, false>(x, (Acc)e2.v, acc);
             }
         }
-        const int orow = FIB ? (int)(sfib[sl] - row0) : sl;
-        const uint32_t off = (uint32_t)(orow * cps + r) * 16u;
-        typename Vec16<TO>::type o;
-#pragma unroll
-        for (int t = 0; t < V; ++t) o[t] = (TO)acc[t];
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, o), orr, off, 0, 0);
-        if (SPLIT) {
-            typename Vec16<TO>::type o2;
-#pragma unroll
-            for (int t = 0; t < V; ++t) o2[t] = (TO)(acc[t] - (Acc)o[t]);
-            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, o2), buf_rsrc(Tlo + row0 * ldT, outb), off,
-                                                   0, 0);
-        }
-    }
+        store(sl, acc);
+    };
+    for (int sl = tsl; sl < ns; sl += spi) one(sl);
 }
 
 template <class TO>
