@@ -502,6 +502,7 @@ def main():
                     "stored oracle reference")
     ap.add_argument("--no-c5", action="store_true", help="skip the learned-start leg at 4000^3 / 10M nonzeros")
     ap.add_argument("--no-order4", action="store_true", help="skip the fourth-order leg (100^4)")
+    ap.add_argument("--no-stream", action="store_true", help="skip the host-streamed MP leg")
     ap.add_argument("--c5-leg", action="store_true", help="internal: run the 4000^3 learned-start leg, print one "
                     "JSON line")
     ap.add_argument("--copy-calib", action="store_true",
@@ -692,6 +693,10 @@ def main():
     if not args.no_unbal:
         line["unbalanced"] = unbalanced_leg(tk, dev, args.sweeps)
 
+    if not args.no_stream and args.algo == "mp":
+        line["streamed"] = streamed_leg(tk, dev, idx, vals, dims, J, args.sweeps,
+                                        st["sweeps_ms"] / max(1, sweeps))
+
     if not args.no_order4:
         line["fourth_order"] = fourth_order_leg(tk, dev)
 
@@ -759,6 +764,32 @@ def fourth_order_leg(tk, dev):
             out[f"{algo}_{prec}"] = e
             log(f"fourth order {algo} {prec}: {e}")
     out["nnz"] = int(nnz)
+    return out
+
+
+def streamed_leg(tk, dev, idx, vals, dims, J, sweeps, incore_ms_per_sweep):
+    """MP of the benchmark tensor held in host memory and streamed through two
+    64 MiB device slab buffers (tucker_mp_streamed), mixed precision, same
+    sweep count, from the random start: host preparation (the six sorted
+    orderings), time per sweep against the in-core sweep, bytes uploaded per
+    sweep and the upload rate they imply."""
+    import torch
+    slab = 64 << 20
+    tk.mp_streamed(idx, vals, dims, J, slab, precision="mixed", max_iters=1, tol=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = tk.mp_streamed(idx, vals, dims, J, slab, precision="mixed", max_iters=sweeps, tol=0.0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = r.stats["sweeps_ms"] / max(1, r.iters)
+    out = {"slab_bytes": slab, "sweeps": r.iters, "wall_ms": round(1000 * wall, 1),
+           "host_prep_ms": round(r.stats["prep_ms"], 1), "ms_per_sweep": round(per, 3),
+           "incore_ms_per_sweep": round(incore_ms_per_sweep, 3),
+           "bytes_per_sweep": int(r.stats["streamed_bytes"] / max(1, r.iters)),
+           "slabs_per_sweep": round(r.stats["streamed_slabs"] / max(1, r.iters), 1),
+           "upload_gb_per_s": round(r.stats["streamed_bytes"] / (r.stats["sweeps_ms"] / 1000.0) / 1e9, 2),
+           "fit": r.fits[-1]}
+    log(f"streamed: {out}")
     return out
 
 

@@ -226,6 +226,8 @@ typedef struct tk_stats {
     double  core_norm;      /* ||G||_F of the returned core */
     double  ttmc_sweep_ms[64]; /* opts.timing = 1: the TTMc phase's time in sweep t
                                (t < 64; its share of ttmc_ms), 0 beyond */
+    int64_t streamed_bytes; /* tucker_mp_streamed: bytes uploaded from host memory */
+    int64_t streamed_slabs; /* tucker_mp_streamed: slabs uploaded */
 } tk_stats;
 
 /* Fill *opt with: FP32, HO-SVD init, 50 sweeps, tol 1e-4, eig cap 400

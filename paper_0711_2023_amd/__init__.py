@@ -15,7 +15,7 @@ from dataclasses import dataclass
 __all__ = [
     "TuckerError", "lib", "hooi", "mp", "sp", "hosvd", "fit", "workspace_bytes", "default_opts",
     "FP64", "FP32", "MIXED_BF16", "MIXED_BF16X3", "INIT_HOSVD", "INIT_GIVEN", "INIT_LEARNED", "INIT_RANDOM",
-    "Result", "LIB_PATH", "fit_static", "SYMBOLS", "lead_eig", "learn_param_count", "learn_sketch", "learn_forward",
+    "Result", "LIB_PATH", "fit_static", "mp_streamed", "SYMBOLS", "lead_eig", "learn_param_count", "learn_sketch", "learn_forward",
     "learn_backward", "learn_align", "learn_adam", "learn_test_width", "batched",
 ]
 
@@ -39,7 +39,7 @@ SYMBOLS = ["tucker_default_opts", "tucker_workspace_bytes", "tucker_hooi", "tuck
            "tucker_learn_param_count", "tucker_learn_sketch_workspace", "tucker_learn_sketch",
            "tucker_learn_forward", "tucker_learn_backward_workspace", "tucker_learn_backward",
            "tucker_learn_test_width", "tucker_learn_align_workspace", "tucker_learn_align", "tucker_learn_adam",
-           "tucker_batched_workspace_bytes", "tucker_batched"]
+           "tucker_batched_workspace_bytes", "tucker_batched", "tucker_mp_streamed_workspace", "tucker_mp_streamed"]
 
 
 class tk_coo(ctypes.Structure):
@@ -96,7 +96,8 @@ class tk_stats(ctypes.Structure):
                 ("core_ms", ctypes.c_double),
                 ("nnz_unique", ctypes.c_int64), ("eig_iters", ctypes.c_int32), ("eig_noconv", ctypes.c_int32),
                 ("norm_x", ctypes.c_double), ("init_fallbacks", ctypes.c_int32), ("hosvd_fit", ctypes.c_double),
-                ("core_norm", ctypes.c_double), ("ttmc_sweep_ms", ctypes.c_double * 64)]
+                ("core_norm", ctypes.c_double), ("ttmc_sweep_ms", ctypes.c_double * 64),
+                ("streamed_bytes", ctypes.c_int64), ("streamed_slabs", ctypes.c_int64)]
 
 
 class TuckerError(RuntimeError):
@@ -160,8 +161,12 @@ def lib():
         L.tucker_batched_workspace_bytes.argtypes = [i32, i32, P(tk_coo), P(i32), P(tk_opts), P(tk_tune), P(sz)]
         L.tucker_batched.argtypes = [i32, i32, P(tk_coo), P(i32), P(tk_opts), P(vp), P(vp), P(ctypes.c_double),
                                      P(i32), P(i32), P(tk_stats), P(tk_tune), i32, P(vp), sz, P(vp)]
+        L.tucker_mp_streamed_workspace.argtypes = [P(tk_coo), P(i32), P(tk_opts), sz, P(sz)]
+        L.tucker_mp_streamed.argtypes = [P(tk_coo), P(i32), P(tk_opts), sz, vp, P(vp), P(ctypes.c_double), P(i32),
+                                         P(tk_stats), vp, sz, vp]
         for name in SYMBOLS:
-            if name.startswith("tucker_learn") or name.startswith("tucker_batched"):
+            if name.startswith("tucker_learn") or name.startswith("tucker_batched") or \
+                    name.startswith("tucker_mp_streamed"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -412,6 +417,57 @@ def fit_static(idx, vals, dims, core, factors, stream=None) -> float:
     _check(lib().tucker_fit_static(ctypes.byref(coo.c), Jc, G.data_ptr(), fptrs, ctypes.byref(out),
                                    ctypes.c_void_p(s.cuda_stream)))
     return float(out.value)
+
+
+class _HostCoo:
+    """A tk_coo over host arrays (the streamed entry point reads them there)."""
+
+    def __init__(self, idx, vals, dims):
+        import numpy as np
+        self.idx = [np.ascontiguousarray(idx[n], dtype=np.int32) for n in range(3)]
+        self.vals = np.ascontiguousarray(vals, dtype=np.float64)
+        self.dims = (ctypes.c_int64 * 3)(*[int(d) for d in dims])
+        self.c = tk_coo()
+        self.c.order = 3
+        self.c.nnz = int(self.vals.size)
+        self.c.dims = self.dims
+        for n in range(3):
+            self.c.idx[n] = self.idx[n].ctypes.data
+        self.c.vals = self.vals.ctypes.data
+
+
+def mp_streamed(idx, vals, dims, core_dims, slab_bytes, precision="fp32", init=INIT_RANDOM, max_iters=50, tol=1e-4,
+                eig_max_iters=None, eig_tol=None, seed=None, factors=None, workspace=None, stream=None,
+                device="cuda") -> Result:
+    """MP of a tensor in HOST memory (numpy int32 [3, nnz] and float64 [nnz]),
+    streamed through two device slab buffers of slab_bytes each. Results on
+    the device as for ``mp``."""
+    import torch
+    dev = torch.device(device)
+    coo = _HostCoo(idx, vals, dims)
+    o = _opts(precision, init, max_iters, tol, eig_max_iters, eig_tol, False, None, seed)
+    J = [int(j) for j in core_dims]
+    Jc = (ctypes.c_int32 * 3)(*J)
+    need = ctypes.c_size_t(0)
+    _check(lib().tucker_mp_streamed_workspace(ctypes.byref(coo.c), Jc, ctypes.byref(o), int(slab_bytes),
+                                              ctypes.byref(need)))
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
+    G = torch.empty(J, dtype=torch.float64, device=dev)
+    if factors is None:
+        facs = [torch.empty((int(dims[n]), J[n]), dtype=torch.float64, device=dev) for n in range(3)]
+    else:
+        facs = [f.to(device=dev, dtype=torch.float64).contiguous().clone() for f in factors]
+    fptrs = (ctypes.c_void_p * 3)(*[f.data_ptr() for f in facs])
+    hist = (ctypes.c_double * max(1, int(max_iters)))()
+    done = ctypes.c_int32(0)
+    st = tk_stats()
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    status = _check(lib().tucker_mp_streamed(ctypes.byref(coo.c), Jc, ctypes.byref(o), int(slab_bytes),
+                                             G.data_ptr(), fptrs, hist, ctypes.byref(done), ctypes.byref(st),
+                                             workspace.data_ptr(), int(workspace.numel()),
+                                             ctypes.c_void_p(s.cuda_stream)))
+    return Result(G, facs, [hist[i] for i in range(done.value)], int(done.value), _stats_dict(st), status)
 
 
 # ---------------------------------------------------------------- learned start

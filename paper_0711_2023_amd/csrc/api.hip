@@ -7,6 +7,7 @@
 // Ritz values of the eigensolver's Rayleigh-Ritz steps, and one fit value
 // per sweep.
 #include "../../include/tucker.h"
+#include "../../include/tucker_stream.h"
 #include "common.h"
 #include "guards.h"
 #include "timer.h"
@@ -21,6 +22,8 @@
 namespace tk {
 
 static thread_local char g_err[320];
+
+void g_err_clear() { g_err[0] = 0; }
 
 void set_hip_error(hipError_t e, const char *where) {
     if (g_err[0]) return;
@@ -952,9 +955,14 @@ __global__ void __launch_bounds__(256) k_normalise_cols(double *F, int64_t I, in
     for (int64_t i = threadIdx.x; i < I; i += blockDim.x) F[i * J + r] *= inv;
 }
 
+hipError_t random_start_fill(double *F, int64_t I, int J, int n, uint64_t seed, hipStream_t s) {
+    k_random_start<<<J, 256, 0, s>>>(F, I, J, n, seed);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
 static int random_mode(Plan &p, int n, double *F, uint64_t seed, hipStream_t s) {
-    k_random_start<<<p.J[n], 256, 0, s>>>(F, p.I[n], p.J[n], n, seed);
-    ST(hipGetLastError());
+    ST(random_start_fill(F, p.I[n], p.J[n], n, seed, s));
     ST(refresh_copies(p, n, F, s));
     return TK_OK;
 }
@@ -1836,4 +1844,17 @@ extern "C" int tucker_batched(int32_t algo, int32_t count, const tk_coo *X, cons
         if (status[t] > 0) worst = status[t];
     }
     return worst;
+}
+
+extern "C" int tucker_mp_streamed_workspace(const tk_coo *X, const int32_t *core_dims, const tk_opts *opt,
+                                            size_t slab_bytes, size_t *bytes) {
+    return tk::mp_streamed_workspace(X, core_dims, opt, slab_bytes, bytes);
+}
+
+extern "C" int tucker_mp_streamed(const tk_coo *X, const int32_t *core_dims, const tk_opts *opt, size_t slab_bytes,
+                                  double *core, double *const *factors, double *fit_history, int32_t *iters_done,
+                                  tk_stats *stats, void *workspace, size_t workspace_bytes, void *stream) {
+    tk::g_err_clear();
+    return tk::mp_streamed(X, core_dims, opt, slab_bytes, core, factors, fit_history, iters_done, stats, workspace,
+                           workspace_bytes, stream);
 }

@@ -23,6 +23,8 @@ enum Prec { P64 = 0, P32 = 1, PBF16 = 2 };
 // Records the first failing HIP call of the current thread; returned as text
 // by tucker_strerror(TK_ERR_DEVICE).
 void set_hip_error(hipError_t e, const char *where);
+// Forget the calling thread's recorded HIP error (at the start of a call).
+void g_err_clear();
 
 #define TK_HIP(call)                                   \
     do {                                               \
@@ -303,6 +305,18 @@ int learn_test_width(int J);
 hipError_t learn_start(const float *R, int64_t rows, int J, const double *H, double *F, double *theta, double *gC,
                        double *Q, double *HQ, double *C, double *V, void *eigw, double *part, int64_t part_elems,
                        hipStream_t s);
+
+// ---------------------------------------------------------------- api.hip
+// The random start of TK_INIT_RANDOM: F (I x J) with entries uniform on
+// [0, 1) from SplitMix64 output n * 2^40 + i * J + r, columns normalised.
+hipError_t random_start_fill(double *F, int64_t I, int J, int n, uint64_t seed, hipStream_t s);
+
+// ---------------------------------------------------------------- stream.hip
+// Multislice Projection streamed from host memory (tucker_mp_streamed).
+int mp_streamed_workspace(const tk_coo *X, const int32_t *J, const tk_opts *o, size_t slab_bytes, size_t *bytes);
+int mp_streamed(const tk_coo *X, const int32_t *J, const tk_opts *o, size_t slab_bytes, double *core,
+                double *const *F, double *hist, int32_t *iters_done, tk_stats *stats, void *ws, size_t wsb,
+                void *stream);
 
 // ---------------------------------------------------------------- order_n.hip
 // Fourth-order HO-SVD, HOOI and MP behind tucker_hosvd, tucker_hooi and

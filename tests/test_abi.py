@@ -462,3 +462,48 @@ def test_fourth_order_options_checked_on_host():
                        1 << 30, None) == tk.TK_ERR_ARG
     assert L.tucker_hooi(ctypes.byref(c), J, ctypes.byref(o), 0x40, facs, hist, ctypes.byref(done), None, 0x50, 16,
                          None) == tk.TK_ERR_WORKSPACE
+
+
+def test_streamed_mp_checks_on_host():
+    """The streamed MP reads host arrays: its arguments, slab size and the
+    data's index and value checks all run on the host, before device work."""
+    import numpy as np
+    L = tk.lib()
+    idx = np.array([[0, 1, 2, 3], [0, 1, 2, 0], [1, 1, 1, 1]], dtype=np.int32)
+    vals = np.array([1.0, 2.0, 3.0, 4.0])
+    coo = tk._HostCoo(idx, vals, (4, 3, 2))
+    J = (ctypes.c_int32 * 3)(2, 2, 1)
+    o = tk._opts("fp64", init=tk.INIT_RANDOM)
+    out = ctypes.c_size_t(0)
+    assert L.tucker_mp_streamed_workspace(ctypes.byref(coo.c), J, ctypes.byref(o), 1 << 16, ctypes.byref(out)) == 0
+    ws_small = out.value
+    assert L.tucker_mp_streamed_workspace(ctypes.byref(coo.c), J, ctypes.byref(o), 1 << 20, ctypes.byref(out)) == 0
+    assert out.value > ws_small
+    # a slab that cannot hold one slice of a projection (400 rows of 16 bytes
+    # against the smallest slab of 256 bytes)
+    wide = tk._HostCoo(idx, vals, (400, 3, 2))
+    assert L.tucker_mp_streamed_workspace(ctypes.byref(wide.c), J, ctypes.byref(o), 8, ctypes.byref(out)) == \
+        tk.TK_ERR_ARG
+    for field, value in (("init", tk.INIT_HOSVD), ("precision", tk.MIXED_BF16X3), ("max_iters", 0)):
+        ob = tk._opts("fp64", init=tk.INIT_RANDOM)
+        setattr(ob, field, value)
+        assert L.tucker_mp_streamed_workspace(ctypes.byref(coo.c), J, ctypes.byref(ob), 1 << 16,
+                                              ctypes.byref(out)) == tk.TK_ERR_ARG
+    facs = (ctypes.c_void_p * 3)(0x10, 0x20, 0x30)
+    hist = (ctypes.c_double * 50)()
+    done = ctypes.c_int32(0)
+    assert L.tucker_mp_streamed_workspace(ctypes.byref(coo.c), J, ctypes.byref(o), 1 << 16, ctypes.byref(out)) == 0
+    need = out.value
+    # workspace too small, then index and value errors found on the host
+    assert L.tucker_mp_streamed(ctypes.byref(coo.c), J, ctypes.byref(o), 1 << 16, 0x40, facs, hist,
+                                ctypes.byref(done), None, 0x50, 16, None) == tk.TK_ERR_WORKSPACE
+    bad = idx.copy()
+    bad[1, 2] = 7
+    cb = tk._HostCoo(bad, vals, (4, 3, 2))
+    assert L.tucker_mp_streamed(ctypes.byref(cb.c), J, ctypes.byref(o), 1 << 16, 0x40, facs, hist,
+                                ctypes.byref(done), None, 0x50, need, None) == tk.TK_ERR_INDEX
+    vb = vals.copy()
+    vb[3] = np.nan
+    cv = tk._HostCoo(idx, vb, (4, 3, 2))
+    assert L.tucker_mp_streamed(ctypes.byref(cv.c), J, ctypes.byref(o), 1 << 16, 0x40, facs, hist,
+                                ctypes.byref(done), None, 0x50, need, None) == tk.TK_ERR_VALUE
