@@ -15,7 +15,7 @@ from dataclasses import dataclass
 __all__ = [
     "TuckerError", "lib", "hooi", "mp", "sp", "hosvd", "fit", "workspace_bytes", "default_opts",
     "FP64", "FP32", "MIXED_BF16", "MIXED_BF16X3", "INIT_HOSVD", "INIT_GIVEN", "INIT_LEARNED", "INIT_RANDOM",
-    "Result", "LIB_PATH", "fit_static", "mp_streamed", "SYMBOLS", "lead_eig", "learn_param_count", "learn_sketch", "learn_forward",
+    "Result", "LIB_PATH", "fit_static", "mp_streamed", "mp_implicit", "SYMBOLS", "lead_eig", "learn_param_count", "learn_sketch", "learn_forward",
     "learn_backward", "learn_align", "learn_adam", "learn_test_width", "batched",
 ]
 
@@ -39,7 +39,8 @@ SYMBOLS = ["tucker_default_opts", "tucker_workspace_bytes", "tucker_hooi", "tuck
            "tucker_learn_param_count", "tucker_learn_sketch_workspace", "tucker_learn_sketch",
            "tucker_learn_forward", "tucker_learn_backward_workspace", "tucker_learn_backward",
            "tucker_learn_test_width", "tucker_learn_align_workspace", "tucker_learn_align", "tucker_learn_adam",
-           "tucker_batched_workspace_bytes", "tucker_batched", "tucker_mp_streamed_workspace", "tucker_mp_streamed"]
+           "tucker_batched_workspace_bytes", "tucker_batched", "tucker_mp_streamed_workspace", "tucker_mp_streamed",
+           "tucker_mp_implicit_workspace", "tucker_mp_implicit"]
 
 
 class tk_coo(ctypes.Structure):
@@ -164,9 +165,12 @@ def lib():
         L.tucker_mp_streamed_workspace.argtypes = [P(tk_coo), P(i32), P(tk_opts), sz, P(sz)]
         L.tucker_mp_streamed.argtypes = [P(tk_coo), P(i32), P(tk_opts), sz, vp, P(vp), P(ctypes.c_double), P(i32),
                                          P(tk_stats), vp, sz, vp]
+        L.tucker_mp_implicit_workspace.argtypes = [P(tk_coo), P(i32), P(tk_opts), P(sz)]
+        L.tucker_mp_implicit.argtypes = [P(tk_coo), P(i32), P(tk_opts), vp, P(vp), P(ctypes.c_double), P(i32),
+                                         P(tk_stats), vp, sz, vp]
         for name in SYMBOLS:
             if name.startswith("tucker_learn") or name.startswith("tucker_batched") or \
-                    name.startswith("tucker_mp_streamed"):
+                    name.startswith("tucker_mp_streamed") or name.startswith("tucker_mp_implicit"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -262,7 +266,7 @@ def _stats_dict(s: tk_stats) -> dict:
 
 def _run(fn_name: str, algo: int, idx, vals, dims, core_dims, *, precision="fp32", init=INIT_HOSVD,
          max_iters=50, tol=1e-4, eig_max_iters=None, eig_tol=None, timing=False, factors=None, workspace=None,
-         stream=None, model=None, seed=None, tune=None, hosvd_fit=False, trace=0) -> Result:
+         stream=None, model=None, seed=None, tune=None, hosvd_fit=False, trace=0, ws_query=None) -> Result:
     """`model`: float32 tensor of learn_param_count() parameters on the GPU,
     used with init=INIT_LEARNED. `tune`: launch choices (see make_tune).
     `trace`: room for that many per-launch events (0 = no trace); they are
@@ -285,7 +289,10 @@ def _run(fn_name: str, algo: int, idx, vals, dims, core_dims, *, precision="fp32
     N = len(J)
     Jc = (ctypes.c_int32 * N)(*J)
     need = ctypes.c_size_t(0)
-    _check(lib().tucker_workspace_bytes(algo, ctypes.byref(coo.c), Jc, ctypes.byref(o), ctypes.byref(need)))
+    if ws_query is None:
+        _check(lib().tucker_workspace_bytes(algo, ctypes.byref(coo.c), Jc, ctypes.byref(o), ctypes.byref(need)))
+    else:
+        _check(getattr(lib(), ws_query)(ctypes.byref(coo.c), Jc, ctypes.byref(o), ctypes.byref(need)))
     if workspace is None or workspace.numel() < need.value:
         workspace = torch.empty(int(need.value), dtype=torch.uint8, device=dev)
     G = torch.empty(J, dtype=torch.float64, device=dev)
@@ -320,6 +327,17 @@ def mp(idx, vals, dims, core_dims, **kw) -> Result:
     """Multislice Projection (Figure 7; Figure 8 for a fourth-order tensor).
     Same arguments as ``hooi``."""
     return _run("tucker_mp", ALGO_MP, idx, vals, dims, core_dims, **kw)
+
+
+def mp_implicit(idx, vals, dims, core_dims, **kw) -> Result:
+    """Multislice Projection through implicit Gram products over the
+    non-empty fibres (tucker_mp_implicit): the decomposition of ``mp`` for
+    tensors much sparser than the squares of their mode sizes. Same
+    arguments as ``mp``; starts INIT_RANDOM (the default here) or
+    INIT_GIVEN."""
+    kw.setdefault("init", INIT_RANDOM)
+    return _run("tucker_mp_implicit", ALGO_MP, idx, vals, dims, core_dims, ws_query="tucker_mp_implicit_workspace",
+                **kw)
 
 
 def sp(idx, vals, dims, core_dims, **kw) -> Result:

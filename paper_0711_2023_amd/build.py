@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtucker.so")
-SOURCES = ["prep.hip", "project.hip", "mfma.hip", "eig.hip", "learn.hip", "api.hip", "noalloc.hip", "order_n.hip", "stream.hip"]
+SOURCES = ["prep.hip", "project.hip", "mfma.hip", "eig.hip", "learn.hip", "api.hip", "noalloc.hip", "order_n.hip", "stream.hip", "implicit.hip"]
 ARCH = os.environ.get("TUCKER_OFFLOAD_ARCH", "gfx950")
 
 

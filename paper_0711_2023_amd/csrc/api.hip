@@ -8,6 +8,7 @@
 // per sweep.
 #include "../../include/tucker.h"
 #include "../../include/tucker_stream.h"
+#include "../../include/tucker_implicit.h"
 #include "common.h"
 #include "guards.h"
 #include "timer.h"
@@ -1856,5 +1857,18 @@ extern "C" int tucker_mp_streamed(const tk_coo *X, const int32_t *core_dims, con
                                   tk_stats *stats, void *workspace, size_t workspace_bytes, void *stream) {
     tk::g_err_clear();
     return tk::mp_streamed(X, core_dims, opt, slab_bytes, core, factors, fit_history, iters_done, stats, workspace,
+                           workspace_bytes, stream);
+}
+
+extern "C" int tucker_mp_implicit_workspace(const tk_coo *X, const int32_t *core_dims, const tk_opts *opt,
+                                            size_t *bytes) {
+    return tk::mp_implicit_workspace(X, core_dims, opt, bytes);
+}
+
+extern "C" int tucker_mp_implicit(const tk_coo *X, const int32_t *core_dims, const tk_opts *opt, double *core,
+                                  double *const *factors, double *fit_history, int32_t *iters_done, tk_stats *stats,
+                                  void *workspace, size_t workspace_bytes, void *stream) {
+    tk::g_err_clear();
+    return tk::mp_implicit(X, core_dims, opt, core, factors, fit_history, iters_done, stats, workspace,
                            workspace_bytes, stream);
 }

@@ -249,7 +249,15 @@ int eig_block_width(int n, int J);
 // and the converged block on exit. F receives the J leading eigenvectors
 // (n x J row-major, sign-canonical); theta (device, b) the Ritz values.
 // Returns 0 or a hip error; *iters / *noconv report convergence.
+// The matrix of a solve given as an operator instead of explicitly: apply
+// writes Y (n x w, row stride ldy) = A X for X (n x w, row stride ldx), A
+// symmetric PSD, on stream s. Solves with n <= 140 need A explicitly.
+struct EigOp {
+    hipError_t (*apply)(const void *ctx, const double *X, int64_t ldx, int w, double *Y, int64_t ldy, hipStream_t s);
+    const void *ctx;
+};
 struct EigOpts {
+    const EigOp *op = nullptr;  // set: M is not read (may be null), products go through op
     int max_iters = 400;
     double tol = 1e-10;
     int degree = 60;
@@ -317,6 +325,12 @@ int mp_streamed_workspace(const tk_coo *X, const int32_t *J, const tk_opts *o, s
 int mp_streamed(const tk_coo *X, const int32_t *J, const tk_opts *o, size_t slab_bytes, double *core,
                 double *const *F, double *hist, int32_t *iters_done, tk_stats *stats, void *ws, size_t wsb,
                 void *stream);
+
+// ---------------------------------------------------------------- implicit.hip
+// Multislice Projection through implicit Gram products (tucker_mp_implicit).
+int mp_implicit_workspace(const tk_coo *X, const int32_t *J, const tk_opts *o, size_t *bytes);
+int mp_implicit(const tk_coo *X, const int32_t *J, const tk_opts *o, double *core, double *const *F, double *hist,
+                int32_t *iters_done, tk_stats *stats, void *ws, size_t wsb, void *stream);
 
 // ---------------------------------------------------------------- order_n.hip
 // Fourth-order HO-SVD, HOOI and MP behind tucker_hosvd, tucker_hooi and

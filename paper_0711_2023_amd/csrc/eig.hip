@@ -852,6 +852,7 @@ static hipError_t skinny(SkinnyArgs g, double *part, int64_t part_elems, hipStre
 // ------------------------------------------------------------------ workspace
 struct EigLayout {
     double *W, *Y0, *Y1, *Y2, *S, *V, *Vg, *Rinv, *theta, *res, *norms, *split, *thall;
+    double *Yop, *Cop, *thl;  // operator solves: A X, locked-part coefficients, locked Ritz values
     int *colmap;
     int64_t split_elems;
 };
@@ -871,6 +872,9 @@ static EigLayout eig_layout(Arena &ar, int n, int b) {
     L.norms = ar.take<double>(b);
     L.thall = ar.take<double>(b);
     L.colmap = ar.take<int>(b);
+    L.Yop = ar.take<double>(nb);
+    L.Cop = ar.take<double>((int64_t)b * b);
+    L.thl = ar.take<double>(b);
     // split-K partial strips: (strips x K ranges) <= 512 for every product
     // (see skinny_split), each 16 rows by at most b columns rounded up to 16
     L.split_elems = (int64_t)512 * 16 * (ceil_div(b, 16) * 16);
@@ -924,6 +928,63 @@ static hipError_t dgemm(int M, int N, int K, const double *A, int64_t lda, bool 
     g.part = nullptr;
     return skinny(g, split, split_elems, s);
 }
+
+// C[i][j] *= d[i] for the Lk x w matrix C.
+__global__ void k_rowscale(double *C, int rows, int w, const double *d) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < rows * w; t += gridDim.x * blockDim.x) C[t] *= d[t / w];
+}
+
+// Y = alpha (P - D) + beta E1 + gamma E2 elementwise over n x w (Y, D, E1,
+// E2 with row stride ldy, P with stride ldp; D is Y itself or absent).
+__global__ void k_comb(double *Y, int64_t ldy, const double *P, int64_t ldp, int64_t n, int w, double alpha,
+                       double beta, const double *E1, double gamma, const double *E2, int has_d) {
+    const int64_t tot = n * w;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / w;
+        const int j = (int)(t - i * w);
+        double v = P[i * ldp + j];
+        if (has_d) v -= Y[i * ldy + j];
+        v *= alpha;
+        if (E1) v += beta * E1[i * ldy + j];
+        if (E2) v += gamma * E2[i * ldy + j];
+        Y[i * ldy + j] = v;
+    }
+}
+
+// Products with the solve's matrix: Y = alpha A X + beta E1 + gamma E2,
+// from the explicit (deflated) M, or from the operator with the locked pairs
+// (columns [0, Lk) of XL, Ritz values in thl) taken out:
+// A' X = A X - XL diag(thl) XL^T X.
+struct MProd {
+    const double *M;
+    int n;
+    const EigOp *op;
+    EigLayout *L;
+    const double *XL;  // locked columns (row stride b)
+    int b;
+    hipStream_t s;
+    hipError_t operator()(const double *X, int64_t ldx, int w, double *Y, int64_t ldy, double alpha, double beta,
+                          const double *E1, double gamma, const double *E2, int Lk) const {
+        if (!op)
+            return dgemm(n, w, n, M, n, false, X, ldx, Y, ldy, alpha, beta, E1, gamma, E2, L->split, L->split_elems,
+                         s);
+        TK_HIP(op->apply(op->ctx, X, ldx, w, L->Yop, w, s));
+        if (Lk > 0) {
+            TK_HIP(dgemm(Lk, w, n, XL, b, true, X, ldx, L->Cop, w, 1.0, 0.0, nullptr, 0.0, nullptr, L->split,
+                         L->split_elems, s));
+            k_rowscale<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div((int64_t)Lk * w, 256), 1024)), 256, 0,
+                         s>>>(L->Cop, Lk, w, L->thl);
+            TK_LAUNCHED();
+            TK_HIP(dgemm(n, w, Lk, XL, b, false, L->Cop, w, Y, ldy, 1.0, 0.0, nullptr, 0.0, nullptr, L->split,
+                         L->split_elems, s));
+        }
+        k_comb<<<(unsigned)std::min<int64_t>(ceil_div((int64_t)n * w, 256), 65536), 256, 0, s>>>(
+            Y, ldy, L->Yop, w, n, w, alpha, beta, beta != 0.0 ? E1 : nullptr, gamma, gamma != 0.0 ? E2 : nullptr,
+            Lk > 0 ? 1 : 0);
+        TK_LAUNCHED();
+        return hipSuccess;
+    }
+};
 
 // Orthonormalise columns [c0, c0+w) of X (n x b, row-major) in place:
 // column scaling, one shifted CholeskyQR pass, one plain pass.
@@ -988,7 +1049,7 @@ static hipError_t orthonormalise(const double *src, double *X, int64_t n, int b,
 // Column 0 of X <- normalised M^steps x0 (products alternate between X and
 // Y0, ending in X), then theta[0] = x^T M x, the Rayleigh quotient that the
 // deflation and the output use.
-static hipError_t power_lock(const double *M, int n, int b, double *X, int steps, EigLayout &L, hipStream_t s) {
+static hipError_t power_lock(const MProd &mp, int n, int b, double *X, int steps, EigLayout &L, hipStream_t s) {
     double *src = X, *dst = L.Y0;
     if (steps & 1) {  // an odd count ends in Y0: start from a copy there
         TK_HIP(hipMemcpy2DAsync(L.Y0, sizeof(double) * b, X, sizeof(double) * b, sizeof(double), n,
@@ -997,8 +1058,7 @@ static hipError_t power_lock(const double *M, int n, int b, double *X, int steps
         dst = X;
     }
     for (int k = 0; k < steps; ++k) {
-        TK_HIP(dgemm(n, 1, n, M, n, false, src, b, dst, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
-                     s));
+        TK_HIP(mp(src, b, 1, dst, b, 1.0, 0.0, nullptr, 0.0, nullptr, 0));
         k_colnorm<<<1, 256, 0, s>>>(dst, n, b, 0, L.norms);
         TK_LAUNCHED();
         k_colscale<<<(unsigned)std::min<int64_t>(ceil_div(n, 256), 65536), 256, 0, s>>>(dst, dst, n, b, 0, 1, L.norms,
@@ -1007,7 +1067,7 @@ static hipError_t power_lock(const double *M, int n, int b, double *X, int steps
         std::swap(src, dst);
     }
     // src == X now; theta = x^T (M x)
-    TK_HIP(dgemm(n, 1, n, M, n, false, X, b, L.Y1, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
+    TK_HIP(mp(X, b, 1, L.Y1, b, 1.0, 0.0, nullptr, 0.0, nullptr, 0));
     TK_HIP(dgemm(1, 1, n, X, b, true, L.Y1, b, L.theta, 1, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems,
                  s));
     return hipSuccess;
@@ -1053,6 +1113,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
     Arena ar;
     ar.base = reinterpret_cast<char *>(work);
     EigLayout L = eig_layout(ar, n, b);
+    if (o.op && n <= kDirectMax) return hipErrorInvalidValue;  // small solves need M explicitly
     if (n <= kDirectMax) {
         TK_HIP(jacobi(M, n, n, L.theta, L.V, L.Vg, s, o.direct_sweeps));
         k_extract<<<J, 256, 0, s>>>(L.V, n, n, J, F, nullptr);
@@ -1076,7 +1137,8 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
     int deg_cap = o.warm ? std::max(1, std::min(o.warm_degree, o.degree)) : o.degree;
     bool full_step = false;  // the last filter had the full degree
     double *Xc = X;
-    double *Md = M;  // deflated in place
+    double *Md = M;  // deflated in place (an operator solve deflates in its products instead)
+    const MProd mprod{Md, n, o.op, &L, X, b, s};
     std::vector<double> tha;
     // Intermediate Rayleigh-Ritz steps use one Jacobi sweep: an approximate
     // rotation is enough to pick the leading directions of the block (it is
@@ -1099,7 +1161,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
         const int w = final_rr ? J - Lk : b - Lk;
         double *Xa = Xc + Lk, *Wa = L.W + Lk;
         // Rayleigh-Ritz on the active columns
-        TK_HIP(dgemm(n, w, n, Md, n, false, Xa, b, Wa, b, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
+        TK_HIP(mprod(Xa, b, w, Wa, b, 1.0, 0.0, nullptr, 0.0, nullptr, Lk));
         ++matvecs;
         TK_HIP(dgemm(w, w, n, Xa, b, true, Wa, b, L.S, w, 1.0, 0.0, nullptr, 0.0, nullptr, L.split, L.split_elems, s));
         TK_HIP(jacobi(L.S, w, w, L.theta, L.V, L.Vg, s, final_rr ? 30 : 1, final_off2));
@@ -1159,7 +1221,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
             res[0] > lock_tol) {
             const double rate = tha[1] / tha[0];
             const int steps = std::min(60, 2 + (int)std::ceil(std::log(lock_tol / res[0]) / std::log(rate)));
-            TK_HIP(power_lock(Md, n, b, Xc, steps, L, s));
+            TK_HIP(power_lock(mprod, n, b, Xc, steps, L, s));
             double th1 = 0.0;
             TK_HIP(hipMemcpyAsync(&th1, L.theta, sizeof(double), hipMemcpyDeviceToHost, s));
             TK_HIP(hipStreamSynchronize(s));
@@ -1168,9 +1230,13 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
             newl = 1;
         }
         if (newl > 0) {
-            k_deflate<<<(unsigned)std::min<int64_t>(ceil_div((int64_t)n * n, 256), 65536), 256, 0, s>>>(
-                Md, n, Xc, b, Lk, newl, L.theta);
-            TK_LAUNCHED();
+            if (o.op) {
+                TK_HIP(hipMemcpyAsync(L.thl + Lk, L.theta, sizeof(double) * newl, hipMemcpyDeviceToDevice, s));
+            } else {
+                k_deflate<<<(unsigned)std::min<int64_t>(ceil_div((int64_t)n * n, 256), 65536), 256, 0, s>>>(
+                    Md, n, Xc, b, Lk, newl, L.theta);
+                TK_LAUNCHED();
+            }
             for (int j = 0; j < newl; ++j) thL.push_back(tha[j]);
             Lk += newl;
         }
@@ -1183,8 +1249,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
         double *Ya = L.Y0 + Lk, *Yb = L.Y1 + Lk, *Yc = L.Y2 + Lk;
         double *cur = Ya;
         if (mu <= 0.0) {
-            TK_HIP(dgemm(n, wa, n, Md, n, false, Xf, b, Ya, b, 1.0 / std::max(top, 1e-300), 0.0, nullptr, 0.0,
-                         nullptr, L.split, L.split_elems, s));
+            TK_HIP(mprod(Xf, b, wa, Ya, b, 1.0 / std::max(top, 1e-300), 0.0, nullptr, 0.0, nullptr, Lk));
             ++matvecs;
             full_step = true;
         } else {
@@ -1197,8 +1262,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
             const int degree = std::max(1, std::min(deg_cap, dmax));
             full_step = deg_cap >= o.degree || degree == dmax;
             double sig = 1.0 / t;
-            TK_HIP(dgemm(n, wa, n, Md, n, false, Xf, b, Ya, b, sig / e, -c * sig / e, Xf, 0.0, nullptr, L.split,
-                         L.split_elems, s));
+            TK_HIP(mprod(Xf, b, wa, Ya, b, sig / e, -c * sig / e, Xf, 0.0, nullptr, Lk));
             ++matvecs;
             const double *prev = Xf;
             double *bufs[3] = {Ya, Yb, Yc};
@@ -1209,8 +1273,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
                 int ni = (ci + 1) % 3;
                 if (bufs[ni] == prev) ni = (ni + 1) % 3;
                 double *nxt = bufs[ni];
-                TK_HIP(dgemm(n, wa, n, Md, n, false, cur, b, nxt, b, al, -c * al, cur, -sig * sig2, prev, L.split,
-                             L.split_elems, s));
+                TK_HIP(mprod(cur, b, wa, nxt, b, al, -c * al, cur, -sig * sig2, prev, Lk));
                 ++matvecs;
                 prev = cur;
                 cur = nxt;

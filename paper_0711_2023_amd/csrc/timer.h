@@ -45,15 +45,20 @@ struct Timer {
         tag.resize(used / 2 + 1);
         tag[used / 2] = Tag{k, mode, prec};
     }
+    // begin / end pairs may enclose kernel() pairs and other begin / end
+    // pairs (a phase around the launches it times)
+    std::vector<size_t> open;
     void begin(int k, int mode = -1, int prec = -1) {
         if (!on) return;
         reserve_pair(k, mode, prec);
         (void)hipEventRecord(ev[used], s);
+        open.push_back(used);
+        used += 2;
     }
     void end() {
-        if (!on) return;
-        (void)hipEventRecord(ev[used + 1], s);
-        used += 2;
+        if (!on || open.empty()) return;
+        (void)hipEventRecord(ev[open.back() + 1], s);
+        open.pop_back();
     }
     // A pair for a single kernel that records them itself at its start and
     // end (kernel time without the dispatch gap an event bracket includes).

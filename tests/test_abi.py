@@ -507,3 +507,47 @@ def test_streamed_mp_checks_on_host():
     cv = tk._HostCoo(idx, vb, (4, 3, 2))
     assert L.tucker_mp_streamed(ctypes.byref(cv.c), J, ctypes.byref(o), 1 << 16, 0x40, facs, hist,
                                 ctypes.byref(done), None, 0x50, need, None) == tk.TK_ERR_VALUE
+
+
+def test_implicit_mp_checks_on_host():
+    """tucker_mp_implicit rejects bad problems and options before device
+    work; its workspace bound grows with the nonzeros (fibres), not with the
+    mode sizes squared."""
+    L = tk.lib()
+    J = (ctypes.c_int32 * 3)(4, 3, 2)
+    out = ctypes.c_size_t(0)
+    o = tk._opts("fp64", init=tk.INIT_RANDOM)
+    c, _d = _coo((20000, 20000, 20000), nnz=1000)
+    assert L.tucker_mp_implicit_workspace(ctypes.byref(c), J, ctypes.byref(o), ctypes.byref(out)) == 0
+    small = out.value
+    c2, _d2 = _coo((20000, 20000, 20000), nnz=100_000)
+    assert L.tucker_mp_implicit_workspace(ctypes.byref(c2), J, ctypes.byref(o), ctypes.byref(out)) == 0
+    big = out.value
+    # the dense slot pointers (three orderings of 20000^2 slots) are the same
+    # in both; the difference is per nonzero / fibre
+    per_nz = (big - small) / 99_000
+    assert 100 < per_nz < 4000
+    for field, value in (("init", tk.INIT_HOSVD), ("init", tk.INIT_LEARNED), ("precision", tk.MIXED_BF16X3),
+                         ("max_iters", 0), ("hosvd_fit", 1), ("eig_max_iters", 0)):
+        ob = tk._opts("fp64", init=tk.INIT_RANDOM)
+        setattr(ob, field, value)
+        assert L.tucker_mp_implicit_workspace(ctypes.byref(c), J, ctypes.byref(ob), ctypes.byref(out)) == \
+            tk.TK_ERR_ARG, (field, value)
+    # core larger than 128, core larger than the mode, a pair of modes with
+    # 2^31 slots, order 4
+    for dims, core in (((300, 300, 300), (129, 3, 2)), ((3, 300, 300), (4, 3, 2)),
+                       ((50000, 50000, 10), (4, 3, 2))):
+        cc, _dd = _coo(dims, nnz=10)
+        Jc = (ctypes.c_int32 * 3)(*core)
+        assert L.tucker_mp_implicit_workspace(ctypes.byref(cc), Jc, ctypes.byref(o), ctypes.byref(out)) == \
+            tk.TK_ERR_ARG, dims
+    c4, _d4 = _coo((10, 9, 8), nnz=5, order=4)
+    assert L.tucker_mp_implicit_workspace(ctypes.byref(c4), J, ctypes.byref(o), ctypes.byref(out)) == tk.TK_ERR_ARG
+    facs = (ctypes.c_void_p * 3)(0x10, 0x20, 0x30)
+    hist = (ctypes.c_double * 50)()
+    done = ctypes.c_int32(0)
+    c3, _d3 = _coo((10, 9, 8), nnz=5)
+    assert L.tucker_mp_implicit(ctypes.byref(c3), J, ctypes.byref(o), None, facs, hist, ctypes.byref(done), None,
+                                0x50, 1 << 30, None) == tk.TK_ERR_ARG
+    assert L.tucker_mp_implicit(ctypes.byref(c3), J, ctypes.byref(o), 0x40, facs, hist, ctypes.byref(done), None,
+                                0x50, 16, None) == tk.TK_ERR_WORKSPACE
