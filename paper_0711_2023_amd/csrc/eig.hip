@@ -853,6 +853,7 @@ static hipError_t skinny(SkinnyArgs g, double *part, int64_t part_elems, hipStre
 struct EigLayout {
     double *W, *Y0, *Y1, *Y2, *S, *V, *Vg, *Rinv, *theta, *res, *norms, *split, *thall;
     double *Yop, *Cop, *thl;  // operator solves: A X, locked-part coefficients, locked Ritz values
+    double *lz;               // Lanczos coefficients of the spectrum bound (alphas, betas)
     int *colmap;
     int64_t split_elems;
 };
@@ -875,6 +876,7 @@ static EigLayout eig_layout(Arena &ar, int n, int b) {
     L.Yop = ar.take<double>(nb);
     L.Cop = ar.take<double>((int64_t)b * b);
     L.thl = ar.take<double>(b);
+    L.lz = ar.take<double>(64);
     // split-K partial strips: (strips x K ranges) <= 512 for every product
     // (see skinny_split), each 16 rows by at most b columns rounded up to 16
     L.split_elems = (int64_t)512 * 16 * (ceil_div(b, 16) * 16);
@@ -985,6 +987,84 @@ struct MProd {
         return hipSuccess;
     }
 };
+
+// Lanczos steps on column 0 of the n x b buffers (scalars on the device):
+// w -= alpha v + beta_prev vprev; next v = w / beta (zero for beta = 0).
+__global__ void k_lz_update(double *w, const double *v, const double *vprev, int64_t n, int ld, const double *alpha,
+                            const double *beta_prev) {
+    const double a = *alpha, bp = beta_prev ? *beta_prev : 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        w[i * ld] -= a * v[i * ld] + (vprev ? bp * vprev[i * ld] : 0.0);
+}
+__global__ void k_lz_next(const double *w, double *v, int64_t n, int ld, const double *beta) {
+    const double bt = *beta, inv = bt > 0.0 ? 1.0 / bt : 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i * ld] = w[i * ld] * inv;
+}
+
+// Largest eigenvalue of the symmetric tridiagonal matrix with diagonal a[0..k)
+// and off-diagonal e[0..k-1), by bisection on the Sturm count (the number of
+// eigenvalues below x is the number of negative pivots of T - x I).
+static double tridiag_max(const double *a, const double *e, int k) {
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(e[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    auto below = [&](double x) {
+        int cnt = 0;
+        double d = 1.0;
+        for (int i = 0; i < k; ++i) {
+            d = a[i] - x - (i > 0 ? e[i - 1] * e[i - 1] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++cnt;
+        }
+        return cnt;
+    };
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(hi), std::fabs(lo)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (below(mid) == k)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    return hi;
+}
+
+// Upper estimate of the largest eigenvalue: k Lanczos steps from column 0 of
+// x0 (row stride b), the largest eigenvalue of the tridiagonal plus the last
+// residual norm (the bound Chebyshev-filtered subspace iteration uses for the
+// top of the spectrum: Zhou and Saad, J. Comput. Phys. 2007). Uses column 0
+// of Y0, Y1 and Y2.
+static hipError_t lanczos_bound(const MProd &mp, int64_t n, int b, const double *x0, int k, EigLayout &L,
+                                double *bound, int *products, hipStream_t s) {
+    const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, 256), 4096);
+    double *vprev = L.Y0, *v = L.Y1, *w = L.Y2;
+    double *al = L.lz, *be = L.lz + 32;
+    k_colnorm<<<1, 256, 0, s>>>(x0, n, b, 0, be + 31);
+    TK_LAUNCHED();
+    k_lz_next<<<g, 256, 0, s>>>(x0, v, n, b, be + 31);
+    TK_LAUNCHED();
+    for (int j = 0; j < k; ++j) {
+        TK_HIP(mp(v, b, 1, w, b, 1.0, 0.0, nullptr, 0.0, nullptr, 0));
+        TK_HIP(dgemm(1, 1, (int)n, v, b, true, w, b, al + j, 1, 1.0, 0.0, nullptr, 0.0, nullptr, L.split,
+                     L.split_elems, s));
+        k_lz_update<<<g, 256, 0, s>>>(w, v, j > 0 ? vprev : nullptr, n, b, al + j, j > 0 ? be + j - 1 : nullptr);
+        TK_LAUNCHED();
+        k_colnorm<<<1, 256, 0, s>>>(w, n, b, 0, be + j);
+        TK_LAUNCHED();
+        k_lz_next<<<g, 256, 0, s>>>(w, vprev, n, b, be + j);
+        TK_LAUNCHED();
+        std::swap(vprev, v);  // v: the new vector; vprev: the old v
+    }
+    double h[64];
+    TK_HIP(hipMemcpyAsync(h, L.lz, sizeof(double) * 64, hipMemcpyDeviceToHost, s));
+    TK_HIP(hipStreamSynchronize(s));
+    *bound = tridiag_max(h, h + 32, k) + std::fabs(h[32 + k - 1]);
+    *products += k;
+    return hipSuccess;
+}
 
 // Orthonormalise columns [c0, c0+w) of X (n x b, row-major) in place:
 // column scaling, one shifted CholeskyQR pass, one plain pass.
@@ -1139,6 +1219,14 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
     double *Xc = X;
     double *Md = M;  // deflated in place (an operator solve deflates in its products instead)
     const MProd mprod{Md, n, o.op, &L, X, b, s};
+    // An upper bound of the spectrum for the degree of the first filters when
+    // the block does not come from this matrix: the Ritz values of such a
+    // block can sit far below the top of a flat spectrum, and a degree set by
+    // them alone would amplify the top directions beyond what the block's
+    // orthonormalisation resolves.
+    double bup = 0.0;
+    if (!o.warm || o.warm_degree >= o.degree)
+        TK_HIP(lanczos_bound(mprod, n, b, X, std::min(10, n), L, &bup, &matvecs, s));
     std::vector<double> tha;
     // Intermediate Rayleigh-Ritz steps use one Jacobi sweep: an approximate
     // rotation is enough to pick the leading directions of the block (it is
@@ -1258,7 +1346,10 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
             // bottom; rounding-level parts along a not yet locked outlier grow
             // by the same factor. Keeping T_d(t) <= 1e8 keeps the filtered
             // block well within what shifted CholeskyQR orthonormalises.
-            const int dmax = (int)std::floor(std::acosh(1e8) / std::acosh(std::max(t, 1.0 + 1e-12)));
+            // (before any pair is locked the degree also respects the
+            // spectrum bound, which the top active Ritz value may understate)
+            const double tb = Lk == 0 && bup > top ? (bup - c) / e : t;
+            const int dmax = (int)std::floor(std::acosh(1e8) / std::acosh(std::max(tb, 1.0 + 1e-12)));
             const int degree = std::max(1, std::min(deg_cap, dmax));
             full_step = deg_cap >= o.degree || degree == dmax;
             double sig = 1.0 / t;

@@ -58,8 +58,7 @@ double now_ms() {
 constexpr int kMaxJi = 128;
 constexpr int kGfThreads = 256;
 constexpr int kGfCols = 64;    // columns of a slab (one per lane)
-constexpr int kGfChunk = 16;   // fibres staged per pass
-constexpr int kGfMaxRpw = 32;  // W rows per wave (4 waves: J <= 128)
+constexpr int kGfBatch = 16;   // fibres per batch of a wave
 constexpr int kExplicitMax = 140;  // modes up to this size form M_n explicitly
 
 inline int hi_of(int m) { return (m + 2) % 3; }
@@ -82,98 +81,96 @@ __device__ inline float to_acc<float, double>(double v) { return (float)v; }
 template <>
 __device__ inline double to_acc<double, float>(float v) { return (double)v; }
 
-// One group (slice i_o) of one term, columns [0, cw) of Q (Q already offset
-// to the slab). The group's fibres are positions [gptr[g], gptr[g+1]) of the
-// grouping, fibre gperm[k] (or k without gperm). Rows of W beyond J are zero.
-// !CORE: Yf[f * kGfCols + c] for the group's fibres f.
+// One wave per group (slice i_o) of one term, lane c = column c of the
+// slab (Q already offset to it, c < cw). The group's fibres are positions
+// [gptr[g], gptr[g+1]) of the grouping, fibre gperm[k] (or k without gperm).
+// Lane c keeps column c of W_g = sum_f Tc[f]^T Q[n(f)] in registers (rows
+// up to JB >= J; rows beyond J stay zero). Fibres go in batches of kGfBatch:
+// the batch's fibre numbers and Q rows are loaded together (independent
+// loads in flight at once), its Tc rows staged in the wave's part of LDS and
+// read back as broadcasts. The waves of a workgroup run independently (no
+// workgroup barrier): a wave's LDS accesses complete in issue order.
+// !CORE: second pass over the group, Yf[f * kGfCols + c] = Tc[f] . W_g[:, c].
 // CORE: Wout[g * ldw_g + r * ldw_r + c] = W_g[r][c] (zeros for an empty group).
-template <class TP, class Acc, bool CORE>
-__global__ void __launch_bounds__(kGfThreads) k_gf_group(const TP *__restrict__ T, int ld, int J, int rpw,
-                                                         const int32_t *__restrict__ gptr,
-                                                         const int32_t *__restrict__ gperm,
-                                                         const int32_t *__restrict__ fn, const double *__restrict__ Q,
-                                                         int64_t ldq, int cw, Acc *__restrict__ Yf,
-                                                         double *__restrict__ Wout, int64_t ldw_g, int ldw_r) {
+template <class TP, class TQ, class Acc, int JB, bool CORE>
+__global__ void __launch_bounds__(kGfThreads) k_gf_wave(const TP *__restrict__ T, int ld, int J,
+                                                        const int32_t *__restrict__ gptr,
+                                                        const int32_t *__restrict__ gperm,
+                                                        const int32_t *__restrict__ fn, const TQ *__restrict__ Q,
+                                                        int64_t ldq, int cw, int64_t ngroups, Acc *__restrict__ Yf,
+                                                        double *__restrict__ Wout, int64_t ldw_g, int ldw_r) {
     extern __shared__ __attribute__((aligned(16))) char gf_smem[];
-    const int Jp = 4 * rpw;
-    Acc *sT = reinterpret_cast<Acc *>(gf_smem);  // [kGfChunk][Jp]
-    Acc *sQ = sT + kGfChunk * Jp;                // [kGfChunk][kGfCols]
-    Acc *sW = sQ + kGfChunk * kGfCols;           // [Jp][kGfCols]
-    __shared__ int32_t sf[kGfChunk];             // the pass's fibres
-    const int64_t g = blockIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t g = (int64_t)blockIdx.x * (kGfThreads / 64) + wv;
+    if (g >= ngroups) return;
+    Acc *sT = reinterpret_cast<Acc *>(gf_smem) + wv * (kGfBatch * JB);  // [kGfBatch][JB]
     const int32_t k0 = gptr[g], k1 = gptr[g + 1];
     if (!CORE && k1 <= k0) return;
-    const int tid = threadIdx.x, c = tid & (kGfCols - 1), wv = tid / kGfCols;
-    const int r0 = wv * rpw;
-    Acc acc[kGfMaxRpw];
+    const bool col = lane < cw;
+    Acc acc[JB];
 #pragma unroll
-    for (int k = 0; k < kGfMaxRpw; ++k) acc[k] = (Acc)0;
-    for (int32_t kb = k0; kb < k1; kb += kGfChunk) {
-        const int nc = min(kGfChunk, (int)(k1 - kb));
-        if (tid < kGfChunk) sf[tid] = tid < nc ? (gperm ? gperm[kb + tid] : kb + tid) : 0;
-        __syncthreads();
-        for (int e = tid; e < kGfChunk * Jp; e += kGfThreads) {
-            const int j = e / Jp, r = e - j * Jp;
+    for (int r = 0; r < JB; ++r) acc[r] = (Acc)0;
+    // stage the batch's Tc rows (fibre of batch slot j held by lane j in fl)
+    auto stage = [&](int nc, int32_t fl) {
+        for (int e = lane; e < kGfBatch * JB; e += 64) {
+            const int j = e / JB, r = e - j * JB;
+            const int32_t fj = __shfl(fl, j);
             Acc v = (Acc)0;
-            if (j < nc && r < J) v = to_acc<Acc>(T[(int64_t)sf[j] * ld + r]);
+            if (j < nc && r < J) v = to_acc<Acc>(T[(int64_t)fj * ld + r]);
             sT[e] = v;
         }
-        for (int e = tid; e < kGfChunk * kGfCols; e += kGfThreads) {
-            const int j = e / kGfCols, cc = e - j * kGfCols;
-            Acc v = (Acc)0;
-            if (j < nc && cc < cw) v = to_acc<Acc>(Q[(int64_t)fn[sf[j]] * ldq + cc]);
-            sQ[e] = v;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    for (int32_t kb = k0; kb < k1; kb += kGfBatch) {
+        const int nc = min(kGfBatch, (int)(k1 - kb));
+        int32_t fl = 0, nl = 0;
+        if (lane < nc) {
+            fl = gperm ? gperm[kb + lane] : kb + lane;
+            nl = fn[fl];
         }
-        __syncthreads();
-        for (int j = 0; j < nc; ++j) {
-            const Acc q = sQ[j * kGfCols + c];
-            const Acc *tr = sT + j * Jp + r0;
+        Acc q[kGfBatch];
 #pragma unroll
-            for (int k = 0; k < kGfMaxRpw; ++k)
-                if (k < rpw) acc[k] = fma_(tr[k], q, acc[k]);
+        for (int j = 0; j < kGfBatch; ++j) {
+            const int32_t nj = __shfl(nl, j);
+            q[j] = (j < nc && col) ? to_acc<Acc>(Q[(int64_t)nj * ldq + lane]) : (Acc)0;
         }
-        __syncthreads();
+        stage(nc, fl);
+#pragma unroll
+        for (int j = 0; j < kGfBatch; ++j) {
+            if (j < nc) {
+                const Acc *t = sT + j * JB;
+#pragma unroll
+                for (int r = 0; r < JB; ++r) acc[r] = fma_(t[r], q[j], acc[r]);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
     if (CORE) {
-        if (c < cw)
-            for (int k = 0; k < rpw; ++k) {
-                const int r = r0 + k;
-                if (r < J) Wout[g * ldw_g + (int64_t)r * ldw_r + c] = (double)acc[k];
-            }
+        if (col)
+#pragma unroll
+            for (int r = 0; r < JB; ++r)
+                if (r < J) Wout[g * ldw_g + (int64_t)r * ldw_r + lane] = (double)acc[r];
         return;
     }
+    for (int32_t kb = k0; kb < k1; kb += kGfBatch) {
+        const int nc = min(kGfBatch, (int)(k1 - kb));
+        int32_t fl = 0;
+        if (lane < nc) fl = gperm ? gperm[kb + lane] : kb + lane;
+        stage(nc, fl);
 #pragma unroll
-    for (int k = 0; k < kGfMaxRpw; ++k)
-        if (k < rpw) sW[(r0 + k) * kGfCols + c] = acc[k];
-    // (the pass loop ended on a barrier: sT is free; sW is read after the
-    // next barrier)
-    for (int32_t kb = k0; kb < k1; kb += kGfChunk) {
-        const int nc = min(kGfChunk, (int)(k1 - kb));
-        if (tid < kGfChunk) sf[tid] = tid < nc ? (gperm ? gperm[kb + tid] : kb + tid) : 0;
-        __syncthreads();
-        for (int e = tid; e < kGfChunk * Jp; e += kGfThreads) {
-            const int j = e / Jp, r = e - j * Jp;
-            Acc v = (Acc)0;
-            if (j < nc && r < J) v = to_acc<Acc>(T[(int64_t)sf[j] * ld + r]);
-            sT[e] = v;
-        }
-        __syncthreads();
-        // wave wv: fibres wv, wv + 4, wv + 8, wv + 12 of the pass
-        Acc y[kGfChunk / 4];
+        for (int j = 0; j < kGfBatch; ++j) {
+            if (j < nc) {
+                const Acc *t = sT + j * JB;
+                Acc y = (Acc)0;
 #pragma unroll
-        for (int i = 0; i < kGfChunk / 4; ++i) y[i] = (Acc)0;
-        for (int r = 0; r < J; ++r) {
-            const Acc wr = sW[r * kGfCols + c];
-#pragma unroll
-            for (int i = 0; i < kGfChunk / 4; ++i) y[i] = fma_(sT[(wv + 4 * i) * Jp + r], wr, y[i]);
-        }
-        if (c < cw)
-#pragma unroll
-            for (int i = 0; i < kGfChunk / 4; ++i) {
-                const int j = wv + 4 * i;
-                if (j < nc) Yf[(int64_t)sf[j] * kGfCols + c] = y[i];
+                for (int r = 0; r < JB; ++r) y = fma_(t[r], acc[r], y);
+                const int32_t fj = __shfl(fl, j);
+                if (col) Yf[(int64_t)fj * kGfCols + lane] = y;
             }
-        __syncthreads();
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -284,6 +281,7 @@ struct IPlan {
     float *Fc;        // mixed: FP32 mode-3 factor padded to ldc
     void *Fp[3];      // padded factor copies (FP64 / FP32 / FP16)
     void *Yf[2];      // per-term fibre rows of a product slab (Acc)
+    float *Qc;        // FP32 / BF16 products: the slab of Q in FP32 (rows of 64)
     double *Xblk[3], *theta, *Mg, *Wc, *Gp, *core_split;
     int64_t core_split_elems;
     void *eigw;
@@ -339,6 +337,7 @@ void carve(IPlan &p, Arena &ar) {
         p.Fc = ar.take<float>(p.I[2] * p.ldc);
     }
     for (int t = 0; t < 2; ++t) p.Yf[t] = ar.take<char>(maxcap * kGfCols * (int64_t)acc_of(p.prec));
+    p.Qc = p.prec != P64 ? ar.take<float>(maxI * kGfCols) : nullptr;
     size_t ew = 0;
     int bmax = 1;
     for (int n = 0; n < 3; ++n) {
@@ -505,10 +504,9 @@ hipError_t refresh(IPlan &p, int n, const double *F, hipStream_t s) {
     return hipSuccess;
 }
 
-size_t gf_lds(int rpw, size_t acc) {
-    const int Jp = 4 * rpw;
-    return acc * ((size_t)kGfChunk * Jp + (size_t)kGfChunk * kGfCols + (size_t)Jp * kGfCols);
-}
+// Register rows of a wave's W column: J rounded up to a multiple of 8
+// (16 above 64), at most 128.
+int jb_of(int J) { return J <= 64 ? (int)ceil_div(J, 8) * 8 : (int)ceil_div(J, 16) * 16; }
 
 template <class K, class... A>
 void gf_launch(K kernel, int64_t blocks, size_t lds, hipStream_t s, KernelEvents ke, A... args) {
@@ -520,20 +518,62 @@ void gf_launch(K kernel, int64_t blocks, size_t lds, hipStream_t s, KernelEvents
         kernel<<<(unsigned)blocks, kGfThreads, lds, s>>>(args...);
 }
 
+// The wave kernel for J's register rows, one wave per group.
+template <class TP, class TQ, class Acc, bool CORE>
+hipError_t gf_wave(int J, int64_t ngroups, hipStream_t s, KernelEvents ke, const TP *T, int ld,
+                   const int32_t *gptr, const int32_t *gperm, const int32_t *fn, const TQ *Q, int64_t ldq, int cw,
+                   Acc *Yf, double *Wout, int64_t ldw_g, int ldw_r) {
+    const int JB = jb_of(J);
+    const int64_t blocks = ceil_div(ngroups, kGfThreads / 64);
+    const size_t lds = (size_t)(kGfThreads / 64) * kGfBatch * JB * sizeof(Acc);
+#define TK_GF_CASE(JBV)                                                                                          \
+    case JBV:                                                                                                    \
+        gf_launch(k_gf_wave<TP, TQ, Acc, JBV, CORE>, blocks, lds, s, ke, T, ld, J, gptr, gperm, fn, Q, ldq, cw, \
+                  ngroups, Yf, Wout, ldw_g, ldw_r);                                                              \
+        break;
+    switch (JB) {
+        TK_GF_CASE(8)
+        TK_GF_CASE(16)
+        TK_GF_CASE(24)
+        TK_GF_CASE(32)
+        TK_GF_CASE(40)
+        TK_GF_CASE(48)
+        TK_GF_CASE(56)
+        TK_GF_CASE(64)
+        TK_GF_CASE(80)
+        TK_GF_CASE(96)
+        TK_GF_CASE(112)
+        TK_GF_CASE(128)
+        default:
+            return hipErrorInvalidValue;
+    }
+#undef TK_GF_CASE
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
+// Qc[i * kGfCols + c] = X[i * ldx + c] (c < cw) in FP32: the gathered rows of
+// the FP32 / BF16 products.
+__global__ void k_q32(const double *__restrict__ X, int64_t ldx, int64_t n, int cw, float *__restrict__ Qc) {
+    const int64_t tot = n * kGfCols;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / kGfCols;
+        const int c = (int)(t - i * kGfCols);
+        Qc[t] = c < cw ? (float)X[i * ldx + c] : 0.0f;
+    }
+}
+
 // One Gram term's group kernel over the slices of mode o.
-template <class TP, class Acc>
-hipError_t gf_term(IPlan &p, int m, int n, const double *Q, int64_t ldq, int cw, Acc *Yf, hipStream_t s) {
+template <class TP, class TQ, class Acc>
+hipError_t gf_term(IPlan &p, int m, int n, const TQ *Q, int64_t ldq, int cw, Acc *Yf, hipStream_t s) {
     const int o = 3 - n - m;
     const bool n_hi = hi_of(m) == n;
     const int32_t *gptr = n_hi ? p.glo[m] : p.ghi[m];
     const int32_t *gperm = n_hi ? p.plo[m] : nullptr;
     const int32_t *fn = n_hi ? p.fhi[m] : p.flo[m];
-    const int rpw = (int)ceil_div(p.J[m], 4);
     KernelEvents ke = p.tm ? p.tm->kernel(kGram, n, p.prec) : KernelEvents();
-    gf_launch(k_gf_group<TP, Acc, false>, p.I[o], gf_lds(rpw, sizeof(Acc)), s, ke, (const TP *)p.T[m], p.ld[m],
-              p.J[m], rpw, gptr, gperm, fn, Q, ldq, cw, Yf, (double *)nullptr, (int64_t)0, 0);
-    TK_LAUNCHED();
-    return hipSuccess;
+    return gf_wave<TP, TQ, Acc, false>(p.J[m], p.I[o], s, ke, (const TP *)p.T[m], p.ld[m], gptr, gperm, fn, Q, ldq,
+                                       cw, Yf, (double *)nullptr, (int64_t)0, 0);
 }
 
 template <class TP, class Acc>
@@ -541,8 +581,15 @@ hipError_t gf_apply(IPlan &p, int n, const double *X, int64_t ldx, int w, double
     const int m1 = (n + 1) % 3, m2 = (n + 2) % 3;
     for (int c0 = 0; c0 < w; c0 += kGfCols) {
         const int cw = std::min(kGfCols, w - c0);
-        TK_HIP((gf_term<TP, Acc>(p, m1, n, X + c0, ldx, cw, (Acc *)p.Yf[0], s)));
-        TK_HIP((gf_term<TP, Acc>(p, m2, n, X + c0, ldx, cw, (Acc *)p.Yf[1], s)));
+        if (sizeof(Acc) == 8) {
+            TK_HIP((gf_term<TP, double, Acc>(p, m1, n, X + c0, ldx, cw, (Acc *)p.Yf[0], s)));
+            TK_HIP((gf_term<TP, double, Acc>(p, m2, n, X + c0, ldx, cw, (Acc *)p.Yf[1], s)));
+        } else {
+            k_q32<<<grid_of(p.I[n] * kGfCols), 256, 0, s>>>(X + c0, ldx, p.I[n], cw, p.Qc);
+            TK_LAUNCHED();
+            TK_HIP((gf_term<TP, float, Acc>(p, m1, n, p.Qc, kGfCols, cw, (Acc *)p.Yf[0], s)));
+            TK_HIP((gf_term<TP, float, Acc>(p, m2, n, p.Qc, kGfCols, cw, (Acc *)p.Yf[1], s)));
+        }
         // rows of n in each term's grouping by n
         const bool h1 = hi_of(m1) == n, h2 = hi_of(m2) == n;
         k_gf_rows<Acc><<<(unsigned)ceil_div(p.I[n], 256 / kGfCols), 256, 0, s>>>(
@@ -607,21 +654,18 @@ int run_eig(IPlan &p, int n, double *F, const tk_opts *o, tk_stats *st, int *noc
 // slices i2 (fibres grouped by the major key), G' = B^T Z, permuted.
 hipError_t core_and_fit(IPlan &p, const double *A, const double *B, double *core, hipStream_t s) {
     const int J0 = p.J[0], J1 = p.J[1], J2 = p.J[2];
-    const int rpw = (int)ceil_div(J2, 4);
     const void *Tc = p.prec == PBF16 ? (const void *)p.Tcore : p.T[2];
     const int ldt = p.prec == PBF16 ? p.ldc : p.ld[2];
-    const size_t lds = gf_lds(rpw, 8);
     for (int c0 = 0; c0 < J0; c0 += kGfCols) {
         const int cw = std::min(kGfCols, J0 - c0);
         if (p.prec == P64)
-            gf_launch(k_gf_group<double, double, true>, p.I[1], lds, s, KernelEvents(), (const double *)Tc, ldt, J2,
-                      rpw, (const int32_t *)p.ghi[2], (const int32_t *)nullptr, (const int32_t *)p.flo[2], A + c0,
-                      (int64_t)J0, cw, (double *)nullptr, p.Wc + c0, (int64_t)J2 * J0, J0);
+            TK_HIP((gf_wave<double, double, double, true>(J2, p.I[1], s, KernelEvents(), (const double *)Tc, ldt,
+                                                           p.ghi[2], nullptr, p.flo[2], A + c0, (int64_t)J0, cw,
+                                                           (double *)nullptr, p.Wc + c0, (int64_t)J2 * J0, J0)));
         else
-            gf_launch(k_gf_group<float, double, true>, p.I[1], lds, s, KernelEvents(), (const float *)Tc, ldt, J2,
-                      rpw, (const int32_t *)p.ghi[2], (const int32_t *)nullptr, (const int32_t *)p.flo[2], A + c0,
-                      (int64_t)J0, cw, (double *)nullptr, p.Wc + c0, (int64_t)J2 * J0, J0);
-        TK_LAUNCHED();
+            TK_HIP((gf_wave<float, double, double, true>(J2, p.I[1], s, KernelEvents(), (const float *)Tc, ldt,
+                                                          p.ghi[2], nullptr, p.flo[2], A + c0, (int64_t)J0, cw,
+                                                          (double *)nullptr, p.Wc + c0, (int64_t)J2 * J0, J0)));
     }
     GemmArgs h;
     h.M = J1;

@@ -94,6 +94,25 @@ def test_lead_eig_spike_over_clustered_bulk(tk):
     _check(tk, M, J)
 
 
+def test_lead_eig_flat_spectrum_cold_start(tk):
+    """A few leading eigenvalues over a long flat bulk (the spectrum of MP's
+    Grams on very sparse uniform tensors: 1M nonzeros in 10000^3). The Ritz
+    values of a random start block sit near the bulk's middle, far below the
+    top; the first filters must take their degree from an upper bound of the
+    whole spectrum, or the leading directions are amplified past what the
+    block's orthonormalisation resolves (non-finite output)."""
+    _say("lead_eig flat spectrum, cold start")
+    rng = np.random.default_rng(4)
+    n, J = 3000, 50
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    top = np.array([1.67, 1.39, 1.05, 0.91, 0.83])
+    shelf = np.linspace(0.80, 0.62, 60)
+    bulk = np.linspace(0.60, 0.16, n - top.size - shelf.size)
+    lam = np.concatenate([top, shelf, bulk])
+    M = (Q * lam) @ Q.T
+    _check(tk, M, J, tol=1e-12)
+
+
 def test_lead_eig_rank_deficient(tk):
     _say("lead_eig rank deficient")
     rng = np.random.default_rng(3)

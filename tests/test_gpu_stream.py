@@ -67,8 +67,12 @@ def test_fp64_matches_incore_and_oracle(tk, tensor, slab_bytes):
     _say(f"  slabs {r.stats['streamed_slabs']} bytes {r.stats['streamed_bytes']}: |d| in-core {d_in:.2e} "
          f"oracle {d_or:.2e}")
     assert d_in < 1e-10 and d_or < 1e-9
+    # the cores: norms within 1e-8 (the eigensolver tolerance); entries within 1e-6 (near-tied
+    # trailing eigenvalues leave their eigenvectors free to rotate by about
+    # the rounding of M over the gap, which the fit does not see)
     G, Gc = r.core.cpu().numpy(), c.core.cpu().numpy()
-    assert np.abs(G - Gc).max() < 1e-9 * np.abs(Gc).max()
+    assert abs(np.linalg.norm(G) - np.linalg.norm(Gc)) < 1e-8 * np.linalg.norm(Gc)
+    assert np.abs(G - Gc).max() < 1e-6 * np.abs(Gc).max()
     for F in r.factors:
         F = F.cpu().numpy()
         assert np.abs(F.T @ F - np.eye(F.shape[1])).max() < 1e-10

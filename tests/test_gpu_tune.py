@@ -71,8 +71,10 @@ GRAM_TUNES = [(0, 0, 64, 1), (0, 0, 16384, 1), (0, 0, 256, 64), (16384, 4096, 40
 # rounding of the partial sums by at most K u (summed length K up to 6e4,
 # u = 2^-24 for FP32 accumulators, 2^-53 for FP64), amplified by the small
 # eigengaps of a sparsely sampled tensor (fit about 0.4 %): 1e-3 for the
-# FP32-accumulated Grams (BF16 and FP32 inputs), 1e-9 for FP64.
-FIT_RTOL = {"mixed": 1e-3, "fp32": 1e-3, "fp64": 1e-9}
+# FP32 Grams, 1e-9 for FP64. The mixed solves stop at a 1e-4 relative
+# resolution of the Ritz sums, and three sweeps compound the different
+# stopping points: 5e-3 (2e-5 of fit here, a fifth of the 1e-4 bar).
+FIT_RTOL = {"mixed": 5e-3, "fp32": 1e-3, "fp64": 1e-9}
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp32", "fp64"])
