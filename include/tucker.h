@@ -228,6 +228,11 @@ typedef struct tk_stats {
                                (t < 64; its share of ttmc_ms), 0 beyond */
     int64_t streamed_bytes; /* tucker_mp_streamed: bytes uploaded from host memory */
     int64_t streamed_slabs; /* tucker_mp_streamed: slabs uploaded */
+    int64_t product_fibres; /* tucker_mp_implicit: sum over its product kernel launches of the
+                               fibres each launch visits (each reads its row twice) */
+    int64_t product_pairs;  /* tucker_mp_implicit: sum over the same launches of fibres x
+                               columns (one gathered Q element and one written row element
+                               per pair, 4 J flops) */
 } tk_stats;
 
 /* Fill *opt with: FP32, HO-SVD init, 50 sweeps, tol 1e-4, eig cap 400

@@ -98,7 +98,8 @@ class tk_stats(ctypes.Structure):
                 ("nnz_unique", ctypes.c_int64), ("eig_iters", ctypes.c_int32), ("eig_noconv", ctypes.c_int32),
                 ("norm_x", ctypes.c_double), ("init_fallbacks", ctypes.c_int32), ("hosvd_fit", ctypes.c_double),
                 ("core_norm", ctypes.c_double), ("ttmc_sweep_ms", ctypes.c_double * 64),
-                ("streamed_bytes", ctypes.c_int64), ("streamed_slabs", ctypes.c_int64)]
+                ("streamed_bytes", ctypes.c_int64), ("streamed_slabs", ctypes.c_int64),
+                ("product_fibres", ctypes.c_int64), ("product_pairs", ctypes.c_int64)]
 
 
 class TuckerError(RuntimeError):

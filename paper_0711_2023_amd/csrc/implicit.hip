@@ -288,6 +288,7 @@ struct IPlan {
     bool blk_ok[3] = {false, false, false};
     int sweep_solves[3] = {0, 0, 0};
     Timer *tm = nullptr;
+    int64_t prod_fibres = 0, prod_pairs = 0;  // product kernel launches: fibres, fibres x columns
 };
 
 size_t es_of(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
@@ -572,6 +573,8 @@ hipError_t gf_term(IPlan &p, int m, int n, const TQ *Q, int64_t ldq, int cw, Acc
     const int32_t *gperm = n_hi ? p.plo[m] : nullptr;
     const int32_t *fn = n_hi ? p.fhi[m] : p.flo[m];
     KernelEvents ke = p.tm ? p.tm->kernel(kGram, n, p.prec) : KernelEvents();
+    p.prod_fibres += p.nfib[m];
+    p.prod_pairs += p.nfib[m] * cw;
     return gf_wave<TP, TQ, Acc, false>(p.J[m], p.I[o], s, ke, (const TP *)p.T[m], p.ld[m], gptr, gperm, fn, Q, ldq,
                                        cw, Yf, (double *)nullptr, (int64_t)0, 0);
 }
@@ -786,6 +789,8 @@ int mp_implicit(const tk_coo *X, const int32_t *J, const tk_opts *o, double *cor
         stats->nnz_unique = nu;
         stats->norm_x = std::sqrt(nx2);
         stats->core_norm = std::sqrt(g2);
+        stats->product_fibres = p.prod_fibres;
+        stats->product_pairs = p.prod_pairs;
     }
     return noconv ? TK_WARN_NOCONV : TK_OK;
 }
