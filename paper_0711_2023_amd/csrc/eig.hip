@@ -770,6 +770,58 @@ __global__ void k_skinny_reduce(SkinnyArgs g, int NC) {
     }
 }
 
+// Narrow products (N <= 8 columns, A row-major): the N columns of B are
+// staged in LDS once per workgroup ([K][NB], zero beyond N), then each wave
+// takes whole rows of A, lanes striding over K with coalesced row reads,
+// and reduces its N sums across the wave (fixed order). Power steps and
+// products with few active columns read all of A for a handful of columns;
+// this spends them over many workgroups instead of one 16-row strip each.
+constexpr int kNarrowRows = 8;  // rows per workgroup (two per wave)
+template <int NB>
+__global__ void __launch_bounds__(256) k_narrow(SkinnyArgs g) {
+    extern __shared__ double xs[];  // [K][NB]
+    for (int t = threadIdx.x; t < g.K * NB; t += 256) {
+        const int k = t / NB, j = t - k * NB;
+        xs[t] = j < g.N ? g.B[(int64_t)k * g.ldb + j] : 0.0;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int rr = 0; rr < kNarrowRows / 4; ++rr) {
+        const int i = blockIdx.x * kNarrowRows + wave * (kNarrowRows / 4) + rr;
+        if (i >= g.M) break;
+        const double *arow = g.A + (int64_t)i * g.lda;
+        double acc[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[j] = 0.0;
+        for (int k = l; k < g.K; k += 64) {
+            const double a = arow[k];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) acc[j] = __builtin_fma(a, xs[k * NB + j], acc[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            for (int d = 32; d >= 1; d >>= 1) acc[j] += __shfl_xor(acc[j], d, 64);
+#pragma unroll
+        for (int j = 0; j < NB; ++j)
+            if (l == j && j < g.N) skinny_out(g, i, j, acc[j]);
+    }
+}
+
+template <int NB>
+static void narrow_launch(const SkinnyArgs &g, hipStream_t s) {
+    const size_t lds = sizeof(double) * (size_t)g.K * NB;
+    hipFuncSetAttribute((const void *)k_narrow<NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_narrow<NB><<<(unsigned)ceil_div(g.M, kNarrowRows), 256, lds, s>>>(g);
+}
+
+// The narrow form applies (row-major A, at most 8 columns whose K x 8 block
+// fits 64 KiB of LDS).
+static int narrow_width(const SkinnyArgs &g) {
+    if (g.at || g.N > 8 || g.K < 64) return 0;
+    const int nb = g.N <= 1 ? 1 : (g.N <= 2 ? 2 : (g.N <= 4 ? 4 : 8));
+    return (int64_t)g.K * nb * 8 <= 65536 ? nb : 0;
+}
+
 // K ranges: enough workgroups to cover the chip (about 512), each range at
 // least 64 long and a multiple of 16.
 static void skinny_split(int M, int K, int *S, int *Kc) {
@@ -804,6 +856,19 @@ static hipError_t skinny(SkinnyArgs g, double *part, int64_t part_elems, hipStre
         g.part = nullptr;
         const int64_t total = (int64_t)g.M * g.N;
         k_skinny_reduce<<<(unsigned)std::min<int64_t>(ceil_div(total, 256), 2048), 256, 0, s>>>(g, NT * 16);
+        TK_LAUNCHED();
+        return hipSuccess;
+    }
+    if (const int nb = narrow_width(g)) {
+        g.S = 1;
+        g.Kc = g.K;
+        g.part = nullptr;
+        switch (nb) {
+            case 1: narrow_launch<1>(g, s); break;
+            case 2: narrow_launch<2>(g, s); break;
+            case 4: narrow_launch<4>(g, s); break;
+            default: narrow_launch<8>(g, s); break;
+        }
         TK_LAUNCHED();
         return hipSuccess;
     }
@@ -1129,7 +1194,12 @@ static hipError_t orthonormalise(const double *src, double *X, int64_t n, int b,
 // Column 0 of X <- normalised M^steps x0 (products alternate between X and
 // Y0, ending in X), then theta[0] = x^T M x, the Rayleigh quotient that the
 // deflation and the output use.
-static hipError_t power_lock(const MProd &mp, int n, int b, double *X, int steps, EigLayout &L, hipStream_t s) {
+static hipError_t power_lock(const MProd &mp, int n, int b, double *X, int steps, double theta_est, EigLayout &L,
+                             hipStream_t s) {
+    // each product is scaled by 1 / (the current estimate of the leading
+    // eigenvalue), which keeps the vector's norm near one; it is normalised
+    // every eighth step and after the last
+    const double inv = theta_est > 0.0 ? 1.0 / theta_est : 1.0;
     double *src = X, *dst = L.Y0;
     if (steps & 1) {  // an odd count ends in Y0: start from a copy there
         TK_HIP(hipMemcpy2DAsync(L.Y0, sizeof(double) * b, X, sizeof(double) * b, sizeof(double), n,
@@ -1138,12 +1208,14 @@ static hipError_t power_lock(const MProd &mp, int n, int b, double *X, int steps
         dst = X;
     }
     for (int k = 0; k < steps; ++k) {
-        TK_HIP(mp(src, b, 1, dst, b, 1.0, 0.0, nullptr, 0.0, nullptr, 0));
-        k_colnorm<<<1, 256, 0, s>>>(dst, n, b, 0, L.norms);
-        TK_LAUNCHED();
-        k_colscale<<<(unsigned)std::min<int64_t>(ceil_div(n, 256), 65536), 256, 0, s>>>(dst, dst, n, b, 0, 1, L.norms,
-                                                                                         0x9e3779b9ull + k);
-        TK_LAUNCHED();
+        TK_HIP(mp(src, b, 1, dst, b, inv, 0.0, nullptr, 0.0, nullptr, 0));
+        if ((k & 7) == 7 || k == steps - 1) {
+            k_colnorm<<<1, 256, 0, s>>>(dst, n, b, 0, L.norms);
+            TK_LAUNCHED();
+            k_colscale<<<(unsigned)std::min<int64_t>(ceil_div(n, 256), 65536), 256, 0, s>>>(dst, dst, n, b, 0, 1,
+                                                                                             L.norms, 0x9e3779b9ull + k);
+            TK_LAUNCHED();
+        }
         std::swap(src, dst);
     }
     // src == X now; theta = x^T (M x)
@@ -1309,7 +1381,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
             res[0] > lock_tol) {
             const double rate = tha[1] / tha[0];
             const int steps = std::min(60, 2 + (int)std::ceil(std::log(lock_tol / res[0]) / std::log(rate)));
-            TK_HIP(power_lock(mprod, n, b, Xc, steps, L, s));
+            TK_HIP(power_lock(mprod, n, b, Xc, steps, tha[0], L, s));
             double th1 = 0.0;
             TK_HIP(hipMemcpyAsync(&th1, L.theta, sizeof(double), hipMemcpyDeviceToHost, s));
             TK_HIP(hipStreamSynchronize(s));
