@@ -20,6 +20,10 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 enum Prec { P64 = 0, P32 = 1, PBF16 = 2 };
 
+// Raise kernel fn's dynamic LDS limit to at least `bytes` (one runtime call
+// the first time a kernel needs more than it was given before; thread safe).
+void lds_limit(const void *fn, size_t bytes);
+
 // Records the first failing HIP call of the current thread; returned as text
 // by tucker_strerror(TK_ERR_DEVICE).
 void set_hip_error(hipError_t e, const char *where);

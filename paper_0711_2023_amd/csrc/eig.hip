@@ -27,6 +27,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 namespace tk {
@@ -45,6 +47,30 @@ int eig_block_width(int n, int J) {
     int b = std::min(J + p, kMaxBlock);
     b = std::min(b, n);
     return std::max(b, J);
+}
+
+void lds_limit(const void *fn, size_t bytes) {
+    static std::mutex mu;
+    static std::unordered_map<const void *, size_t> given;
+    std::lock_guard<std::mutex> g(mu);
+    size_t &v = given[fn];
+    if (bytes > v) {
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        v = bytes;
+    }
+}
+
+// Per-thread pinned host buffer for the solver's small read-backs (1024
+// doubles, allocated on a thread's first solve and kept for its life), or
+// null when pinned memory is not to be had.
+static double *pinned_scratch() {
+    thread_local double *p = nullptr;
+    thread_local bool tried = false;
+    if (!tried) {
+        tried = true;
+        if (hipHostMalloc((void **)&p, sizeof(double) * 1024, hipHostMallocDefault) != hipSuccess) p = nullptr;
+    }
+    return p;
 }
 
 // ------------------------------------------------------------------ small kernels
@@ -810,7 +836,7 @@ __global__ void __launch_bounds__(256) k_narrow(SkinnyArgs g) {
 template <int NB>
 static void narrow_launch(const SkinnyArgs &g, hipStream_t s) {
     const size_t lds = sizeof(double) * (size_t)g.K * NB;
-    hipFuncSetAttribute((const void *)k_narrow<NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    lds_limit((const void *)k_narrow<NB>, lds);
     k_narrow<NB><<<(unsigned)ceil_div(g.M, kNarrowRows), 256, lds, s>>>(g);
 }
 
@@ -843,7 +869,7 @@ template <int NT>
 static void skinny_launch(const SkinnyArgs &g, hipStream_t s) {
     const int strips = (g.M + 15) / 16;
     const size_t lds = sizeof(double) * 4 * 16 * NT * 16;
-    hipFuncSetAttribute((const void *)k_skinny<NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    lds_limit((const void *)k_skinny<NT>, lds);
     k_skinny<NT><<<(unsigned)(strips * g.S), 256, lds, s>>>(g);
 }
 
@@ -880,12 +906,10 @@ static hipError_t skinny(SkinnyArgs g, double *part, int64_t part_elems, hipStre
         const size_t lds = sizeof(double) * kSkinnyWideWaves * kSkinnyTPW * 256;
         const unsigned grid = (unsigned)(((g.M + 15) / 16) * NG);
         if (g.at) {
-            hipFuncSetAttribute((const void *)k_skinny_wide<kSkinnyTPW, true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            lds_limit((const void *)k_skinny_wide<kSkinnyTPW, true>, lds);
             k_skinny_wide<kSkinnyTPW, true><<<grid, 64 * kSkinnyWideWaves, lds, s>>>(g, NG);
         } else {
-            hipFuncSetAttribute((const void *)k_skinny_wide<kSkinnyTPW, false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            lds_limit((const void *)k_skinny_wide<kSkinnyTPW, false>, lds);
             k_skinny_wide<kSkinnyTPW, false><<<grid, 64 * kSkinnyWideWaves, lds, s>>>(g, NG);
         }
         TK_LAUNCHED();
@@ -933,8 +957,8 @@ static EigLayout eig_layout(Arena &ar, int n, int b) {
     L.V = ar.take<double>((int64_t)b * b);
     L.Vg = ar.take<double>((int64_t)b * b);
     L.Rinv = ar.take<double>((int64_t)b * b);
-    L.theta = ar.take<double>(b);
-    L.res = ar.take<double>(b);
+    L.theta = ar.take<double>(2 * (int64_t)b);  // Ritz values, then the residual norms: one read-back
+    L.res = L.theta + b;
     L.norms = ar.take<double>(b);
     L.thall = ar.take<double>(b);
     L.colmap = ar.take<int>(b);
@@ -959,11 +983,11 @@ static hipError_t jacobi(const double *H, int ldh, int b, double *theta, double 
                          int sweeps = 30, double off2 = 1e-26) {
     if (b <= kJacobiVLds) {
         size_t lds = sizeof(double) * 2 * (size_t)b * b;
-        hipFuncSetAttribute((const void *)k_jacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        lds_limit((const void *)k_jacobi<true>, lds);
         k_jacobi<true><<<1, kJacobiThreads, lds, s>>>(H, ldh, b, sweeps, off2, theta, Vout, Vg);
     } else {
         size_t lds = sizeof(double) * (size_t)b * b;
-        hipFuncSetAttribute((const void *)k_jacobi<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        lds_limit((const void *)k_jacobi<false>, lds);
         k_jacobi<false><<<1, kJacobiThreads, lds, s>>>(H, ldh, b, sweeps, off2, theta, Vout, Vg);
     }
     TK_LAUNCHED();
@@ -1055,11 +1079,40 @@ struct MProd {
 
 // Lanczos steps on column 0 of the n x b buffers (scalars on the device):
 // w -= alpha v + beta_prev vprev; next v = w / beta (zero for beta = 0).
-__global__ void k_lz_update(double *w, const double *v, const double *vprev, int64_t n, int ld, const double *alpha,
-                            const double *beta_prev) {
-    const double a = *alpha, bp = beta_prev ? *beta_prev : 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        w[i * ld] -= a * v[i * ld] + (vprev ? bp * vprev[i * ld] : 0.0);
+// Sum over a 1024-thread workgroup in a fixed order (red: 16 doubles).
+__device__ inline double block_sum(double x, double *red) {
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+    return t;
+}
+// One Lanczos step after w = A v, in one workgroup: alpha = v.w;
+// w -= alpha v + beta_prev vprev; beta = ||w||; vnext = w / beta (vnext may
+// be vprev's buffer: it is written after every read of vprev).
+__global__ void __launch_bounds__(1024) k_lz_step(double *w, const double *v, const double *vprev, double *vnext,
+                                                  int64_t n, int ld, double *alpha_out, const double *beta_prev,
+                                                  double *beta_out) {
+    __shared__ double red[16];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) a += v[i * ld] * w[i * ld];
+    a = block_sum(a, red);
+    const double bp = beta_prev ? *beta_prev : 0.0;
+    double q = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const double x = w[i * ld] - (a * v[i * ld] + (beta_prev ? bp * vprev[i * ld] : 0.0));
+        w[i * ld] = x;
+        q += x * x;
+    }
+    const double bt = sqrt(block_sum(q, red));
+    const double inv = bt > 0.0 ? 1.0 / bt : 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) vnext[i * ld] = w[i * ld] * inv;
+    if (threadIdx.x == 0) {
+        *alpha_out = a;
+        *beta_out = bt;
+    }
 }
 __global__ void k_lz_next(const double *w, double *v, int64_t n, int ld, const double *beta) {
     const double bt = *beta, inv = bt > 0.0 ? 1.0 / bt : 0.0;
@@ -1113,17 +1166,12 @@ static hipError_t lanczos_bound(const MProd &mp, int64_t n, int b, const double 
     TK_LAUNCHED();
     for (int j = 0; j < k; ++j) {
         TK_HIP(mp(v, b, 1, w, b, 1.0, 0.0, nullptr, 0.0, nullptr, 0));
-        TK_HIP(dgemm(1, 1, (int)n, v, b, true, w, b, al + j, 1, 1.0, 0.0, nullptr, 0.0, nullptr, L.split,
-                     L.split_elems, s));
-        k_lz_update<<<g, 256, 0, s>>>(w, v, j > 0 ? vprev : nullptr, n, b, al + j, j > 0 ? be + j - 1 : nullptr);
-        TK_LAUNCHED();
-        k_colnorm<<<1, 256, 0, s>>>(w, n, b, 0, be + j);
-        TK_LAUNCHED();
-        k_lz_next<<<g, 256, 0, s>>>(w, vprev, n, b, be + j);
+        k_lz_step<<<1, 1024, 0, s>>>(w, v, vprev, vprev, n, b, al + j, j > 0 ? be + j - 1 : nullptr, be + j);
         TK_LAUNCHED();
         std::swap(vprev, v);  // v: the new vector; vprev: the old v
     }
-    double h[64];
+    double hb[64];
+    double *h = pinned_scratch() ? pinned_scratch() + 512 : hb;
     TK_HIP(hipMemcpyAsync(h, L.lz, sizeof(double) * 64, hipMemcpyDeviceToHost, s));
     TK_HIP(hipStreamSynchronize(s));
     *bound = tridiag_max(h, h + 32, k) + std::fabs(h[32 + k - 1]);
@@ -1154,11 +1202,11 @@ hipError_t chol_inv_upper(const double *S, int w, double shift, double *Rinv, hi
     if (w <= kCholBlkMax) {
         const int W = (w + 15) & ~15;
         const size_t lds = sizeof(double) * (2 * (size_t)W * W + (kCholBlkThreads / 64) * 256);
-        hipFuncSetAttribute((const void *)k_chol_inv_blk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        lds_limit((const void *)k_chol_inv_blk, lds);
         k_chol_inv_blk<<<1, kCholBlkThreads, lds, s>>>(S, w, w, shift, Rinv);
     } else {
         const size_t lds = sizeof(double) * ((size_t)w * w + w);
-        hipFuncSetAttribute((const void *)k_chol_inv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        lds_limit((const void *)k_chol_inv, lds);
         k_chol_inv<<<1, 1024, lds, s>>>(S, w, w, shift, Rinv);
     }
     TK_LAUNCHED();
@@ -1291,14 +1339,12 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
     double *Xc = X;
     double *Md = M;  // deflated in place (an operator solve deflates in its products instead)
     const MProd mprod{Md, n, o.op, &L, X, b, s};
-    // An upper bound of the spectrum for the degree of the first filters when
-    // the block does not come from this matrix: the Ritz values of such a
-    // block can sit far below the top of a flat spectrum, and a degree set by
-    // them alone would amplify the top directions beyond what the block's
-    // orthonormalisation resolves.
+    // An upper bound of the spectrum for the degree of the first filters of a
+    // cold start: the Ritz values of a random block can sit far below the top
+    // of a flat spectrum, and a degree set by them alone would amplify the
+    // top directions beyond what the block's orthonormalisation resolves.
     double bup = 0.0;
-    if (!o.warm || o.warm_degree >= o.degree)
-        TK_HIP(lanczos_bound(mprod, n, b, X, std::min(10, n), L, &bup, &matvecs, s));
+    if (!o.warm) TK_HIP(lanczos_bound(mprod, n, b, X, std::min(8, n), L, &bup, &matvecs, s));
     std::vector<double> tha;
     // Intermediate Rayleigh-Ritz steps use one Jacobi sweep: an approximate
     // rotation is enough to pick the leading directions of the block (it is
@@ -1335,9 +1381,14 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
                                 hipMemcpyDeviceToDevice, s));
         k_resid<<<w, 256, 0, s>>>(L.Y1, L.Y0, L.theta, n, w, L.res);
         TK_LAUNCHED();
-        TK_HIP(hipMemcpyAsync(h.data(), L.theta, sizeof(double) * w, hipMemcpyDeviceToHost, s));
-        TK_HIP(hipMemcpyAsync(h.data() + b, L.res, sizeof(double) * w, hipMemcpyDeviceToHost, s));
-        TK_HIP(hipStreamSynchronize(s));
+        if (double *pin = pinned_scratch()) {
+            TK_HIP(hipMemcpyAsync(pin, L.theta, sizeof(double) * 2 * b, hipMemcpyDeviceToHost, s));
+            TK_HIP(hipStreamSynchronize(s));
+            std::copy(pin, pin + 2 * b, h.begin());
+        } else {
+            TK_HIP(hipMemcpyAsync(h.data(), L.theta, sizeof(double) * 2 * b, hipMemcpyDeviceToHost, s));
+            TK_HIP(hipStreamSynchronize(s));
+        }
         tha.assign(h.data(), h.data() + w);
         const double *res = h.data() + b;
         double E = 0;

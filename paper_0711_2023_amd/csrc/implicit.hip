@@ -511,7 +511,7 @@ int jb_of(int J) { return J <= 64 ? (int)ceil_div(J, 8) * 8 : (int)ceil_div(J, 1
 
 template <class K, class... A>
 void gf_launch(K kernel, int64_t blocks, size_t lds, hipStream_t s, KernelEvents ke, A... args) {
-    hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    lds_limit((const void *)kernel, lds);
     if (ke.start && ke.stop)
         hipExtLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kGfThreads), (uint32_t)lds, s, ke.start, ke.stop,
                               0u, args...);
