@@ -73,6 +73,17 @@ static double *pinned_scratch() {
     return p;
 }
 
+// Wait for the stream's work by polling (the solver's host decisions follow
+// each wait at once; polling returns sooner than a blocking wait), then a
+// blocking wait if it takes longer than about a tenth of a second.
+static hipError_t wait_stream(hipStream_t s) {
+    for (int i = 0; i < 100000; ++i) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e != hipErrorNotReady) return e;
+    }
+    return hipStreamSynchronize(s);
+}
+
 // ------------------------------------------------------------------ small kernels
 __device__ inline uint64_t mix64(uint64_t z) {
     z += 0x9E3779B97F4A7C15ull;
@@ -1173,7 +1184,7 @@ static hipError_t lanczos_bound(const MProd &mp, int64_t n, int b, const double 
     double hb[64];
     double *h = pinned_scratch() ? pinned_scratch() + 512 : hb;
     TK_HIP(hipMemcpyAsync(h, L.lz, sizeof(double) * 64, hipMemcpyDeviceToHost, s));
-    TK_HIP(hipStreamSynchronize(s));
+    TK_HIP(wait_stream(s));
     *bound = tridiag_max(h, h + 32, k) + std::fabs(h[32 + k - 1]);
     *products += k;
     return hipSuccess;
@@ -1383,7 +1394,7 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
         TK_LAUNCHED();
         if (double *pin = pinned_scratch()) {
             TK_HIP(hipMemcpyAsync(pin, L.theta, sizeof(double) * 2 * b, hipMemcpyDeviceToHost, s));
-            TK_HIP(hipStreamSynchronize(s));
+            TK_HIP(wait_stream(s));
             std::copy(pin, pin + 2 * b, h.begin());
         } else {
             TK_HIP(hipMemcpyAsync(h.data(), L.theta, sizeof(double) * 2 * b, hipMemcpyDeviceToHost, s));
@@ -1433,9 +1444,10 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
             const double rate = tha[1] / tha[0];
             const int steps = std::min(60, 2 + (int)std::ceil(std::log(lock_tol / res[0]) / std::log(rate)));
             TK_HIP(power_lock(mprod, n, b, Xc, steps, tha[0], L, s));
-            double th1 = 0.0;
-            TK_HIP(hipMemcpyAsync(&th1, L.theta, sizeof(double), hipMemcpyDeviceToHost, s));
-            TK_HIP(hipStreamSynchronize(s));
+            double th1 = 0.0, *pin = pinned_scratch();
+            TK_HIP(hipMemcpyAsync(pin ? pin + 600 : &th1, L.theta, sizeof(double), hipMemcpyDeviceToHost, s));
+            TK_HIP(wait_stream(s));
+            if (pin) th1 = pin[600];
             matvecs += steps + 1;
             tha[0] = th1;
             newl = 1;
@@ -1508,13 +1520,23 @@ hipError_t lead_eig(double *M, int n, int J, double *X, double *F, double *theta
     std::vector<int> perm(J);
     for (int j = 0; j < J; ++j) perm[j] = j;
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) { return all[a] > all[c]; });
-    std::vector<double> sorted(J);
-    for (int j = 0; j < J; ++j) sorted[j] = all[perm[j]];
-    TK_HIP(hipMemcpyAsync(L.colmap, perm.data(), sizeof(int) * J, hipMemcpyHostToDevice, s));
-    TK_HIP(hipMemcpyAsync(theta_dev, sorted.data(), sizeof(double) * J, hipMemcpyHostToDevice, s));
+    // uploaded from the thread's pinned buffer (its region is written again
+    // only after this thread's next solve has waited on its stream), so no
+    // wait here; from pageable vectors with a wait when there is none
+    double *pin = pinned_scratch();
+    double *sorted = pin ? pin + 640 : all.data();
+    int *pm = pin ? reinterpret_cast<int *>(pin + 640 + kMaxBlock) : perm.data();
+    std::vector<double> sv(J);
+    for (int j = 0; j < J; ++j) sv[j] = all[perm[j]];
+    for (int j = 0; j < J; ++j) {
+        sorted[j] = sv[j];
+        pm[j] = perm[j];
+    }
+    TK_HIP(hipMemcpyAsync(L.colmap, pm, sizeof(int) * J, hipMemcpyHostToDevice, s));
+    TK_HIP(hipMemcpyAsync(theta_dev, sorted, sizeof(double) * J, hipMemcpyHostToDevice, s));
     k_extract<<<J, 256, 0, s>>>(Xc, n, b, J, F, L.colmap);
     TK_LAUNCHED();
-    TK_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
+    if (!pin) TK_HIP(hipStreamSynchronize(s));  // host vectors above go out of scope
     return hipSuccess;
 }
 
