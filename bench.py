@@ -395,9 +395,11 @@ def ttmc_rates(results, nu, first_sweep=2):
     return statistics.median(meds)
 
 
-def proj_roofline(results, dims, J, nu, F, prec, fp64, fs, kernel, core_only=False):
+def proj_roofline(results, dims, J, nu, F, prec, fp64, fs, kernel, core_only=False, dual=False):
     """Roofline of the projection launches of one output precision: ratio of
-    the summed algorithmic (method-minimal) bytes to the summed launch time."""
+    the summed algorithmic (method-minimal) bytes to the summed launch time.
+    dual: the core's FP32 launch also writes the BF16 Gram copy of the same
+    fibres (2 more bytes per output element)."""
     byt, ms, exe, n = 0.0, 0.0, 0.0, 0
     for r in results:
         for e in events(r, "project"):
@@ -405,8 +407,8 @@ def proj_roofline(results, dims, J, nu, F, prec, fp64, fs, kernel, core_only=Fal
                 continue
             m, s = e["mode"], ELEM[prec]
             ld = ld_of(J[m], 4) if core_only else ld_of(J[m], s)
-            byt += proj_min_bytes(nu, F[m], J[m], s, fp64)
-            exe += proj_exec_bytes(nu, F[m], J[m], s, fp64, dims[m], fs, ld)
+            byt += proj_min_bytes(nu, F[m], J[m], s, fp64) + (F[m] * J[m] * 2 if dual else 0)
+            exe += proj_exec_bytes(nu, F[m], J[m], s, fp64, dims[m], fs, ld) + (F[m] * ld * 2 if dual else 0)
             ms += e["ms"]
             n += 1
     if n == 0:
@@ -604,8 +606,9 @@ def main():
                    "dims": list(dims), "nnz": nnz, "core": list(J), "algo": args.algo,
                    "precision": args.precision, "sweeps": sweeps, "seed": w["seed"]},
         "value_definition": "3*nnz / (summed HIP-event time of every projection launch of the sweep, including "
-                            "the FP32 projection for the core, plus HOOI second-stage products), median over sweeps "
-                            "2..10, median over steps",
+                            "the FP32 projection for the core (in mixed precision one launch that also writes mode "
+                            "3's BF16 Gram copy), plus HOOI second-stage products), median over sweeps 2..10, median "
+                            "over steps",
         "roofline": roof_proj,
         "phase_ms_per_sweep": {k: round(st[k] / max(1, sweeps), 4) for k in
                                ("project_ms", "ttmc_ms", "gram_ms", "eig_ms", "core_ms")},
@@ -617,10 +620,15 @@ def main():
     forms = {}
     if args.algo == "mp":
         if args.precision == "mixed":
-            # the FP32 projection of mode 3 that feeds the core (the fourth launch of a sweep)
+            # the FP32 projection of mode 3 that feeds the core; when the sweep
+            # has no BF16 launch of mode 3, that launch also wrote the BF16
+            # Gram copy (the dual form: three launches per sweep)
+            dual = not any(e["mode"] == 2 and e["precision"] == 2 for r in results for e in events(r, "project"))
             forms["core_projection_fp32"] = proj_roofline(
-                results, dims, J, nu, F, 1, False, 4, "k_project_vec<float, float, float> (fibre list, core input)",
-                core_only=True)
+                results, dims, J, nu, F, 1, False, 4,
+                "k_project_vec<float, float, float, ..., DUAL> (fibre list, core input + BF16 Gram copy)" if dual
+                else "k_project_vec<float, float, float> (fibre list, core input)", core_only=True, dual=dual)
+            forms["core_projection_fp32"]["dual"] = dual
         forms[f"gram_{args.precision}"] = gram_roofline(results, dims, J, occ, pcode)
     line["roofline_forms"] = forms
 

@@ -1054,9 +1054,31 @@ static int hosvd_report_around_start(Plan &p, const tk_opts *o, double *core, do
 
 // MP and SP core from T(2)(C): the projection itself when it is FP64 or
 // FP32, else (BF16 Grams) an FP32 projection with rows of ldc for it.
-static hipError_t slice_core(Plan &p, const double *A, const double *B, double *core, hipStream_t s, Timer &tm) {
+// The last projection of an MP / SP sweep, T(2)(C), which both the core and
+// the next sweep's first Gram read. Mixed precision without split parts: one
+// pass writes the core's FP32 copy (from the FP32 factor rows) and the BF16
+// Gram copy rounded from it; *core_done then says that slice_core need not
+// project again.
+static hipError_t project_last(Plan &p, const double *C, hipStream_t s, Timer &tm, bool *core_done) {
+    *core_done = false;
+    const FibreList fl = fibres_of(p, 2, true);
+    if (p.prec == PBF16 && !p.split && p.Fc &&
+        project_dual_ok(p.Fc, p.I[2], p.ldc, p.Tcore, (const bf16 *)p.T[2], p.ldT[2], p.nslots[2], p.nnz, p.tune,
+                        fl)) {
+        TK_HIP(project_dual(p.ptr[2], p.lidx[2], p.lval32[2], p.Fc, p.I[2], p.ldc, p.J[2], p.nslots[2], p.nnz,
+                            p.Tcore, (bf16 *)p.T[2], p.ldT[2], s, p.tune, tm.kernel(kProj, 2, P32), fl));
+        *core_done = true;
+        return hipSuccess;
+    }
+    return project_m(p, 2, C, p.T[2], p.prec, s, 0, tm.kernel(kProj, 2, p.prec));
+}
+
+static hipError_t slice_core(Plan &p, const double *A, const double *B, double *core, hipStream_t s, Timer &tm,
+                             bool projected = false) {
     const void *T2c = p.T[2];
-    if (p.prec == PBF16) {
+    if (p.prec == PBF16 && projected) {
+        T2c = p.Tcore;
+    } else if (p.prec == PBF16) {
         TK_HIP((project<float, float, float>(p.ptr[2], p.lidx[2], p.lval32[2], p.Fc, p.I[2], p.ldc, p.J[2], p.ldc,
                                              p.nslots[2], p.nnz, p.Tcore, s, p.tune, tm.kernel(kProj, 2, P32),
                                              fibres_of(p, 2, true))));
@@ -1124,9 +1146,10 @@ extern "C" int tucker_mp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         tm.begin(kEig, 2, P64);
         if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
         tm.end();
-        ST(project_m(p, 2, C, p.T[2], prec, s, 0, tm.kernel(kProj, 2, prec)));
+        bool core_done = false;
+        ST(project_last(p, C, s, tm, &core_done));
         // core from T(2)(C) (FP64 or FP32, never BF16)
-        ST(slice_core(p, A, B, core, s, tm));
+        ST(slice_core(p, A, B, core, s, tm, core_done));
         double fit = 0;
         if ((st = finish_fit(p, core, s, &fit, &g2))) return st;
         tm.collect();
@@ -1427,8 +1450,9 @@ extern "C" int tucker_sp(const tk_coo *X, const int32_t *J, const tk_opts *o, do
         if ((st = run_eig(p, 2, p.Mg, C, true, o, stats, &noconv, s))) return st;
         tm.end();
         // T(2)(C): the core now, mode 1's Gram in the next sweep
-        ST(project_m(p, 2, C, p.T[2], prec, s, 0, tm.kernel(kProj, 2, prec)));
-        ST(slice_core(p, A, B, core, s, tm));
+        bool core_done = false;
+        ST(project_last(p, C, s, tm, &core_done));
+        ST(slice_core(p, A, B, core, s, tm, core_done));
         double fit = 0;
         if ((st = finish_fit(p, core, s, &fit, &g2))) return st;
         tm.collect();

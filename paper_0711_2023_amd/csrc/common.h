@@ -200,6 +200,18 @@ hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, cons
 hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *lval, const float *F, int64_t rowsF,
                          int ld, int J, int64_t nslots, int64_t nnz, bf16 *Thi, bf16 *Tlo, hipStream_t s,
                          const Tune &tn = Tune(), KernelEvents ke = KernelEvents(), FibreList fl = FibreList());
+// FP32 projection into T over the fibre list fl (rows of ld, a multiple of
+// 4, as the factor rows F) that also writes each output rounded to BF16 into
+// T2 (rows of ld2 = ld or ld + 4, a multiple of 8; columns from ld on are
+// written as zeros, the rows of empty fibres keep what T2 holds), in one pass
+// over the nonzeros. Only where
+// project_dual_ok holds (the fibre-list vector form with 32-bit offsets for
+// both outputs); else hipErrorInvalidValue and nothing is launched.
+bool project_dual_ok(const float *F, int64_t rowsF, int ld, const float *T, const bf16 *T2, int ld2,
+                     int64_t nslots, int64_t nnz, const Tune &tn, const FibreList &fl);
+hipError_t project_dual(const int32_t *ptr, const int32_t *lidx, const float *lval, const float *F, int64_t rowsF,
+                        int ld, int J, int64_t nslots, int64_t nnz, float *T, bf16 *T2, int ld2, hipStream_t s,
+                        const Tune &tn, KernelEvents ke, FibreList fl);
 // out[i * ld + r] = in[i * J + r] for r < J, zero for J <= r < ld.
 template <class TO>
 hipError_t pad_rows(const double *in, int64_t rows, int J, int ld, TO *out, hipStream_t s);

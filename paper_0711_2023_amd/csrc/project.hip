@@ -200,14 +200,19 @@ __device__ inline void load_row(__amdgpu_buffer_rsrc_t r, uint32_t off, u32x4 (&
 // and only their rows are written; the rows of empty fibres keep what the
 // buffer holds (zeros written once before the first such projection). Else
 // the units are all slots and empty ones are written as zeros.
-template <class TV, class TF, class TO, bool SPLIT = false, bool FIB = false>
+// DUAL (FP32 output): each chunk is also written rounded to BF16 into T2,
+// whose rows have stride ld2 (ldT or ldT + 4, a multiple of 8; the same
+// fibre's row, its last 4 columns written as zeros when ld2 > ldT), so that
+// one pass over the nonzeros serves both an FP32 and a BF16 consumer.
+template <class TV, class TF, class TO, bool SPLIT = false, bool FIB = false, bool DUAL = false>
 __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__restrict__ ptr,
                                                               const int32_t *__restrict__ fib,
                                                               const int32_t *__restrict__ lidx,
                                                               const TV *__restrict__ lval,
                                                               const TF *__restrict__ F, uint32_t Fbytes, int32_t J,
                                                               int32_t ldT, int32_t spw, int32_t cap, int64_t nslots,
-                                                              TO *__restrict__ T, TO *__restrict__ Tlo = nullptr) {
+                                                              TO *__restrict__ T, TO *__restrict__ Tlo,
+                                                              bf16 *__restrict__ T2, int32_t ld2) {
     typedef typename AccOf<TV>::type Acc;
     constexpr int V = 16 / sizeof(TO);              // outputs per chunk
     constexpr int NL = V * (int)sizeof(TF) / 16;    // 16-byte factor loads per chunk
@@ -260,6 +265,23 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
             for (int t = 0; t < V; ++t) o2[t] = (TO)(acc[t] - (Acc)o[t]);
             __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, o2), buf_rsrc(Tlo + row0 * ldT, outb), off,
                                                    0, 0);
+        }
+        if (DUAL) {  // V = 4 FP32 outputs -> 4 BF16 (8 bytes)
+            typedef bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+            bf16x4 h;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) h[t] = (bf16)acc[t];
+            const uint32_t off2 = ((uint32_t)orow * (uint32_t)ld2 + (uint32_t)r * 4u) * 2u;
+            const __amdgpu_buffer_rsrc_t r2 = buf_rsrc(T2 + row0 * ld2, (uint32_t)nrows * (uint32_t)ld2 * 2u);
+            if (r == cps - 1 && ld2 > ldT) {
+                // the row's last chunk also writes the 4 zero padding columns:
+                // whole rows, with no holes that split the memory lines
+                const u32x2 hv = __builtin_bit_cast(u32x2, h);
+                __builtin_amdgcn_raw_buffer_store_b128(u32x4{hv[0], hv[1], 0u, 0u}, r2, off2, 0, 0);
+            } else {
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, h), r2, off2, 0, 0);
+            }
         }
     };
     // one unit of the run, with any of its nonzeros read from global memory
@@ -394,12 +416,12 @@ hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, cons
             const ProjShape sh = proj_shape(fl.n, ldT, tn, cap_max);
             launch(k_project_vec<TV, TF, TO, false, true>, sh.blocks, vec_lds<TV>(sh, true), s, ke, fl.fptr, fl.fib,
                    lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap, fl.n, T,
-                   (TO *)nullptr);
+                   (TO *)nullptr, (bf16 *)nullptr, (int32_t)0);
         } else {
             const ProjShape sh = proj_shape(nslots, ldT, tn, cap_max);
             launch(k_project_vec<TV, TF, TO, false, false>, sh.blocks, vec_lds<TV>(sh, false), s, ke, ptr,
                    (const int32_t *)nullptr, lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw,
-                   (int32_t)sh.cap, nslots, T, (TO *)nullptr);
+                   (int32_t)sh.cap, nslots, T, (TO *)nullptr, (bf16 *)nullptr, (int32_t)0);
         }
     } else {
         const ProjShape sh = proj_shape(nslots, ldT, tn, 4096);
@@ -407,6 +429,30 @@ hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, cons
         launch(k_project<TV, TF, TO>, sh.blocks, lds, s, ke, ptr, lidx, lval, F, (int32_t)ldF, (int32_t)J,
                (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap, nslots, T);
     }
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
+bool project_dual_ok(const float *F, int64_t rowsF, int ld, const float *T, const bf16 *T2, int ld2,
+                     int64_t nslots, int64_t nnz, const Tune &tn, const FibreList &fl) {
+    return nslots > 0 && ld > 0 &&
+           vec_ok<float, float, float>(F, rowsF, ld, T, proj_shape(nslots, ld, tn, 4096).spw, nnz) &&
+           ((uintptr_t)T2 & 15) == 0 && (ld2 == ld || ld2 == ld + 4) && ld2 % 8 == 0 &&
+           fib_ok<float>(fl, nslots, ld) &&
+           nslots * (int64_t)ld2 * 2 < (int64_t(1) << 31);
+}
+
+hipError_t project_dual(const int32_t *ptr, const int32_t *lidx, const float *lval, const float *F, int64_t rowsF,
+                        int ld, int J, int64_t nslots, int64_t nnz, float *T, bf16 *T2, int ld2, hipStream_t s,
+                        const Tune &tn, KernelEvents ke, FibreList fl) {
+    (void)ptr;
+    if (!project_dual_ok(F, rowsF, ld, T, T2, ld2, nslots, nnz, tn, fl)) return hipErrorInvalidValue;
+    if (fl.n <= 0) return hipSuccess;  // no nonzeros: every row keeps its zeros
+    const uint32_t Fb = (uint32_t)(rowsF * ld * (int64_t)sizeof(float));
+    const ProjShape sh = proj_shape(fl.n, ld, tn, 4096);
+    launch(k_project_vec<float, float, float, false, true, true>, sh.blocks, vec_lds<float>(sh, true), s, ke, fl.fptr,
+           fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw, (int32_t)sh.cap, fl.n, T,
+           (float *)nullptr, T2, (int32_t)ld2);
     TK_LAUNCHED();
     return hipSuccess;
 }
@@ -423,12 +469,13 @@ hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *l
         if (fl.n <= 0) return hipSuccess;
         const ProjShape sh = proj_shape(fl.n, ld, tn, 4096);
         launch(k_project_vec<float, float, bf16, true, true>, sh.blocks, vec_lds<float>(sh, true), s, ke, fl.fptr,
-               fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw, (int32_t)sh.cap, fl.n, Thi, Tlo);
+               fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw, (int32_t)sh.cap, fl.n, Thi, Tlo,
+               (bf16 *)nullptr, (int32_t)0);
     } else {
         const ProjShape sh = proj_shape(nslots, ld, tn, 4096);
         launch(k_project_vec<float, float, bf16, true, false>, sh.blocks, vec_lds<float>(sh, false), s, ke, ptr,
                (const int32_t *)nullptr, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw,
-               (int32_t)sh.cap, nslots, Thi, Tlo);
+               (int32_t)sh.cap, nslots, Thi, Tlo, (bf16 *)nullptr, (int32_t)0);
     }
     TK_LAUNCHED();
     return hipSuccess;
