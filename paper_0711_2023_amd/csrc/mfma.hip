@@ -98,6 +98,9 @@ template <>
 __device__ inline bf16 cvt<bf16, double>(double x) { return (bf16)(float)x; }
 
 // ------------------------------------------------------------------ Gram
+constexpr int kGramWideMin = 768;  // BF16 Grams of at least this order use 256-row tiles
+constexpr int kGramRing = 4;       // stages in flight in k_gram_dl
+
 struct GramTermK {
     const void *base, *base_b;
     int64_t s_row, s_chunk, chunk_len, nchunks;
@@ -124,13 +127,13 @@ __device__ inline void pair_decode(int pair, int &ti, int &tj) {
 template <class E> struct GramKS { static constexpr int v = 128 / sizeof(E); };
 template <> struct GramKS<bf16> { static constexpr int v = 64; };
 
-template <class P, int WT> struct GramCfg {
+template <class P, int TBK_, int NT> struct GramCfg {
     typedef typename P::E E;
-    static constexpr int TBK = 2 * WT;            // output tile
+    static constexpr int TBK = TBK_;              // output tile
     static constexpr int KS = GramKS<E>::v;       // stage depth
     static constexpr int VW = 16 / sizeof(E);     // elements per 16-byte vector
     static constexpr int TPR = KS / VW;           // threads per row per stage (8)
-    static constexpr int RPP = 256 / TPR;         // rows per load pass (32)
+    static constexpr int RPP = NT / TPR;          // rows per load pass (32 for 256 threads)
     static constexpr int PASSES = TBK / RPP;      // load passes per operand
     static constexpr int LDK = sizeof(E) == 2 ? KS + 8 : KS + 1;
 };
@@ -193,13 +196,19 @@ __device__ inline void store_stage(const StageRegs<Cfg, VEC> &R, typename Cfg::E
     }
 }
 
-template <class P, int WT, bool VEC>
-__global__ void __launch_bounds__(256) k_gram(GramKArgs g, typename P::Acc *partials) {
-    typedef GramCfg<P, WT> Cfg;
+// WR x WC waves, each computing a WTR x WTC part of the TBK x TBK output
+// tile (TBK = WR WTR = WC WTC); both operand row blocks of a stage in LDS
+// (gram_lds_bytes).
+template <class P, int WTR, int WTC, int WR, int WC, bool VEC>
+__global__ void __launch_bounds__(64 * WR * WC) k_gram(GramKArgs g, typename P::Acc *partials) {
+    constexpr int NT = 64 * WR * WC, TBK0 = WR * WTR;
+    static_assert(WC * WTC == TBK0, "square output tiles");
+    typedef GramCfg<P, TBK0, NT> Cfg;
     typedef typename P::E E;
     constexpr int TBK = Cfg::TBK, KS = Cfg::KS, LDK = Cfg::LDK;
-    __shared__ __attribute__((aligned(16))) E As[TBK * LDK];
-    __shared__ __attribute__((aligned(16))) E Bs[TBK * LDK];
+    constexpr int NBR = WTR / P::BT, NBC = WTC / P::BT;
+    extern __shared__ __attribute__((aligned(16))) char gram_smem[];
+    E *As = reinterpret_cast<E *>(gram_smem), *Bs = As + TBK * LDK;
     // XCD-aware item map: consecutive blocks go to different XCDs, so block
     // g runs on XCD g % 8; all tile pairs of one K-split share one XCD (and
     // its L2) by giving split s to XCD s % 8.
@@ -222,17 +231,17 @@ __global__ void __launch_bounds__(256) k_gram(GramKArgs g, typename P::Acc *part
     const int64_t kbeg = (int64_t)split * t.kper;
     const int64_t kend = kbeg + t.kper < K ? kbeg + t.kper : K;
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w / WC, wc = w % WC;
     const int kv = tid % Cfg::TPR, rr = tid / Cfg::TPR;
     int64_t k = kbeg + kv * Cfg::VW;
     int64_t kc = k / t.chunk_len, kr = k - kc * t.chunk_len;
     const int64_t rowA0 = (int64_t)ti * TBK, rowB0 = (int64_t)tj * TBK;
 
-    typename P::Frag acc[P::NB][P::NB];
+    typename P::Frag acc[NBR][NBC];
 #pragma unroll
-    for (int a = 0; a < P::NB; ++a)
+    for (int a = 0; a < NBR; ++a)
 #pragma unroll
-        for (int b = 0; b < P::NB; ++b) frag_zero<typename P::Frag, P::NV>(acc[a][b]);
+        for (int b = 0; b < NBC; ++b) frag_zero<typename P::Frag, P::NV>(acc[a][b]);
 
     StageRegs<Cfg, VEC> ra, rb;
     load_stage<Cfg, VEC>(ra, base, t, rowA0, g.n, k, kend, kc, kr, rr);
@@ -256,22 +265,245 @@ __global__ void __launch_bounds__(256) k_gram(GramKArgs g, typename P::Acc *part
 #pragma unroll
         for (int q = 0; q < KS; q += P::KI)
 #pragma unroll
-            for (int a = 0; a < P::NB; ++a)
+            for (int a = 0; a < NBR; ++a)
 #pragma unroll
-                for (int b = 0; b < P::NB; ++b)
-                    P::template mma_ld<LDK>(As, Bsrc, wr * WT + a * P::BT, wc * WT + b * P::BT, q, acc[a][b]);
+                for (int b = 0; b < NBC; ++b)
+                    P::template mma_ld<LDK>(As, Bsrc, wr * WTR + a * P::BT, wc * WTC + b * P::BT, q, acc[a][b]);
         __syncthreads();
     }
     typename P::Acc *out = partials + ((int64_t)pair * g.splits_total + sidx) * TBK * TBK;
 #pragma unroll
-    for (int a = 0; a < P::NB; ++a)
+    for (int a = 0; a < NBR; ++a)
 #pragma unroll
-        for (int b = 0; b < P::NB; ++b)
+        for (int b = 0; b < NBC; ++b)
 #pragma unroll
             for (int v = 0; v < P::NV; ++v) {
-                int r = wr * WT + a * P::BT + P::orow(v, lane);
-                int c = wc * WT + b * P::BT + P::ocol(v, lane);
+                int r = wr * WTR + a * P::BT + P::orow(v, lane);
+                int c = wc * WTC + b * P::BT + P::ocol(v, lane);
                 out[r * TBK + c] = acc[a][b][v];
+            }
+}
+
+// LDS of a k_gram launch: both operand row blocks of one stage.
+template <class P, int TBK>
+constexpr size_t gram_lds_bytes() {
+    return 2 * (size_t)TBK * GramCfg<P, TBK, 256>::LDK * sizeof(typename P::E);
+}
+
+// BF16 Gram with 256-row output tiles whose operand stages go from memory
+// straight into LDS (buffer loads with the LDS destination: no staging
+// registers), in a ring of four stages, so that the loads of a stage are
+// issued three stages ahead of the matrix-core work on it and a stage costs
+// one workgroup barrier. Stages are 32 K columns deep; an operand stage is
+// 256 LDS rows of 64 bytes, each filled by one 16-row wave load, the four
+// 16-byte chunks of row r at slots c ^ gram_dl_swz(r), so that fragment
+// reads of consecutive rows fall on distinct banks. Elements past the
+// split, the term or the order read as zeros (the load's offset is made out
+// of range). Eight waves as in k_gram<PolBF16, 64, 128, 4, 2>; the same
+// items, partial tiles and reduction.
+constexpr int kGramDlKS = 32, kGramDlRowB = 64, kGramDlStage = 256 * kGramDlRowB;
+constexpr uint32_t kGramDlOob = 0x80000000u;
+
+// Slot permutation of the chunks of LDS row r: chunk c sits at slot
+// c ^ gram_dl_swz(r). Any 8 aligned consecutive rows (two 16-byte units per
+// row in 128 bytes) and any 16 aligned consecutive rows (four per row in
+// 256 bytes) then read one chunk index from distinct units.
+__device__ inline int gram_dl_swz(int r) { return ((r >> 2) & 1) | ((((r >> 1) ^ (r >> 3)) & 1) << 1); }
+
+struct GramDlLane {
+    __amdgpu_buffer_rsrc_t ra, rb;
+    uint32_t rowA[2], rowB[2];  // element offsets of the lane's two rows per operand
+    bool okA[2], okB[2];
+    int64_t k, kc, kr, kend, chunk_len, s_chunk;
+};
+
+template <int SLOT>
+__device__ inline char *gram_dl_slot(bool b);
+
+__shared__ __attribute__((aligned(16))) char gram_dl_a0[kGramDlStage], gram_dl_b0[kGramDlStage];
+__shared__ __attribute__((aligned(16))) char gram_dl_a1[kGramDlStage], gram_dl_b1[kGramDlStage];
+__shared__ __attribute__((aligned(16))) char gram_dl_a2[kGramDlStage], gram_dl_b2[kGramDlStage];
+__shared__ __attribute__((aligned(16))) char gram_dl_a3[kGramDlStage], gram_dl_b3[kGramDlStage];
+template <> __device__ inline char *gram_dl_slot<0>(bool b) { return b ? gram_dl_b0 : gram_dl_a0; }
+template <> __device__ inline char *gram_dl_slot<1>(bool b) { return b ? gram_dl_b1 : gram_dl_a1; }
+template <> __device__ inline char *gram_dl_slot<2>(bool b) { return b ? gram_dl_b2 : gram_dl_a2; }
+template <> __device__ inline char *gram_dl_slot<3>(bool b) { return b ? gram_dl_b3 : gram_dl_a3; }
+
+// The lane's loads of the next stage into ring slot SLOT: two 16-row wave
+// loads per operand (rows 16 w and 16 (w + 8) of the tile), then the K
+// position moves on by one stage.
+template <int SLOT>
+__device__ inline void gram_dl_issue(GramDlLane &L, bool diag, int w) {
+    typedef __attribute__((address_space(3))) void lds_void;
+    const bool kin = L.k < L.kend;
+    const uint32_t koff = (uint32_t)(L.kc * L.s_chunk + L.kr);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        char *dst = gram_dl_slot<SLOT>(false) + (16 * (w + 8 * h)) * kGramDlRowB;
+        const uint32_t off = kin && L.okA[h] ? (L.rowA[h] + koff) * 2u : kGramDlOob;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(L.ra, (lds_void *)dst, 16, off, 0, 0, 0);
+    }
+    if (!diag) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            char *dst = gram_dl_slot<SLOT>(true) + (16 * (w + 8 * h)) * kGramDlRowB;
+            const uint32_t off = kin && L.okB[h] ? (L.rowB[h] + koff) * 2u : kGramDlOob;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(L.rb, (lds_void *)dst, 16, off, 0, 0, 0);
+        }
+    }
+    L.k += kGramDlKS;
+    L.kr += kGramDlKS;
+    while (L.kr >= L.chunk_len) {
+        L.kr -= L.chunk_len;
+        ++L.kc;
+    }
+}
+
+// The six fragments of one 16-deep step, read in one asm block that waits
+// for them itself (the compiler would otherwise make every LDS read wait
+// for all buffer loads in flight, as it cannot tell the ring slots apart).
+__device__ inline void gram_dl_frags(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3,
+                                     bf16x8 (&fa)[2], bf16x8 (&fb)[4]) {
+    asm volatile(
+        "ds_read_b128 %0, %6\n\t"
+        "ds_read_b128 %1, %7\n\t"
+        "ds_read_b128 %2, %8\n\t"
+        "ds_read_b128 %3, %9\n\t"
+        "ds_read_b128 %4, %10\n\t"
+        "ds_read_b128 %5, %11\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(fa[0]), "=&v"(fa[1]), "=&v"(fb[0]), "=&v"(fb[1]), "=&v"(fb[2]), "=&v"(fb[3])
+        : "v"(a0), "v"(a1), "v"(b0), "v"(b1), "v"(b2), "v"(b3)
+        : "memory");
+}
+
+__device__ inline uint32_t lds_addr(const char *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)p;
+}
+
+template <int SLOT>
+__device__ inline void gram_dl_mma(floatx16 (&acc)[2][4], bool diag, int wr, int wc, int lane) {
+    const uint32_t A = lds_addr(gram_dl_slot<SLOT>(false));
+    const uint32_t B = diag ? A : lds_addr(gram_dl_slot<SLOT>(true));
+#pragma unroll
+    for (int q = 0; q < kGramDlKS / 16; ++q) {
+        const int ch = 2 * q + (lane >> 5);
+        uint32_t ad[6];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int r = wr * 64 + a * 32 + (lane & 31);
+            ad[a] = A + r * kGramDlRowB + ((ch ^ gram_dl_swz(r)) << 4);
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int r = wc * 128 + b * 32 + (lane & 31);
+            ad[2 + b] = B + r * kGramDlRowB + ((ch ^ gram_dl_swz(r)) << 4);
+        }
+        bf16x8 fa[2], fb[4];
+        gram_dl_frags(ad[0], ad[1], ad[2], ad[3], ad[4], ad[5], fa, fb);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+}
+
+// Wait until at most n (0, 2, 4, 6 or 8) of the wave's buffer loads are in
+// flight.
+__device__ inline void gram_dl_wait(int n) {
+    // s_waitcnt immediates: vmcnt n, expcnt and lgkmcnt not waited on
+    switch (n) {
+        case 0: __builtin_amdgcn_s_waitcnt(0x0f70); break;
+        case 2: __builtin_amdgcn_s_waitcnt(0x0f72); break;
+        case 4: __builtin_amdgcn_s_waitcnt(0x0f74); break;
+        case 6: __builtin_amdgcn_s_waitcnt(0x0f76); break;
+        default: __builtin_amdgcn_s_waitcnt(0x0f78); break;
+    }
+}
+
+template <int SLOT>
+__device__ inline void gram_dl_step(GramDlLane &L, floatx16 (&acc)[2][4], int s, int nst, int lps, bool diag, int w,
+                                    int wr, int wc, int lane) {
+    // this wave's loads of stage s have landed once only the later issued
+    // stages (at most two) are in flight; the barrier makes every wave's part
+    // visible and frees the slot read by stage s - 1
+    const int issued = s + kGramRing - 1 < nst ? s + kGramRing - 1 : nst;
+    gram_dl_wait((issued - s - 1) * lps);
+    // a bare barrier: every LDS read of the wave has completed (the reads
+    // wait for themselves) and its loads of stage s have landed
+    asm volatile("s_barrier" ::: "memory");
+    if (s + kGramRing - 1 < nst) gram_dl_issue<(SLOT + kGramRing - 1) % kGramRing>(L, diag, w);
+    gram_dl_mma<SLOT>(acc, diag, wr, wc, lane);
+}
+
+__global__ void __launch_bounds__(512) k_gram_dl(GramKArgs g, float *partials) {
+    const int gx = blockIdx.x % 8, gq = blockIdx.x / 8;
+    const int rnd = gq / g.npairs, pair = gq - rnd * g.npairs;
+    const int sidx = rnd * 8 + gx;
+    if (sidx >= g.splits_total) return;
+    int term = 0;
+    for (int q = 1; q < g.nterms; ++q)
+        if (sidx >= g.t[q].split_begin) term = q;
+    const GramTermK t = g.t[term];
+    const int split = sidx - t.split_begin;
+    int ti, tj;
+    pair_decode(pair, ti, tj);
+    const bool diag = ti == tj && t.base_b == t.base;
+    const int64_t K = t.chunk_len * t.nchunks;
+    const int64_t kbeg = (int64_t)split * t.kper;
+    const int64_t kend = kbeg + t.kper < K ? kbeg + t.kper : K;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+    // the operand's extent in bytes (the host has checked it is below 2^31)
+    const uint32_t nbytes =
+        (uint32_t)((((int64_t)g.n - 1) * t.s_row + (t.nchunks - 1) * t.s_chunk + t.chunk_len) * 2);
+    GramDlLane L;
+    L.ra = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(t.base), (short)0, (int)nbytes, 0x00020000);
+    L.rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(t.base_b), (short)0, (int)nbytes, 0x00020000);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int64_t ra = (int64_t)ti * 256 + 16 * (w + 8 * h) + (lane >> 2);
+        const int64_t rb = (int64_t)tj * 256 + 16 * (w + 8 * h) + (lane >> 2);
+        L.okA[h] = ra < g.n;
+        L.okB[h] = rb < g.n;
+        L.rowA[h] = (uint32_t)((L.okA[h] ? ra : 0) * t.s_row);
+        L.rowB[h] = (uint32_t)((L.okB[h] ? rb : 0) * t.s_row);
+    }
+    // the lane's chunk of each row: its slot lane % 4 of row lane / 4 (mod
+    // 16) holds chunk c
+    const int c = (lane & 3) ^ gram_dl_swz(lane >> 2);
+    L.k = kbeg + 8 * c;
+    L.kend = kend;
+    L.chunk_len = t.chunk_len;
+    L.s_chunk = t.s_chunk;
+    L.kc = L.k / t.chunk_len;
+    L.kr = L.k - L.kc * t.chunk_len;
+    const int nst = (int)((kend - kbeg + kGramDlKS - 1) / kGramDlKS);
+    const int lps = diag ? 2 : 4;
+
+    floatx16 acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) frag_zero<floatx16, 16>(acc[a][b]);
+    if (nst > 0) gram_dl_issue<0>(L, diag, w);
+    if (nst > 1) gram_dl_issue<1>(L, diag, w);
+    if (nst > 2) gram_dl_issue<2>(L, diag, w);
+    for (int s = 0; s < nst; s += kGramRing) {
+        gram_dl_step<0>(L, acc, s, nst, lps, diag, w, wr, wc, lane);
+        if (s + 1 < nst) gram_dl_step<1>(L, acc, s + 1, nst, lps, diag, w, wr, wc, lane);
+        if (s + 2 < nst) gram_dl_step<2>(L, acc, s + 2, nst, lps, diag, w, wr, wc, lane);
+        if (s + 3 < nst) gram_dl_step<3>(L, acc, s + 3, nst, lps, diag, w, wr, wc, lane);
+    }
+    float *out = partials + ((int64_t)pair * g.splits_total + sidx) * 256 * 256;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int r = wr * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int cc = wc * 128 + b * 32 + (lane & 31);
+                out[r * 256 + cc] = acc[a][b][v];
             }
 }
 
@@ -305,13 +537,19 @@ struct GramPlan {
 
 static GramPlan gram_plan(int n, int prec, int nterms, const int64_t *K, const Tune &tn) {
     GramPlan p;
-    p.TBK = prec == P64 ? 64 : 128;
+    // BF16 operands of a large Gram: 256-row tiles (eight waves, one
+    // workgroup per CU), which read each operand byte half as often as
+    // 128-row tiles; else 128 (64 for FP64)
+    p.TBK = prec == P64 ? 64 : (prec == PBF16 && n >= kGramWideMin ? 256 : 128);
     p.KS = prec == P64 ? 16 : (prec == P32 ? 32 : 64);
     p.acc_size = prec == P64 ? 8 : 4;
     int nt = (int)ceil_div(n, p.TBK);
     p.npairs = nt * (nt + 1) / 2;
-    // about tn.gram_items blocks in flight, at least tn.gram_min_stages stages per block
-    int want = (int)std::max<int64_t>(1, ceil_div(tn.gram_items, (int64_t)p.npairs * nterms));
+    // about tn.gram_items blocks in flight (a quarter for 256-row tiles, one
+    // workgroup per CU: rounded down, so that they fit one round), at least
+    // tn.gram_min_stages stages per block
+    int want = p.TBK == 256 ? (int)std::max<int64_t>(1, (tn.gram_items / 4) / ((int64_t)p.npairs * nterms))
+                            : (int)std::max<int64_t>(1, ceil_div(tn.gram_items, (int64_t)p.npairs * nterms));
     p.splits_total = 0;
     for (int t = 0; t < nterms; ++t) {
         int64_t Kt = K[t] > 0 ? K[t] : 1;
@@ -331,12 +569,16 @@ size_t gram_scratch_bytes(int n, int prec, int nterms, const int64_t *K, const T
     return (size_t)p.npairs * p.splits_total * p.TBK * p.TBK * p.acc_size;
 }
 
-template <class P, int WT, class Acc>
+template <class P, int WTR, int WTC, int WR, int WC, class Acc>
 static hipError_t launch_gram(const GramKArgs &g, bool vec, unsigned blocks, Acc *scratch, hipStream_t s) {
-    if (vec)
-        k_gram<P, WT, true><<<blocks, 256, 0, s>>>(g, scratch);
-    else
-        k_gram<P, WT, false><<<blocks, 256, 0, s>>>(g, scratch);
+    constexpr size_t lds = gram_lds_bytes<P, WR * WTR>();
+    if (vec) {
+        lds_limit((const void *)k_gram<P, WTR, WTC, WR, WC, true>, lds);
+        k_gram<P, WTR, WTC, WR, WC, true><<<blocks, 64 * WR * WC, lds, s>>>(g, scratch);
+    } else {
+        lds_limit((const void *)k_gram<P, WTR, WTC, WR, WC, false>, lds);
+        k_gram<P, WTR, WTC, WR, WC, false><<<blocks, 64 * WR * WC, lds, s>>>(g, scratch);
+    }
     TK_LAUNCHED();
     return hipSuccess;
 }
@@ -373,13 +615,25 @@ hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, v
     const int64_t total = (int64_t)p.npairs * p.TBK * p.TBK;
     const int rblocks = (int)std::min<int64_t>(ceil_div(total, 256), 65536);
     if (prec == P64) {
-        TK_HIP((launch_gram<PolF64<32>, 32>(g, vec, blocks, (double *)scratch, s)));
+        TK_HIP((launch_gram<PolF64<32>, 32, 32, 2, 2>(g, vec, blocks, (double *)scratch, s)));
         k_gram_reduce<double><<<rblocks, 256, 0, s>>>((const double *)scratch, p.splits_total, p.TBK, n, total, M);
     } else if (prec == P32) {
-        TK_HIP((launch_gram<PolF32<64>, 64>(g, vec, blocks, (float *)scratch, s)));
+        TK_HIP((launch_gram<PolF32<64>, 64, 64, 2, 2>(g, vec, blocks, (float *)scratch, s)));
         k_gram_reduce<float><<<rblocks, 256, 0, s>>>((const float *)scratch, p.splits_total, p.TBK, n, total, M);
     } else {
-        TK_HIP((launch_gram<PolBF16<64>, 64>(g, vec, blocks, (float *)scratch, s)));
+        // direct LDS staging where every operand's extent fits the 32-bit
+        // offsets of a buffer load
+        bool dl = vec && p.TBK == 256;
+        for (int t = 0; t < nterms && dl; ++t)
+            dl = (((int64_t)n - 1) * g.t[t].s_row + (g.t[t].nchunks - 1) * g.t[t].s_chunk + g.t[t].chunk_len) * 2 <
+                 (int64_t(1) << 31);
+        if (dl) {
+            k_gram_dl<<<blocks, 512, 0, s>>>(g, (float *)scratch);
+            TK_LAUNCHED();
+        } else if (p.TBK == 256)
+            TK_HIP((launch_gram<PolBF16<64>, 64, 128, 4, 2>(g, vec, blocks, (float *)scratch, s)));
+        else
+            TK_HIP((launch_gram<PolBF16<64>, 64, 64, 2, 2>(g, vec, blocks, (float *)scratch, s)));
         k_gram_reduce<float><<<rblocks, 256, 0, s>>>((const float *)scratch, p.splits_total, p.TBK, n, total, M);
     }
     TK_LAUNCHED();
