@@ -448,7 +448,9 @@ def gram_roofline(results, dims, J, occ, prec, algo="mp"):
     peak = PEAK_TFLOPS[PREC_NAME[prec]]
     tf = dense / (ms / 1000.0) / 1e12
     tfm = minimal / (ms / 1000.0) / 1e12
-    return {"kernel": "k_gram", "bound": "mfma", "operands": PREC_NAME[prec], "achieved": round(tf, 2),
+    # BF16 Grams of order >= 768 run the 256-row-tile kernel with the LDS ring
+    kern = "k_gram_dl" if prec == 2 and algo == "mp" and min(dims) >= 768 else "k_gram"
+    return {"kernel": kern, "bound": "mfma", "operands": PREC_NAME[prec], "achieved": round(tf, 2),
             "peak": peak, "unit": "TFLOP/s", "frac": round(tf / peak, 4),
             "achieved_minimal_flops": round(tfm, 2), "frac_minimal_flops": round(tfm / peak, 4),
             "dense_flops_per_launch": int(dense / n), "minimal_flops_per_launch": int(minimal / n),
