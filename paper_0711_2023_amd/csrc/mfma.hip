@@ -100,6 +100,7 @@ __device__ inline bf16 cvt<bf16, double>(double x) { return (bf16)(float)x; }
 // ------------------------------------------------------------------ Gram
 constexpr int kGramWideMin = 768;  // BF16 Grams of at least this order use 256-row tiles
 constexpr int kGramRing = 4;       // stages in flight in k_gram_dl
+constexpr int kGramDlWaves = 8;    // waves of a k_gram_dl workgroup (8: 64 x 128 each; 4: 128 x 128)
 
 struct GramTermK {
     const void *base, *base_b;
@@ -299,8 +300,10 @@ constexpr size_t gram_lds_bytes() {
 // 16-byte chunks of row r at slots c ^ gram_dl_swz(r), so that fragment
 // reads of consecutive rows fall on distinct banks. Elements past the
 // split, the term or the order read as zeros (the load's offset is made out
-// of range). Eight waves as in k_gram<PolBF16, 64, 128, 4, 2>; the same
-// items, partial tiles and reduction.
+// of range). kGramDlWaves waves (eight, each 64 x 128 as in
+// k_gram<PolBF16, 64, 128, 4, 2>; four of 128 x 128 read half the fragment
+// bytes per matrix-core step but ran 4 % slower); the same items, partial
+// tiles and reduction as k_gram.
 constexpr int kGramDlKS = 32, kGramDlRowB = 64, kGramDlStage = 256 * kGramDlRowB;
 constexpr uint32_t kGramDlOob = 0x80000000u;
 
@@ -312,8 +315,8 @@ __device__ inline int gram_dl_swz(int r) { return ((r >> 2) & 1) | ((((r >> 1) ^
 
 struct GramDlLane {
     __amdgpu_buffer_rsrc_t ra, rb;
-    uint32_t rowA[2], rowB[2];  // element offsets of the lane's two rows per operand
-    bool okA[2], okB[2];
+    uint32_t rowA[4], rowB[4];  // element offsets of the lane's rows (one per wave load of an operand)
+    bool okA[4], okB[4];
     int64_t k, kc, kr, kend, chunk_len, s_chunk;
 };
 
@@ -329,24 +332,25 @@ template <> __device__ inline char *gram_dl_slot<1>(bool b) { return b ? gram_dl
 template <> __device__ inline char *gram_dl_slot<2>(bool b) { return b ? gram_dl_b2 : gram_dl_a2; }
 template <> __device__ inline char *gram_dl_slot<3>(bool b) { return b ? gram_dl_b3 : gram_dl_a3; }
 
-// The lane's loads of the next stage into ring slot SLOT: two 16-row wave
-// loads per operand (rows 16 w and 16 (w + 8) of the tile), then the K
+// The lane's loads of the next stage into ring slot SLOT: 16 / NW wave loads
+// of 16 rows per operand (rows 16 (w + NW h) of the tile), then the K
 // position moves on by one stage.
-template <int SLOT>
+template <int SLOT, int NW>
 __device__ inline void gram_dl_issue(GramDlLane &L, bool diag, int w) {
     typedef __attribute__((address_space(3))) void lds_void;
+    constexpr int H = 16 / NW;
     const bool kin = L.k < L.kend;
     const uint32_t koff = (uint32_t)(L.kc * L.s_chunk + L.kr);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        char *dst = gram_dl_slot<SLOT>(false) + (16 * (w + 8 * h)) * kGramDlRowB;
+    for (int h = 0; h < H; ++h) {
+        char *dst = gram_dl_slot<SLOT>(false) + (16 * (w + NW * h)) * kGramDlRowB;
         const uint32_t off = kin && L.okA[h] ? (L.rowA[h] + koff) * 2u : kGramDlOob;
         __builtin_amdgcn_raw_ptr_buffer_load_lds(L.ra, (lds_void *)dst, 16, off, 0, 0, 0);
     }
     if (!diag) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            char *dst = gram_dl_slot<SLOT>(true) + (16 * (w + 8 * h)) * kGramDlRowB;
+        for (int h = 0; h < H; ++h) {
+            char *dst = gram_dl_slot<SLOT>(true) + (16 * (w + NW * h)) * kGramDlRowB;
             const uint32_t off = kin && L.okB[h] ? (L.rowB[h] + koff) * 2u : kGramDlOob;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(L.rb, (lds_void *)dst, 16, off, 0, 0, 0);
         }
@@ -359,11 +363,10 @@ __device__ inline void gram_dl_issue(GramDlLane &L, bool diag, int w) {
     }
 }
 
-// The six fragments of one 16-deep step, read in one asm block that waits
-// for them itself (the compiler would otherwise make every LDS read wait
-// for all buffer loads in flight, as it cannot tell the ring slots apart).
-__device__ inline void gram_dl_frags(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3,
-                                     bf16x8 (&fa)[2], bf16x8 (&fb)[4]) {
+// The fragments of one 16-deep step, read in one asm block that waits for
+// them itself (the compiler would otherwise make every LDS read wait for all
+// buffer loads in flight, as it cannot tell the ring slots apart).
+__device__ inline void gram_dl_frags(const uint32_t (&ad)[6], bf16x8 (&f)[6]) {
     asm volatile(
         "ds_read_b128 %0, %6\n\t"
         "ds_read_b128 %1, %7\n\t"
@@ -372,8 +375,23 @@ __device__ inline void gram_dl_frags(uint32_t a0, uint32_t a1, uint32_t b0, uint
         "ds_read_b128 %4, %10\n\t"
         "ds_read_b128 %5, %11\n\t"
         "s_waitcnt lgkmcnt(0)"
-        : "=&v"(fa[0]), "=&v"(fa[1]), "=&v"(fb[0]), "=&v"(fb[1]), "=&v"(fb[2]), "=&v"(fb[3])
-        : "v"(a0), "v"(a1), "v"(b0), "v"(b1), "v"(b2), "v"(b3)
+        : "=&v"(f[0]), "=&v"(f[1]), "=&v"(f[2]), "=&v"(f[3]), "=&v"(f[4]), "=&v"(f[5])
+        : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5])
+        : "memory");
+}
+__device__ inline void gram_dl_frags(const uint32_t (&ad)[8], bf16x8 (&f)[8]) {
+    asm volatile(
+        "ds_read_b128 %0, %8\n\t"
+        "ds_read_b128 %1, %9\n\t"
+        "ds_read_b128 %2, %10\n\t"
+        "ds_read_b128 %3, %11\n\t"
+        "ds_read_b128 %4, %12\n\t"
+        "ds_read_b128 %5, %13\n\t"
+        "ds_read_b128 %6, %14\n\t"
+        "ds_read_b128 %7, %15\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(f[0]), "=&v"(f[1]), "=&v"(f[2]), "=&v"(f[3]), "=&v"(f[4]), "=&v"(f[5]), "=&v"(f[6]), "=&v"(f[7])
+        : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5]), "v"(ad[6]), "v"(ad[7])
         : "memory");
 }
 
@@ -381,62 +399,72 @@ __device__ inline uint32_t lds_addr(const char *p) {
     return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)p;
 }
 
-template <int SLOT>
-__device__ inline void gram_dl_mma(floatx16 (&acc)[2][4], bool diag, int wr, int wc, int lane) {
+// One stage of matrix-core work on ring slot SLOT: the wave's WTR x 128
+// part of the tile (NBR x 4 fragments of 32 x 32), rows from wr WTR,
+// columns from wc 128.
+template <int SLOT, int NBR>
+__device__ inline void gram_dl_mma(floatx16 (&acc)[NBR][4], bool diag, int wr, int wc, int lane) {
     const uint32_t A = lds_addr(gram_dl_slot<SLOT>(false));
     const uint32_t B = diag ? A : lds_addr(gram_dl_slot<SLOT>(true));
 #pragma unroll
     for (int q = 0; q < kGramDlKS / 16; ++q) {
         const int ch = 2 * q + (lane >> 5);
-        uint32_t ad[6];
+        uint32_t ad[NBR + 4];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const int r = wr * 64 + a * 32 + (lane & 31);
+        for (int a = 0; a < NBR; ++a) {
+            const int r = wr * 32 * NBR + a * 32 + (lane & 31);
             ad[a] = A + r * kGramDlRowB + ((ch ^ gram_dl_swz(r)) << 4);
         }
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int r = wc * 128 + b * 32 + (lane & 31);
-            ad[2 + b] = B + r * kGramDlRowB + ((ch ^ gram_dl_swz(r)) << 4);
+            ad[NBR + b] = B + r * kGramDlRowB + ((ch ^ gram_dl_swz(r)) << 4);
         }
-        bf16x8 fa[2], fb[4];
-        gram_dl_frags(ad[0], ad[1], ad[2], ad[3], ad[4], ad[5], fa, fb);
+        bf16x8 f[NBR + 4];
+        gram_dl_frags(ad, f);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < NBR; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+            for (int b = 0; b < 4; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f[a], f[NBR + b], acc[a][b], 0, 0, 0);
     }
 }
 
-// Wait until at most n (0, 2, 4, 6 or 8) of the wave's buffer loads are in
-// flight.
+// Wait until at most n (0, 2, 4, 6, 8, 12 or 16) of the wave's buffer loads
+// are in flight.
 __device__ inline void gram_dl_wait(int n) {
-    // s_waitcnt immediates: vmcnt n, expcnt and lgkmcnt not waited on
+    // s_waitcnt immediates: vmcnt n (bits 3:0 and 15:14), expcnt and lgkmcnt
+    // not waited on
     switch (n) {
         case 0: __builtin_amdgcn_s_waitcnt(0x0f70); break;
         case 2: __builtin_amdgcn_s_waitcnt(0x0f72); break;
         case 4: __builtin_amdgcn_s_waitcnt(0x0f74); break;
         case 6: __builtin_amdgcn_s_waitcnt(0x0f76); break;
-        default: __builtin_amdgcn_s_waitcnt(0x0f78); break;
+        case 8: __builtin_amdgcn_s_waitcnt(0x0f78); break;
+        case 12: __builtin_amdgcn_s_waitcnt(0x0f7c); break;
+        default: __builtin_amdgcn_s_waitcnt(0x4f70); break;
     }
 }
 
-template <int SLOT>
-__device__ inline void gram_dl_step(GramDlLane &L, floatx16 (&acc)[2][4], int s, int nst, int lps, bool diag, int w,
-                                    int wr, int wc, int lane) {
+template <int SLOT, int NW, int NBR>
+__device__ inline void gram_dl_step(GramDlLane &L, floatx16 (&acc)[NBR][4], int s, int nst, int lps, bool diag,
+                                    int w, int wr, int wc, int lane) {
     // this wave's loads of stage s have landed once only the later issued
-    // stages (at most two) are in flight; the barrier makes every wave's part
-    // visible and frees the slot read by stage s - 1
+    // stages (at most two) are in flight
     const int issued = s + kGramRing - 1 < nst ? s + kGramRing - 1 : nst;
     gram_dl_wait((issued - s - 1) * lps);
     // a bare barrier: every LDS read of the wave has completed (the reads
-    // wait for themselves) and its loads of stage s have landed
+    // wait for themselves) and its loads of stage s have landed; after it no
+    // wave reads the slot of stage s - 1, which the next loads refill
     asm volatile("s_barrier" ::: "memory");
-    if (s + kGramRing - 1 < nst) gram_dl_issue<(SLOT + kGramRing - 1) % kGramRing>(L, diag, w);
-    gram_dl_mma<SLOT>(acc, diag, wr, wc, lane);
+    if (s + kGramRing - 1 < nst) gram_dl_issue<(SLOT + kGramRing - 1) % kGramRing, NW>(L, diag, w);
+    gram_dl_mma<SLOT, NBR>(acc, diag, wr, wc, lane);
 }
 
-__global__ void __launch_bounds__(512) k_gram_dl(GramKArgs g, float *partials) {
+// NW waves as NW / 2 x 2, each computing a (512 / NW) x 128 part of the tile.
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_gram_dl(GramKArgs g, float *partials) {
+    constexpr int NBR = 16 / NW, H = 16 / NW;
     const int gx = blockIdx.x % 8, gq = blockIdx.x / 8;
     const int rnd = gq / g.npairs, pair = gq - rnd * g.npairs;
     const int sidx = rnd * 8 + gx;
@@ -460,9 +488,9 @@ __global__ void __launch_bounds__(512) k_gram_dl(GramKArgs g, float *partials) {
     L.ra = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(t.base), (short)0, (int)nbytes, 0x00020000);
     L.rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(t.base_b), (short)0, (int)nbytes, 0x00020000);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int64_t ra = (int64_t)ti * 256 + 16 * (w + 8 * h) + (lane >> 2);
-        const int64_t rb = (int64_t)tj * 256 + 16 * (w + 8 * h) + (lane >> 2);
+    for (int h = 0; h < H; ++h) {
+        const int64_t ra = (int64_t)ti * 256 + 16 * (w + NW * h) + (lane >> 2);
+        const int64_t rb = (int64_t)tj * 256 + 16 * (w + NW * h) + (lane >> 2);
         L.okA[h] = ra < g.n;
         L.okB[h] = rb < g.n;
         L.rowA[h] = (uint32_t)((L.okA[h] ? ra : 0) * t.s_row);
@@ -478,30 +506,30 @@ __global__ void __launch_bounds__(512) k_gram_dl(GramKArgs g, float *partials) {
     L.kc = L.k / t.chunk_len;
     L.kr = L.k - L.kc * t.chunk_len;
     const int nst = (int)((kend - kbeg + kGramDlKS - 1) / kGramDlKS);
-    const int lps = diag ? 2 : 4;
+    const int lps = diag ? H : 2 * H;
 
-    floatx16 acc[2][4];
+    floatx16 acc[NBR][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NBR; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) frag_zero<floatx16, 16>(acc[a][b]);
-    if (nst > 0) gram_dl_issue<0>(L, diag, w);
-    if (nst > 1) gram_dl_issue<1>(L, diag, w);
-    if (nst > 2) gram_dl_issue<2>(L, diag, w);
+    if (nst > 0) gram_dl_issue<0, NW>(L, diag, w);
+    if (nst > 1) gram_dl_issue<1, NW>(L, diag, w);
+    if (nst > 2) gram_dl_issue<2, NW>(L, diag, w);
     for (int s = 0; s < nst; s += kGramRing) {
-        gram_dl_step<0>(L, acc, s, nst, lps, diag, w, wr, wc, lane);
-        if (s + 1 < nst) gram_dl_step<1>(L, acc, s + 1, nst, lps, diag, w, wr, wc, lane);
-        if (s + 2 < nst) gram_dl_step<2>(L, acc, s + 2, nst, lps, diag, w, wr, wc, lane);
-        if (s + 3 < nst) gram_dl_step<3>(L, acc, s + 3, nst, lps, diag, w, wr, wc, lane);
+        gram_dl_step<0, NW, NBR>(L, acc, s, nst, lps, diag, w, wr, wc, lane);
+        if (s + 1 < nst) gram_dl_step<1, NW, NBR>(L, acc, s + 1, nst, lps, diag, w, wr, wc, lane);
+        if (s + 2 < nst) gram_dl_step<2, NW, NBR>(L, acc, s + 2, nst, lps, diag, w, wr, wc, lane);
+        if (s + 3 < nst) gram_dl_step<3, NW, NBR>(L, acc, s + 3, nst, lps, diag, w, wr, wc, lane);
     }
     float *out = partials + ((int64_t)pair * g.splits_total + sidx) * 256 * 256;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NBR; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const int r = wr * 64 + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int r = wr * 32 * NBR + a * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const int cc = wc * 128 + b * 32 + (lane & 31);
                 out[r * 256 + cc] = acc[a][b][v];
             }
@@ -628,7 +656,7 @@ hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, v
             dl = (((int64_t)n - 1) * g.t[t].s_row + (g.t[t].nchunks - 1) * g.t[t].s_chunk + g.t[t].chunk_len) * 2 <
                  (int64_t(1) << 31);
         if (dl) {
-            k_gram_dl<<<blocks, 512, 0, s>>>(g, (float *)scratch);
+            k_gram_dl<kGramDlWaves><<<blocks, 64 * kGramDlWaves, 0, s>>>(g, (float *)scratch);
             TK_LAUNCHED();
         } else if (p.TBK == 256)
             TK_HIP((launch_gram<PolBF16<64>, 64, 128, 4, 2>(g, vec, blocks, (float *)scratch, s)));
