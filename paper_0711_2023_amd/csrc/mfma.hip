@@ -684,13 +684,29 @@ struct GemmKArgs {
     int64_t kper;
 };
 
+// K stage of k_gemm: the policy's. Each stage's loads go into registers
+// while the matrix cores work on the previous stage (the batched second
+// stage of HOOI's chain and the core contractions, 64 x 64 outputs over
+// K = 1000, are bound by those loads' latency). Stages of two and four
+// times the depth (more loads in flight, more registers, fewer waves per
+// SIMD) measured slower.
+template <class P> struct GemmStage {
+    static constexpr int KS = P::KS;
+    static constexpr int LDK = P::LDK;
+};
+template <class P>
+constexpr size_t gemm_lds_bytes() {
+    return (size_t)2 * 64 * GemmStage<P>::LDK * sizeof(typename P::E);
+}
+
 template <class P, class TA, class TBm, class TO>
 __global__ void __launch_bounds__(256) k_gemm(GemmKArgs g) {
     typedef typename P::E E;
     constexpr int WT = 32, BM = 64, BN = 64;
-    constexpr int KS = P::KS, LDK = P::LDK;
-    __shared__ E As[BM * LDK];
-    __shared__ E Bs[BN * LDK];
+    constexpr int KS = GemmStage<P>::KS, LDK = GemmStage<P>::LDK;
+    constexpr int NA = BM * KS / 256, NBL = BN * KS / 256;  // elements per thread and stage
+    extern __shared__ __attribute__((aligned(16))) char gemm_smem[];
+    E *As = reinterpret_cast<E *>(gemm_smem), *Bs = As + BM * LDK;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
     const int n0 = blockIdx.x * BN, m0 = blockIdx.y * BM;
     const int zb = blockIdx.z / g.splitk, split = blockIdx.z - zb * g.splitk;
@@ -705,39 +721,59 @@ __global__ void __launch_bounds__(256) k_gemm(GemmKArgs g) {
 #pragma unroll
         for (int b = 0; b < P::NB; ++b) frag_zero<typename P::Frag, P::NV>(acc[a][b]);
 
-    for (int64_t k0 = kbeg; k0 < kend; k0 += KS) {
-        // A tile: BM rows x KS
-        if (g.a_trans) {
-            // A(i,k) = A[k*lda + i]: i fastest
-            for (int e = tid; e < BM * KS; e += 256) {
-                int ii = e % BM, kk = e / BM;
-                int64_t i = m0 + ii, k = k0 + kk;
-                E v = (i < g.M && k < kend) ? cvt<E>(A[k * g.lda + i]) : (E)0;
-                As[ii * LDK + kk] = v;
-            }
-        } else {
-            for (int e = tid; e < BM * KS; e += 256) {
-                int kk = e % KS, ii = e / KS;
-                int64_t i = m0 + ii, k = k0 + kk;
-                E v = (i < g.M && k < kend) ? cvt<E>(A[i * g.lda + k]) : (E)0;
-                As[ii * LDK + kk] = v;
-            }
-        }
-        // B tile: BN cols x KS, B(k,j) = B[k*ldb + j]: j fastest
-        for (int e = tid; e < BN * KS; e += 256) {
-            int jj = e % BN, kk = e / BN;
-            int64_t j = n0 + jj, k = k0 + kk;
-            E v = (j < g.N && k < kend) ? cvt<E>(B[k * g.ldb + j]) : (E)0;
-            Bs[jj * LDK + kk] = v;
-        }
-        __syncthreads();
+    // element u of the thread's share of a stage: A tile BM rows x KS (i
+    // fastest when A is stored transposed, else k), B tile BN cols x KS (j
+    // fastest)
+    E ra[NA], rb[NBL];
+    auto load = [&](int64_t k0) {
 #pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + u * 256;
+            int ii, kk;
+            if (g.a_trans) {
+                ii = e % BM;
+                kk = e / BM;
+            } else {
+                kk = e % KS;
+                ii = e / KS;
+            }
+            const int64_t i = m0 + ii, k = k0 + kk;
+            ra[u] = (i < g.M && k < kend) ? cvt<E>(g.a_trans ? A[k * g.lda + i] : A[i * g.lda + k]) : (E)0;
+        }
+#pragma unroll
+        for (int u = 0; u < NBL; ++u) {
+            const int e = tid + u * 256;
+            const int jj = e % BN, kk = e / BN;
+            const int64_t j = n0 + jj, k = k0 + kk;
+            rb[u] = (j < g.N && k < kend) ? cvt<E>(B[k * g.ldb + j]) : (E)0;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int u = 0; u < NA; ++u) {
+            const int e = tid + u * 256;
+            const int ii = g.a_trans ? e % BM : e / KS, kk = g.a_trans ? e / BM : e % KS;
+            As[ii * LDK + kk] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NBL; ++u) {
+            const int e = tid + u * 256;
+            Bs[(e % BN) * LDK + e / BN] = rb[u];
+        }
+    };
+    if (kbeg < kend) load(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += KS) {
+        store();
+        __syncthreads();
+        // the next stage's loads in flight while the matrix cores work
+        if (k0 + KS < kend) load(k0 + KS);
+#pragma unroll 1
         for (int q = 0; q < KS; q += P::KI)
 #pragma unroll
             for (int a = 0; a < P::NB; ++a)
 #pragma unroll
                 for (int b = 0; b < P::NB; ++b)
-                    P::mma(As, Bs, wr * WT + a * P::BT, wc * WT + b * P::BT, q, acc[a][b]);
+                    P::template mma_ld<LDK>(As, Bs, wr * WT + a * P::BT, wc * WT + b * P::BT, q, acc[a][b]);
         __syncthreads();
     }
 #pragma unroll
@@ -800,10 +836,11 @@ static hipError_t launch_gemm(const GemmArgs &a, hipStream_t s) {
     g.E1 = a.E1;
     g.E2 = a.E2;
     g.split = a.split_scratch;
-    g.kper = ceil_div(ceil_div(a.K, g.splitk), P::KS) * P::KS;
+    g.kper = ceil_div(ceil_div(a.K, g.splitk), GemmStage<P>::KS) * GemmStage<P>::KS;
     if (g.splitk > 1) g.splitk = (int)ceil_div(a.K, g.kper);
     dim3 grid((unsigned)ceil_div(a.N, 64), (unsigned)ceil_div(a.M, 64), (unsigned)(a.batch * g.splitk));
-    k_gemm<P, TA, TBm, TO><<<grid, 256, 0, s>>>(g);
+    lds_limit((const void *)k_gemm<P, TA, TBm, TO>, gemm_lds_bytes<P>());
+    k_gemm<P, TA, TBm, TO><<<grid, 256, gemm_lds_bytes<P>(), s>>>(g);
     TK_LAUNCHED();
     if (g.splitk > 1) {
         int64_t total = (int64_t)a.M * a.N * a.batch;
