@@ -166,6 +166,9 @@ struct Plan {
     // buffers zeroed once per call (zero_projections)
     int32_t *fib[3] = {nullptr, nullptr, nullptr}, *fptr[3] = {nullptr, nullptr, nullptr};
     int64_t nfib[3] = {0, 0, 0};
+    // the fibres of each list with more than kLongFibre nonzeros
+    int32_t *lf[3] = {nullptr, nullptr, nullptr};
+    int64_t nlong[3] = {0, 0, 0};
 };
 
 static size_t elem_size(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
@@ -251,6 +254,7 @@ static void carve(Plan &p, Arena &ar) {
             const int64_t cap = std::min(p.nslots[m], nnz);
             p.fib[m] = ar.take<int32_t>(cap);
             p.fptr[m] = ar.take<int32_t>(cap + 1);
+            p.lf[m] = ar.take<int32_t>(nnz / (kLongFibre + 1) + 1);
         }
         for (int m = 0; m < 3; ++m) p.T[m] = ar.take<char>((int64_t)(p.nslots[m] * p.ldT[m] * es));
         if (p.split)
@@ -549,6 +553,11 @@ static FibreList fibres_of(const Plan &p, int m, bool zeroed_target) {
         fl.fib = p.fib[m];
         fl.fptr = p.fptr[m];
         fl.n = p.nfib[m];
+        if (p.nlong[m] > 0) {
+            fl.lf = p.lf[m];
+            fl.nlong = p.nlong[m];
+            fl.maxlen = kLongFibre;
+        }
     }
     return fl;
 }
@@ -609,6 +618,20 @@ static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double
     ST(hipStreamSynchronize(s));
     if (int r = prep_status(flags)) return order_failed(r);
     for (int m = 0; m < 3; ++m) p.nfib[m] = nfib[m];
+    // the long fibres of each list (their own projection launch)
+    if (p.fib[0]) {
+        int32_t nlong[3] = {0, 0, 0};
+        for (int m = 0; m < 3; ++m) {
+            ST(long_fibres(p.fptr[m], nfib[m], kLongFibre, p.nnz / (kLongFibre + 1) + 1, p.lf[m], p.counts,
+                           p.cursor, p.scan, p.flags, s));
+            ST(hipMemcpyAsync(&nlong[m], p.cursor + nfib[m], 4, hipMemcpyDeviceToHost, s));
+            ST(hipStreamSynchronize(s));  // the next list reuses the scan buffers
+        }
+        ST(hipMemcpyAsync(&flags, p.flags, 4, hipMemcpyDeviceToHost, s));
+        ST(hipStreamSynchronize(s));
+        if (int r = prep_status(flags)) return order_failed(r);
+        for (int m = 0; m < 3; ++m) p.nlong[m] = nlong[m];
+    }
     *nu_out = nu;
     *normx2_out = nx2;
     if (!(nx2 > 0.0)) return TK_ERR_EMPTY;

@@ -98,6 +98,14 @@ hipError_t build_order(const int32_t *const idx[3], int64_t nnz, const int64_t d
 hipError_t fibre_list(const int32_t *ptr, int64_t nslots, int64_t cap, int32_t *fib, int32_t *fptr, int32_t *flag_tmp,
                       int32_t *pos_tmp, int32_t *scan_scratch, int32_t *flags, hipStream_t s);
 
+// The fibres of a fibre list (fptr[0..n]) with more than maxlen nonzeros:
+// lf[k] = index of the k-th of them (ascending), their number at
+// pos_tmp[n] (device). lf has room for cap entries; a count beyond cap sets
+// kFlagOrderCheck in *flags and writes nothing out of range.
+// flag_tmp: n ints; pos_tmp: n + 1 ints; scan_scratch as scan.
+hipError_t long_fibres(const int32_t *fptr, int64_t n, int32_t maxlen, int64_t cap, int32_t *lf, int32_t *flag_tmp,
+                       int32_t *pos_tmp, int32_t *scan_scratch, int32_t *flags, hipStream_t s);
+
 // The counting sort of build_order on explicit key digits: slot =
 // ihi[p] * Ilo + ilo[p] (nslots of them), within a slot by (im[p], p).
 hipError_t build_order_keys(const int32_t *ihi, const int32_t *ilo, const int32_t *im, int64_t nnz, int32_t Ilo,
@@ -176,10 +184,19 @@ struct KernelEvents {
 // ---------------------------------------------------------------- project.hip
 // The non-empty fibres of an ordering (fibre_list): n fibres, fib[f] their
 // slots, fptr[f] their first entries. Empty (fib == nullptr) = not given.
+// Long fibres (more than maxlen nonzeros) listed in lf (nlong of them, as
+// indices into the list) are skipped by the per-thread walk of the vector
+// projection and projected by one workgroup each.
 struct FibreList {
     const int32_t *fib = nullptr, *fptr = nullptr;
     int64_t n = 0;
+    const int32_t *lf = nullptr;
+    int64_t nlong = 0;
+    int32_t maxlen = 0x7fffffff;
 };
+// Fibres with more nonzeros than this go to the one-workgroup-per-fibre
+// projection (one thread walking them would hold its workgroup back).
+constexpr int32_t kLongFibre = 32;
 // T[slot * ldT + r] = sum over the slot's entries of lval * F[lidx * ldF + r]
 // for r < J, zero for J <= r < ldT; slots = I_hi * I_lo, dense and
 // zero-filled; F has rowsF rows (the leaf mode's size) and the ordering at

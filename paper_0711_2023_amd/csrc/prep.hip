@@ -191,6 +191,35 @@ hipError_t fibre_list(const int32_t *ptr, int64_t nslots, int64_t cap, int32_t *
     return hipSuccess;
 }
 
+__global__ void k_long_flags(const int32_t *__restrict__ fptr, int64_t n, int32_t maxlen, int32_t *__restrict__ flag) {
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < n; f += (int64_t)gridDim.x * blockDim.x)
+        flag[f] = fptr[f + 1] - fptr[f] > maxlen ? 1 : 0;
+}
+
+__global__ void k_long_scatter(const int32_t *__restrict__ flag, const int32_t *__restrict__ pos, int64_t n,
+                               int64_t cap, int32_t *__restrict__ lf, int32_t *__restrict__ flags) {
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < n; f += (int64_t)gridDim.x * blockDim.x) {
+        if (flag[f]) {
+            const int32_t k = pos[f];
+            if (k >= 0 && (int64_t)k < cap)
+                lf[k] = (int32_t)f;
+            else
+                atomicOr(flags, kFlagOrderCheck);
+        }
+    }
+}
+
+hipError_t long_fibres(const int32_t *fptr, int64_t n, int32_t maxlen, int64_t cap, int32_t *lf, int32_t *flag_tmp,
+                       int32_t *pos_tmp, int32_t *scan_scratch, int32_t *flags, hipStream_t s) {
+    if (n <= 0) return fill_i32(pos_tmp, 1, 0, s);
+    k_long_flags<<<grid_for(n), 256, 0, s>>>(fptr, n, maxlen, flag_tmp);
+    TK_LAUNCHED();
+    TK_HIP(scan_exclusive(flag_tmp, pos_tmp, n, scan_scratch, s));
+    k_long_scatter<<<grid_for(n), 256, 0, s>>>(flag_tmp, pos_tmp, n, cap, lf, flags);
+    TK_LAUNCHED();
+    return hipSuccess;
+}
+
 // ------------------------------------------------------------------ validation
 __global__ void k_validate(const int32_t *i0, const int32_t *i1, const int32_t *i2, const double *v, int64_t nnz,
                            int32_t I0, int32_t I1, int32_t I2, int32_t *flags) {

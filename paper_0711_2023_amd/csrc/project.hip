@@ -199,7 +199,9 @@ __device__ inline void load_row(__amdgpu_buffer_rsrc_t r, uint32_t off, u32x4 (&
 // the fibre pointer list, fib[f] the slot of fibre f, nslots their number)
 // and only their rows are written; the rows of empty fibres keep what the
 // buffer holds (zeros written once before the first such projection). Else
-// the units are all slots and empty ones are written as zeros.
+// the units are all slots and empty ones are written as zeros. Under FIB,
+// fibres with more than maxlen nonzeros are skipped (not written): the
+// long-fibre launch projects them.
 // DUAL (FP32 output): each chunk is also written rounded to BF16 into T2,
 // whose rows have stride ld2 (ldT or ldT + 4, a multiple of 8; the same
 // fibre's row, its last 4 columns written as zeros when ld2 > ldT), so that
@@ -212,7 +214,8 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
                                                               const TF *__restrict__ F, uint32_t Fbytes, int32_t J,
                                                               int32_t ldT, int32_t spw, int32_t cap, int64_t nslots,
                                                               TO *__restrict__ T, TO *__restrict__ Tlo,
-                                                              bf16 *__restrict__ T2, int32_t ld2) {
+                                                              bf16 *__restrict__ T2, int32_t ld2,
+                                                              int32_t maxlen) {
     typedef typename AccOf<TV>::type Acc;
     constexpr int V = 16 / sizeof(TO);              // outputs per chunk
     constexpr int NL = V * (int)sizeof(TF) / 16;    // 16-byte factor loads per chunk
@@ -287,6 +290,8 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
     // one unit of the run, with any of its nonzeros read from global memory
     // when they lie beyond the staged ones
     auto one = [&](int sl) {
+        // a unit longer than maxlen is another launch's (k_project_long)
+        if (FIB && sptr[sl + 1] - sptr[sl] > maxlen) return;
         int a = 0, b = 0;
         if (col_on) {
             a = sptr[sl] - q0;
@@ -320,6 +325,77 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
         store(sl, acc);
     };
     for (int sl = tsl; sl < ns; sl += spi) one(sl);
+}
+
+// The fibres the vector kernel skips (more than maxlen nonzeros): one
+// workgroup per fibre of the list lf. Its threads are (group, chunk) pairs:
+// the fibre's nonzeros are dealt round robin to G = kProjThreads / cps
+// groups, each thread accumulates its 16-byte output chunk over its group's
+// nonzeros, and the G partial rows are summed in LDS in group order (a fixed
+// order, the same bits on every run), then written as the vector kernel
+// writes a row (SPLIT: rounded part and remainder; DUAL: also the BF16 copy,
+// its padding columns zero).
+template <class TV, class TF, class TO, bool SPLIT = false, bool DUAL = false>
+__global__ void __launch_bounds__(kProjThreads) k_project_long(const int32_t *__restrict__ fptr,
+                                                               const int32_t *__restrict__ fib,
+                                                               const int32_t *__restrict__ lf,
+                                                               const int32_t *__restrict__ lidx,
+                                                               const TV *__restrict__ lval,
+                                                               const TF *__restrict__ F, uint32_t Fbytes, int32_t J,
+                                                               int32_t ldT, TO *__restrict__ T, TO *__restrict__ Tlo,
+                                                               bf16 *__restrict__ T2, int32_t ld2) {
+    typedef typename AccOf<TV>::type Acc;
+    constexpr int V = 16 / sizeof(TO);
+    constexpr int NL = V * (int)sizeof(TF) / 16;
+    extern __shared__ __attribute__((aligned(16))) char long_smem[];
+    Acc *red = reinterpret_cast<Acc *>(long_smem);  // [G][ldT]
+    const int f = lf[blockIdx.x];
+    const int a = fptr[f], b = fptr[f + 1];
+    const int64_t row = fib[f];
+    const int cps = ldT / V, G = kProjThreads / cps;
+    const int tid = threadIdx.x, g = tid / cps, r = tid - g * cps;
+    const uint32_t rowb = (uint32_t)ldT * sizeof(TF), coloff = (uint32_t)r * V * sizeof(TF);
+    const __amdgpu_buffer_rsrc_t fr = buf_rsrc(F, Fbytes);
+    Acc acc[V];
+#pragma unroll
+    for (int t = 0; t < V; ++t) acc[t] = (Acc)0;
+    if (g < G && r * V < J) {
+        for (int p = a + g; p < b; p += G) {
+            u32x4 x[NL];
+            load_row<NL>(fr, __umul24((uint32_t)lidx[p], rowb) + coloff, x);
+            fma_row<TF, NL, Acc, false>(x, (Acc)lval[p], acc);
+        }
+    }
+    if (g < G)
+#pragma unroll
+        for (int t = 0; t < V; ++t) red[g * ldT + r * V + t] = acc[t];
+    __syncthreads();
+    if (tid >= cps) return;
+    Acc sum[V];
+#pragma unroll
+    for (int t = 0; t < V; ++t) sum[t] = red[tid * V + t];
+    for (int gg = 1; gg < G; ++gg)
+#pragma unroll
+        for (int t = 0; t < V; ++t) sum[t] += red[gg * ldT + tid * V + t];
+    typename Vec16<TO>::type o;
+#pragma unroll
+    for (int t = 0; t < V; ++t) o[t] = (TO)sum[t];
+    *reinterpret_cast<typename Vec16<TO>::type *>(T + row * ldT + tid * V) = o;
+    if (SPLIT) {
+        typename Vec16<TO>::type o2;
+#pragma unroll
+        for (int t = 0; t < V; ++t) o2[t] = (TO)(sum[t] - (Acc)o[t]);
+        *reinterpret_cast<typename Vec16<TO>::type *>(Tlo + row * ldT + tid * V) = o2;
+    }
+    if (DUAL) {  // V = 4 FP32 outputs -> 4 BF16, the row's last chunk with the 4 padding zeros
+        typedef bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        bf16x4 h;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) h[t] = (bf16)sum[t];
+        bf16 *dst = T2 + row * ld2 + tid * 4;
+        *reinterpret_cast<bf16x4 *>(dst) = h;
+        if (tid == cps - 1 && ld2 > ldT) *reinterpret_cast<bf16x4 *>(dst + 4) = bf16x4{0, 0, 0, 0};
+    }
 }
 
 template <class TO>
@@ -381,11 +457,26 @@ static bool vec_ok(const TF *F, int64_t rowsF, int ld, const void *T, int spw, i
 // kernel's own start / end events.
 template <class K, class... A>
 static void launch(K kernel, int64_t blocks, size_t lds, hipStream_t s, KernelEvents ke, A... args) {
-    if (ke.start && ke.stop)
+    if (ke.start || ke.stop)
         hipExtLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kProjThreads), (uint32_t)lds, s, ke.start, ke.stop,
                               0u, args...);
     else
         kernel<<<(unsigned)blocks, kProjThreads, lds, s>>>(args...);
+}
+
+// The events of a projection made of the vector launch and, when the list
+// has long fibres, the long-fibre launch after it: the start on the first,
+// the stop on the last.
+static KernelEvents first_of(KernelEvents ke, const FibreList &fl) {
+    return fl.nlong > 0 ? KernelEvents{ke.start, nullptr} : ke;
+}
+static KernelEvents last_of(KernelEvents ke) { return KernelEvents{nullptr, ke.stop}; }
+
+// LDS of a long-fibre launch: G partial rows of ldT accumulators.
+template <class TV, class TO>
+static size_t long_lds(int ldT) {
+    const int V = 16 / (int)sizeof(TO), cps = ldT / V;
+    return (size_t)(kProjThreads / cps) * ldT * sizeof(typename AccOf<TV>::type);
 }
 
 // A fibre list is usable when the whole output fits 32-bit buffer offsets
@@ -414,14 +505,21 @@ hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, cons
         if (fib_ok<TO>(fl, nslots, ldT)) {
             if (fl.n <= 0) return hipSuccess;  // no nonzeros: every row keeps its zeros
             const ProjShape sh = proj_shape(fl.n, ldT, tn, cap_max);
-            launch(k_project_vec<TV, TF, TO, false, true>, sh.blocks, vec_lds<TV>(sh, true), s, ke, fl.fptr, fl.fib,
-                   lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap, fl.n, T,
-                   (TO *)nullptr, (bf16 *)nullptr, (int32_t)0);
+            launch(k_project_vec<TV, TF, TO, false, true>, sh.blocks, vec_lds<TV>(sh, true), s, first_of(ke, fl),
+                   fl.fptr, fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap,
+                   fl.n, T, (TO *)nullptr, (bf16 *)nullptr, (int32_t)0, fl.maxlen);
+            if (fl.nlong > 0) {
+                TK_LAUNCHED();
+                launch(k_project_long<TV, TF, TO>, fl.nlong, long_lds<TV, TO>(ldT), s, last_of(ke), fl.fptr, fl.fib,
+                       fl.lf, lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, T, (TO *)nullptr, (bf16 *)nullptr,
+                       (int32_t)0);
+            }
         } else {
             const ProjShape sh = proj_shape(nslots, ldT, tn, cap_max);
             launch(k_project_vec<TV, TF, TO, false, false>, sh.blocks, vec_lds<TV>(sh, false), s, ke, ptr,
                    (const int32_t *)nullptr, lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw,
-                   (int32_t)sh.cap, nslots, T, (TO *)nullptr, (bf16 *)nullptr, (int32_t)0);
+                   (int32_t)sh.cap, nslots, T, (TO *)nullptr, (bf16 *)nullptr, (int32_t)0,
+                   (int32_t)0x7fffffff);
         }
     } else {
         const ProjShape sh = proj_shape(nslots, ldT, tn, 4096);
@@ -450,10 +548,16 @@ hipError_t project_dual(const int32_t *ptr, const int32_t *lidx, const float *lv
     if (fl.n <= 0) return hipSuccess;  // no nonzeros: every row keeps its zeros
     const uint32_t Fb = (uint32_t)(rowsF * ld * (int64_t)sizeof(float));
     const ProjShape sh = proj_shape(fl.n, ld, tn, 4096);
-    launch(k_project_vec<float, float, float, false, true, true>, sh.blocks, vec_lds<float>(sh, true), s, ke, fl.fptr,
-           fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw, (int32_t)sh.cap, fl.n, T,
-           (float *)nullptr, T2, (int32_t)ld2);
+    launch(k_project_vec<float, float, float, false, true, true>, sh.blocks, vec_lds<float>(sh, true), s,
+           first_of(ke, fl), fl.fptr, fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw,
+           (int32_t)sh.cap, fl.n, T, (float *)nullptr, T2, (int32_t)ld2, fl.maxlen);
     TK_LAUNCHED();
+    if (fl.nlong > 0) {
+        launch(k_project_long<float, float, float, false, true>, fl.nlong, long_lds<float, float>(ld), s, last_of(ke),
+               fl.fptr, fl.fib, fl.lf, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, T, (float *)nullptr, T2,
+               (int32_t)ld2);
+        TK_LAUNCHED();
+    }
     return hipSuccess;
 }
 
@@ -468,14 +572,21 @@ hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *l
     if (fib_ok<bf16>(fl, nslots, ld)) {
         if (fl.n <= 0) return hipSuccess;
         const ProjShape sh = proj_shape(fl.n, ld, tn, 4096);
-        launch(k_project_vec<float, float, bf16, true, true>, sh.blocks, vec_lds<float>(sh, true), s, ke, fl.fptr,
-               fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw, (int32_t)sh.cap, fl.n, Thi, Tlo,
-               (bf16 *)nullptr, (int32_t)0);
+        launch(k_project_vec<float, float, bf16, true, true>, sh.blocks, vec_lds<float>(sh, true), s,
+               first_of(ke, fl), fl.fptr, fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw,
+               (int32_t)sh.cap, fl.n, Thi, Tlo, (bf16 *)nullptr, (int32_t)0, fl.maxlen);
+        if (fl.nlong > 0) {
+            TK_LAUNCHED();
+            launch(k_project_long<float, float, bf16, true>, fl.nlong, long_lds<float, bf16>(ld), s, last_of(ke),
+                   fl.fptr, fl.fib, fl.lf, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, Thi, Tlo, (bf16 *)nullptr,
+                   (int32_t)0);
+        }
     } else {
         const ProjShape sh = proj_shape(nslots, ld, tn, 4096);
         launch(k_project_vec<float, float, bf16, true, false>, sh.blocks, vec_lds<float>(sh, false), s, ke, ptr,
                (const int32_t *)nullptr, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw,
-               (int32_t)sh.cap, nslots, Thi, Tlo, (bf16 *)nullptr, (int32_t)0);
+               (int32_t)sh.cap, nslots, Thi, Tlo, (bf16 *)nullptr, (int32_t)0,
+               (int32_t)0x7fffffff);
     }
     TK_LAUNCHED();
     return hipSuccess;

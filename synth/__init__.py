@@ -27,6 +27,7 @@ __all__ = [
     "superdiagonal",
     "matrix_as_tensor",
     "planted_tucker",
+    "skewed_sparse",
     "batch_configs",
     "with_duplicates",
     "WORKLOADS",
@@ -167,6 +168,42 @@ def planted_tucker(dims, core, nnz: int, noise: float, seed: int):
         vals[sel] = ((bj @ h) * ck).sum(axis=1)                # b_j^T H_i c_k per nonzero
     vals /= np.sqrt(np.mean(vals * vals))
     vals += noise * rng.standard_normal(vals.size)
+    return idx, vals, dims
+
+
+def skewed_sparse(dims, nnz: int, s: float, seed: int):
+    """nnz distinct coordinates whose every index follows a truncated Zipf
+    law, P(i) proportional to (i + 1)^-s on [0, I_m), drawn independently per
+    mode, with U(0,1) values: a few slices and fibres hold most of the
+    nonzeros, as in term-frequency tensors, and the fibres near the origin are
+    dense. Duplicate draws are dropped and drawing continues until nnz distinct
+    cells are found."""
+    dims = tuple(int(d) for d in dims)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cdf = []
+    for d in dims:
+        w = (np.arange(1, d + 1, dtype=np.float64)) ** (-float(s))
+        c = np.cumsum(w)
+        cdf.append(c / c[-1])
+    total = int(np.prod(dims, dtype=np.int64))
+    if nnz > total // 2:
+        raise ValueError("too many nonzeros for a skewed draw")
+    picked = np.empty(0, dtype=np.int64)
+    for _ in range(200):
+        need = nnz - picked.size
+        if need <= 0:
+            break
+        m = int(need * 1.3) + 64
+        lin = np.zeros(m, dtype=np.int64)
+        for c, d in zip(cdf, dims):
+            i = np.minimum(np.searchsorted(c, rng.random(m), side="right"), d - 1)
+            lin = lin * d + i
+        picked = np.unique(np.concatenate([picked, lin]))
+    if picked.size < nnz:
+        raise ValueError("skewed draw did not reach nnz distinct cells")
+    lin = rng.permutation(picked)[:nnz]
+    idx = _unravel(lin, dims)
+    vals = rng.random(nnz)
     return idx, vals, dims
 
 
