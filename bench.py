@@ -508,6 +508,7 @@ def main():
     ap.add_argument("--no-order4", action="store_true", help="skip the fourth-order leg (100^4)")
     ap.add_argument("--no-stream", action="store_true", help="skip the host-streamed MP leg")
     ap.add_argument("--no-implicit", action="store_true", help="skip the Gram-free MP leg (10000^3, 1M nonzeros)")
+    ap.add_argument("--no-skewed", action="store_true", help="skip the Zipf-skewed 1000^3 / 1M projection leg")
     ap.add_argument("--c5-leg", action="store_true", help="internal: run the 4000^3 learned-start leg, print one "
                     "JSON line")
     ap.add_argument("--copy-calib", action="store_true",
@@ -714,6 +715,9 @@ def main():
     if not args.no_implicit:
         line["implicit_low_occupancy"] = implicit_leg(tk, dev)
 
+    if not args.no_skewed and args.algo == "mp":
+        line["skewed"] = skewed_leg(tk, dev, dims, J, roof_proj["avg_launch_ms"])
+
     if not args.no_c5:
         # in a child process with a time limit (own device memory, about 40 GB)
         cmd = [sys.executable, os.path.abspath(__file__), "--c5-leg"]
@@ -861,6 +865,46 @@ def implicit_leg(tk, dev, with_dense=True):
     log(f"implicit: {out}")
     del di, dv
     torch.cuda.empty_cache()
+    return out
+
+
+def skewed_leg(tk, dev, dims_u, J, uniform_launch_ms):
+    """The headline workload's shape with skewed coordinates: 1000^3, 1M
+    distinct nonzeros whose indices follow a truncated Zipf law (exponent
+    1.0, synth.skewed_sparse), core 50^3, MP mixed, 4 sweeps. Per-mode
+    projection time per launch (sweeps 2..4) beside the uniform tensor's, the
+    fibres the long-fibre launch takes (more than 16 nonzeros) and their share
+    of the nonzeros, and the projected nnz/s over the sweep's projections."""
+    import numpy as np
+    import torch
+    import synth
+    idx, vals, dims = synth.skewed_sparse(dims_u, 1_000_000, 1.0, 7)
+    fib, longf, longnz = [], [], []
+    for m in range(3):
+        a, b = [n for n in range(3) if n != m]
+        _, cnt = np.unique(idx[a].astype(np.int64) * dims[b] + idx[b], return_counts=True)
+        fib.append(int(cnt.size))
+        longf.append(int((cnt > 16).sum()))
+        longnz.append(round(float(cnt[cnt > 16].sum()) / idx.shape[1], 4))
+    di = torch.from_numpy(idx.astype(np.int32)).to(dev)
+    dv = torch.from_numpy(vals).to(dev)
+    tk.mp(di, dv, dims, J, precision="mixed", max_iters=4, tol=0.0)
+    r = tk.mp(di, dv, dims, J, precision="mixed", max_iters=4, tol=0.0, timing=True, trace=4096)
+    per = {}
+    for e in events(r, "project"):
+        per.setdefault((e["mode"], e["precision"]), []).append(e["ms"])
+    launch_us = {f"mode{m + 1}_{PREC_NAME[p]}": round(1000 * statistics.median(v), 2)
+                 for (m, p), v in sorted(per.items())}
+    sweep_proj_ms = sum(statistics.median(v) for v in per.values())
+    nu = r.stats["nnz_unique"]
+    out = {"workload": "sparse 1000x1000x1000, 1,000,000 distinct nonzeros with Zipf(1.0) indices in every mode, "
+                       "U(0,1) values, core 50^3, MP mixed, 4 sweeps",
+           "fibres_per_mode": fib, "long_fibres_per_mode": longf, "long_fibre_nnz_share": longnz,
+           "projection_us_per_launch": launch_us,
+           "uniform_bf16_projection_us_per_launch": round(1000 * uniform_launch_ms, 2),
+           "projected_nnz_per_s": 3 * nu / (sweep_proj_ms / 1000.0),
+           "ms_per_sweep": round(r.stats["sweeps_ms"] / max(1, r.iters), 3), "fit": r.fits[-1]}
+    log(f"skewed: {out}")
     return out
 
 

@@ -195,8 +195,11 @@ struct FibreList {
     int32_t maxlen = 0x7fffffff;
 };
 // Fibres with more nonzeros than this go to the one-workgroup-per-fibre
-// projection (one thread walking them would hold its workgroup back).
-constexpr int32_t kLongFibre = 32;
+// projection (one thread walking them would hold its workgroup back). On a
+// Zipf-skewed 1000^3 tensor with 1M nonzeros 16 beat 8, 32 and 64 (61, 72,
+// 75 and 110 us per BF16 projection); 8 also slowed uniform tensors, whose
+// longest fibres hold about 8.
+constexpr int32_t kLongFibre = 16;
 // T[slot * ldT + r] = sum over the slot's entries of lval * F[lidx * ldF + r]
 // for r < J, zero for J <= r < ldT; slots = I_hi * I_lo, dense and
 // zero-filled; F has rowsF rows (the leaf mode's size) and the ordering at

@@ -329,14 +329,18 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
 
 // The fibres the vector kernel skips (more than maxlen nonzeros): one
 // workgroup per fibre of the list lf. Its threads are (group, chunk) pairs:
-// the fibre's nonzeros are dealt round robin to G = kProjThreads / cps
+// the fibre's nonzeros are dealt round robin to G = kLongThreads / cps
 // groups, each thread accumulates its 16-byte output chunk over its group's
 // nonzeros, and the G partial rows are summed in LDS in group order (a fixed
 // order, the same bits on every run), then written as the vector kernel
 // writes a row (SPLIT: rounded part and remainder; DUAL: also the BF16 copy,
 // its padding columns zero).
+// Threads of a long-fibre workgroup (64 and 128 measured slower on the
+// Zipf-skewed 1000^3 tensor: 66-116 and 58-90 us per projection against
+// 61-79 us).
+constexpr int kLongThreads = 256;
 template <class TV, class TF, class TO, bool SPLIT = false, bool DUAL = false>
-__global__ void __launch_bounds__(kProjThreads) k_project_long(const int32_t *__restrict__ fptr,
+__global__ void __launch_bounds__(kLongThreads) k_project_long(const int32_t *__restrict__ fptr,
                                                                const int32_t *__restrict__ fib,
                                                                const int32_t *__restrict__ lf,
                                                                const int32_t *__restrict__ lidx,
@@ -352,7 +356,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project_long(const int32_t *__
     const int f = lf[blockIdx.x];
     const int a = fptr[f], b = fptr[f + 1];
     const int64_t row = fib[f];
-    const int cps = ldT / V, G = kProjThreads / cps;
+    const int cps = ldT / V, G = kLongThreads / cps;
     const int tid = threadIdx.x, g = tid / cps, r = tid - g * cps;
     const uint32_t rowb = (uint32_t)ldT * sizeof(TF), coloff = (uint32_t)r * V * sizeof(TF);
     const __amdgpu_buffer_rsrc_t fr = buf_rsrc(F, Fbytes);
@@ -464,6 +468,16 @@ static void launch(K kernel, int64_t blocks, size_t lds, hipStream_t s, KernelEv
         kernel<<<(unsigned)blocks, kProjThreads, lds, s>>>(args...);
 }
 
+// A long-fibre launch: one workgroup of kLongThreads per long fibre.
+template <class K, class... A>
+static void launch_long(K kernel, int64_t blocks, size_t lds, hipStream_t s, KernelEvents ke, A... args) {
+    if (ke.start || ke.stop)
+        hipExtLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kLongThreads), (uint32_t)lds, s, ke.start, ke.stop,
+                              0u, args...);
+    else
+        kernel<<<(unsigned)blocks, kLongThreads, lds, s>>>(args...);
+}
+
 // The events of a projection made of the vector launch and, when the list
 // has long fibres, the long-fibre launch after it: the start on the first,
 // the stop on the last.
@@ -476,7 +490,7 @@ static KernelEvents last_of(KernelEvents ke) { return KernelEvents{nullptr, ke.s
 template <class TV, class TO>
 static size_t long_lds(int ldT) {
     const int V = 16 / (int)sizeof(TO), cps = ldT / V;
-    return (size_t)(kProjThreads / cps) * ldT * sizeof(typename AccOf<TV>::type);
+    return (size_t)(kLongThreads / cps) * ldT * sizeof(typename AccOf<TV>::type);
 }
 
 // A fibre list is usable when the whole output fits 32-bit buffer offsets
@@ -510,7 +524,7 @@ hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, cons
                    fl.n, T, (TO *)nullptr, (bf16 *)nullptr, (int32_t)0, fl.maxlen);
             if (fl.nlong > 0) {
                 TK_LAUNCHED();
-                launch(k_project_long<TV, TF, TO>, fl.nlong, long_lds<TV, TO>(ldT), s, last_of(ke), fl.fptr, fl.fib,
+                launch_long(k_project_long<TV, TF, TO>, fl.nlong, long_lds<TV, TO>(ldT), s, last_of(ke), fl.fptr, fl.fib,
                        fl.lf, lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, T, (TO *)nullptr, (bf16 *)nullptr,
                        (int32_t)0);
             }
@@ -553,7 +567,7 @@ hipError_t project_dual(const int32_t *ptr, const int32_t *lidx, const float *lv
            (int32_t)sh.cap, fl.n, T, (float *)nullptr, T2, (int32_t)ld2, fl.maxlen);
     TK_LAUNCHED();
     if (fl.nlong > 0) {
-        launch(k_project_long<float, float, float, false, true>, fl.nlong, long_lds<float, float>(ld), s, last_of(ke),
+        launch_long(k_project_long<float, float, float, false, true>, fl.nlong, long_lds<float, float>(ld), s, last_of(ke),
                fl.fptr, fl.fib, fl.lf, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, T, (float *)nullptr, T2,
                (int32_t)ld2);
         TK_LAUNCHED();
@@ -577,7 +591,7 @@ hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *l
                (int32_t)sh.cap, fl.n, Thi, Tlo, (bf16 *)nullptr, (int32_t)0, fl.maxlen);
         if (fl.nlong > 0) {
             TK_LAUNCHED();
-            launch(k_project_long<float, float, bf16, true>, fl.nlong, long_lds<float, bf16>(ld), s, last_of(ke),
+            launch_long(k_project_long<float, float, bf16, true>, fl.nlong, long_lds<float, bf16>(ld), s, last_of(ke),
                    fl.fptr, fl.fib, fl.lf, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, Thi, Tlo, (bf16 *)nullptr,
                    (int32_t)0);
         }

@@ -1,6 +1,6 @@
 """Skewed tensors: every index drawn from a truncated Zipf law (synth.skewed_sparse),
 so a few fibres hold hundreds of nonzeros while most hold one or two, as in
-term-frequency data. Fibres with more than kLongFibre (32) nonzeros are
+term-frequency data. Fibres with more than kLongFibre (16) nonzeros are
 projected by one workgroup each (k_project_long: nonzeros dealt round robin to
 thread groups, partial rows summed in a fixed order), the rest by the
 per-thread walk, which skips the long ones.
