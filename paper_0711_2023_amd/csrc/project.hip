@@ -201,21 +201,19 @@ __device__ inline void load_row(__amdgpu_buffer_rsrc_t r, uint32_t off, u32x4 (&
 // buffer holds (zeros written once before the first such projection). Else
 // the units are all slots and empty ones are written as zeros. Under FIB,
 // fibres with more than maxlen nonzeros are skipped (not written): the
-// long-fibre launch projects them.
+// long-fibre workgroups of k_project_fused project them.
 // DUAL (FP32 output): each chunk is also written rounded to BF16 into T2,
 // whose rows have stride ld2 (ldT or ldT + 4, a multiple of 8; the same
 // fibre's row, its last 4 columns written as zeros when ld2 > ldT), so that
 // one pass over the nonzeros serves both an FP32 and a BF16 consumer.
-template <class TV, class TF, class TO, bool SPLIT = false, bool FIB = false, bool DUAL = false>
-__global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__restrict__ ptr,
-                                                              const int32_t *__restrict__ fib,
-                                                              const int32_t *__restrict__ lidx,
-                                                              const TV *__restrict__ lval,
-                                                              const TF *__restrict__ F, uint32_t Fbytes, int32_t J,
-                                                              int32_t ldT, int32_t spw, int32_t cap, int64_t nslots,
-                                                              TO *__restrict__ T, TO *__restrict__ Tlo,
-                                                              bf16 *__restrict__ T2, int32_t ld2,
-                                                              int32_t maxlen) {
+// (The body of workgroup blk; k_project_vec and k_project_fused launch it.)
+template <class TV, class TF, class TO, bool SPLIT, bool FIB, bool DUAL>
+__device__ inline void project_vec_body(int64_t blk, const int32_t *__restrict__ ptr,
+                                        const int32_t *__restrict__ fib, const int32_t *__restrict__ lidx,
+                                        const TV *__restrict__ lval, const TF *__restrict__ F, uint32_t Fbytes,
+                                        int32_t J, int32_t ldT, int32_t spw, int32_t cap, int64_t nslots,
+                                        TO *__restrict__ T, TO *__restrict__ Tlo, bf16 *__restrict__ T2, int32_t ld2,
+                                        int32_t maxlen) {
     typedef typename AccOf<TV>::type Acc;
     constexpr int V = 16 / sizeof(TO);              // outputs per chunk
     constexpr int NL = V * (int)sizeof(TF) / 16;    // 16-byte factor loads per chunk
@@ -224,7 +222,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
     int32_t *sfib = smem + ((spw + 4) & ~3);  // FIB: slots of the run's fibres
     NzPair<TV> *snz = reinterpret_cast<NzPair<TV> *>(smem + ((spw + 4) & ~3) + (FIB ? ((spw + 3) & ~3) : 0));
     const int tid = threadIdx.x;
-    const int64_t s0 = (int64_t)blockIdx.x * spw;
+    const int64_t s0 = blk * spw;
     const int ns = (int)(s0 + spw <= nslots ? spw : nslots - s0);
     // uniform across the workgroup (the descriptors below must be scalar)
     const int32_t q0 = __builtin_amdgcn_readfirstlane(stage_ptr(ptr, s0, ns, sptr));
@@ -290,7 +288,8 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
     // one unit of the run, with any of its nonzeros read from global memory
     // when they lie beyond the staged ones
     auto one = [&](int sl) {
-        // a unit longer than maxlen is another launch's (k_project_long)
+        // a unit longer than maxlen belongs to a long-fibre workgroup
+        // (project_long_body)
         if (FIB && sptr[sl + 1] - sptr[sl] > maxlen) return;
         int a = 0, b = 0;
         if (col_on) {
@@ -327,8 +326,22 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
     for (int sl = tsl; sl < ns; sl += spi) one(sl);
 }
 
+template <class TV, class TF, class TO, bool SPLIT = false, bool FIB = false, bool DUAL = false>
+__global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__restrict__ ptr,
+                                                              const int32_t *__restrict__ fib,
+                                                              const int32_t *__restrict__ lidx,
+                                                              const TV *__restrict__ lval,
+                                                              const TF *__restrict__ F, uint32_t Fbytes, int32_t J,
+                                                              int32_t ldT, int32_t spw, int32_t cap, int64_t nslots,
+                                                              TO *__restrict__ T, TO *__restrict__ Tlo,
+                                                              bf16 *__restrict__ T2, int32_t ld2,
+                                                              int32_t maxlen) {
+    project_vec_body<TV, TF, TO, SPLIT, FIB, DUAL>(blockIdx.x, ptr, fib, lidx, lval, F, Fbytes, J, ldT, spw, cap,
+                                                   nslots, T, Tlo, T2, ld2, maxlen);
+}
+
 // The fibres the vector kernel skips (more than maxlen nonzeros): one
-// workgroup per fibre of the list lf. Its threads are (group, chunk) pairs:
+// workgroup per fibre of the list lf (k_project_fused). Its threads are (group, chunk) pairs:
 // the fibre's nonzeros are dealt round robin to G = kLongThreads / cps
 // groups, each thread accumulates its 16-byte output chunk over its group's
 // nonzeros, and the G partial rows are summed in LDS in group order (a fixed
@@ -339,21 +352,19 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
 // Zipf-skewed 1000^3 tensor: 66-116 and 58-90 us per projection against
 // 61-79 us).
 constexpr int kLongThreads = 256;
-template <class TV, class TF, class TO, bool SPLIT = false, bool DUAL = false>
-__global__ void __launch_bounds__(kLongThreads) k_project_long(const int32_t *__restrict__ fptr,
-                                                               const int32_t *__restrict__ fib,
-                                                               const int32_t *__restrict__ lf,
-                                                               const int32_t *__restrict__ lidx,
-                                                               const TV *__restrict__ lval,
-                                                               const TF *__restrict__ F, uint32_t Fbytes, int32_t J,
-                                                               int32_t ldT, TO *__restrict__ T, TO *__restrict__ Tlo,
-                                                               bf16 *__restrict__ T2, int32_t ld2) {
+template <class TV, class TF, class TO, bool SPLIT, bool DUAL>
+__device__ inline void project_long_body(int64_t blk, const int32_t *__restrict__ fptr,
+                                         const int32_t *__restrict__ fib, const int32_t *__restrict__ lf,
+                                         const int32_t *__restrict__ lidx, const TV *__restrict__ lval,
+                                         const TF *__restrict__ F, uint32_t Fbytes, int32_t J, int32_t ldT,
+                                         TO *__restrict__ T, TO *__restrict__ Tlo, bf16 *__restrict__ T2,
+                                         int32_t ld2) {
     typedef typename AccOf<TV>::type Acc;
     constexpr int V = 16 / sizeof(TO);
     constexpr int NL = V * (int)sizeof(TF) / 16;
     extern __shared__ __attribute__((aligned(16))) char long_smem[];
     Acc *red = reinterpret_cast<Acc *>(long_smem);  // [G][ldT]
-    const int f = lf[blockIdx.x];
+    const int f = lf[blk];
     const int a = fptr[f], b = fptr[f + 1];
     const int64_t row = fib[f];
     const int cps = ldT / V, G = kLongThreads / cps;
@@ -400,6 +411,28 @@ __global__ void __launch_bounds__(kLongThreads) k_project_long(const int32_t *__
         *reinterpret_cast<bf16x4 *>(dst) = h;
         if (tid == cps - 1 && ld2 > ldT) *reinterpret_cast<bf16x4 *>(dst + 4) = bf16x4{0, 0, 0, 0};
     }
+}
+
+// The vector kernel's workgroups over the fibre list (the first nmain) and
+// one workgroup per long fibre after them, in one launch, so that the long
+// fibres run beside the tail of the rest instead of after it.
+static_assert(kLongThreads == kProjThreads, "one launch: the same workgroup size");
+template <class TV, class TF, class TO, bool SPLIT = false, bool DUAL = false>
+__global__ void __launch_bounds__(kProjThreads) k_project_fused(const int32_t *__restrict__ fptr,
+                                                                const int32_t *__restrict__ fib,
+                                                                const int32_t *__restrict__ lidx,
+                                                                const TV *__restrict__ lval,
+                                                                const TF *__restrict__ F, uint32_t Fbytes, int32_t J,
+                                                                int32_t ldT, int32_t spw, int32_t cap, int64_t nfib,
+                                                                TO *__restrict__ T, TO *__restrict__ Tlo,
+                                                                bf16 *__restrict__ T2, int32_t ld2, int32_t maxlen,
+                                                                const int32_t *__restrict__ lf, int64_t nmain) {
+    if ((int64_t)blockIdx.x < nmain)
+        project_vec_body<TV, TF, TO, SPLIT, true, DUAL>(blockIdx.x, fptr, fib, lidx, lval, F, Fbytes, J, ldT, spw,
+                                                        cap, nfib, T, Tlo, T2, ld2, maxlen);
+    else
+        project_long_body<TV, TF, TO, SPLIT, DUAL>((int64_t)blockIdx.x - nmain, fptr, fib, lf, lidx, lval, F, Fbytes,
+                                                   J, ldT, T, Tlo, T2, ld2);
 }
 
 template <class TO>
@@ -461,30 +494,12 @@ static bool vec_ok(const TF *F, int64_t rowsF, int ld, const void *T, int spw, i
 // kernel's own start / end events.
 template <class K, class... A>
 static void launch(K kernel, int64_t blocks, size_t lds, hipStream_t s, KernelEvents ke, A... args) {
-    if (ke.start || ke.stop)
+    if (ke.start && ke.stop)
         hipExtLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kProjThreads), (uint32_t)lds, s, ke.start, ke.stop,
                               0u, args...);
     else
         kernel<<<(unsigned)blocks, kProjThreads, lds, s>>>(args...);
 }
-
-// A long-fibre launch: one workgroup of kLongThreads per long fibre.
-template <class K, class... A>
-static void launch_long(K kernel, int64_t blocks, size_t lds, hipStream_t s, KernelEvents ke, A... args) {
-    if (ke.start || ke.stop)
-        hipExtLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kLongThreads), (uint32_t)lds, s, ke.start, ke.stop,
-                              0u, args...);
-    else
-        kernel<<<(unsigned)blocks, kLongThreads, lds, s>>>(args...);
-}
-
-// The events of a projection made of the vector launch and, when the list
-// has long fibres, the long-fibre launch after it: the start on the first,
-// the stop on the last.
-static KernelEvents first_of(KernelEvents ke, const FibreList &fl) {
-    return fl.nlong > 0 ? KernelEvents{ke.start, nullptr} : ke;
-}
-static KernelEvents last_of(KernelEvents ke) { return KernelEvents{nullptr, ke.stop}; }
 
 // LDS of a long-fibre launch: G partial rows of ldT accumulators.
 template <class TV, class TO>
@@ -519,15 +534,15 @@ hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, cons
         if (fib_ok<TO>(fl, nslots, ldT)) {
             if (fl.n <= 0) return hipSuccess;  // no nonzeros: every row keeps its zeros
             const ProjShape sh = proj_shape(fl.n, ldT, tn, cap_max);
-            launch(k_project_vec<TV, TF, TO, false, true>, sh.blocks, vec_lds<TV>(sh, true), s, first_of(ke, fl),
-                   fl.fptr, fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap,
-                   fl.n, T, (TO *)nullptr, (bf16 *)nullptr, (int32_t)0, fl.maxlen);
-            if (fl.nlong > 0) {
-                TK_LAUNCHED();
-                launch_long(k_project_long<TV, TF, TO>, fl.nlong, long_lds<TV, TO>(ldT), s, last_of(ke), fl.fptr, fl.fib,
-                       fl.lf, lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, T, (TO *)nullptr, (bf16 *)nullptr,
-                       (int32_t)0);
-            }
+            if (fl.nlong > 0)
+                launch(k_project_fused<TV, TF, TO>, sh.blocks + fl.nlong,
+                       std::max(vec_lds<TV>(sh, true), long_lds<TV, TO>(ldT)), s, ke, fl.fptr, fl.fib, lidx, lval, F,
+                       Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap, fl.n, T, (TO *)nullptr,
+                       (bf16 *)nullptr, (int32_t)0, fl.maxlen, fl.lf, sh.blocks);
+            else
+                launch(k_project_vec<TV, TF, TO, false, true>, sh.blocks, vec_lds<TV>(sh, true), s, ke, fl.fptr,
+                       fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap, fl.n,
+                       T, (TO *)nullptr, (bf16 *)nullptr, (int32_t)0, fl.maxlen);
         } else {
             const ProjShape sh = proj_shape(nslots, ldT, tn, cap_max);
             launch(k_project_vec<TV, TF, TO, false, false>, sh.blocks, vec_lds<TV>(sh, false), s, ke, ptr,
@@ -562,16 +577,16 @@ hipError_t project_dual(const int32_t *ptr, const int32_t *lidx, const float *lv
     if (fl.n <= 0) return hipSuccess;  // no nonzeros: every row keeps its zeros
     const uint32_t Fb = (uint32_t)(rowsF * ld * (int64_t)sizeof(float));
     const ProjShape sh = proj_shape(fl.n, ld, tn, 4096);
-    launch(k_project_vec<float, float, float, false, true, true>, sh.blocks, vec_lds<float>(sh, true), s,
-           first_of(ke, fl), fl.fptr, fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw,
-           (int32_t)sh.cap, fl.n, T, (float *)nullptr, T2, (int32_t)ld2, fl.maxlen);
+    if (fl.nlong > 0)
+        launch(k_project_fused<float, float, float, false, true>, sh.blocks + fl.nlong,
+               std::max(vec_lds<float>(sh, true), long_lds<float, float>(ld)), s, ke, fl.fptr, fl.fib, lidx, lval, F,
+               Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw, (int32_t)sh.cap, fl.n, T, (float *)nullptr, T2,
+               (int32_t)ld2, fl.maxlen, fl.lf, sh.blocks);
+    else
+        launch(k_project_vec<float, float, float, false, true, true>, sh.blocks, vec_lds<float>(sh, true), s, ke,
+               fl.fptr, fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw, (int32_t)sh.cap, fl.n,
+               T, (float *)nullptr, T2, (int32_t)ld2, fl.maxlen);
     TK_LAUNCHED();
-    if (fl.nlong > 0) {
-        launch_long(k_project_long<float, float, float, false, true>, fl.nlong, long_lds<float, float>(ld), s, last_of(ke),
-               fl.fptr, fl.fib, fl.lf, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, T, (float *)nullptr, T2,
-               (int32_t)ld2);
-        TK_LAUNCHED();
-    }
     return hipSuccess;
 }
 
@@ -586,15 +601,15 @@ hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *l
     if (fib_ok<bf16>(fl, nslots, ld)) {
         if (fl.n <= 0) return hipSuccess;
         const ProjShape sh = proj_shape(fl.n, ld, tn, 4096);
-        launch(k_project_vec<float, float, bf16, true, true>, sh.blocks, vec_lds<float>(sh, true), s,
-               first_of(ke, fl), fl.fptr, fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw,
-               (int32_t)sh.cap, fl.n, Thi, Tlo, (bf16 *)nullptr, (int32_t)0, fl.maxlen);
-        if (fl.nlong > 0) {
-            TK_LAUNCHED();
-            launch_long(k_project_long<float, float, bf16, true>, fl.nlong, long_lds<float, bf16>(ld), s, last_of(ke),
-                   fl.fptr, fl.fib, fl.lf, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, Thi, Tlo, (bf16 *)nullptr,
-                   (int32_t)0);
-        }
+        if (fl.nlong > 0)
+            launch(k_project_fused<float, float, bf16, true>, sh.blocks + fl.nlong,
+                   std::max(vec_lds<float>(sh, true), long_lds<float, bf16>(ld)), s, ke, fl.fptr, fl.fib, lidx, lval,
+                   F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw, (int32_t)sh.cap, fl.n, Thi, Tlo,
+                   (bf16 *)nullptr, (int32_t)0, fl.maxlen, fl.lf, sh.blocks);
+        else
+            launch(k_project_vec<float, float, bf16, true, true>, sh.blocks, vec_lds<float>(sh, true), s, ke,
+                   fl.fptr, fl.fib, lidx, lval, F, Fb, (int32_t)J, (int32_t)ld, (int32_t)sh.spw, (int32_t)sh.cap,
+                   fl.n, Thi, Tlo, (bf16 *)nullptr, (int32_t)0, fl.maxlen);
     } else {
         const ProjShape sh = proj_shape(nslots, ld, tn, 4096);
         launch(k_project_vec<float, float, bf16, true, false>, sh.blocks, vec_lds<float>(sh, false), s, ke, ptr,
