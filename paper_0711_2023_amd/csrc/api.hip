@@ -166,9 +166,11 @@ struct Plan {
     // buffers zeroed once per call (zero_projections)
     int32_t *fib[3] = {nullptr, nullptr, nullptr}, *fptr[3] = {nullptr, nullptr, nullptr};
     int64_t nfib[3] = {0, 0, 0};
-    // the fibres of each list with more than kLongFibre nonzeros
+    // the fibres of each list with more than maxlen[m] nonzeros (the limit
+    // of the output type of that ordering's sweep projections)
     int32_t *lf[3] = {nullptr, nullptr, nullptr};
     int64_t nlong[3] = {0, 0, 0};
+    int32_t maxlen[3] = {kLongFibreWide, kLongFibreWide, kLongFibreWide};
 };
 
 static size_t elem_size(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
@@ -254,7 +256,7 @@ static void carve(Plan &p, Arena &ar) {
             const int64_t cap = std::min(p.nslots[m], nnz);
             p.fib[m] = ar.take<int32_t>(cap);
             p.fptr[m] = ar.take<int32_t>(cap + 1);
-            p.lf[m] = ar.take<int32_t>(nnz / (kLongFibre + 1) + 1);
+            p.lf[m] = ar.take<int32_t>(nnz / (kLongFibreWide + 1) + 1);
         }
         for (int m = 0; m < 3; ++m) p.T[m] = ar.take<char>((int64_t)(p.nslots[m] * p.ldT[m] * es));
         if (p.split)
@@ -556,7 +558,7 @@ static FibreList fibres_of(const Plan &p, int m, bool zeroed_target) {
         if (p.nlong[m] > 0) {
             fl.lf = p.lf[m];
             fl.nlong = p.nlong[m];
-            fl.maxlen = kLongFibre;
+            fl.maxlen = p.maxlen[m];
         }
     }
     return fl;
@@ -622,7 +624,11 @@ static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double
     if (p.fib[0]) {
         int32_t nlong[3] = {0, 0, 0};
         for (int m = 0; m < 3; ++m) {
-            ST(long_fibres(p.fptr[m], nfib[m], kLongFibre, p.nnz / (kLongFibre + 1) + 1, p.lf[m], p.counts,
+            // BF16 rows, except mode 3's in mixed precision, which come from
+            // the FP32 projection for the core (project_dual)
+            const bool bf16_rows = p.prec == PBF16 && (m < 2 || p.split);
+            p.maxlen[m] = bf16_rows ? kLongFibreBf16 : kLongFibreWide;
+            ST(long_fibres(p.fptr[m], nfib[m], p.maxlen[m], p.nnz / (kLongFibreWide + 1) + 1, p.lf[m], p.counts,
                            p.cursor, p.scan, p.flags, s));
             ST(hipMemcpyAsync(&nlong[m], p.cursor + nfib[m], 4, hipMemcpyDeviceToHost, s));
             ST(hipStreamSynchronize(s));  // the next list reuses the scan buffers

@@ -194,12 +194,16 @@ struct FibreList {
     int64_t nlong = 0;
     int32_t maxlen = 0x7fffffff;
 };
-// Fibres with more nonzeros than this go to the one-workgroup-per-fibre
-// projection (one thread walking them would hold its workgroup back). On a
-// Zipf-skewed 1000^3 tensor with 1M nonzeros 16 beat 8, 32 and 64 (61, 72,
-// 75 and 110 us per BF16 projection); 8 also slowed uniform tensors, whose
-// longest fibres hold about 8.
-constexpr int32_t kLongFibre = 16;
+// Fibres with more nonzeros than a limit go to the one-workgroup-per-fibre
+// projection (one thread walking them would hold its workgroup back). The
+// limit depends on the output row: BF16 rows (7 chunks of 16 bytes at J = 50,
+// so 36 nonzero groups per long-fibre workgroup) keep fibres up to 16 in the
+// per-thread walk, FP32 and FP64 rows (13 or 25 chunks, fewer groups) up to
+// 8. On a Zipf-skewed 1000^3 tensor with 1M nonzeros, BF16 projections took
+// 57, 43-47 and 40-41 us at limits 8, 12 and 16, FP32 ones 40, 48-51 and
+// 55-57 us; uniform tensors were unchanged at every limit.
+constexpr int32_t kLongFibreBf16 = 16;
+constexpr int32_t kLongFibreWide = 8;
 // T[slot * ldT + r] = sum over the slot's entries of lval * F[lidx * ldF + r]
 // for r < J, zero for J <= r < ldT; slots = I_hi * I_lo, dense and
 // zero-filled; F has rowsF rows (the leaf mode's size) and the ordering at

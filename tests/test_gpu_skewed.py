@@ -1,8 +1,9 @@
 """Skewed tensors: every index drawn from a truncated Zipf law (synth.skewed_sparse),
 so a few fibres hold hundreds of nonzeros while most hold one or two, as in
-term-frequency data. Fibres with more than kLongFibre (16) nonzeros are
-projected by one workgroup each (k_project_long: nonzeros dealt round robin to
-thread groups, partial rows summed in a fixed order), the rest by the
+term-frequency data. Fibres with more than 16 (BF16 rows) or 8 (FP32 and FP64
+rows) nonzeros are projected by one workgroup each, in the same launch as the
+rest (k_project_fused: nonzeros dealt round robin to thread groups, partial
+rows summed in a fixed order); the rest go to the
 per-thread walk, which skips the long ones.
 
 * MP (Figure 7, pseudo HO-SVD start of Section 4.4) in FP64 against the FP64
