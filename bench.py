@@ -873,19 +873,21 @@ def skewed_leg(tk, dev, dims_u, J, uniform_launch_ms):
     distinct nonzeros whose indices follow a truncated Zipf law (exponent
     1.0, synth.skewed_sparse), core 50^3, MP mixed, 4 sweeps. Per-mode
     projection time per launch (sweeps 2..4) beside the uniform tensor's, the
-    fibres the long-fibre launch takes (more than 16 nonzeros) and their share
-    of the nonzeros, and the projected nnz/s over the sweep's projections."""
+    fibres the long-fibre workgroups take (more than 16 nonzeros for the BF16
+    projections of modes 1 and 2, more than 8 for mode 3's FP32 one) and their
+    share of the nonzeros, and the projected nnz/s over the sweep's
+    projections."""
     import numpy as np
     import torch
     import synth
     idx, vals, dims = synth.skewed_sparse(dims_u, 1_000_000, 1.0, 7)
     fib, longf, longnz = [], [], []
-    for m in range(3):
+    for m, lim in zip(range(3), (16, 16, 8)):
         a, b = [n for n in range(3) if n != m]
         _, cnt = np.unique(idx[a].astype(np.int64) * dims[b] + idx[b], return_counts=True)
         fib.append(int(cnt.size))
-        longf.append(int((cnt > 16).sum()))
-        longnz.append(round(float(cnt[cnt > 16].sum()) / idx.shape[1], 4))
+        longf.append(int((cnt > lim).sum()))
+        longnz.append(round(float(cnt[cnt > lim].sum()) / idx.shape[1], 4))
     di = torch.from_numpy(idx.astype(np.int32)).to(dev)
     dv = torch.from_numpy(vals).to(dev)
     tk.mp(di, dv, dims, J, precision="mixed", max_iters=4, tol=0.0)
