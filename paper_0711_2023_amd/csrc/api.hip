@@ -171,6 +171,10 @@ struct Plan {
     int32_t *lf[3] = {nullptr, nullptr, nullptr};
     int64_t nlong[3] = {0, 0, 0};
     int32_t maxlen[3] = {kLongFibreWide, kLongFibreWide, kLongFibreWide};
+    // HOOI (projections that write every slot): the slots of each ordering
+    // with more than kLongFibreBf16 nonzeros
+    int32_t *ls[3] = {nullptr, nullptr, nullptr};
+    int64_t nls[3] = {0, 0, 0};
 };
 
 static size_t elem_size(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
@@ -267,6 +271,7 @@ static void carve(Plan &p, Arena &ar) {
             p.Fc = ar.take<float>(p.I[2] * p.ldc);
         }
     } else if (p.algo == TK_ALGO_HOOI) {
+        for (int m = 0; m < 3; ++m) p.ls[m] = ar.take<int32_t>(nnz / (kLongFibreBf16 + 1) + 1);
         p.T[2] = ar.take<char>((int64_t)(p.nslots[2] * p.J[2] * es));
         if (prec == PBF16)
             p.T0f = ar.take<float>(p.nslots[0] * p.J[0]);
@@ -551,6 +556,11 @@ static int order_failed(int r) {
 // projection goes to a buffer zeroed by zero_projections), else none.
 static FibreList fibres_of(const Plan &p, int m, bool zeroed_target) {
     FibreList fl;
+    if (p.ls[m] && p.nls[m] > 0) {  // every slot written: no zeroed target needed
+        fl.ls = p.ls[m];
+        fl.nls = p.nls[m];
+        fl.slot_maxlen = kLongFibreBf16;
+    }
     if (p.fib[m] && zeroed_target) {
         fl.fib = p.fib[m];
         fl.fptr = p.fptr[m];
@@ -620,7 +630,21 @@ static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double
     ST(hipStreamSynchronize(s));
     if (int r = prep_status(flags)) return order_failed(r);
     for (int m = 0; m < 3; ++m) p.nfib[m] = nfib[m];
-    // the long fibres of each list (their own projection launch)
+    // HOOI: the long slots of each ordering
+    if (p.ls[0]) {
+        int32_t nls[3] = {0, 0, 0};
+        for (int m = 0; m < 3; ++m) {
+            ST(long_fibres(p.ptr[m], p.nslots[m], kLongFibreBf16, p.nnz / (kLongFibreBf16 + 1) + 1, p.ls[m],
+                           p.counts, p.cursor, p.scan, p.flags, s));
+            ST(hipMemcpyAsync(&nls[m], p.cursor + p.nslots[m], 4, hipMemcpyDeviceToHost, s));
+            ST(hipStreamSynchronize(s));  // the next list reuses the scan buffers
+        }
+        ST(hipMemcpyAsync(&flags, p.flags, 4, hipMemcpyDeviceToHost, s));
+        ST(hipStreamSynchronize(s));
+        if (int r = prep_status(flags)) return order_failed(r);
+        for (int m = 0; m < 3; ++m) p.nls[m] = nls[m];
+    }
+    // the long fibres of each list (their own workgroups in the projection launch)
     if (p.fib[0]) {
         int32_t nlong[3] = {0, 0, 0};
         for (int m = 0; m < 3; ++m) {
@@ -672,14 +696,19 @@ static hipError_t project_m(Plan &p, int m, const double *F64, void *T, int out_
         return project<float, f16, bf16>(ptr, lidx, p.lval32[m], (const f16 *)p.Fp[m], I, ld, J, ld, ns, p.nnz,
                                          (bf16 *)T, s, p.tune, ke, fl);
     }
+    // rows of J (HOOI): every slot is written; only the long-slot list applies
+    FibreList sl;
+    sl.ls = fl.ls;
+    sl.nls = fl.nls;
+    sl.slot_maxlen = fl.slot_maxlen;
     if (out_prec == P64)
         return project<double, double, double>(ptr, lidx, p.lval64[m], F64, I, J, J, ld, ns, p.nnz, (double *)T, s,
-                                               p.tune, ke);
+                                               p.tune, ke, sl);
     if (out_prec == P32)
         return project<float, float, float>(ptr, lidx, p.lval32[m], p.F32[m], I, J, J, ld, ns, p.nnz, (float *)T, s,
-                                            p.tune, ke);
+                                            p.tune, ke, sl);
     return project<float, float, bf16>(ptr, lidx, p.lval32[m], p.F32[m], I, J, J, ld, ns, p.nnz, (bf16 *)T, s,
-                                       p.tune, ke);
+                                       p.tune, ke, sl);
 }
 
 static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s) {

@@ -186,13 +186,19 @@ struct KernelEvents {
 // slots, fptr[f] their first entries. Empty (fib == nullptr) = not given.
 // Long fibres (more than maxlen nonzeros) listed in lf (nlong of them, as
 // indices into the list) are skipped by the per-thread walk of the vector
-// projection and projected by one workgroup each.
+// projection and projected by one workgroup each; the same for long slots
+// (ls) when a projection writes every slot.
 struct FibreList {
     const int32_t *fib = nullptr, *fptr = nullptr;
     int64_t n = 0;
     const int32_t *lf = nullptr;
     int64_t nlong = 0;
     int32_t maxlen = 0x7fffffff;
+    // Projections that write every slot (no list): the slots with more than
+    // slot_maxlen nonzeros (ls, nls of them), projected by one workgroup each.
+    const int32_t *ls = nullptr;
+    int64_t nls = 0;
+    int32_t slot_maxlen = 0x7fffffff;
 };
 // Fibres with more nonzeros than a limit go to the one-workgroup-per-fibre
 // projection (one thread walking them would hold its workgroup back). The

@@ -81,20 +81,21 @@ __device__ inline void nz_at(int p, int nst, int32_t q0, const int32_t *sidx, co
     }
 }
 
-// General form: any row stride; lanes cover consecutive elements.
+// General form: any row stride; lanes cover consecutive elements. Slots
+// with more than maxlen nonzeros are skipped (not written): the long-row
+// workgroups of k_project_gen_fused project them. (The body of workgroup
+// blk; k_project and k_project_gen_fused launch it.)
 template <class TV, class TF, class TO>
-__global__ void __launch_bounds__(kProjThreads) k_project(const int32_t *__restrict__ ptr,
-                                                          const int32_t *__restrict__ lidx,
-                                                          const TV *__restrict__ lval, const TF *__restrict__ F,
-                                                          int32_t ldF, int32_t J, int32_t ldT, int32_t spw,
-                                                          int32_t cap,
-                                                          int64_t nslots, TO *__restrict__ T) {
+__device__ inline void project_gen_body(int64_t blk, const int32_t *__restrict__ ptr,
+                                        const int32_t *__restrict__ lidx, const TV *__restrict__ lval,
+                                        const TF *__restrict__ F, int32_t ldF, int32_t J, int32_t ldT, int32_t spw,
+                                        int32_t cap, int64_t nslots, TO *__restrict__ T, int32_t maxlen) {
     typedef typename AccOf<TV>::type Acc;
     extern __shared__ __attribute__((aligned(16))) int32_t smem[];
     int32_t *sptr = smem, *sidx = smem + ((spw + 4) & ~3);
     TV *sval = reinterpret_cast<TV *>(sidx + ((cap + 3) & ~3));
     const int tid = threadIdx.x;
-    const int64_t s0 = (int64_t)blockIdx.x * spw;
+    const int64_t s0 = blk * spw;
     const int ns = (int)(s0 + spw <= nslots ? spw : nslots - s0);
     const int32_t q0 = stage_ptr(ptr, s0, ns, sptr);
     const int nq = sptr[ns] - q0;
@@ -109,6 +110,7 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const int32_t *__restr
     TO *out = T + s0 * ldT;
     for (int qb = tid; qb < nel; qb += kProjThreads * kProjU) {
         int r[kProjU], a[kProjU], b[kProjU], id[kProjU];
+        bool skip[kProjU];
         Acc acc[kProjU];
         TV v[kProjU];
 #pragma unroll
@@ -120,7 +122,8 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const int32_t *__restr
             r[u] = q - sl * ldT;
             a[u] = 0;
             b[u] = 0;
-            if (q < nel && r[u] < J) {
+            skip[u] = q < nel && sptr[sl + 1] - sptr[sl] > maxlen;
+            if (q < nel && r[u] < J && !skip[u]) {
                 a[u] = sptr[sl] - q0;
                 b[u] = sptr[sl + 1] - q0;
             }
@@ -142,9 +145,63 @@ __global__ void __launch_bounds__(kProjThreads) k_project(const int32_t *__restr
 #pragma unroll
         for (int u = 0; u < kProjU; ++u) {
             const int q = qb + u * kProjThreads;
-            if (q < nel) out[q] = (TO)acc[u];
+            if (q < nel && !skip[u]) out[q] = (TO)acc[u];
         }
     }
+}
+
+template <class TV, class TF, class TO>
+__global__ void __launch_bounds__(kProjThreads) k_project(const int32_t *__restrict__ ptr,
+                                                          const int32_t *__restrict__ lidx,
+                                                          const TV *__restrict__ lval, const TF *__restrict__ F,
+                                                          int32_t ldF, int32_t J, int32_t ldT, int32_t spw,
+                                                          int32_t cap, int64_t nslots, TO *__restrict__ T) {
+    project_gen_body<TV, TF, TO>(blockIdx.x, ptr, lidx, lval, F, ldF, J, ldT, spw, cap, nslots, T, 0x7fffffff);
+}
+
+// A slot the general form skips (more than maxlen nonzeros), by one
+// workgroup: G = kProjThreads / ldT groups take its nonzeros round robin,
+// each thread one column, and the groups' partial rows are summed in LDS in
+// group order (fixed: the same bits on every run).
+template <class TV, class TF, class TO>
+__device__ inline void project_long_rows_body(int64_t blk, const int32_t *__restrict__ ptr,
+                                              const int32_t *__restrict__ ls, const int32_t *__restrict__ lidx,
+                                              const TV *__restrict__ lval, const TF *__restrict__ F, int32_t ldF,
+                                              int32_t J, int32_t ldT, TO *__restrict__ T) {
+    typedef typename AccOf<TV>::type Acc;
+    extern __shared__ __attribute__((aligned(16))) char long_rows_smem[];
+    Acc *red = reinterpret_cast<Acc *>(long_rows_smem);  // [G][ldT]
+    const int64_t slot = ls[blk];
+    const int a = ptr[slot], b = ptr[slot + 1];
+    const int G = kProjThreads / ldT;
+    const int tid = threadIdx.x, g = tid / ldT, c = tid - g * ldT;
+    Acc acc = (Acc)0;
+    if (g < G && c < J)
+        for (int p = a + g; p < b; p += G) acc += (Acc)lval[p] * (Acc)F[(int64_t)lidx[p] * ldF + c];
+    if (g < G) red[g * ldT + c] = acc;
+    __syncthreads();
+    if (tid < ldT) {
+        Acc sum = red[tid];
+        for (int gg = 1; gg < G; ++gg) sum += red[gg * ldT + tid];
+        T[slot * ldT + tid] = (TO)sum;
+    }
+}
+
+// The general form's workgroups (the first nmain) and one workgroup per long
+// slot after them, in one launch.
+template <class TV, class TF, class TO>
+__global__ void __launch_bounds__(kProjThreads) k_project_gen_fused(const int32_t *__restrict__ ptr,
+                                                                    const int32_t *__restrict__ lidx,
+                                                                    const TV *__restrict__ lval,
+                                                                    const TF *__restrict__ F, int32_t ldF, int32_t J,
+                                                                    int32_t ldT, int32_t spw, int32_t cap,
+                                                                    int64_t nslots, TO *__restrict__ T,
+                                                                    int32_t maxlen, const int32_t *__restrict__ ls,
+                                                                    int64_t nmain) {
+    if ((int64_t)blockIdx.x < nmain)
+        project_gen_body<TV, TF, TO>(blockIdx.x, ptr, lidx, lval, F, ldF, J, ldT, spw, cap, nslots, T, maxlen);
+    else
+        project_long_rows_body<TV, TF, TO>((int64_t)blockIdx.x - nmain, ptr, ls, lidx, lval, F, ldF, J, ldT, T);
 }
 
 // A staged nonzero: leaf index and value side by side (one LDS read).
@@ -199,8 +256,8 @@ __device__ inline void load_row(__amdgpu_buffer_rsrc_t r, uint32_t off, u32x4 (&
 // the fibre pointer list, fib[f] the slot of fibre f, nslots their number)
 // and only their rows are written; the rows of empty fibres keep what the
 // buffer holds (zeros written once before the first such projection). Else
-// the units are all slots and empty ones are written as zeros. Under FIB,
-// fibres with more than maxlen nonzeros are skipped (not written): the
+// the units are all slots and empty ones are written as zeros. Units (fibres
+// or slots) with more than maxlen nonzeros are skipped (not written): the
 // long-fibre workgroups of k_project_fused project them.
 // DUAL (FP32 output): each chunk is also written rounded to BF16 into T2,
 // whose rows have stride ld2 (ldT or ldT + 4, a multiple of 8; the same
@@ -290,7 +347,7 @@ __device__ inline void project_vec_body(int64_t blk, const int32_t *__restrict__
     auto one = [&](int sl) {
         // a unit longer than maxlen belongs to a long-fibre workgroup
         // (project_long_body)
-        if (FIB && sptr[sl + 1] - sptr[sl] > maxlen) return;
+        if (sptr[sl + 1] - sptr[sl] > maxlen) return;
         int a = 0, b = 0;
         if (col_on) {
             a = sptr[sl] - q0;
@@ -366,7 +423,7 @@ __device__ inline void project_long_body(int64_t blk, const int32_t *__restrict_
     Acc *red = reinterpret_cast<Acc *>(long_smem);  // [G][ldT]
     const int f = lf[blk];
     const int a = fptr[f], b = fptr[f + 1];
-    const int64_t row = fib[f];
+    const int64_t row = fib ? fib[f] : f;  // a slot list names the rows itself
     const int cps = ldT / V, G = kLongThreads / cps;
     const int tid = threadIdx.x, g = tid / cps, r = tid - g * cps;
     const uint32_t rowb = (uint32_t)ldT * sizeof(TF), coloff = (uint32_t)r * V * sizeof(TF);
@@ -415,9 +472,10 @@ __device__ inline void project_long_body(int64_t blk, const int32_t *__restrict_
 
 // The vector kernel's workgroups over the fibre list (the first nmain) and
 // one workgroup per long fibre after them, in one launch, so that the long
-// fibres run beside the tail of the rest instead of after it.
+// fibres run beside the tail of the rest instead of after it. Without FIB
+// the units are all slots and lf lists long slots (fib null).
 static_assert(kLongThreads == kProjThreads, "one launch: the same workgroup size");
-template <class TV, class TF, class TO, bool SPLIT = false, bool DUAL = false>
+template <class TV, class TF, class TO, bool SPLIT = false, bool DUAL = false, bool FIB = true>
 __global__ void __launch_bounds__(kProjThreads) k_project_fused(const int32_t *__restrict__ fptr,
                                                                 const int32_t *__restrict__ fib,
                                                                 const int32_t *__restrict__ lidx,
@@ -428,8 +486,8 @@ __global__ void __launch_bounds__(kProjThreads) k_project_fused(const int32_t *_
                                                                 bf16 *__restrict__ T2, int32_t ld2, int32_t maxlen,
                                                                 const int32_t *__restrict__ lf, int64_t nmain) {
     if ((int64_t)blockIdx.x < nmain)
-        project_vec_body<TV, TF, TO, SPLIT, true, DUAL>(blockIdx.x, fptr, fib, lidx, lval, F, Fbytes, J, ldT, spw,
-                                                        cap, nfib, T, Tlo, T2, ld2, maxlen);
+        project_vec_body<TV, TF, TO, SPLIT, FIB, DUAL>(blockIdx.x, fptr, fib, lidx, lval, F, Fbytes, J, ldT, spw,
+                                                       cap, nfib, T, Tlo, T2, ld2, maxlen);
     else
         project_long_body<TV, TF, TO, SPLIT, DUAL>((int64_t)blockIdx.x - nmain, fptr, fib, lf, lidx, lval, F, Fbytes,
                                                    J, ldT, T, Tlo, T2, ld2);
@@ -545,16 +603,28 @@ hipError_t project(const int32_t *ptr, const int32_t *lidx, const TV *lval, cons
                        T, (TO *)nullptr, (bf16 *)nullptr, (int32_t)0, fl.maxlen);
         } else {
             const ProjShape sh = proj_shape(nslots, ldT, tn, cap_max);
-            launch(k_project_vec<TV, TF, TO, false, false>, sh.blocks, vec_lds<TV>(sh, false), s, ke, ptr,
-                   (const int32_t *)nullptr, lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw,
-                   (int32_t)sh.cap, nslots, T, (TO *)nullptr, (bf16 *)nullptr, (int32_t)0,
-                   (int32_t)0x7fffffff);
+            if (fl.nls > 0)  // long slots: their own workgroups in the same launch
+                launch(k_project_fused<TV, TF, TO, false, false, false>, sh.blocks + fl.nls,
+                       std::max(vec_lds<TV>(sh, false), long_lds<TV, TO>(ldT)), s, ke, ptr, (const int32_t *)nullptr,
+                       lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap, nslots, T,
+                       (TO *)nullptr, (bf16 *)nullptr, (int32_t)0, fl.slot_maxlen, fl.ls, sh.blocks);
+            else
+                launch(k_project_vec<TV, TF, TO, false, false>, sh.blocks, vec_lds<TV>(sh, false), s, ke, ptr,
+                       (const int32_t *)nullptr, lidx, lval, F, Fb, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw,
+                       (int32_t)sh.cap, nslots, T, (TO *)nullptr, (bf16 *)nullptr, (int32_t)0,
+                       (int32_t)0x7fffffff);
         }
     } else {
         const ProjShape sh = proj_shape(nslots, ldT, tn, 4096);
         const size_t lds = sizeof(int32_t) * (((sh.spw + 4) & ~3) + ((sh.cap + 3) & ~3)) + sizeof(TV) * sh.cap;
-        launch(k_project<TV, TF, TO>, sh.blocks, lds, s, ke, ptr, lidx, lval, F, (int32_t)ldF, (int32_t)J,
-               (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap, nslots, T);
+        if (fl.nls > 0 && ldT <= kProjThreads)  // long slots: their own workgroups in the same launch
+            launch(k_project_gen_fused<TV, TF, TO>, sh.blocks + fl.nls,
+                   std::max(lds, (size_t)(kProjThreads / ldT) * ldT * sizeof(typename AccOf<TV>::type)), s, ke, ptr,
+                   lidx, lval, F, (int32_t)ldF, (int32_t)J, (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap, nslots,
+                   T, fl.slot_maxlen, fl.ls, sh.blocks);
+        else
+            launch(k_project<TV, TF, TO>, sh.blocks, lds, s, ke, ptr, lidx, lval, F, (int32_t)ldF, (int32_t)J,
+                   (int32_t)ldT, (int32_t)sh.spw, (int32_t)sh.cap, nslots, T);
     }
     TK_LAUNCHED();
     return hipSuccess;

@@ -12,6 +12,8 @@ per-thread walk, which skips the long ones.
 * The reduced forms (FP32, mixed BF16 with the dual mode-3 projection,
   split-BF16) against the same oracle trajectory at their tolerances.
 * Run to run: the mixed decomposition twice, bitwise equal.
+* SP (Figure 5, shared random start) and HOOI (Figure 3, whose projections
+  write every slot: long slots get the same treatment) against the oracle.
 """
 import sys
 
@@ -91,3 +93,33 @@ def test_skewed_mp_run_to_run(tk, skewed):
     for a, b in zip(r1.factors, r2.factors):
         assert torch.equal(a, b)
     assert torch.equal(r1.core, r2.core)
+
+
+def test_skewed_sp_fp64_matches_oracle(tk, skewed):
+    # Slice Projection (Figure 5) from the SplitMix64 random start both sides
+    # draw (seed 0x5EED): its three projections take the same long-fibre path
+    dims, X, ref, di, dv = skewed
+    _say(f"skewed {dims}: sp fp64")
+    C0 = O.random_start(dims[2], CORE[2], 2, 0x5EED)
+    ref_sp = O.sp_algorithm(X, CORE, C0, 3, 0.0, fit="identity")
+    r = tk.sp(di, dv, dims, CORE, precision="fp64", max_iters=3, tol=0.0, seed=0x5EED, eig_tol=1e-14)
+    np.testing.assert_allclose(r.fits, ref_sp.fits, rtol=0, atol=1e-10)
+    g = r.core.cpu().numpy()
+    assert abs(np.linalg.norm(g) - np.linalg.norm(ref_sp.core)) <= 1e-10 * np.linalg.norm(ref_sp.core)
+
+
+@pytest.fixture(scope="module")
+def skewed_hooi(skewed):
+    dims, X, ref, di, dv = skewed
+    return O.hooi(X, CORE, 3, 0.0, fit="identity")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6), ("mixed", 1e-4)])
+def test_skewed_hooi_matches_oracle(tk, skewed, skewed_hooi, prec, tol):
+    # HOOI (Figure 3) projects into every slot: its slots of more than 16
+    # nonzeros get one workgroup each in the same launch
+    dims, X, ref, di, dv = skewed
+    _say(f"skewed {dims}: hooi {prec}")
+    kw = {"eig_tol": 1e-14} if prec == "fp64" else {}
+    r = tk.hooi(di, dv, dims, CORE, precision=prec, max_iters=3, tol=0.0, **kw)
+    assert max(abs(a - b) for a, b in zip(r.fits, skewed_hooi.fits)) <= tol
