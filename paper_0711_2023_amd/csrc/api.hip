@@ -172,7 +172,8 @@ struct Plan {
     int64_t nlong[3] = {0, 0, 0};
     int32_t maxlen[3] = {kLongFibreWide, kLongFibreWide, kLongFibreWide};
     // HOOI (projections that write every slot): the slots of each ordering
-    // with more than kLongFibreBf16 nonzeros
+    // with more than kLongFibreWide nonzeros (on the Zipf-skewed 1000^3
+    // tensor 8 beat 16: 214 against 358 us per projection, 91 us uniform)
     int32_t *ls[3] = {nullptr, nullptr, nullptr};
     int64_t nls[3] = {0, 0, 0};
 };
@@ -271,7 +272,7 @@ static void carve(Plan &p, Arena &ar) {
             p.Fc = ar.take<float>(p.I[2] * p.ldc);
         }
     } else if (p.algo == TK_ALGO_HOOI) {
-        for (int m = 0; m < 3; ++m) p.ls[m] = ar.take<int32_t>(nnz / (kLongFibreBf16 + 1) + 1);
+        for (int m = 0; m < 3; ++m) p.ls[m] = ar.take<int32_t>(nnz / (kLongFibreWide + 1) + 1);
         p.T[2] = ar.take<char>((int64_t)(p.nslots[2] * p.J[2] * es));
         if (prec == PBF16)
             p.T0f = ar.take<float>(p.nslots[0] * p.J[0]);
@@ -559,7 +560,7 @@ static FibreList fibres_of(const Plan &p, int m, bool zeroed_target) {
     if (p.ls[m] && p.nls[m] > 0) {  // every slot written: no zeroed target needed
         fl.ls = p.ls[m];
         fl.nls = p.nls[m];
-        fl.slot_maxlen = kLongFibreBf16;
+        fl.slot_maxlen = kLongFibreWide;
     }
     if (p.fib[m] && zeroed_target) {
         fl.fib = p.fib[m];
@@ -634,7 +635,7 @@ static int prep(Plan &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double
     if (p.ls[0]) {
         int32_t nls[3] = {0, 0, 0};
         for (int m = 0; m < 3; ++m) {
-            ST(long_fibres(p.ptr[m], p.nslots[m], kLongFibreBf16, p.nnz / (kLongFibreBf16 + 1) + 1, p.ls[m],
+            ST(long_fibres(p.ptr[m], p.nslots[m], kLongFibreWide, p.nnz / (kLongFibreWide + 1) + 1, p.ls[m],
                            p.counts, p.cursor, p.scan, p.flags, s));
             ST(hipMemcpyAsync(&nls[m], p.cursor + p.nslots[m], 4, hipMemcpyDeviceToHost, s));
             ST(hipStreamSynchronize(s));  // the next list reuses the scan buffers

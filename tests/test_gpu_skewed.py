@@ -116,7 +116,7 @@ def skewed_hooi(skewed):
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6), ("mixed", 1e-4)])
 def test_skewed_hooi_matches_oracle(tk, skewed, skewed_hooi, prec, tol):
-    # HOOI (Figure 3) projects into every slot: its slots of more than 16
+    # HOOI (Figure 3) projects into every slot: its slots of more than 8
     # nonzeros get one workgroup each in the same launch
     dims, X, ref, di, dv = skewed
     _say(f"skewed {dims}: hooi {prec}")
