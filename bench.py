@@ -629,8 +629,8 @@ def main():
             dual = not any(e["mode"] == 2 and e["precision"] == 2 for r in results for e in events(r, "project"))
             forms["core_projection_fp32"] = proj_roofline(
                 results, dims, J, nu, F, 1, False, 4,
-                "k_project_vec<float, float, float, ..., DUAL>, as k_project_fused<..., true> when the list has fibres of more "
-                "than 8 nonzeros (fibre list, core input + BF16 Gram copy)" if dual
+                "k_project_vec<float, float, float, ..., DUAL>, as k_project_fused<..., true> when the list has "
+                "fibres of more than 8 nonzeros (fibre list, core input + BF16 Gram copy)" if dual
                 else "k_project_vec<float, float, float> (fibre list, core input)", core_only=True, dual=dual)
             forms["core_projection_fp32"]["dual"] = dual
         forms[f"gram_{args.precision}"] = gram_roofline(results, dims, J, occ, pcode)

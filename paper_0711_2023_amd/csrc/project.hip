@@ -397,18 +397,19 @@ __global__ void __launch_bounds__(kProjThreads) k_project_vec(const int32_t *__r
                                                    nslots, T, Tlo, T2, ld2, maxlen);
 }
 
-// The fibres the vector kernel skips (more than maxlen nonzeros): one
-// workgroup per fibre of the list lf (k_project_fused). Its threads are (group, chunk) pairs:
-// the fibre's nonzeros are dealt round robin to G = kLongThreads / cps
-// groups, each thread accumulates its 16-byte output chunk over its group's
-// nonzeros, and the G partial rows are summed in LDS in group order (a fixed
-// order, the same bits on every run), then written as the vector kernel
-// writes a row (SPLIT: rounded part and remainder; DUAL: also the BF16 copy,
-// its padding columns zero).
 // Threads of a long-fibre workgroup (64 and 128 measured slower on the
 // Zipf-skewed 1000^3 tensor: 66-116 and 58-90 us per projection against
 // 61-79 us).
 constexpr int kLongThreads = 256;
+
+// The fibres the vector kernel skips (more than maxlen nonzeros): one
+// workgroup per fibre of the list lf (k_project_fused). Its threads are
+// (group, chunk) pairs: the fibre's nonzeros are dealt round robin to
+// G = kLongThreads / cps groups, each thread accumulates its 16-byte output
+// chunk over its group's nonzeros, and the G partial rows are summed in LDS
+// in group order (a fixed order, the same bits on every run), then written
+// as the vector kernel writes a row (SPLIT: rounded part and remainder;
+// DUAL: also the BF16 copy, its padding columns zero).
 template <class TV, class TF, class TO, bool SPLIT, bool DUAL>
 __device__ inline void project_long_body(int64_t blk, const int32_t *__restrict__ fptr,
                                          const int32_t *__restrict__ fib, const int32_t *__restrict__ lf,
