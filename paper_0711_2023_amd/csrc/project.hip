@@ -281,18 +281,38 @@ __device__ inline void project_vec_body(int64_t blk, const int32_t *__restrict__
     const int tid = threadIdx.x;
     const int64_t s0 = blk * spw;
     const int ns = (int)(s0 + spw <= nslots ? spw : nslots - s0);
-    // uniform across the workgroup (the descriptors below must be scalar)
-    const int32_t q0 = __builtin_amdgcn_readfirstlane(stage_ptr(ptr, s0, ns, sptr));
-    const int nq = __builtin_amdgcn_readfirstlane(sptr[ns] - q0);
+    // The run's first and end nonzero straight from memory (uniform across
+    // the workgroup: the descriptors below must be scalar), so that loading
+    // the nonzeros waits for nothing but these; then every staging load of a
+    // thread (pointers, fibre slots, nonzeros, SU of each per pass) is in
+    // flight before its LDS writes: one or two trips to memory per run
+    // instead of one per element a thread stages.
+    const int32_t q0 = __builtin_amdgcn_readfirstlane(ptr[s0]);
+    const int nq = __builtin_amdgcn_readfirstlane(ptr[s0 + ns] - q0);
     const int nst = nq < cap ? nq : cap;
-    for (int i = tid; i < nst; i += kProjThreads) {
-        NzPair<TV> e{};
-        e.i = lidx[q0 + i];
-        e.v = lval[q0 + i];
-        snz[i] = e;
+    constexpr int SU = 4;
+    for (int i0 = tid; i0 <= ns || i0 < nst; i0 += SU * kProjThreads) {
+        int32_t pv[SU], fv[SU];
+        NzPair<TV> e[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int i = i0 + u * kProjThreads;
+            pv[u] = i <= ns ? ptr[s0 + i] : 0;
+            fv[u] = FIB && i < ns ? fib[s0 + i] : 0;
+            e[u] = NzPair<TV>{};
+            if (i < nst) {
+                e[u].i = lidx[q0 + i];
+                e[u].v = lval[q0 + i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int i = i0 + u * kProjThreads;
+            if (i <= ns) sptr[i] = pv[u];
+            if (FIB && i < ns) sfib[i] = fv[u];
+            if (i < nst) snz[i] = e[u];
+        }
     }
-    if (FIB)
-        for (int i = tid; i < ns; i += kProjThreads) sfib[i] = fib[s0 + i];
     __syncthreads();
     const int cps = ldT / V;            // chunks per slot
     const int spi = kProjThreads / cps; // slots per pass of the workgroup
