@@ -499,26 +499,39 @@ hipError_t sumsq(const double *v, int64_t n, double *partials, double *out, hipS
 }
 
 // ------------------------------------------------------------------ HO-SVD Gram
-// One wave owns row i of H = X_(n) X_(n)^T and keeps it in LDS. The wave
-// walks the mode-n slice i (leaf-(n+1) ordering: slots (i, i_{n+2}), leaf
-// index i_{n+1}); each entry x of the slice belongs to the mode-n fibre
+// A workgroup of W waves owns row i of H = X_(n) X_(n)^T. The mode-n slice i
+// (leaf-(n+1) ordering: slots (i, i_{n+2}), leaf index i_{n+1}) is cut into W
+// contiguous slot ranges, one per wave, and each wave keeps its own partial
+// row in LDS. Each entry x of the slice belongs to the mode-n fibre
 // (i_{n+1}, i_{n+2}), whose entries (i', x') in the leaf-n ordering add
-// x * x' to H[i][i']. Lanes take 64 slots at a time and emit one product per
-// round; the lane owning column i' (i' mod 64) applies the round's products
-// in lane order, so every H[i][i'] is summed in an order fixed by the data.
-__global__ void __launch_bounds__(64) k_hosvd_gram(int32_t In, int32_t In1, int32_t In2, const int32_t *ptr_n,
-                                                   const int32_t *lidx_n, const double *lval_n, const int32_t *ptr_s,
-                                                   const int32_t *lidx_s, const double *lval_s, double *H) {
-    extern __shared__ double hrow[];
+// x * x' to H[i][i']. Lanes take 64 slots at a time and make one product per
+// round; the lane that made a product adds it to the partial row itself.
+// Lanes whose columns share a key (column mod kHosvdTag) within a round add
+// in lane order, one pass per depth of collision: the pending lanes post
+// their lane id to the key's tag with an LDS atomic minimum, the lane whose
+// id stands there adds and resets the tag. The partial rows are summed in
+// wave order at the end, so every H[i][i'] is summed in an order fixed by
+// the data and W.
+constexpr int kHosvdTag = 512;
+constexpr int kHosvdMaxWaves = 16;
+
+__global__ void __launch_bounds__(64 * kHosvdMaxWaves)
+    k_hosvd_gram(int32_t In, int32_t In1, int32_t In2, const int32_t *ptr_n, const int32_t *lidx_n,
+                 const double *lval_n, const int32_t *ptr_s, const int32_t *lidx_s, const double *lval_s, double *H) {
+    extern __shared__ double part[];
+    const int W = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = blockIdx.x;
-    const int lane = threadIdx.x;
-    for (int c = lane; c < In; c += 64) hrow[c] = 0.0;
+    double *hrow = part + (int64_t)w * In;
+    int32_t *tag = reinterpret_cast<int32_t *>(part + (int64_t)W * In) + w * kHosvdTag;
+    for (int c = threadIdx.x; c < W * In; c += blockDim.x) part[c] = 0.0;
+    for (int c = lane; c < kHosvdTag; c += 64) tag[c] = 64;
     __syncthreads();
     const int64_t slot0 = (int64_t)i * In2;
-    for (int64_t base = 0; base < In2; base += 64) {
+    const int64_t lo = (int64_t)In2 * w / W, hi = (int64_t)In2 * (w + 1) / W;
+    for (int64_t base = lo; base < hi; base += 64) {
         const int64_t i2 = base + lane;
         int32_t e = 0, e_end = 0;
-        if (i2 < In2) {
+        if (i2 < hi) {
             e = ptr_s[slot0 + i2];
             e_end = ptr_s[slot0 + i2 + 1];
         }
@@ -533,11 +546,11 @@ __global__ void __launch_bounds__(64) k_hosvd_gram(int32_t In, int32_t In1, int3
             q_end = ptr_n[f + 1];
             ++e;
         }
-        uint64_t act = __ballot(q < q_end);
-        while (act) {
-            int32_t ci = -1;
+        while (__ballot(q < q_end)) {
+            bool pend = q < q_end;
+            int32_t ci = 0;
             double cv = 0.0;
-            if (q < q_end) {
+            if (pend) {
                 ci = lidx_n[q];
                 cv = x * lval_n[q];
                 ++q;
@@ -550,20 +563,27 @@ __global__ void __launch_bounds__(64) k_hosvd_gram(int32_t In, int32_t In1, int3
                     ++e;
                 }
             }
-            uint64_t m = act;
-            while (m) {
-                int src = __builtin_ctzll(m);
-                m &= m - 1;
-                int32_t cis = __shfl(ci, src, 64);
-                double cvs = __shfl(cv, src, 64);
-                if ((cis & 63) == lane) hrow[cis] += cvs;
+            const int key = ci & (kHosvdTag - 1);
+            while (__ballot(pend)) {
+                if (pend) atomicMin(&tag[key], lane);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                if (pend && __hip_atomic_load(&tag[key], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) == lane) {
+                    double h = __hip_atomic_load(&hrow[ci], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    __hip_atomic_store(&hrow[ci], h + cv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    __hip_atomic_store(&tag[key], 64, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    pend = false;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
-            act = __ballot(q < q_end);
         }
     }
     __syncthreads();
     double *row = H + (int64_t)i * In;
-    for (int c = lane; c < In; c += 64) row[c] = hrow[c];
+    for (int c = threadIdx.x; c < In; c += blockDim.x) {
+        double s = part[c];
+        for (int v = 1; v < W; ++v) s += part[(int64_t)v * In + c];
+        row[c] = s;
+    }
 }
 
 // H <- (H + H^T) / 2, elementwise symmetric result.
@@ -589,8 +609,15 @@ hipError_t hosvd_gram(int n, const int64_t dims[3], const int32_t *ptr_n, const 
 hipError_t hosvd_gram_sized(int32_t In, int32_t In1, int32_t In2, const int32_t *ptr_n, const int32_t *lidx_n,
                             const double *lval_n, const int32_t *ptr_s, const int32_t *lidx_s, const double *lval_s,
                             double *H, hipStream_t s) {
-    size_t lds = sizeof(double) * (size_t)In;
-    k_hosvd_gram<<<In, 64, lds, s>>>(In, In1, In2, ptr_n, lidx_n, lval_n, ptr_s, lidx_s, lval_s, H);
+    // About four waves per SIMD over the rows; no more waves than 64-slot
+    // batches in a row; the partial rows and tags within the LDS budget.
+    const size_t per_wave = sizeof(double) * (size_t)In + sizeof(int32_t) * kHosvdTag;
+    int64_t W = std::min<int64_t>({kHosvdMaxWaves, std::max<int64_t>(1, ceil_div(4096, In)),
+                                   std::max<int64_t>(1, ceil_div(In2, 64))});
+    while (W > 1 && (size_t)W * per_wave > 65536) --W;
+    const size_t lds = (size_t)W * per_wave;
+    if (lds > 65536) lds_limit((const void *)k_hosvd_gram, lds);
+    k_hosvd_gram<<<In, (unsigned)(64 * W), lds, s>>>(In, In1, In2, ptr_n, lidx_n, lval_n, ptr_s, lidx_s, lval_s, H);
     TK_LAUNCHED();
     k_symmetrize<<<grid_for((int64_t)In * In), 256, 0, s>>>(H, In);
     TK_LAUNCHED();
