@@ -1067,8 +1067,14 @@ struct MProd {
     hipStream_t s;
     hipError_t operator()(const double *X, int64_t ldx, int w, double *Y, int64_t ldy, double alpha, double beta,
                           const double *E1, double gamma, const double *E2, int Lk) const {
+        // M is symmetric bit for bit (the Grams write both triangles from
+        // one sum; deflation keeps it), so it can be read as its own
+        // transpose: a wave's 16 x 4 operand load then spans 16 consecutive
+        // columns of 4 rows (4 cache lines) instead of 16 rows (16 lines),
+        // and every product term, and so the result, is the same. Products
+        // of at most 8 columns keep the row-major narrow kernel.
         if (!op)
-            return dgemm(n, w, n, M, n, false, X, ldx, Y, ldy, alpha, beta, E1, gamma, E2, L->split, L->split_elems,
+            return dgemm(n, w, n, M, n, w > 8, X, ldx, Y, ldy, alpha, beta, E1, gamma, E2, L->split, L->split_elems,
                          s);
         TK_HIP(op->apply(op->ctx, X, ldx, w, L->Yop, w, s));
         if (Lk > 0) {
