@@ -535,24 +535,55 @@ __global__ void __launch_bounds__(64 * NW) k_gram_dl(GramKArgs g, float *partial
             }
 }
 
+// The split partials of every tile pair summed into M, both triangles. A
+// workgroup takes one 32 x 32 block of a tile: each thread sums four of its
+// elements over the splits in split order (FP64, from zero), writes them to
+// the block's own place in rows of 32, and the block goes through LDS to be
+// written to its mirror in rows of 32 as well. Of a diagonal tile only the
+// blocks on and below the diagonal are read, and each element above the
+// diagonal takes its mirror's sum, so M is symmetric bit for bit.
+constexpr int kGramRedB = 32;
 template <class Acc>
-__global__ void k_gram_reduce(const Acc *partials, int splits_total, int TBK, int n, int64_t total, double *M) {
+__global__ void __launch_bounds__(256) k_gram_reduce(const Acc *partials, int splits_total, int TBK, int n,
+                                                     double *M) {
+    __shared__ double blk[kGramRedB][kGramRedB + 1];
+    const int nb = TBK / kGramRedB;
+    const int pair = blockIdx.x / (nb * nb), q = blockIdx.x - pair * nb * nb;
+    const int br = q / nb, bc = q - br * nb;
+    int ti, tj;
+    pair_decode(pair, ti, tj);
+    const bool dtile = ti == tj;
+    if (dtile && bc > br) return;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     const int64_t tile = (int64_t)TBK * TBK;
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        int pair = (int)(idx / tile);
-        int64_t rc = idx - pair * tile;
-        int r = (int)(rc / TBK), c = (int)(rc - (int64_t)r * TBK);
-        int ti, tj;
-        pair_decode(pair, ti, tj);
-        int64_t i = (int64_t)ti * TBK + r, j = (int64_t)tj * TBK + c;
-        if (i >= n || j >= n) continue;
-        if (ti == tj && c > r) continue;
-        double sum = 0.0;
-        const Acc *p = partials + (int64_t)pair * splits_total * tile + rc;
-        for (int s = 0; s < splits_total; ++s) sum += (double)p[s * tile];
-        M[i * n + j] = sum;
-        M[j * n + i] = sum;
+    const Acc *p = partials + (int64_t)pair * splits_total * tile + (int64_t)(br * kGramRedB) * TBK + bc * kGramRedB;
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < splits_total; ++s) {
+        const Acc *ps = p + s * tile;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sum[e] += (double)ps[(ty + 8 * e) * TBK + tx];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) blk[ty + 8 * e][tx] = sum[e];
+    __syncthreads();
+    const int64_t I0 = (int64_t)ti * TBK + br * kGramRedB, J0 = (int64_t)tj * TBK + bc * kGramRedB;
+    if (dtile && br == bc) {  // a block on the diagonal: both triangles from the lower one
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = ty + 8 * e, c = tx;
+            if (I0 + r < n && J0 + c < n) M[(I0 + r) * n + J0 + c] = c <= r ? blk[r][c] : blk[c][r];
+        }
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = ty + 8 * e, c = tx;
+        if (I0 + r < n && J0 + c < n) M[(I0 + r) * n + J0 + c] = blk[r][c];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int c = ty + 8 * e, r = tx;
+        if (J0 + c < n && I0 + r < n) M[(J0 + c) * n + I0 + r] = blk[r][c];
     }
 }
 
@@ -640,14 +671,13 @@ hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, v
               reinterpret_cast<uintptr_t>(g.t[t].base_b) % 16 == 0;
     }
     const unsigned blocks = (unsigned)(8 * p.npairs * ceil_div(p.splits_total, 8));
-    const int64_t total = (int64_t)p.npairs * p.TBK * p.TBK;
-    const int rblocks = (int)std::min<int64_t>(ceil_div(total, 256), 65536);
+    const unsigned rblocks = (unsigned)(p.npairs * (p.TBK / kGramRedB) * (p.TBK / kGramRedB));
     if (prec == P64) {
         TK_HIP((launch_gram<PolF64<32>, 32, 32, 2, 2>(g, vec, blocks, (double *)scratch, s)));
-        k_gram_reduce<double><<<rblocks, 256, 0, s>>>((const double *)scratch, p.splits_total, p.TBK, n, total, M);
+        k_gram_reduce<double><<<rblocks, 256, 0, s>>>((const double *)scratch, p.splits_total, p.TBK, n, M);
     } else if (prec == P32) {
         TK_HIP((launch_gram<PolF32<64>, 64, 64, 2, 2>(g, vec, blocks, (float *)scratch, s)));
-        k_gram_reduce<float><<<rblocks, 256, 0, s>>>((const float *)scratch, p.splits_total, p.TBK, n, total, M);
+        k_gram_reduce<float><<<rblocks, 256, 0, s>>>((const float *)scratch, p.splits_total, p.TBK, n, M);
     } else {
         // direct LDS staging where every operand's extent fits the 32-bit
         // offsets of a buffer load
@@ -662,7 +692,7 @@ hipError_t gram(int n, int prec, int nterms, const GramTerm *terms, double *M, v
             TK_HIP((launch_gram<PolBF16<64>, 64, 128, 4, 2>(g, vec, blocks, (float *)scratch, s)));
         else
             TK_HIP((launch_gram<PolBF16<64>, 64, 64, 2, 2>(g, vec, blocks, (float *)scratch, s)));
-        k_gram_reduce<float><<<rblocks, 256, 0, s>>>((const float *)scratch, p.splits_total, p.TBK, n, total, M);
+        k_gram_reduce<float><<<rblocks, 256, 0, s>>>((const float *)scratch, p.splits_total, p.TBK, n, M);
     }
     TK_LAUNCHED();
     return hipSuccess;
