@@ -459,13 +459,20 @@ __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double *Hin, in
         int nrot = 0;
         for (int r = 0; r < m - 1; ++r) {
             for (int k = tid; k < half; k += nth) {
+                // round r of the round-robin schedule: pair 0 is (0, 1 + r),
+                // pair k is (1 + (k + r) mod (m - 1), 1 + (m - 1 - k + r) mod
+                // (m - 1)); both sums lie below 2 (m - 1), so one conditional
+                // subtraction takes the remainder
                 int a, c;
                 if (k == 0) {
                     a = 0;
-                    c = 1 + (r % (m - 1));
+                    c = 1 + r;
                 } else {
-                    a = 1 + ((k + r) % (m - 1));
-                    c = 1 + ((m - 1 - k + r) % (m - 1));
+                    int x = k + r, y = m - 1 - k + r;
+                    if (x >= m - 1) x -= m - 1;
+                    if (y >= m - 1) y -= m - 1;
+                    a = 1 + x;
+                    c = 1 + y;
                 }
                 int p = a < c ? a : c, q = a < c ? c : a;
                 double cc = 1.0, ss = 0.0;
@@ -476,7 +483,7 @@ __global__ void __launch_bounds__(kJacobiThreads) k_jacobi(const double *Hin, in
                         double tau = (aqq - app) / (2.0 * apq);
                         double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         if (fabs(tau) > 1e150) t = 0.5 / tau;
-                        cc = 1.0 / sqrt(1.0 + t * t);
+                        cc = rsqrt(1.0 + t * t);
                         ss = t * cc;
                     }
                 }
