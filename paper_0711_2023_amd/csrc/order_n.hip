@@ -39,6 +39,14 @@ namespace {
 
 constexpr int kMaxJn = 128;
 constexpr int64_t kMaxStartDim = 8192;
+// Start Grams from the dense unfolding: X_(n) X_(n)^T costs about
+// nnz * (nnz / cells) * I_n products when walked sparsely, and 2 I_n cells
+// flops on FP64 MFMA when X_(n) is held dense; the dense form wins from a
+// density of about one cell in sixteen (measured at 100^4 with 10 % of the
+// cells: 4.2 ms per sparse Gram), and is taken there if the tensor has at
+// most kDenseStartCells cells (2 GiB of doubles).
+constexpr int64_t kDenseStartCells = int64_t(1) << 28;
+constexpr int64_t kDenseStartInv = 16;
 
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -90,6 +98,7 @@ struct PlanN {
     int64_t ybytes = 0;
     double *Mg = nullptr, *theta = nullptr, *Xblk[kMaxOrder] = {}, *core_split = nullptr;
     void *gram_scratch = nullptr, *eigw = nullptr;
+    double *dense = nullptr;  // dense unfolding for the start Grams (null: sparse form)
     int64_t core_split_elems = 0;
     bool blk_ok[kMaxOrder] = {};
     int sweep_solves[kMaxOrder] = {};
@@ -149,6 +158,17 @@ void plan_init(PlanN &p, int algo, int prec, const tk_coo *X, const int32_t *J, 
         const int v = 16 / elem_of(prec);
         p.ld[m] = (int)ceil_div(p.J[m], v) * v;
     }
+}
+
+// Whether the HO-SVD start Grams take the dense form (see kDenseStartCells).
+bool dense_start(const PlanN &p) {
+    if (p.init != TK_INIT_HOSVD) return false;
+    int64_t cells = 1;
+    for (int k = 0; k < p.N; ++k) {
+        cells *= p.I[k];
+        if (cells > kDenseStartCells) return false;
+    }
+    return p.nnz * kDenseStartInv >= cells;
 }
 
 void carve(PlanN &p, Arena &ar) {
@@ -227,6 +247,16 @@ void carve(PlanN &p, Arena &ar) {
                 if (j != n && j != m) k *= p.J[j];
             K[0] = k;
             gs = std::max(gs, gram_scratch_bytes((int)p.I[n], p.prec == P64 ? P64 : P32, 1, K, p.tune));
+        }
+    }
+    p.dense = nullptr;
+    if (dense_start(p)) {
+        int64_t cells = 1;
+        for (int k = 0; k < N; ++k) cells *= p.I[k];
+        p.dense = ar.take<double>(cells);
+        for (int n = 0; n < N; ++n) {
+            const int64_t K = cells / p.I[n];
+            gs = std::max(gs, gram_scratch_bytes((int)p.I[n], P64, 1, &K, p.tune));
         }
     }
     p.gram_scratch = ar.take<char>((int64_t)gs);
@@ -534,8 +564,28 @@ int run_eig(PlanN &p, int n, double *M, double *F, bool warm, const tk_opts *o, 
     return TK_OK;
 }
 
+// The leaf-n ordering's nonzeros written into the dense unfolding D
+// (I_n rows of S, zeroed beforehand): D[i_n][slot] = x; every cell holds at
+// most one nonzero once duplicates are summed.
+__global__ void k_dense_unfold(const int32_t *ptr, const int32_t *lidx, const double *lval, int64_t S, double *D) {
+    for (int64_t sl = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; sl < S; sl += (int64_t)gridDim.x * blockDim.x)
+        for (int32_t e = ptr[sl]; e < ptr[sl + 1]; ++e) D[(int64_t)lidx[e] * S + sl] = lval[e];
+}
+
 // A(n) from X_(n) X_(n)^T (Figure 2; the start of Figures 4 and 8).
 int hosvd_mode(PlanN &p, int n, double *F, const tk_opts *o, tk_stats *st, int *noconv, hipStream_t s) {
+    if (p.dense) {
+        // X_(n) dense: row i_n, column = slot of the leaf-n ordering (any
+        // fixed numbering of the other modes' cells gives the same Gram)
+        const int64_t S = p.nslots[n];
+        STN(fill_f64(p.dense, p.I[n] * S, 0.0, s));
+        k_dense_unfold<<<(unsigned)std::min<int64_t>(ceil_div(S, 256), 65536), 256, 0, s>>>(
+            p.ptr[n], p.lidx[n], p.lval64[n], S, p.dense);
+        STN(hipGetLastError());
+        const GramTerm t{p.dense, S, 0, S, 1};
+        STN(gram((int)p.I[n], P64, 1, &t, p.Mg, p.gram_scratch, s, p.tune));
+        return run_eig(p, n, p.Mg, F, false, o, st, noconv, s);
+    }
     const int n1 = (n + 1) % p.N;
     int64_t S = 1;
     for (int k = 0; k < p.N; ++k)

@@ -8,7 +8,12 @@ the order-N FP64 oracle (oracle/tucker_n.py: Figures 2, 4 and 8).
   reproduces the third-order GPU results; duplicates are summed; the order
   of distinct nonzeros changes no bit;
 * the paper's shape: 60^4 at 10 % density with core 20^4, HOOI and MP
-  against the oracle.
+  against the oracle;
+* the HO-SVD start Grams come from the dense unfolding where at least one
+  cell in sixteen holds a nonzero (the ragged tensor: 9000 nonzeros in
+  96,577 cells, and every other tensor above) and from the sparse walk
+  below that (31 x 27 x 19 x 23 with 6000 nonzeros in 365,769 cells): both
+  forms are checked against the oracle.
 """
 import sys
 
@@ -86,6 +91,27 @@ def test_hosvd_matches_oracle(tk, ragged):
     _say(f"order 4 hosvd: gpu {r.fits[0]:.12f} oracle {ref.fits[0]:.12f}")
     assert abs(r.fits[0] - ref.fits[0]) < 1e-10
     np.testing.assert_allclose(r.core.cpu().numpy(), ref.core, rtol=0, atol=1e-9 * np.abs(ref.core).max())
+
+
+@pytest.mark.parametrize("algo", ["mp", "hooi", "hosvd"])
+def test_sparse_start_matches_oracle(tk, algo):
+    idx, vals, dims = synth.uniform_sparse((31, 27, 19, 23), 6000, 405)
+    assert 16 * len(vals) < int(np.prod(dims))  # below the dense-start density
+    J = (4, 5, 3, 4)
+    X = ON.SparseTensorN(idx, vals, dims)
+    di, dv = _dev(idx, vals)
+    _say(f"order 4 sparse start {algo} fp64 {dims} core {J}")
+    if algo == "hosvd":
+        ref = ON.hosvd(X, J)
+        r = tk.hosvd(di, dv, dims, J)
+        assert abs(r.fits[0] - ref.fits[0]) < 1e-10
+        np.testing.assert_allclose(r.core.cpu().numpy(), ref.core, rtol=0, atol=1e-9 * np.abs(ref.core).max())
+    else:
+        ref = getattr(ON, algo)(X, J, 4, 0.0)
+        r = getattr(tk, algo)(di, dv, dims, J, precision="fp64", max_iters=4, tol=0.0)
+        d = np.max(np.abs(np.array(r.fits) - np.array(ref.fits)))
+        _say(f"  gpu {r.fits[-1]:.9f} oracle {ref.fits[-1]:.9f} max|d| {d:.2e}")
+        assert d < 1e-9
 
 
 @pytest.mark.parametrize("algo", ["mp", "hooi", "hosvd"])
