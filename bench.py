@@ -359,9 +359,22 @@ PREC_NAME = {0: "fp64", 1: "fp32", 2: "bf16"}
 
 
 def ld_of(J, s):
-    """Row stride of an MP projection: J rounded up to whole 16 bytes."""
+    """J rounded up to whole 16 bytes (rows of the low-occupancy product and
+    of FP32 / FP64 MP projections)."""
     v = 16 // s
     return (J + v - 1) // v * v
+
+
+def ld_mp(J, s):
+    """Row stride of an MP projection: 16-byte rows, and BF16 rows padded on
+    to whole 128-byte lines where that adds at most a sixth (the library's
+    rule)."""
+    ld = ld_of(J, s)
+    if s == 2:
+        line = (ld * 2 + 127) // 128 * 64
+        if 6 * line <= 7 * ld:
+            return line
+    return ld
 
 
 def proj_min_bytes(nnz, F, J, s, fp64):
@@ -406,9 +419,9 @@ def proj_roofline(results, dims, J, nu, F, prec, fp64, fs, kernel, core_only=Fal
             if e["precision"] != prec or (core_only and e["mode"] != 2):
                 continue
             m, s = e["mode"], ELEM[prec]
-            ld = ld_of(J[m], 4) if core_only else ld_of(J[m], s)
+            ld = ld_of(J[m], 4) if core_only else ld_mp(J[m], s)
             byt += proj_min_bytes(nu, F[m], J[m], s, fp64) + (F[m] * J[m] * 2 if dual else 0)
-            exe += proj_exec_bytes(nu, F[m], J[m], s, fp64, dims[m], fs, ld) + (F[m] * ld * 2 if dual else 0)
+            exe += proj_exec_bytes(nu, F[m], J[m], s, fp64, dims[m], fs, ld) + (F[m] * ld_mp(J[m], 2) * 2 if dual else 0)
             ms += e["ms"]
             n += 1
     if n == 0:

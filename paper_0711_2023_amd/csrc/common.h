@@ -232,7 +232,7 @@ hipError_t project_split(const int32_t *ptr, const int32_t *lidx, const float *l
                          const Tune &tn = Tune(), KernelEvents ke = KernelEvents(), FibreList fl = FibreList());
 // FP32 projection into T over the fibre list fl (rows of ld, a multiple of
 // 4, as the factor rows F) that also writes each output rounded to BF16 into
-// T2 (rows of ld2 = ld or ld + 4, a multiple of 8; columns from ld on are
+// T2 (rows of ld2 = ld or ld + 4 + 8k, a multiple of 8; columns from ld on are
 // written as zeros, the rows of empty fibres keep what T2 holds), in one pass
 // over the nonzeros. Only where
 // project_dual_ok holds (the fibre-list vector form with 32-bit offsets for

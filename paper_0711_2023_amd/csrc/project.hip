@@ -353,10 +353,13 @@ __device__ inline void project_vec_body(int64_t blk, const int32_t *__restrict__
             const uint32_t off2 = ((uint32_t)orow * (uint32_t)ld2 + (uint32_t)r * 4u) * 2u;
             const __amdgpu_buffer_rsrc_t r2 = buf_rsrc(T2 + row0 * ld2, (uint32_t)nrows * (uint32_t)ld2 * 2u);
             if (r == cps - 1 && ld2 > ldT) {
-                // the row's last chunk also writes the 4 zero padding columns:
-                // whole rows, with no holes that split the memory lines
+                // the row's last chunk also writes the zero padding columns
+                // (4, then 8 per further store): whole rows, with no holes
+                // that split the memory lines
                 const u32x2 hv = __builtin_bit_cast(u32x2, h);
                 __builtin_amdgcn_raw_buffer_store_b128(u32x4{hv[0], hv[1], 0u, 0u}, r2, off2, 0, 0);
+                for (uint32_t z = 16u; z < (uint32_t)(ld2 - ldT + 4) * 2u; z += 16u)
+                    __builtin_amdgcn_raw_buffer_store_b128(u32x4{0u, 0u, 0u, 0u}, r2, off2 + z, 0, 0);
             } else {
                 __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, h), r2, off2, 0, 0);
             }
@@ -480,14 +483,15 @@ __device__ inline void project_long_body(int64_t blk, const int32_t *__restrict_
         for (int t = 0; t < V; ++t) o2[t] = (TO)(sum[t] - (Acc)o[t]);
         *reinterpret_cast<typename Vec16<TO>::type *>(Tlo + row * ldT + tid * V) = o2;
     }
-    if (DUAL) {  // V = 4 FP32 outputs -> 4 BF16, the row's last chunk with the 4 padding zeros
+    if (DUAL) {  // V = 4 FP32 outputs -> 4 BF16, the row's last chunk with the padding zeros
         typedef bf16 bf16x4 __attribute__((ext_vector_type(4)));
         bf16x4 h;
 #pragma unroll
         for (int t = 0; t < 4; ++t) h[t] = (bf16)sum[t];
         bf16 *dst = T2 + row * ld2 + tid * 4;
         *reinterpret_cast<bf16x4 *>(dst) = h;
-        if (tid == cps - 1 && ld2 > ldT) *reinterpret_cast<bf16x4 *>(dst + 4) = bf16x4{0, 0, 0, 0};
+        if (tid == cps - 1)
+            for (int c = ldT; c < ld2; c += 4) *reinterpret_cast<bf16x4 *>(T2 + row * ld2 + c) = bf16x4{0, 0, 0, 0};
     }
 }
 
@@ -655,7 +659,7 @@ bool project_dual_ok(const float *F, int64_t rowsF, int ld, const float *T, cons
                      int64_t nslots, int64_t nnz, const Tune &tn, const FibreList &fl) {
     return nslots > 0 && ld > 0 &&
            vec_ok<float, float, float>(F, rowsF, ld, T, proj_shape(nslots, ld, tn, 4096).spw, nnz) &&
-           ((uintptr_t)T2 & 15) == 0 && (ld2 == ld || ld2 == ld + 4) && ld2 % 8 == 0 &&
+           ((uintptr_t)T2 & 15) == 0 && (ld2 == ld || (ld2 >= ld + 4 && (ld2 - ld - 4) % 8 == 0)) && ld2 % 8 == 0 &&
            fib_ok<float>(fl, nslots, ld) &&
            nslots * (int64_t)ld2 * 2 < (int64_t(1) << 31);
 }
