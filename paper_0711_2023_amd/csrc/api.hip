@@ -465,7 +465,7 @@ static void plan_init(Plan &p, int algo, int prec, const tk_coo *X, const int32_
         p.ldT[m] = p.ldG[m];
         // BF16 rows padded on to whole 128-byte lines where that adds at most
         // a sixth to the row: the projection then stores whole lines (at
-        // J = 50, rows of 64 instead of 56: 24.8 -> 22.6 us per launch at
+        // J = 50, rows of 64 instead of 56: 24.8 -> 22.0 us per launch at
         // 1000^3), and the Grams skip the extra columns
         const int64_t line = ceil_div((int64_t)p.ldG[m] * 2, 128) * 64;
         if (slice_algo(algo) && prec == PBF16 && 6 * line <= 7 * (int64_t)p.ldG[m]) p.ldT[m] = (int)line;
