@@ -887,7 +887,7 @@ def skewed_leg(tk, dev, dims_u, J, uniform_launch_ms):
     distinct nonzeros whose indices follow a truncated Zipf law (exponent
     1.0, synth.skewed_sparse), core 50^3, MP mixed, 4 sweeps. Per-mode
     projection time per launch (sweeps 2..4) beside the uniform tensor's, the
-    fibres the long-fibre workgroups take (more than 16 nonzeros for the BF16
+    fibres the long-fibre workgroups take (more than 12 nonzeros for the BF16
     projections of modes 1 and 2, more than 8 for mode 3's FP32 one) and their
     share of the nonzeros, and the projected nnz/s over the sweep's
     projections."""
@@ -896,7 +896,7 @@ def skewed_leg(tk, dev, dims_u, J, uniform_launch_ms):
     import synth
     idx, vals, dims = synth.skewed_sparse(dims_u, 1_000_000, 1.0, 7)
     fib, longf, longnz = [], [], []
-    for m, lim in zip(range(3), (16, 16, 8)):
+    for m, lim in zip(range(3), (12, 12, 8)):
         a, b = [n for n in range(3) if n != m]
         _, cnt = np.unique(idx[a].astype(np.int64) * dims[b] + idx[b], return_counts=True)
         fib.append(int(cnt.size))

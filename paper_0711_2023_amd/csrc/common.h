@@ -202,13 +202,14 @@ struct FibreList {
 };
 // Fibres with more nonzeros than a limit go to the one-workgroup-per-fibre
 // projection (one thread walking them would hold its workgroup back). The
-// limit depends on the output row: BF16 rows (7 chunks of 16 bytes at J = 50,
-// so 36 nonzero groups per long-fibre workgroup) keep fibres up to 16 in the
+// limit depends on the output row: BF16 rows (8 chunks of 16 bytes at J = 50,
+// so 32 nonzero groups per long-fibre workgroup) keep fibres up to 12 in the
 // per-thread walk, FP32 and FP64 rows (13 or 25 chunks, fewer groups) up to
 // 8. On a Zipf-skewed 1000^3 tensor with 1M nonzeros, BF16 projections took
-// 57, 43-47 and 40-41 us at limits 8, 12 and 16, FP32 ones 40, 48-51 and
-// 55-57 us; uniform tensors were unchanged at every limit.
-constexpr int32_t kLongFibreBf16 = 16;
+// 54, 45, 40 and 42 us at limits 8, 10, 12 and 16 (50 us at 24), FP32 ones
+// 40, 48-51 and 55-57 us at 8, 12 and 16; uniform tensors were unchanged at
+// every limit.
+constexpr int32_t kLongFibreBf16 = 12;
 constexpr int32_t kLongFibreWide = 8;
 // T[slot * ldT + r] = sum over the slot's entries of lval * F[lidx * ldF + r]
 // for r < J, zero for J <= r < ldT; slots = I_hi * I_lo, dense and

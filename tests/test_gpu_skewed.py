@@ -1,6 +1,6 @@
 """Skewed tensors: every index drawn from a truncated Zipf law (synth.skewed_sparse),
 so a few fibres hold hundreds of nonzeros while most hold one or two, as in
-term-frequency data. Fibres with more than 16 (BF16 rows) or 8 (FP32 and FP64
+term-frequency data. Fibres with more than 12 (BF16 rows) or 8 (FP32 and FP64
 rows) nonzeros are projected by one workgroup each, in the same launch as the
 rest (k_project_fused: nonzeros dealt round robin to thread groups, partial
 rows summed in a fixed order); the rest go to the
