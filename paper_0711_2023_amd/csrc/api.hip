@@ -148,7 +148,7 @@ struct Plan {
     void *eigw;
     double *theta;
     float *F32[3] = {nullptr, nullptr, nullptr};
-    bf16 *F16[3] = {nullptr, nullptr, nullptr};
+    bf16 *Fbf[3] = {nullptr, nullptr, nullptr};  // BF16 factor copies (rows of J), MFMA operands of the TTMc
     void *Fp[3] = {nullptr, nullptr, nullptr};  // MP: factor rows padded to ldT, zero padding
                                                 //     (FP64 / FP32; FP16 for BF16 T)
     double *Th = nullptr;  // FP64 T(2) = X x_3 C^T (J3 columns) for the HO-SVD core
@@ -336,7 +336,7 @@ static void carve(Plan &p, Arena &ar) {
         }
         for (int n = 0; n < 3; ++n) {
             p.F32[n] = prec != P64 ? ar.take<float>(p.I[n] * p.J[n]) : nullptr;
-            p.F16[n] = prec == PBF16 ? ar.take<bf16>(p.I[n] * p.J[n]) : nullptr;
+            p.Fbf[n] = prec == PBF16 ? ar.take<bf16>(p.I[n] * p.J[n]) : nullptr;
             // padded factor rows for the projections: FP16 for BF16 T (more
             // significand than BF16 for entries of orthonormal columns, and
             // the projection's FMA takes FP16 operands directly), FP32 for
@@ -727,7 +727,7 @@ static hipError_t project_m(Plan &p, int m, const double *F64, void *T, int out_
 static hipError_t refresh_copies(Plan &p, int n, const double *F, hipStream_t s) {
     const int64_t cnt = p.I[n] * p.J[n];
     if (p.F32[n]) TK_HIP(convert_f64<float>(F, p.F32[n], cnt, s));
-    if (p.F16[n]) TK_HIP(convert_f64<bf16>(F, p.F16[n], cnt, s));
+    if (p.Fbf[n]) TK_HIP(convert_f64<bf16>(F, p.Fbf[n], cnt, s));
     if (p.Fc && n == 2) TK_HIP(pad_rows<float>(F, p.I[2], p.J[2], p.ldc, p.Fc, s));
     if (p.Fp[n]) {
         if (p.prec == P64)
@@ -1314,7 +1314,7 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
     for (int t = 1; t <= std::max(maxit, 1); ++t) {
         const bool last_only = (maxit == 0);
         ST(project_m(p, 2, C, p.T[2], tprec, s, 0, tm.kernel(kProj, 2, tprec)));
-        const void *Bop = prec == P64 ? (const void *)B : (prec == P32 ? (const void *)p.F32[1] : (const void *)p.F16[1]);
+        const void *Bop = prec == P64 ? (const void *)B : (prec == P32 ? (const void *)p.F32[1] : (const void *)p.Fbf[1]);
         // mode 0: Y0[q][i0][r2] = sum_i1 B[i1][q] T2[i1][i0][r2]
         tm.begin(kTtmc, 0, kprec01);
         ST(ttm(J1, (int)(I0 * J2), (int)I1, 1, Bop, J1, p.T[2], I0 * J2, 0, p.Y, I0 * J2, 0, kprec01,
@@ -1337,7 +1337,7 @@ extern "C" int tucker_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, 
         if (last_only) {
             // max_iters == 0: A only, then the core below
         }
-        const void *Aop = prec == P64 ? (const void *)A : (prec == P32 ? (const void *)p.F32[0] : (const void *)p.F16[0]);
+        const void *Aop = prec == P64 ? (const void *)A : (prec == P32 ? (const void *)p.F32[0] : (const void *)p.Fbf[0]);
         // mode 1: Y1[i1][p][r2] = sum_i0 A[i0][p] T2[i1][i0][r2]
         if (!last_only) {
             tm.begin(kTtmc, 1, kprec01);

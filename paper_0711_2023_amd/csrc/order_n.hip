@@ -93,7 +93,7 @@ struct PlanN {
     int ldc = 0;
     void *Fp[kMaxOrder] = {};
     float *F32[kMaxOrder] = {};
-    bf16 *F16[kMaxOrder] = {};
+    bf16 *Fbf[kMaxOrder] = {};  // BF16 factor copies (rows of J), MFMA operands
     void *Y[2] = {nullptr, nullptr};
     int64_t ybytes = 0;
     double *Mg = nullptr, *theta = nullptr, *Xblk[kMaxOrder] = {}, *core_split = nullptr;
@@ -273,7 +273,7 @@ void carve(PlanN &p, Arena &ar) {
     for (int n = 0; n < N; ++n) {
         p.Fp[n] = ar.take<char>(p.I[n] * p.ld[n] * (int64_t)(p.prec == P64 ? 8 : (p.prec == P32 ? 4 : 2)));
         p.F32[n] = p.prec != P64 ? ar.take<float>(p.I[n] * p.J[n]) : nullptr;
-        p.F16[n] = p.prec == PBF16 ? ar.take<bf16>(p.I[n] * p.J[n]) : nullptr;
+        p.Fbf[n] = p.prec == PBF16 ? ar.take<bf16>(p.I[n] * p.J[n]) : nullptr;
     }
     int64_t nJ = 1;
     for (int n = 0; n < N; ++n) nJ *= p.J[n];
@@ -405,7 +405,7 @@ int prep(PlanN &p, const tk_coo *X, hipStream_t s, int64_t *nu_out, double *nx2_
 hipError_t refresh(PlanN &p, int n, const double *F, hipStream_t s) {
     const int64_t cnt = p.I[n] * p.J[n];
     if (p.F32[n]) TK_HIP(convert_f64<float>(F, p.F32[n], cnt, s));
-    if (p.F16[n]) TK_HIP(convert_f64<bf16>(F, p.F16[n], cnt, s));
+    if (p.Fbf[n]) TK_HIP(convert_f64<bf16>(F, p.Fbf[n], cnt, s));
     if (p.prec == P64)
         TK_HIP(pad_rows<double>(F, p.I[n], p.J[n], p.ld[n], (double *)p.Fp[n], s));
     else if (p.prec == P32)
@@ -769,7 +769,7 @@ int order_n_hooi(const tk_coo *X, const int32_t *J, const tk_opts *o, double *co
                 if (sh.mode[a] == n) continue;
                 const int k = sh.mode[a];
                 const void *A = kind == P64 ? (const void *)F[k]
-                                : (kind == P32 ? (const void *)p.F32[k] : (const void *)p.F16[k]);
+                                : (kind == P32 ? (const void *)p.F32[k] : (const void *)p.Fbf[k]);
                 STN(contract(p, src, sh, a, A, kind, yt, p.Y[buf], s));
                 src = p.Y[buf];
                 buf ^= 1;
